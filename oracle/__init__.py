@@ -1,0 +1,190 @@
+"""FP64 CPU oracle for the DirectLiNGAM causal-ordering search.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the yardstick the GPU library is
+checked against.  Only the test-suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it.  The GPU library neither
+imports nor links it, and shares no code with it.
+
+The arithmetic lives in ``lingam_oracle.c`` (plain C, FP64, OpenMP over
+candidate variables only); this module compiles it with gcc and wraps it with
+ctypes and numpy.  Each wrapper names the part of the paper it follows:
+
+* :func:`entropy` -- maximum-entropy approximation H(u) used by the pairwise
+  likelihood-ratio measure (the measure DirectLiNGAM's ``_diff_mutual_info``
+  stands for, Section 2.2 and the Hyvarinen-Smith measure cited in Section 1).
+* :func:`pair_measure` -- one ordered pair of Algorithm 1: standardize both
+  columns, the two least-squares residuals, the difference of mutual
+  informations.
+* :func:`causal_order` -- the DirectLiNGAM outer loop (Section 2.2) around
+  Algorithm 1, in literal or memoised ("table") mode, with optional teacher
+  forcing.
+* :func:`step_measures_rows` -- k_list entries of chosen rows at one step.
+* :func:`residualize` -- least-squares removal of one variable's effect.
+* :func:`var_fit` -- least-squares VAR fit with intercept (Section 3.3, the
+  first stage of VarLiNGAM).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lingam_oracle.c")
+_LIB = os.path.join(_HERE, "liblingam_oracle.so")
+
+OK, INVALID, DEGENERATE, NOMEM = 0, -1, -2, -3
+_lock = threading.Lock()
+_lib = None
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O3, OpenMP, no fast-math). Returns the path."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O3", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.lo_entropy.argtypes = [P, i64]
+        lib.lo_entropy.restype = dbl
+        lib.lo_entropy_moments.argtypes = [P, i64, P, P]
+        lib.lo_entropy_moments.restype = None
+        lib.lo_entropy_constants.argtypes = [P, P, P, P]
+        lib.lo_entropy_constants.restype = None
+        lib.lo_pair_measure.argtypes = [P, P, i64, P]
+        lib.lo_pair_measure.restype = ctypes.c_int
+        lib.lo_causal_order.argtypes = [P, i64, i64, i64, P, i32, i32, P, P, P]
+        lib.lo_causal_order.restype = ctypes.c_int
+        lib.lo_step_measures_rows.argtypes = [P, i64, i64, i64, P, i32, P, i32, P]
+        lib.lo_step_measures_rows.restype = ctypes.c_int
+        lib.lo_residualize.argtypes = [P, i64, i64, i64, P, i32, i32]
+        lib.lo_residualize.restype = ctypes.c_int
+        lib.lo_var_fit.argtypes = [P, i64, i64, i64, i32, P, P]
+        lib.lo_var_fit.restype = ctypes.c_int
+        lib.lo_num_threads.argtypes = []
+        lib.lo_num_threads.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise OracleError(code, what)
+
+
+def num_threads() -> int:
+    return int(_load().lo_num_threads())
+
+
+def constants() -> dict:
+    """k1, k2, gamma and H(nu) as the oracle uses them."""
+    vals = [ctypes.c_double() for _ in range(4)]
+    _load().lo_entropy_constants(*[ctypes.byref(v) for v in vals])
+    return dict(zip(("k1", "k2", "gamma", "hnu"), (v.value for v in vals)))
+
+
+def entropy(u) -> float:
+    """H(u) of a sample assumed to have unit variance."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return float(_load().lo_entropy(_ptr(u), u.size))
+
+
+def entropy_moments(u) -> tuple[float, float]:
+    """(E log cosh u, E u exp(-u^2/2))."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _load().lo_entropy_moments(_ptr(u), u.size, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def pair_measure(xi, xj) -> float:
+    """diff(i, j) of Algorithm 1 for raw columns xi, xj (positive: i precedes j)."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    xj = np.ascontiguousarray(xj, dtype=np.float64)
+    assert xi.shape == xj.shape and xi.ndim == 1
+    out = ctypes.c_double()
+    _check(_load().lo_pair_measure(_ptr(xi), _ptr(xj), xi.size, ctypes.byref(out)),
+           "pair_measure")
+    return out.value
+
+
+def causal_order(X, forced=None, mode: str = "literal", with_measures: bool = False):
+    """Causal order of the columns of X (n x d).
+
+    X is cast to float32 first (the GPU receives FP32 data), then to FP64.
+    Returns ``order`` (int32[d]) or ``(order, measures[(d-1), d], gaps[d-1])``.
+    """
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    order = np.empty(d, dtype=np.int32)
+    meas = np.empty((max(d - 1, 1), d), dtype=np.float64) if with_measures else None
+    gaps = np.empty(max(d - 1, 1), dtype=np.float64) if with_measures else None
+    f = None if forced is None else np.ascontiguousarray(forced, dtype=np.int32)
+    flen = 0 if f is None else f.size
+    code = _load().lo_causal_order(
+        _ptr(X), n, d, d, None if f is None else _ptr(f), flen,
+        {"literal": 0, "table": 1}[mode], _ptr(order),
+        None if meas is None else _ptr(meas), None if gaps is None else _ptr(gaps))
+    _check(code, "causal_order")
+    if with_measures:
+        return order, meas[: d - 1], gaps[: d - 1]
+    return order
+
+
+def step_measures_rows(X, prefix, rows) -> np.ndarray:
+    """k_list entries for original columns ``rows`` after regressing out ``prefix``."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    p = np.ascontiguousarray(prefix, dtype=np.int32)
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.empty(r.size, dtype=np.float64)
+    code = _load().lo_step_measures_rows(_ptr(X), n, d, d, _ptr(p) if p.size else None,
+                                         p.size, _ptr(r) if r.size else None, r.size, _ptr(out))
+    _check(code, "step_measures_rows")
+    return out
+
+
+def residualize(X, active, exo) -> np.ndarray:
+    """Copy of X (FP64) with ``exo`` regressed out of every other ``active`` column."""
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    n, d = X.shape
+    a = np.ascontiguousarray(active, dtype=np.int32)
+    _check(_load().lo_residualize(_ptr(X), n, d, d, _ptr(a), a.size, int(exo)), "residualize")
+    return X
+
+
+def var_fit(X, lags: int = 1):
+    """Least-squares VAR(lags) with intercept. Returns (coef[(1+d*lags), d], resid)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T, d = X.shape
+    coef = np.empty((1 + d * lags, d), dtype=np.float64)
+    resid = np.empty((T - lags, d), dtype=np.float64)
+    _check(_load().lo_var_fit(_ptr(X), T, d, d, int(lags), _ptr(coef), _ptr(resid)), "var_fit")
+    return coef, resid
