@@ -1,0 +1,170 @@
+"""Benchmark: DirectLiNGAM causal ordering on one MI355X.
+
+One "step" is one full causal ordering (all d - 1 search steps: pair moments,
+entropies and likelihood ratios, per-variable measures, selection,
+residualisation) of the gene-expression-scale workload: a synthetic linear
+non-Gaussian SEM with d = 1024 variables and n = 8192 samples (ER DAG,
+expected in-degree 4, |w| in [0.5, 2], per-variable noise from {uniform,
+Laplace, exponential - 1}, unit variance).  The input is resident in HBM
+before the timed region.
+
+Metric: sample-pair evaluations per second, where one evaluation is one
+residual-entropy term (log cosh and Gaussian-weighted moment) of one ordered
+pair at one sample; an ordering does n (d^3 - d) / 3 of them.  Also reported:
+the full-ordering time (ms_per_step), the roofline of the pair-moment kernel
+(timed with HIP events on the launch stream over the timed region) and the
+FP64 oracle timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Pair-kernel roofline (VALU-issue bound; see the design notes):
+# one evaluation = 8 FP32 VALU ops + 2 v_exp_f32 (the log of a product is
+# taken once per 16 samples and is not counted).  gfx950 issues 128 FP32
+# lane-ops/clk/CU and 32 transcendental lane-ops/clk/CU from the same issue
+# slots, so an evaluation costs 8/128 + 2/32 CU-clocks.
+N_CU, CLOCK_HZ = 256, 2.4e9
+VALU_PER_EVAL, TRANS_PER_EVAL = 8, 2
+PEAK_EVALS = N_CU * CLOCK_HZ / (VALU_PER_EVAL / 128.0 + TRANS_PER_EVAL / 32.0)
+
+
+def evals_per_ordering(n: int, d: int) -> float:
+    return float(n) * (d ** 3 - d) / 3.0
+
+
+def cpu_baseline(X32, n: int, d: int, target_s: float = 15.0) -> dict:
+    """Time the FP64 oracle (literal Algorithm 1) on k_list rows of step 0."""
+    import numpy as np
+    import oracle
+
+    threads = oracle.num_threads()
+    # calibrate with one row per thread, then scale to ~target_s
+    rows = np.arange(threads, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.step_measures_rows(X32, np.empty(0, np.int32), rows)
+    t1 = time.perf_counter() - t0
+    reps = max(1, min(64, int(target_s / max(t1, 1e-3))))
+    rows = np.arange(min(d, threads * reps), dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.step_measures_rows(X32, np.empty(0, np.int32), rows)
+    dt = time.perf_counter() - t0
+    evals = rows.size * (d - 1) * float(n)  # the algorithmic share of those rows
+    return {"value": evals / dt, "unit": "sample-pair evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"k_list of {rows.size} variables at step 0 of the d={d}, n={n} "
+                      f"workload (literal Algorithm 1, FP64, {dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--d", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the ordering is single-GPU here); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2403_03772_amd as lg
+    from paper_2403_03772_amd import synth
+
+    d, n = args.d, args.n
+    sem = synth.workload_gene_scale(seed=args.seed, d=d, n=n)
+    X32 = np.ascontiguousarray(sem.X, dtype=np.float32)
+    X = torch.as_tensor(X32, device="cuda:0")
+    ws = torch.empty(lg.workspace_size(n, d), dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        lg.causal_order(X, workspace=ws)
+    torch.cuda.synchronize()
+
+    pair_ms = pair_evals = 0.0
+    pair_launches = 0
+    gram_ms = gram_flops = resid_ms = resid_bytes = 0.0
+    orders = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = lg.causal_order(X, workspace=ws, profile=True)
+        p = out["profile"]
+        pair_ms += p.pair_ms
+        pair_launches += p.pair_launches
+        pair_evals += p.pair_evals
+        gram_ms += p.gram_ms
+        gram_flops += p.gram_flops
+        resid_ms += p.resid_ms
+        resid_bytes += p.resid_bytes
+        orders.append(out["order"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    o0 = orders[0].cpu().numpy()
+    for o in orders[1:]:
+        assert np.array_equal(o.cpu().numpy(), o0), "orderings differ between steps"
+    ms_per_step = dt * 1e3 / args.steps
+    evals = evals_per_ordering(n, d)
+    value = evals * args.steps / dt
+    achieved = pair_evals / (pair_ms * 1e-3)
+    rec = {
+        "metric": "sample-pair evals/s (plain DirectLiNGAM ordering, d=1024, n=8192)",
+        "value": value,
+        "unit": "sample-pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "full_ordering_ms": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gene-expression-scale linear non-Gaussian SEM, plain ordering",
+                   "d": d, "n": n, "seed": args.seed, "indeg": 4, "form": "plain"},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_pair",
+            "achieved": achieved / 1e9,
+            "peak": PEAK_EVALS / 1e9,
+            "unit": "Geval/s",
+            "frac": achieved / PEAK_EVALS,
+            "traffic": None,
+            "avg_launch_ms": pair_ms / max(pair_launches, 1),
+            "launches": pair_launches,
+            "share_of_step": pair_ms / (dt * 1e3),
+        },
+        "gram": {"bound": "mfma", "ms": gram_ms / args.steps,
+                 "achieved": gram_flops / (gram_ms * 1e-3) / 1e12 if gram_ms else None,
+                 "peak": 78.6, "unit": "TFLOP/s (fp64)"},
+        "resid": {"bound": "hbm", "ms": resid_ms / args.steps,
+                  "achieved": resid_bytes / (resid_ms * 1e-3) / 1e9 if resid_ms else None,
+                  "peak": 8000.0, "unit": "GB/s"},
+        "learned": None,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(X32, n, d)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

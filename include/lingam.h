@@ -1,0 +1,129 @@
+/*
+ * lingam.h -- C ABI of the MI355X (gfx950) DirectLiNGAM causal-ordering library.
+ *
+ * The library computes the causal-ordering search of DirectLiNGAM
+ * (AcceleratedLiNGAM, arXiv 2403.03772, Section 2.2 and Algorithm 1): at each
+ * step it standardizes the remaining residual columns, scores every pair with
+ * the pairwise likelihood-ratio measure built on the maximum-entropy
+ * approximation of differential entropy, accumulates the per-variable measure
+ * k_i = sum_j min(0, R(i,j))^2, takes the most exogenous variable (largest
+ * -k_i), and regresses it out of all the others (Section 2.2).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller unless a comment
+ *     says "host".  The library never allocates device memory: callers pass a
+ *     workspace sized by the matching *_workspace_size() query.
+ *   - Sample matrices are FP32, row-major n x d with leading dimension
+ *     ldx >= d (samples in rows, variables in columns: the dataset X[m, dim]
+ *     of Algorithm 1).
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *   - Host-detectable errors (NULL pointer, bad size, workspace too small) are
+ *     returned synchronously and enqueue nothing.  Errors the device detects
+ *     (non-finite input, zero-variance column, collinear pair) are returned
+ *     when the call synchronizes (LINGAM_FLAG_NO_SYNC not set), and are also
+ *     copied to opts->dev_status when that pointer is given.
+ *   - lingam_last_error() returns a thread-local message for the last
+ *     non-OK status of the calling thread.
+ */
+#ifndef LINGAM_MI355X_H
+#define LINGAM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LINGAM_OK = 0,
+  LINGAM_E_INVALID = -1,     /* bad argument (host check) or bad forced order */
+  LINGAM_E_DEGENERATE = -2,  /* zero variance, |corr| >= 1 - 1e-12, non-finite data */
+  LINGAM_E_HIP = -3,         /* a HIP runtime call failed */
+  LINGAM_E_WORKSPACE = -4,   /* workspace NULL or smaller than required */
+  LINGAM_E_UNSUPPORTED = -5  /* size beyond the supported range */
+} lingam_status;
+
+/* opts->flags */
+#define LINGAM_FLAG_NO_SYNC 1u /* return after enqueueing; device errors only via dev_status */
+
+/* Per-call profile, filled when opts->profile is non-NULL (forces a sync). */
+typedef struct lingam_profile {
+  double total_ms;        /* enqueue-to-completion of the whole call, HIP events */
+  double pair_ms;         /* summed duration of the pair-moment kernel launches */
+  int64_t pair_launches;  /* number of pair-moment kernel launches */
+  double pair_evals;      /* sample-pair evaluations done by those launches */
+  double gram_ms;         /* duration of the Gram (correlation) kernel */
+  double gram_flops;      /* algorithmic flops of that Gram: 2 * n * d * d */
+  double resid_ms;        /* summed duration of the residualize kernels */
+  double resid_bytes;     /* algorithmic HBM bytes of those: 28 * n * (m - 1) per step */
+} lingam_profile;
+
+typedef struct lingam_opts {
+  uint32_t struct_size;         /* sizeof(lingam_opts): ABI version check */
+  uint32_t flags;               /* LINGAM_FLAG_* */
+  const int32_t* forced_order;  /* device int32[forced_len] or NULL: at step t < forced_len
+                                   take forced_order[t] instead of the argmax (teacher
+                                   forcing / resume); measures are still computed */
+  int32_t forced_len;           /* 0 .. d */
+  int32_t reserved0;
+  double* step_measures;        /* device double[(d-1) * d] or NULL: row t holds the measure
+                                   -k_i of step t by original column id, NaN for columns
+                                   already ordered */
+  double* step_gap;             /* device double[d-1] or NULL: best minus runner-up measure */
+  int32_t* dev_status;          /* device int32 or NULL: receives the device-side status */
+  lingam_profile* profile;      /* HOST pointer or NULL: per-kernel timings (forces sync) */
+} lingam_opts;
+
+/* Fill *opts with defaults (no forcing, no extra outputs, synchronous). */
+void lingam_opts_init(lingam_opts* opts);
+
+/*
+ * Workspace bytes needed by lingam_causal_order for an n x d problem.
+ * Returns 0 for unsupported sizes (n < 2, d < 1, or beyond the supported
+ * range).  `opts` may be NULL.
+ */
+size_t lingam_workspace_size(int64_t n, int64_t d, const lingam_opts* opts);
+
+/*
+ * DirectLiNGAM causal order of the d columns of X (Section 2.2 outer loop
+ * around Algorithm 1).
+ *   X      device FP32 [n x ldx] row-major, read only.
+ *   order  device int32[d]: original column ids, most exogenous first.
+ *   opts   optional (NULL = defaults).
+ *   ws     device workspace of ws_bytes >= lingam_workspace_size(n, d, opts);
+ *          its contents on entry do not matter, on exit they are undefined.
+ * Ties of the measure go to the smallest original column id.
+ * Returns LINGAM_OK or an error status (see the conventions above).
+ */
+int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
+                        const lingam_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for lingam_residualize on an n x d matrix (0 if unsupported). */
+size_t lingam_residualize_workspace_size(int64_t n, int64_t d);
+
+/*
+ * Remove the effect of variable `exo` from every other variable listed in
+ * `active` by least squares (the DirectLiNGAM update of Section 2.2):
+ *   x_v <- x_v - (cov(x_v, x_exo) / var(x_exo)) x_exo,
+ * population (ddof = 0) moments, computed in FP64.  In place on X.
+ *   X       device FP32 [n x ldx] row-major, modified in place (only the
+ *           active columns other than exo change).
+ *   active  device int32[n_active], distinct column ids in [0, d).
+ *   exo     the regressor column id (host value, 0 <= exo < d).
+ * Returns LINGAM_E_DEGENERATE (after a sync) if var(x_exo) == 0.
+ */
+int lingam_residualize(float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* active,
+                       int32_t n_active, int32_t exo, void* ws, size_t ws_bytes, void* stream);
+
+/* Thread-local text of the last error of the calling thread ("" if none). */
+const char* lingam_last_error(void);
+
+/* Library version string. */
+const char* lingam_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINGAM_MI355X_H */

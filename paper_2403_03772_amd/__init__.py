@@ -1,0 +1,30 @@
+"""MI355X (gfx950) DirectLiNGAM causal-ordering library: Python binding.
+
+Argument marshalling over the C ABI of ``liblingam_mi355x.so`` (declared in
+``include/lingam.h``); every step of the search runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream only.
+There is no CPU fallback: importing :mod:`paper_2403_03772_amd.lib` fails when
+the shared library has not been built.
+
+Functions mirror the C entry points:
+
+* :func:`causal_order` -- ``lingam_causal_order`` (DirectLiNGAM ordering,
+  Section 2.2 / Algorithm 1 of AcceleratedLiNGAM).
+* :func:`residualize` -- ``lingam_residualize`` (least-squares removal of one
+  variable's effect, Section 2.2).
+* :func:`workspace_size`, :func:`residualize_workspace_size`.
+"""
+from __future__ import annotations
+
+from .lib import (  # noqa: F401
+    LIB_PATH,
+    LingamError,
+    Profile,
+    causal_order,
+    last_error,
+    load,
+    residualize,
+    residualize_workspace_size,
+    version,
+    workspace_size,
+)

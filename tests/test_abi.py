@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI that need no GPU.
+
+* the shared library loads and exports every function ``include/lingam.h``
+  declares;
+* argument errors the host can see are returned synchronously, before any
+  device work (so they are testable without a GPU);
+* the workspace query rejects unsupported sizes.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2403_03772_amd as pkg
+from paper_2403_03772_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lingam.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(lingam_\w+|varlingam_\w+)\s*\(", text,
+                       flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_is_built():
+    assert os.path.exists(pkg.LIB_PATH), "run `python -m paper_2403_03772_amd.build` first"
+
+
+def test_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert "lingam_causal_order" in names and "lingam_residualize" in names
+    lib = pkg.load()
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_version_and_last_error():
+    assert "gfx950" in pkg.version()
+    assert isinstance(pkg.last_error(), str)
+
+
+def _opts():
+    o = L._Opts()
+    pkg.load().lingam_opts_init(ctypes.byref(o))
+    return o
+
+
+def test_opts_init_sets_struct_size():
+    o = _opts()
+    assert o.struct_size == ctypes.sizeof(L._Opts)
+    assert o.flags == 0 and o.forced_len == 0
+
+
+def _call(X=1, n=100, d=5, ldx=5, order=1, opts=None, ws=1, ws_bytes=1 << 30):
+    lib = pkg.load()
+    return lib.lingam_causal_order(
+        ctypes.c_void_p(X) if X else None, n, d, ldx,
+        ctypes.c_void_p(order) if order else None,
+        ctypes.byref(opts) if opts is not None else None,
+        ctypes.c_void_p(ws) if ws else None, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(X=0), "non-NULL"),
+    (dict(order=0), "non-NULL"),
+    (dict(n=1), "n >= 2"),
+    (dict(n=0), "n >= 2"),
+    (dict(d=0), "d >= 1"),
+    (dict(ldx=4), "ldx"),
+])
+def test_host_argument_errors(kw, msg):
+    assert _call(**kw) == L.E_INVALID
+    assert msg in pkg.last_error()
+
+
+def test_bad_struct_size_and_forcing():
+    o = _opts()
+    o.struct_size = 8
+    assert _call(opts=o) == L.E_INVALID
+    o = _opts()
+    o.forced_len = 6
+    assert _call(opts=o) == L.E_INVALID
+    o = _opts()
+    o.forced_len = 2
+    assert _call(opts=o) == L.E_INVALID  # forced_order is NULL
+
+
+def test_unsupported_sizes():
+    assert _call(d=1 << 20, ldx=1 << 20) == L.E_UNSUPPORTED
+    lib = pkg.load()
+    assert lib.lingam_workspace_size(1, 10, None) == 0
+    assert lib.lingam_workspace_size(100, 0, None) == 0
+    assert lib.lingam_residualize_workspace_size(1, 3) == 0
+
+
+def test_residualize_argument_errors():
+    lib = pkg.load()
+    c = lambda **k: lib.lingam_residualize(
+        ctypes.c_void_p(1) if k.get("X", 1) else None, k.get("n", 10), k.get("d", 3),
+        k.get("ldx", 3), ctypes.c_void_p(1) if k.get("active", 1) else None,
+        k.get("n_active", 2), k.get("exo", 0), ctypes.c_void_p(1), 1 << 20, None)
+    assert c(X=0) == L.E_INVALID
+    assert c(active=0) == L.E_INVALID
+    assert c(n=1) == L.E_INVALID
+    assert c(ldx=2) == L.E_INVALID
+    assert c(n_active=0) == L.E_INVALID
+    assert c(n_active=4) == L.E_INVALID
+    assert c(exo=3) == L.E_INVALID
+    assert c(exo=-1) == L.E_INVALID
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The binding and the library never load the oracle."""
+    src = open(os.path.join(ROOT, "paper_2403_03772_amd", "lib.py")).read()
+    assert "oracle" not in src.replace("# ", "")
+    out = subprocess.run(["ldd", pkg.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in out

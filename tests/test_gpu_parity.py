@@ -1,0 +1,170 @@
+"""GPU parity: the gfx950 library against the FP64 CPU oracle, through the C ABI.
+
+Every comparison is teacher-forced where measures are compared: the oracle is
+forced along the GPU's order, so both score the same residual data.  The
+tolerance rule is in ``gpu_helpers``.  Inputs are seeded synthetic SEMs from
+``paper_2403_03772_amd.synth``.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_03772_amd import synth
+from gpu_helpers import check_step, measure_close, near_tie
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(lib, X, **kw):
+    import torch
+    Xd = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    return lib.causal_order(Xd, **kw)
+
+
+def _compare_full(lib, X, label):
+    """GPU order + measures vs the oracle forced along the GPU order."""
+    out = _run(lib, X, with_measures=True)
+    order = out["order"].cpu().numpy()
+    d = X.shape[1]
+    assert sorted(order.tolist()) == list(range(d)), label
+    if d == 1:
+        return order
+    mg = out["measures"].cpu().numpy()
+    o_ref, mr, _ = oracle.causal_order(X, forced=order, mode="table", with_measures=True)
+    assert list(o_ref) == list(order)
+    for t in range(d - 1):
+        bad, ok = check_step(mg[t], mr[t], order[t])
+        assert bad == 0, f"{label}: step {t}: {bad} measures outside tolerance"
+        assert ok, f"{label}: step {t}: GPU chose {order[t]} outside a near-tie"
+    return order
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_small_workload_matches_oracle(lib, seed):
+    """d = 10, n = 1000, ER in-degree 1.5, uniform noise."""
+    s = synth.workload_small(seed)
+    print(f"case small seed={seed}", flush=True)
+    order = _compare_full(lib, s.X, f"small seed {seed}")
+    assert list(order) == list(oracle.causal_order(s.X, mode="table"))
+
+
+@pytest.mark.parametrize("d,n", [(2, 3), (3, 63), (5, 64), (9, 65), (17, 1000), (37, 777),
+                                 (65, 129), (130, 300)])
+def test_odd_shapes(lib, d, n):
+    """Ragged tiles (d not a multiple of 8) and ragged sample tails."""
+    s = synth.er_sem(d, n, indeg=2.0, noise_family=("uniform", "laplace", "exp"),
+                     seed=d * 1000 + n)
+    print(f"case odd d={d} n={n}", flush=True)
+    _compare_full(lib, s.X, f"d={d} n={n}")
+
+
+def test_paper_two_level_protocol(lib):
+    """Section 3.1 protocol: GPU and sequential orders are the same, 50 seeds."""
+    for seed in range(50):
+        s = synth.two_level_sem(seed=seed)
+        g = _run(lib, s.X).cpu().numpy()
+        o = oracle.causal_order(s.X, mode="table")
+        assert list(g) == list(o), seed
+        assert synth.is_topological(g, s.B)
+
+
+def test_exact_recovery_complete_dag(lib):
+    for seed in range(4):
+        s = synth.er_sem(8, 200_000, complete=True, noise_family="laplace", seed=seed)
+        assert list(_run(lib, s.X).cpu().numpy()) == list(s.order)
+
+
+def test_teacher_forcing(lib):
+    import torch
+    s = synth.er_sem(12, 600, indeg=2.0, noise_family="exp", seed=5)
+    forced = [4, 9, 0]
+    out = _run(lib, s.X, forced=forced, with_measures=True)
+    order = out["order"].cpu().numpy()
+    assert list(order[:3]) == forced
+    _, mr, _ = oracle.causal_order(s.X, forced=order, mode="table", with_measures=True)
+    mg = out["measures"].cpu().numpy()
+    for t in range(11):
+        fin = np.isfinite(mr[t])
+        assert measure_close(mg[t][fin], mr[t][fin]).all(), t
+
+
+def test_determinism(lib):
+    s = synth.er_sem(70, 2000, indeg=3.0, noise_family=("uniform", "laplace", "exp"), seed=7)
+    a = _run(lib, s.X, with_measures=True)
+    b = _run(lib, s.X, with_measures=True)
+    assert np.array_equal(a["order"].cpu().numpy(), b["order"].cpu().numpy())
+    ma, mb = a["measures"].cpu().numpy(), b["measures"].cpu().numpy()
+    assert np.array_equal(np.isnan(ma), np.isnan(mb))
+    assert np.array_equal(ma[~np.isnan(ma)], mb[~np.isnan(mb)])
+
+
+def test_single_and_two_variables(lib):
+    rng = np.random.default_rng(0)
+    assert list(_run(lib, rng.uniform(size=(10, 1))).cpu().numpy()) == [0]
+    x0 = rng.uniform(-1, 1, 5000)
+    X = np.stack([x0 * 1.5 + rng.uniform(-1, 1, 5000), x0], axis=1)
+    assert list(_run(lib, X).cpu().numpy()) == list(oracle.causal_order(X))
+
+
+def test_strided_input(lib):
+    """ldx > d: a column slice of a wider matrix."""
+    import torch
+    s = synth.er_sem(20, 500, indeg=2.0, seed=3)
+    wide = np.zeros((500, 27), dtype=np.float32)
+    wide[:, :20] = s.X
+    W = torch.as_tensor(wide).cuda()
+    g = lib.causal_order(W[:, :20]).cpu().numpy()
+    assert list(g) == list(_run(lib, s.X).cpu().numpy())
+
+
+def test_degenerate_inputs(lib):
+    rng = np.random.default_rng(1)
+    X = rng.uniform(size=(200, 6))
+    for mutate in ("const", "dup", "nan", "inf"):
+        Y = X.copy()
+        if mutate == "const":
+            Y[:, 2] = 0.5
+        elif mutate == "dup":
+            Y[:, 4] = 3.0 * Y[:, 1]
+        elif mutate == "nan":
+            Y[17, 3] = np.nan
+        else:
+            Y[5, 0] = np.inf
+        with pytest.raises(lib.LingamError) as e:
+            _run(lib, Y)
+        assert e.value.code == -2, mutate
+
+
+def test_bad_forced_order(lib):
+    s = synth.er_sem(6, 300, seed=0)
+    with pytest.raises(lib.LingamError) as e:
+        _run(lib, s.X, forced=[2, 2])
+    assert e.value.code == -1
+
+
+def test_residualize_matches_oracle(lib):
+    import torch
+    s = synth.er_sem(9, 3000, indeg=2.0, noise_family="laplace", seed=11)
+    X32 = s.X.astype(np.float32)
+    active = [0, 2, 3, 5, 8]
+    for exo in (3, 8):
+        Xd = torch.as_tensor(X32).cuda()
+        lib.residualize(Xd, active, exo)
+        got = Xd.cpu().numpy()
+        ref = oracle.residualize(X32.astype(np.float64), np.array(active), exo)
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(got - ref)) <= 2e-6 * scale
+        untouched = [v for v in range(9) if v not in active or v == exo]
+        assert np.array_equal(got[:, untouched], X32[:, untouched])
+
+
+def test_residualize_errors(lib):
+    import torch
+    X = torch.ones((50, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.LingamError) as e:
+        lib.residualize(X, [0, 1, 2], 1)
+    assert e.value.code == -2
+    Y = torch.randn((50, 4), device="cuda")
+    with pytest.raises(lib.LingamError) as e:
+        lib.residualize(Y, [0, 7], 0)
+    assert e.value.code == -1
