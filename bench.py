@@ -75,6 +75,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 256 MiB device-to-device with a plain copy "
+                         "kernel (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the ordering is single-GPU here); "
@@ -160,6 +163,13 @@ def main() -> int:
                   "peak": 8000.0, "unit": "GB/s"},
         "learned": None,
     }
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(X32, n, d)
     print(json.dumps(rec), flush=True)

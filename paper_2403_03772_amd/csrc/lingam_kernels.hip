@@ -290,15 +290,16 @@ __global__ __launch_bounds__(256) void k_standardize(double* __restrict__ Zd,
 // the step kernels
 // ---------------------------------------------------------------------------
 
-// Pair moments.  Grid: ntiles * nsplit workgroups of 4 waves.  A workgroup owns
-// an 8 x 8 block of (i, j) positions and one range of samples; wave (wi, wj)
-// owns the 4 x 4 sub-block (i in block bi, j in block bj).  Lanes stride over
-// samples (coalesced 256 B loads per variable row), every lane keeps 64 running
-// sums (16 pairs x 2 directions x {S1, S2}), and the wave ends with an FP64
-// reduce-scatter butterfly after which lane L holds the total of sum L, which it
-// stores: part[((split * ntiles + tile) * 4 + wave) * 64 + L].
-// Sum index: ((a * 4 + b) * 2 + dir) * 2 + which, dir 0 = residual of i on j,
-// which 0 = S1 (log cosh, offset as described in the header), 1 = S2.
+// Pair moments.  Grid: ntiles * 2 * nsplit workgroups of 4 waves.  A
+// workgroup owns an 8 x 8 block of (i, j) positions, one residual direction and
+// one range of samples; wave (wi, wj) owns the 4 x 4 sub-block (i in block bi,
+// j in block bj).  Lanes stride over samples (coalesced 256 B loads per
+// variable row) and every lane keeps 48 running values (16 pairs x {P, S1, S2})
+// for its direction.  The wave ends with an FP64 reduction after which lane
+// L < 32 holds the total of sum L, stored at
+// part[((split * ntiles + tile) * 4 + wave) * 64 + (L / 2) * 4 + dir * 2 + L % 2].
+// Sum index (a * 4 + b) * 2 + which, which 0 = S1 (log cosh, offset as described
+// in the header), 1 = S2; dir 0 = residual of i on j, dir 1 = of j on i.
 __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64_t ldz,
                                               const double* __restrict__ rho, int64_t ldr,
                                               const int32_t* __restrict__ act, int m, int nblk,
@@ -307,24 +308,28 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-  // contiguous range of (tile, split) work so that the rows a tile reads are
-  // shared in that XCD's L2.
-  const int G = ntiles * nsplit;
+  // contiguous range of (tile, direction, split) work so that the rows a tile
+  // reads are shared in that XCD's L2.
+  const int per_tile = 2 * nsplit;
+  const int G = ntiles * per_tile;
   const int b = blockIdx.x;
   const int Q = G >> 3, R = G & 7, x = b & 7, idx = b >> 3;
   const int w = x * Q + (x < R ? x : R) + idx;
-  const int tile = w / nsplit, split = w - tile * nsplit;
+  const int tile = w / per_tile, rem = w - tile * per_tile;
+  const int dir = rem / nsplit, split = rem - dir * nsplit;
   int bi, bj;
   decode_tile(tile, nblk, bi, bj);
   const int wi = wave >> 1, wj = wave & 1;
   if (bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)
   const int pi0 = bi * kTileVars + wi * kWaveVars, pj0 = bj * kTileVars + wj * kWaveVars;
 
-  // coefficients of the 16 pairs: lane q < 16 computes pair (q / 4, q % 4)
+  // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
+  // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
+  // i = pi0 + c.  Lane q < 16 computes the coefficients of walk index q.
   float my_r = 0.f, my_c1h = 0.f, my_c1l = 0.f;
   {
-    const int q = lane & 15;
-    const int pi = pi0 + (q >> 2), pj = pj0 + (q & 3);
+    const int q = lane & 15, a = q >> 2, c = q & 3;
+    const int pi = pi0 + (dir == 0 ? a : c), pj = pj0 + (dir == 0 ? c : a);
     if (pi < m && pj < m && pi < pj) {
       double r = rho[(int64_t)act[pi] * ldr + act[pj]];
       const double lim = 1.0 - kCollinear;
@@ -335,31 +340,33 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
       my_c1l = (float)(c1 - (double)my_c1h);
     }
   }
-  float cr[16], ch[16], cl[16];
+  float kr[16], kh[16], kl[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    cr[q] = readlane_f(my_r, q);
-    ch[q] = readlane_f(my_c1h, q);
-    cl[q] = readlane_f(my_c1l, q);
+    kr[q] = readlane_f(my_r, q);
+    kh[q] = readlane_f(my_c1h, q);
+    kl[q] = readlane_f(my_c1l, q);
   }
-  // row bases (wave-uniform) and a 32-bit per-lane byte offset, so loads use
-  // the scalar-base + vector-offset addressing form
-  const char* zi[4];
-  const char* zj[4];
+  // Row bases (wave-uniform) and a 32-bit per-lane byte offset, so loads use
+  // the scalar-base + vector-offset form.  zr = rows of the regressed
+  // variables (the residual's own variable), zx = rows of the regressors.
+  const int pr0 = dir == 0 ? pi0 : pj0, px0 = dir == 0 ? pj0 : pi0;
+  const char* zr[4];
+  const char* zx[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int pi = pi0 + a, pj = pj0 + a;
-    zi[a] = reinterpret_cast<const char*>(Z + (int64_t)(pi < m ? act[pi] : zero_slot) * ldz);
-    zj[a] = reinterpret_cast<const char*>(Z + (int64_t)(pj < m ? act[pj] : zero_slot) * ldz);
+    const int pr = pr0 + a, px = px0 + a;
+    zr[a] = reinterpret_cast<const char*>(Z + (int64_t)(pr < m ? act[pr] : zero_slot) * ldz);
+    zx[a] = reinterpret_cast<const char*>(Z + (int64_t)(px < m ? act[px] : zero_slot) * ldz);
   }
 
   const int s_begin = split * split_len;
   const int s_end = min(s_begin + split_len, n_pad);
   const int nk = (s_end - s_begin) / 64;
 
-  float P[32], S1[32], S2[32];
+  float P[16], S1[16], S2[16];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) {
+  for (int q = 0; q < 16; ++q) {
     P[q] = 1.f;
     S1[q] = -kS1Start;
     S2[q] = 0.f;
@@ -368,8 +375,8 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
   float xa[4], xb[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    xa[a] = *reinterpret_cast<const float*>(zi[a] + voff);
-    xb[a] = *reinterpret_cast<const float*>(zj[a] + voff);
+    xa[a] = *reinterpret_cast<const float*>(zr[a] + voff);
+    xb[a] = *reinterpret_cast<const float*>(zx[a] + voff);
   }
   int kb = 0;
   for (int k = 0; k < nk; ++k) {
@@ -380,23 +387,21 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
     float na[4], nb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      na[a] = *reinterpret_cast<const float*>(zi[a] + voff);
-      nb[a] = *reinterpret_cast<const float*>(zj[a] + voff);
+      na[a] = *reinterpret_cast<const float*>(zr[a] + voff);
+      nb[a] = *reinterpret_cast<const float*>(zx[a] + voff);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int q = a * 4 + c;
-        eval_dir(xa[a], xb[c], cr[q], ch[q], cl[q], P[2 * q], S1[2 * q], S2[2 * q]);
-        eval_dir(xb[c], xa[a], cr[q], ch[q], cl[q], P[2 * q + 1], S1[2 * q + 1],
-                 S2[2 * q + 1]);
+        eval_dir(xa[a], xb[c], kr[q], kh[q], kl[q], P[q], S1[q], S2[q]);
       }
     }
     if (++kb == kLogBlock || !more) {
       const float off = 1.5f * (float)kb;  // exact
 #pragma unroll
-      for (int q = 0; q < 32; ++q) {
+      for (int q = 0; q < 16; ++q) {
         S1[q] += __builtin_amdgcn_logf(P[q]) - off;
         P[q] = 1.f;
       }
@@ -409,15 +414,18 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
     }
   }
 
-  // FP64 reduce-scatter butterfly over the 64 lanes: afterwards lane L holds sum L
-  double v[64];
+  // FP64 reduction over the 64 lanes: fold the upper half onto the lower, then
+  // a reduce-scatter butterfly over 32 lanes; afterwards lane L < 32 holds sum L.
+  double v[32];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) {
+  for (int q = 0; q < 16; ++q) {
     v[2 * q] = (double)S1[q];
     v[2 * q + 1] = (double)S2[q];
   }
 #pragma unroll
-  for (int half = 32; half >= 1; half >>= 1) {
+  for (int k2 = 0; k2 < 32; ++k2) v[k2] += __shfl_xor(v[k2], 32);
+#pragma unroll
+  for (int half = 16; half >= 1; half >>= 1) {
     const bool up = (lane & half) != 0;
 #pragma unroll
     for (int k2 = 0; k2 < half; ++k2) {
@@ -427,7 +435,12 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
       v[k2] = keep + __shfl_xor(send, half);
     }
   }
-  part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + lane] = v[0];
+  if (lane < 32) {
+    // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
+    const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
+    const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
+    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
+  }
 }
 
 // Sum the sample splits (FP64, fixed order), form both residual entropies and
@@ -751,12 +764,16 @@ StepPlan plan_step(int64_t m, int64_t n_pad, int num_cu) {
   p.nblk = (int)((m + kTileVars - 1) / kTileVars);
   p.ntiles = p.nblk * (p.nblk + 1) / 2;
   const int64_t iters = n_pad / kSampleQuantum;
-  // Enough workgroups to fill every CU several times over: when the pair
-  // triangle is small, split the sample range (partials are combined in FP64).
-  const int64_t target = (int64_t)num_cu * 12;
-  int64_t ns = (target + p.ntiles - 1) / p.ntiles;
+  // Enough workgroups (two per tile, one per residual direction) to fill every
+  // CU several times over: when the pair triangle is small, split the sample
+  // range (partials are combined in FP64), keeping at least kMinIters sample
+  // iterations per split so the per-workgroup set-up and reduction stay small.
+  constexpr int64_t kMinIters = 8;
+  const int64_t target = (int64_t)num_cu * 16;
+  int64_t ns = (target + 2 * p.ntiles - 1) / (2 * p.ntiles);
+  const int64_t cap = iters >= kMinIters ? iters / kMinIters : 1;
+  if (ns > cap) ns = cap;
   if (ns < 1) ns = 1;
-  if (ns > iters) ns = iters;
   const int64_t per = (iters + ns - 1) / ns;
   p.split_len = (int)(per * kSampleQuantum);
   p.nsplit = (int)((iters + per - 1) / per);
@@ -838,7 +855,7 @@ hipError_t launch_standardize(const Layout& L, char* ws, hipStream_t st) {
 }
 
 hipError_t launch_pair(const Layout& L, char* ws, int m, const StepPlan& p, hipStream_t st) {
-  const int G = p.ntiles * p.nsplit;
+  const int G = p.ntiles * 2 * p.nsplit;
   hipLaunchKernelGGL(k_pair, dim3((unsigned)G), dim3(256), 0, st, at<float>(ws, L.z), L.ldz,
                      at<double>(ws, L.rho), L.d, at<int32_t>(ws, L.act), m, p.nblk, p.ntiles,
                      p.nsplit, p.split_len, (int)L.n_pad, (int)L.d, at<double>(ws, L.part));
