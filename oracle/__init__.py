@@ -22,6 +22,9 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
 * :func:`residualize` -- least-squares removal of one variable's effect.
 * :func:`var_fit` -- least-squares VAR fit with intercept (Section 3.3, the
   first stage of VarLiNGAM).
+* :func:`ols_adjacency` -- least-squares regression of every variable on its
+  order predecessors (the instantaneous matrix B0 of VarLiNGAM).
+* :func:`varlingam` -- the three stages of VarLiNGAM together.
 """
 from __future__ import annotations
 
@@ -78,12 +81,16 @@ def _load():
         lib.lo_pair_measure.restype = ctypes.c_int
         lib.lo_causal_order.argtypes = [P, i64, i64, i64, P, i32, i32, P, P, P]
         lib.lo_causal_order.restype = ctypes.c_int
+        lib.lo_causal_order_f64.argtypes = [P, i64, i64, i64, P, i32, i32, P, P, P]
+        lib.lo_causal_order_f64.restype = ctypes.c_int
         lib.lo_step_measures_rows.argtypes = [P, i64, i64, i64, P, i32, P, i32, P]
         lib.lo_step_measures_rows.restype = ctypes.c_int
         lib.lo_residualize.argtypes = [P, i64, i64, i64, P, i32, i32]
         lib.lo_residualize.restype = ctypes.c_int
         lib.lo_var_fit.argtypes = [P, i64, i64, i64, i32, P, P]
         lib.lo_var_fit.restype = ctypes.c_int
+        lib.lo_ols_adjacency.argtypes = [P, i64, i64, i64, P, P]
+        lib.lo_ols_adjacency.restype = ctypes.c_int
         lib.lo_num_threads.argtypes = []
         lib.lo_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -188,3 +195,58 @@ def var_fit(X, lags: int = 1):
     resid = np.empty((T - lags, d), dtype=np.float64)
     _check(_load().lo_var_fit(_ptr(X), T, d, d, int(lags), _ptr(coef), _ptr(resid)), "var_fit")
     return coef, resid
+
+
+def ols_adjacency(E, order) -> np.ndarray:
+    """B[c, p]: coefficient of column p when column c is regressed (with
+    intercept) on every column preceding it in ``order``."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    n, d = E.shape
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    B = np.empty((d, d), dtype=np.float64)
+    _check(_load().lo_ols_adjacency(_ptr(E), n, d, d, _ptr(o), _ptr(B)), "ols_adjacency")
+    return B
+
+
+def varlingam(X, lags: int = 1, forced=None, with_measures: bool = False):
+    """VarLiNGAM (Section 3.3): least-squares VAR(lags) with intercept, the
+    DirectLiNGAM order of its residuals, B0 by least squares on the order.
+
+    Returns a dict with ``coef`` ((1 + d*lags) x d), ``M`` (lags x d x d,
+    M[tau-1][i, j] = coefficient of x_j(t - tau) in the equation of x_i),
+    ``resid``, ``order``, ``B0`` (and ``measures`` / ``gaps``).  The residuals
+    are rounded to FP32 before the ordering, as the GPU receives FP32 data
+    only at the input; see the library's varlingam_fit for its own handling.
+    """
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T, d = X.shape
+    coef, resid = var_fit(X, lags)
+    M = np.stack([coef[1 + (tau - 1) * d: 1 + tau * d].T for tau in range(1, lags + 1)])
+    out = {"coef": coef, "M": M, "resid": resid}
+    if with_measures:
+        order, meas, gaps = _order_fp64(resid, forced, True)
+        out.update(measures=meas, gaps=gaps)
+    else:
+        order = _order_fp64(resid, forced, False)
+    out["order"] = order
+    out["B0"] = ols_adjacency(resid, order)
+    return out
+
+
+def _order_fp64(E, forced, with_measures):
+    """Causal order of FP64 data (no FP32 rounding of the input)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    n, d = E.shape
+    # the oracle's C entry takes FP32 input (what the library receives);
+    # VAR residuals are FP64, so order them through a float64 wrapper
+    order = np.empty(d, dtype=np.int32)
+    meas = np.empty((max(d - 1, 1), d), dtype=np.float64) if with_measures else None
+    gaps = np.empty(max(d - 1, 1), dtype=np.float64) if with_measures else None
+    f = None if forced is None else np.ascontiguousarray(forced, dtype=np.int32)
+    code = _load().lo_causal_order_f64(
+        _ptr(E), n, d, d, None if f is None else _ptr(f), 0 if f is None else f.size, 1,
+        _ptr(order), None if meas is None else _ptr(meas), None if gaps is None else _ptr(gaps))
+    _check(code, "causal_order_f64")
+    if with_measures:
+        return order, meas[: d - 1], gaps[: d - 1]
+    return order

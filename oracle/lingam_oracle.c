@@ -358,12 +358,9 @@ static double* lo_load_columns(const float* X, int64_t n, int64_t d, int64_t ldx
  * mode      0 = literal (Algorithm 1 as written), 1 = table (memoised).
  * Returns LO_OK, LO_INVALID, LO_DEGENERATE or LO_NOMEM.
  */
-int lo_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* forced,
-                    int32_t forced_len, int32_t mode, int32_t* order, double* measures,
-                    double* gaps) {
-  if (!X || !order || n < 2 || d < 1 || ldx < d || forced_len < 0 || forced_len > d)
-    return LO_INVALID;
-  double* Xc = lo_load_columns(X, n, d, ldx);
+static int lo_causal_order_cols(double* Xc, int64_t n, int64_t d, const int32_t* forced,
+                                int32_t forced_len, int32_t mode, int32_t* order,
+                                double* measures, double* gaps) {
   int32_t* U = (int32_t*)malloc(sizeof(int32_t) * (size_t)d);
   double* k_list = (double*)malloc(sizeof(double) * (size_t)d);
   if (!Xc || !U || !k_list) {
@@ -416,6 +413,29 @@ int lo_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, const int
   free(U);
   free(k_list);
   return status;
+}
+
+int lo_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* forced,
+                    int32_t forced_len, int32_t mode, int32_t* order, double* measures,
+                    double* gaps) {
+  if (!X || !order || n < 2 || d < 1 || ldx < d || forced_len < 0 || forced_len > d)
+    return LO_INVALID;
+  double* Xc = lo_load_columns(X, n, d, ldx);
+  if (!Xc) return LO_NOMEM;
+  return lo_causal_order_cols(Xc, n, d, forced, forced_len, mode, order, measures, gaps);
+}
+
+/* The same on FP64 row-major input (VAR residuals are FP64). */
+int lo_causal_order_f64(const double* X, int64_t n, int64_t d, int64_t ldx,
+                        const int32_t* forced, int32_t forced_len, int32_t mode, int32_t* order,
+                        double* measures, double* gaps) {
+  if (!X || !order || n < 2 || d < 1 || ldx < d || forced_len < 0 || forced_len > d)
+    return LO_INVALID;
+  double* Xc = (double*)malloc(sizeof(double) * (size_t)n * (size_t)d);
+  if (!Xc) return LO_NOMEM;
+  for (int64_t v = 0; v < d; ++v)
+    for (int64_t k = 0; k < n; ++k) Xc[v * n + k] = X[k * ldx + v];
+  return lo_causal_order_cols(Xc, n, d, forced, forced_len, mode, order, measures, gaps);
 }
 
 /*
@@ -600,6 +620,81 @@ done:
   free(G);
   free(R);
   free(z);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* adjacency by least squares on order predecessors                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * E      FP64 row-major n x d (leading dimension lde).
+ * order  causal order (original column ids, exogenous first).
+ * B      out, double[d * d] row-major: B[c * d + p] is the coefficient of
+ *        column p in the least-squares regression (with intercept) of column c
+ *        on all columns that precede c in `order`; 0 elsewhere.
+ * Each regression solves its own normal equations on centred data by
+ * Cholesky (plain, one variable at a time).  This is the instantaneous
+ * matrix that VarLiNGAM estimates from the VAR residuals (Section 3.3).
+ */
+int lo_ols_adjacency(const double* E, int64_t n, int64_t d, int64_t lde, const int32_t* order,
+                     double* B) {
+  if (!E || !order || !B || n < 2 || d < 1 || lde < d) return LO_INVALID;
+  double* mu = (double*)malloc(sizeof(double) * (size_t)d);
+  double* C = (double*)malloc(sizeof(double) * (size_t)(d * d));
+  int status = LO_OK;
+  if (!mu || !C) {
+    status = LO_NOMEM;
+    goto done;
+  }
+  for (int64_t v = 0; v < d; ++v) {
+    double s = 0.0;
+    for (int64_t k = 0; k < n; ++k) s += E[k * lde + v];
+    mu[v] = s / (double)n;
+  }
+  /* covariance matrix (ddof = 0; the scale cancels in the coefficients) */
+  for (int64_t a = 0; a < d; ++a)
+    for (int64_t b = a; b < d; ++b) {
+      double s = 0.0;
+      for (int64_t k = 0; k < n; ++k) s += (E[k * lde + a] - mu[a]) * (E[k * lde + b] - mu[b]);
+      C[a * d + b] = C[b * d + a] = s / (double)n;
+    }
+  for (int64_t i = 0; i < d * d; ++i) B[i] = 0.0;
+  for (int64_t k = 1; k < d; ++k) {
+    const int32_t c = order[k];
+    double* G = (double*)malloc(sizeof(double) * (size_t)(k * k));
+    double* r = (double*)malloc(sizeof(double) * (size_t)k);
+    if (!G || !r) {
+      free(G);
+      free(r);
+      status = LO_NOMEM;
+      goto done;
+    }
+    for (int64_t a = 0; a < k; ++a) {
+      for (int64_t b = 0; b < k; ++b) G[a * k + b] = C[(int64_t)order[a] * d + order[b]];
+      r[a] = C[(int64_t)order[a] * d + c];
+    }
+    status = lo_cholesky(G, k);
+    if (!status) {
+      for (int64_t i = 0; i < k; ++i) {
+        double s = r[i];
+        for (int64_t q = 0; q < i; ++q) s -= G[i * k + q] * r[q];
+        r[i] = s / G[i * k + i];
+      }
+      for (int64_t i = k - 1; i >= 0; --i) {
+        double s = r[i];
+        for (int64_t q = i + 1; q < k; ++q) s -= G[q * k + i] * r[q];
+        r[i] = s / G[i * k + i];
+      }
+      for (int64_t a = 0; a < k; ++a) B[(int64_t)c * d + order[a]] = r[a];
+    }
+    free(G);
+    free(r);
+    if (status) goto done;
+  }
+done:
+  free(mu);
+  free(C);
   return status;
 }
 

@@ -325,3 +325,46 @@ def test_var_fit_consistency():
         coef, _ = oracle.var_fit(v.X, lags=1)
         errs.append(np.linalg.norm(coef[1:].T - v.A1))
     assert errs[1] < errs[0] / 2.0
+
+
+# ---------------------------------------------------------------------------
+# VarLiNGAM pieces (Section 3.3)
+# ---------------------------------------------------------------------------
+
+def test_ols_adjacency_matches_lstsq():
+    s = synth.er_sem(7, 3000, indeg=2.0, noise_family="laplace", seed=12)
+    order = s.order
+    B = oracle.ols_adjacency(s.X, order)
+    for k in range(7):
+        c = order[k]
+        P = list(order[:k])
+        row = np.zeros(7)
+        if P:
+            Z = np.hstack([np.ones((3000, 1)), s.X[:, P]])
+            coef, *_ = np.linalg.lstsq(Z, s.X[:, c], rcond=None)
+            row[P] = coef[1:]
+        assert np.max(np.abs(B[c] - row)) < 1e-9, c
+
+
+def test_ols_adjacency_recovers_true_weights():
+    s = synth.er_sem(6, 200_000, indeg=2.5, noise_family="uniform", seed=4, rescale=False)
+    B = oracle.ols_adjacency(s.X, s.order)
+    assert np.max(np.abs(B - s.B)) < 0.02
+
+
+def test_fp64_and_fp32_entries_agree():
+    s = synth.er_sem(9, 800, indeg=2.0, seed=6)
+    X32 = s.X.astype(np.float32)
+    o32, m32, _ = oracle.causal_order(X32, mode="table", with_measures=True)
+    o64, m64, _ = oracle._order_fp64(X32.astype(np.float64), None, True)
+    assert list(o32) == list(o64)
+    fin = np.isfinite(m32)
+    assert np.max(np.abs(m32[fin] - m64[fin])) == 0.0
+
+
+def test_varlingam_recovers_structure():
+    v = synth.var_series(d=8, T=20000, indeg=1.5, seed=2)
+    out = oracle.varlingam(v.X, lags=1)
+    assert np.max(np.abs(out["M"][0] - v.A1)) < 0.05
+    assert synth.is_topological(out["order"], v.B0)
+    assert np.max(np.abs(out["B0"] - v.B0)) < 0.08
