@@ -45,7 +45,14 @@ typedef enum {
 } lingam_status;
 
 /* opts->flags */
-#define LINGAM_FLAG_NO_SYNC 1u /* return after enqueueing; device errors only via dev_status */
+#define LINGAM_FLAG_NO_SYNC 1u  /* return after enqueueing; device errors only via dev_status */
+#define LINGAM_FLAG_GRAPH 2u    /* capture the whole call into one HIP graph, cache the
+                                   instantiated graph per (jobs, buffers, workspace) and
+                                   replay it on identical later calls */
+#define LINGAM_FLAG_AUTOTUNE 4u /* time the candidate split policies of the pair kernel on
+                                   this call's data the first time its size bucket is seen
+                                   (cached per process, and in the file named by the
+                                   environment variable LINGAM_AUTOTUNE_CACHE if set) */
 
 /* Per-call profile, filled when opts->profile is non-NULL (forces a sync). */
 typedef struct lingam_profile {
@@ -99,6 +106,50 @@ size_t lingam_workspace_size(int64_t n, int64_t d, const lingam_opts* opts);
 int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
                         const lingam_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * One job of a batched call: the causal order of d columns of a sample
+ * matrix, optionally over a resampled set of its rows.
+ *   X        device FP32 [n_rows x ldx] row-major, read only (jobs may share it).
+ *   rows     device int32[n] or NULL: sample s of the job is row rows[s] of X
+ *            (bootstrap resampling with replacement); NULL = rows 0 .. n-1.
+ *            Indices outside [0, n_rows) make the job fail with
+ *            LINGAM_E_INVALID.
+ *   n, d     samples and variables of the job (n >= 2, d >= 1).
+ *   order    device int32[d] output, as for lingam_causal_order.
+ *   step_measures / step_gap  optional per-step outputs, as in lingam_opts.
+ */
+typedef struct lingam_job {
+  const float* X;
+  int64_t n_rows;
+  int64_t ldx;
+  const int32_t* rows;
+  int64_t n;
+  int64_t d;
+  int32_t* order;
+  double* step_measures;
+  double* step_gap;
+} lingam_job;
+
+/* Workspace bytes for lingam_batch_causal_order (0 if a job is invalid). */
+size_t lingam_batch_workspace_size(const lingam_job* jobs, int32_t n_jobs,
+                                   const lingam_opts* opts);
+
+/*
+ * The causal orders of many independent jobs (bootstrap resamples, datasets
+ * of uneven n and d) in one batched run: every kernel launch covers the
+ * current step of all jobs still running, so small jobs fill the GPU
+ * together (Section 2.2 search per job, unchanged).
+ *   jobs        HOST array of n_jobs descriptors (device pointers inside).
+ *   job_status  device int32[n_jobs] or NULL: per-job device status.
+ *   opts        flags only (LINGAM_FLAG_GRAPH, _AUTOTUNE, _NO_SYNC, profile);
+ *               forcing and opts-level per-step outputs are rejected.
+ * Returns the first failing job's status, or LINGAM_OK.  A degenerate job
+ * does not stop the others.
+ */
+int lingam_batch_causal_order(const lingam_job* jobs, int32_t n_jobs, int32_t* job_status,
+                              const lingam_opts* opts, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* Workspace bytes for lingam_residualize on an n x d matrix (0 if unsupported). */
 size_t lingam_residualize_workspace_size(int64_t n, int64_t d);
 
@@ -115,6 +166,33 @@ size_t lingam_residualize_workspace_size(int64_t n, int64_t d);
  */
 int lingam_residualize(float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* active,
                        int32_t n_active, int32_t exo, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Workspace bytes for varlingam_fit on a T x d series with `lags` lags
+ * (0 if unsupported: d < 1, lags < 1, or T - lags <= 1 + lags * d).
+ */
+size_t varlingam_workspace_size(int64_t T, int64_t d, int32_t lags, const lingam_opts* opts);
+
+/*
+ * VarLiNGAM (Section 3.3): least-squares VAR(lags) with intercept, the
+ * DirectLiNGAM causal order of its residuals, and the instantaneous matrix B0.
+ *   X      device FP32 [T x ldx] row-major series (time in rows), read only.
+ *   M      device double[lags * d * d] or NULL: M[(tau-1) d d + i d + j] is the
+ *          coefficient of x_j(t - tau) in the equation of x_i(t).
+ *   resid  device FP32 [(T - lags) x d] row-major or NULL: the VAR residuals.
+ *   order  device int32[d]: causal order of the residuals, exogenous first.
+ *   B0     device double[d * d] or NULL: B0[i d + j] is the least-squares
+ *          coefficient of residual j when residual i is regressed (with
+ *          intercept) on all residuals that precede i in `order`; 0 elsewhere.
+ *   opts   as for lingam_causal_order (forcing and per-step outputs apply to
+ *          the ordering of the residuals; n = T - lags there).
+ * The VAR normal equations are formed on FP64 MFMA and solved by Cholesky in
+ * FP64; the residuals stay FP64 for the ordering.  Returns LINGAM_E_DEGENERATE
+ * if the normal equations are not positive definite.
+ */
+int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lags, double* M,
+                  float* resid, int32_t* order, double* B0, const lingam_opts* opts, void* ws,
+                  size_t ws_bytes, void* stream);
 
 /* Thread-local text of the last error of the calling thread ("" if none). */
 const char* lingam_last_error(void);

@@ -12,6 +12,10 @@ Functions mirror the C entry points:
   Section 2.2 / Algorithm 1 of AcceleratedLiNGAM).
 * :func:`residualize` -- ``lingam_residualize`` (least-squares removal of one
   variable's effect, Section 2.2).
+* :func:`varlingam_fit` -- ``varlingam_fit`` (VAR least squares, ordering of
+  the residuals, instantaneous matrix B0; Section 3.3).
+* :func:`batch_causal_order` -- ``lingam_batch_causal_order`` (many
+  independent orderings, e.g. bootstrap resamples, in one batched run).
 * :func:`workspace_size`, :func:`residualize_workspace_size`.
 """
 from __future__ import annotations
@@ -20,11 +24,13 @@ from .lib import (  # noqa: F401
     LIB_PATH,
     LingamError,
     Profile,
+    batch_causal_order,
     causal_order,
     last_error,
     load,
     residualize,
     residualize_workspace_size,
+    varlingam_fit,
     version,
     workspace_size,
 )

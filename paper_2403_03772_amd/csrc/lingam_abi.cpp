@@ -1,17 +1,23 @@
 // C ABI of the library (declared in include/lingam.h): argument validation,
-// workspace planning and the host-side step loop that enqueues the kernels.
+// workspace planning, the split-policy autotuner, HIP-graph capture, and the
+// host-side step loop that enqueues the batched kernels.
 //
 // Control crosses the host/device boundary once per call.  The host knows the
-// number of active variables at every step (m = d - t), so it can enqueue the
-// whole ordering up front; the identity of each step's chosen variable lives
-// only on the device (in the workspace control block and the active list).
+// number of active variables of every job at every step (m = d - t), so it
+// can enqueue (or capture) the whole ordering up front; the identity of each
+// step's chosen variable lives only on the device.
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <list>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/lingam.h"
@@ -33,26 +39,53 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(LINGAM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+#define LG_TRY(call, what)                           \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
 // Largest sizes the kernels' 32-bit sample/variable indexing supports.
 constexpr int64_t kMaxD = 32768;
 constexpr int64_t kMaxN = (int64_t)1 << 30;
+constexpr int kMaxJobs = 65536;
 
-struct DevInfo {
+// --------------------------------------------------------------------------
+// per-device state: CU count, capture stream, graph cache, autotune cache
+// --------------------------------------------------------------------------
+
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct DevState {
   int num_cu = 0;
+  hipStream_t capture = nullptr;
+  std::list<GraphEntry> graphs;  // most recently used first
+  std::map<std::string, lg::Tune> tunes;
+  bool tunes_loaded = false;
 };
 
 std::mutex g_mu;
-std::vector<DevInfo> g_dev;
+std::vector<DevState> g_dev;
+
+int current_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_dev.size() <= *dev) g_dev.resize(*dev + 1);
+  return LINGAM_OK;
+}
 
 int num_cu_of_current(int* out) {
   int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  int rc = current_device(&dev);
+  if (rc != LINGAM_OK) return rc;
   std::lock_guard<std::mutex> lk(g_mu);
-  if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
   if (g_dev[dev].num_cu == 0) {
     int cu = 0;
-    e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
     g_dev[dev].num_cu = cu > 0 ? cu : 1;
   }
@@ -65,7 +98,9 @@ int status_from_device(int32_t s) {
     case 0:
       return LINGAM_OK;
     case LINGAM_E_INVALID:
-      return fail(LINGAM_E_INVALID, "forced_order names a variable that is not active");
+      return fail(LINGAM_E_INVALID,
+                  "forced_order names a variable that is not active, or a row index is out "
+                  "of range");
     case LINGAM_E_DEGENERATE:
       return fail(LINGAM_E_DEGENERATE,
                   "degenerate data: non-finite value, zero-variance column or collinear pair");
@@ -74,7 +109,7 @@ int status_from_device(int32_t s) {
   }
 }
 
-// Event pair recorder for the optional profile.
+// Event recorder for the optional profile.
 struct Timer {
   std::vector<hipEvent_t> ev;
   bool on = false;
@@ -96,6 +131,451 @@ struct Timer {
   }
 };
 
+struct Prof {
+  Timer tm;
+  std::vector<int> pair_ev, resid_ev;
+  int all0 = -1, all1 = -1, g0 = -1, g1 = -1;
+  double pair_evals = 0.0, resid_bytes = 0.0, gram_flops = 0.0;
+};
+
+// --------------------------------------------------------------------------
+// batch plan: [job table][schedule][job 0 regions][job 1 regions]...
+// --------------------------------------------------------------------------
+
+struct HostJob {
+  const float* X;
+  const int32_t* rows;
+  int64_t n_src, ldx, n, d;
+  int32_t* order;
+  double* measures;
+  double* gaps;
+  const int32_t* forced;
+  int32_t forced_len;
+};
+
+struct Plan {
+  int njobs = 0;
+  int cu = 0;
+  size_t table_off = 0, sched_off = 0, total = 0;
+  std::vector<lg::Layout> L;
+  std::vector<size_t> job_off;
+  int max_d = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Plan make_plan(const std::vector<HostJob>& jobs, int cu) {
+  Plan P;
+  P.njobs = (int)jobs.size();
+  P.cu = cu;
+  size_t off = 0;
+  P.table_off = off;
+  off = align256(off + sizeof(lg::JobDev) * (size_t)P.njobs);
+  P.sched_off = off;
+  off = align256(off + lg::sched_bytes(P.njobs));
+  for (const HostJob& j : jobs) {
+    P.L.push_back(lg::make_layout(j.n, j.d, cu));
+    P.job_off.push_back(off);
+    off = align256(off + P.L.back().total);
+    P.max_d = std::max(P.max_d, (int)j.d);
+  }
+  P.total = off;
+  return P;
+}
+
+std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& jobs, char* ws) {
+  std::vector<lg::JobDev> out(P.njobs);
+  for (int k = 0; k < P.njobs; ++k) {
+    const HostJob& h = jobs[k];
+    const lg::Layout& L = P.L[k];
+    char* b = ws + P.job_off[k];
+    lg::JobDev& J = out[k];
+    memset(&J, 0, sizeof(J));
+    J.X = h.X;
+    J.rows = h.rows;
+    J.ldx = h.ldx;
+    J.n = (int32_t)h.n;
+    J.d = (int32_t)h.d;
+    J.n_pad = (int32_t)L.n_pad;
+    J.ldz = (int32_t)L.ldz;
+    J.order = h.order;
+    J.measures = h.measures;
+    J.gaps = h.gaps;
+    J.forced = h.forced;
+    J.forced_len = h.forced_len;
+    J.n_src = (int32_t)std::min<int64_t>(h.n_src, INT32_MAX);
+    J.zd = reinterpret_cast<double*>(b + L.zd);
+    J.z = reinterpret_cast<float*>(b + L.z);
+    J.mu = reinterpret_cast<double*>(b + L.mu);
+    J.sig = reinterpret_cast<double*>(b + L.sig);
+    J.rho = reinterpret_cast<double*>(b + L.rho);
+    J.hm = reinterpret_cast<double*>(b + L.hm);
+    J.act = reinterpret_cast<int32_t*>(b + L.act);
+    J.ctrl = reinterpret_cast<lg::Ctrl*>(b + L.ctrl);
+    J.part = reinterpret_cast<double*>(b + L.part);
+    J.rmat = reinterpret_cast<double*>(b + L.rmat);
+    J.mvec = reinterpret_cast<double*>(b + L.mvec);
+  }
+  return out;
+}
+
+// Host replay of the device schedule: the grid totals of every kernel kind.
+struct StepTotals {
+  int32_t g[lg::kNumKinds] = {0};
+  double pair_evals = 0.0, resid_bytes = 0.0;
+};
+
+StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, lg::Tune tu) {
+  StepTotals T;
+  std::vector<lg::JobStep> js(P.njobs);
+  int64_t items = 0;
+  for (int k = 0; k < P.njobs; ++k) {
+    js[k] = lg::job_step_base((int32_t)jobs[k].d, t);
+    if (js[k].m >= 2 && !js[k].fp64) items += 2LL * js[k].ntiles;
+  }
+  for (int k = 0; k < P.njobs; ++k) {
+    lg::job_split(js[k], (int32_t)P.L[k].n_pad, items, P.cu, tu);
+    for (int kind = 0; kind < lg::kNumKinds; ++kind) T.g[kind] += lg::kind_count(js[k], kind);
+    const int m = js[k].m;
+    if (m >= 2 && !js[k].fp64) T.pair_evals += (double)m * (m - 1) * (double)jobs[k].n;
+    if (m > 2) T.resid_bytes += 28.0 * (double)jobs[k].n * (double)(m - 1);
+  }
+  return T;
+}
+
+int32_t setup_total(const Plan& P, int kind) {
+  int32_t s = 0;
+  for (int k = 0; k < P.njobs; ++k)
+    s += lg::setup_count((int32_t)P.L[k].n_pad, (int32_t)P.L[k].d, kind);
+  return s;
+}
+
+// Enqueue the set-up (job table, init, ingest, moments, Gram, standardize).
+// `after_gram` runs right after the Gram (VarLiNGAM keeps a copy of rho).
+template <typename AfterGram>
+int enqueue_setup(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, hipStream_t st,
+                  Prof* pf, AfterGram after_gram) {
+  lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
+  const lg::SchedDev sc = lg::sched_at(ws + P.sched_off, P.njobs);
+  for (int k = 0; k < P.njobs; k += lg::kJobsPerLaunch)
+    LG_TRY(lg::launch_set_jobs(table, k, dj.data() + k,
+                               std::min(lg::kJobsPerLaunch, P.njobs - k), st),
+           "set jobs");
+  LG_TRY(lg::launch_init(table, P.njobs, st), "init");
+  LG_TRY(lg::launch_setup_schedule(table, P.njobs, sc, st), "setup schedule");
+  LG_TRY(lg::launch_ingest(table, P.njobs, sc, setup_total(P, lg::kSIngest), st), "ingest");
+  const int cols = setup_total(P, lg::kSCols);
+  LG_TRY(lg::launch_moments(table, P.njobs, sc, cols, st), "moments");
+  if (pf && pf->tm.on) pf->g0 = pf->tm.take(st);
+  LG_TRY(lg::launch_gram(table, P.njobs, sc, setup_total(P, lg::kSGram), st), "gram");
+  if (pf && pf->tm.on) pf->g1 = pf->tm.take(st);
+  if (pf)
+    for (int k = 0; k < P.njobs; ++k)
+      pf->gram_flops += 2.0 * (double)P.L[k].n * (double)P.L[k].d * (double)P.L[k].d;
+  LG_TRY(after_gram(), "after gram");
+  LG_TRY(lg::launch_standardize(table, P.njobs, sc, cols, st), "standardize");
+  return LINGAM_OK;
+}
+
+// Enqueue every step of every job.
+int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStream_t st,
+                  lg::Tune tu, Prof* pf) {
+  lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
+  const lg::SchedDev sc = lg::sched_at(ws + P.sched_off, P.njobs);
+  for (int t = 0; t + 1 < P.max_d; ++t) {
+    const StepTotals T = step_totals(jobs, P, t, tu);
+    if (T.g[lg::kKSel] == 0) break;  // every job finished
+    LG_TRY(lg::launch_step_schedule(table, P.njobs, t, P.cu, tu, sc, st), "step schedule");
+    if (T.g[lg::kKPair] > 0) {
+      if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
+      LG_TRY(lg::launch_pair(table, P.njobs, sc, T.g[lg::kKPair], st), "pair");
+      if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
+      if (pf) pf->pair_evals += T.pair_evals;
+      LG_TRY(lg::launch_combine(table, P.njobs, sc, T.g[lg::kKComb], st), "combine");
+    }
+    LG_TRY(lg::launch_pair64(table, P.njobs, sc, T.g[lg::kKP64], st), "pair64");
+    LG_TRY(lg::launch_rowk(table, P.njobs, sc, T.g[lg::kKRowk], st), "rowk");
+    LG_TRY(lg::launch_select(table, P.njobs, t, sc, T.g[lg::kKSel], st), "select");
+    if (T.g[lg::kKRes] > 0) {
+      if (pf && pf->tm.on) pf->resid_ev.push_back(pf->tm.take(st));
+      LG_TRY(lg::launch_resid(table, P.njobs, sc, T.g[lg::kKRes], st), "resid");
+      if (pf && pf->tm.on) pf->resid_ev.push_back(pf->tm.take(st));
+      if (pf) pf->resid_bytes += T.resid_bytes;
+    }
+  }
+  return LINGAM_OK;
+}
+
+// --------------------------------------------------------------------------
+// split-policy autotuner
+// --------------------------------------------------------------------------
+
+const lg::Tune kDefaultTune{16, 8};
+const lg::Tune kCandidates[] = {{8, 8}, {16, 8}, {16, 4}, {32, 4}, {8, 16}, {16, 16}};
+
+int ilog2_ceil(double x) {
+  int k = 0;
+  while ((double)(1LL << k) < x && k < 62) ++k;
+  return k;
+}
+
+// Bucket key: total sample-pair work, largest padded n, number of jobs.
+std::string tune_key(const std::vector<HostJob>& jobs, const Plan& P) {
+  double work = 0.0;
+  int64_t maxn = 0;
+  for (int k = 0; k < P.njobs; ++k) {
+    work += (double)jobs[k].n * ((double)jobs[k].d * jobs[k].d * jobs[k].d) / 3.0;
+    maxn = std::max<int64_t>(maxn, P.L[k].n_pad);
+  }
+  char buf[96];
+  snprintf(buf, sizeof(buf), "gfx950/cu%d/w%d/n%d/j%d", P.cu, ilog2_ceil(work),
+           ilog2_ceil((double)maxn), ilog2_ceil((double)P.njobs));
+  return buf;
+}
+
+// Persistent cache: one "key target min_iters" line per entry in the file named
+// by LINGAM_AUTOTUNE_CACHE (when that variable is set).
+void load_tune_file(DevState& ds) {
+  if (ds.tunes_loaded) return;
+  ds.tunes_loaded = true;
+  const char* path = getenv("LINGAM_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[128];
+  int a, b;
+  while (fscanf(f, "%127s %d %d", key, &a, &b) == 3)
+    if (a >= 1 && a <= lg::kMaxTargetPerCu && b >= lg::kMinMinIters)
+      ds.tunes[key] = lg::Tune{a, b};
+  fclose(f);
+}
+
+void save_tune_file(const DevState& ds) {
+  const char* path = getenv("LINGAM_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (const auto& kv : ds.tunes)
+    fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.target_per_cu, kv.second.min_iters);
+  fclose(f);
+}
+
+// Time the pair kernel of a few sampled steps under every candidate policy on
+// the call's own data (after the set-up; the pair kernel only writes its
+// partial-sum scratch, and every position below m is valid while the active
+// list is still the identity), keep the fastest.
+int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStream_t st,
+             lg::Tune* out) {
+  lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
+  const lg::SchedDev sc = lg::sched_at(ws + P.sched_off, P.njobs);
+  std::vector<int> steps;
+  const int dmax = P.max_d;
+  for (double f : {0.0, 0.25, 0.5, 0.7, 0.85}) {
+    const int t = (int)(f * dmax);
+    if (dmax - t > lg::kFp64MaxM) steps.push_back(t);
+  }
+  *out = kDefaultTune;
+  if (steps.empty()) return LINGAM_OK;
+  Timer tm;
+  double best = 1e300;
+  for (const lg::Tune& c : kCandidates) {
+    std::vector<std::pair<int, int>> ev;
+    for (int t : steps) {
+      const StepTotals T = step_totals(jobs, P, t, c);
+      if (T.g[lg::kKPair] <= 0) continue;
+      LG_TRY(lg::launch_step_schedule(table, P.njobs, t, P.cu, c, sc, st), "tune schedule");
+      const int a = tm.take(st);
+      LG_TRY(lg::launch_pair(table, P.njobs, sc, T.g[lg::kKPair], st), "tune pair");
+      ev.emplace_back(a, tm.take(st));
+    }
+    LG_TRY(hipStreamSynchronize(st), "tune sync");
+    double tot = 0.0;
+    for (auto& e : ev) tot += tm.ms(e.first, e.second);
+    if (!ev.empty() && tot < best) {
+      best = tot;
+      *out = c;
+    }
+  }
+  return LINGAM_OK;
+}
+
+// --------------------------------------------------------------------------
+// one call of the engine
+// --------------------------------------------------------------------------
+
+std::string graph_key(const std::vector<lg::JobDev>& dj, const Plan& P, void* ws, lg::Tune tu) {
+  std::string k;
+  k.append(reinterpret_cast<const char*>(dj.data()), dj.size() * sizeof(lg::JobDev));
+  char buf[96];
+  snprintf(buf, sizeof(buf), "|%p|%zu|%d|%d|%d", ws, P.total, tu.target_per_cu, tu.min_iters,
+           P.cu);
+  k.append(buf);
+  return k;
+}
+
+int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lingam_opts* opts,
+           int32_t* job_status, hipStream_t st, Prof& pf) {
+  if (job_status)
+    LG_TRY(lg::launch_gather_status(reinterpret_cast<lg::JobDev*>(ws + P.table_off), P.njobs,
+                                    job_status, st),
+           "gather status");
+  if (opts->dev_status)
+    LG_TRY(hipMemcpyAsync(opts->dev_status, dj[0].ctrl, sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, st),
+           "status copy");
+  if (pf.tm.on) pf.all1 = pf.tm.take(st);
+  const bool sync = !(opts->flags & LINGAM_FLAG_NO_SYNC) || pf.tm.on;
+  if (!sync) return LINGAM_OK;
+  std::vector<int32_t> st_host(P.njobs, 0);
+  for (int k = 0; k < P.njobs; ++k)
+    LG_TRY(hipMemcpyAsync(&st_host[k], dj[k].ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+           "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (pf.tm.on && opts->profile) {
+    lingam_profile* pr = opts->profile;
+    memset(pr, 0, sizeof(*pr));
+    pr->total_ms = pf.tm.ms(pf.all0, pf.all1);
+    pr->gram_ms = pf.tm.ms(pf.g0, pf.g1);
+    pr->gram_flops = pf.gram_flops;
+    for (size_t k = 0; k + 1 < pf.pair_ev.size(); k += 2)
+      pr->pair_ms += pf.tm.ms(pf.pair_ev[k], pf.pair_ev[k + 1]);
+    pr->pair_launches = (int64_t)(pf.pair_ev.size() / 2);
+    pr->pair_evals = pf.pair_evals;
+    for (size_t k = 0; k + 1 < pf.resid_ev.size(); k += 2)
+      pr->resid_ms += pf.tm.ms(pf.resid_ev[k], pf.resid_ev[k + 1]);
+    pr->resid_bytes = pf.resid_bytes;
+  }
+  for (int k = 0; k < P.njobs; ++k)
+    if (st_host[k] != 0) return status_from_device(st_host[k]);
+  return LINGAM_OK;
+}
+
+// Run a batch: (autotune), set-up, steps, status.  `fill` writes the data rows
+// of jobs that have no X (VarLiNGAM residuals); `after_gram` and `after` hook
+// into the set-up and the end.
+template <typename Fill, typename AfterGram, typename After>
+int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opts* opts,
+               int32_t* job_status, char* ws, hipStream_t st, Fill fill, AfterGram after_gram,
+               After after) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc != LINGAM_OK) return rc;
+  const std::vector<lg::JobDev> dj = device_jobs(P, jobs, ws);
+  Prof pf;
+  pf.tm.on = opts->profile != nullptr;
+
+  // split policy: cached result, or tune now when asked
+  lg::Tune tu = kDefaultTune;
+  const std::string tkey = tune_key(jobs, P);
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_file(g_dev[dev]);
+    auto it = g_dev[dev].tunes.find(tkey);
+    if (it != g_dev[dev].tunes.end()) {
+      tu = it->second;
+      have = true;
+    }
+  }
+  if ((opts->flags & LINGAM_FLAG_AUTOTUNE) && !have) {
+    rc = fill();
+    if (rc != LINGAM_OK) return rc;
+    rc = enqueue_setup(P, dj, ws, st, nullptr, [] { return hipSuccess; });
+    if (rc != LINGAM_OK) return rc;
+    rc = autotune(P, jobs, ws, st, &tu);
+    if (rc != LINGAM_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_dev[dev].tunes[tkey] = tu;
+    save_tune_file(g_dev[dev]);
+  }
+
+  const bool graph = (opts->flags & LINGAM_FLAG_GRAPH) && !pf.tm.on;
+  if (pf.tm.on) pf.all0 = pf.tm.take(st);
+  if (!graph) {
+    rc = fill();
+    if (rc != LINGAM_OK) return rc;
+    rc = enqueue_setup(P, dj, ws, st, &pf, after_gram);
+    if (rc != LINGAM_OK) return rc;
+    rc = enqueue_steps(P, jobs, ws, st, tu, &pf);
+    if (rc != LINGAM_OK) return rc;
+    rc = after();
+    if (rc != LINGAM_OK) return rc;
+    return finish(P, dj, ws, opts, job_status, st, pf);
+  }
+
+  // graph mode: capture the whole call once per (jobs, workspace, policy) and
+  // replay the instantiated graph on later identical calls
+  const std::string gkey = graph_key(dj, P, ws, tu);
+  hipGraphExec_t exec = nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);  // one capture / cache update at a time
+  DevState& ds = g_dev[dev];
+  for (auto it = ds.graphs.begin(); it != ds.graphs.end(); ++it)
+    if (it->key == gkey) {
+      exec = it->exec;
+      ds.graphs.splice(ds.graphs.begin(), ds.graphs, it);
+      break;
+    }
+  if (!exec) {
+    if (!ds.capture) LG_TRY(hipStreamCreateWithFlags(&ds.capture, hipStreamNonBlocking), "stream");
+    hipStream_t cap = ds.capture;
+    LG_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    int rc2 = fill();
+    if (rc2 == LINGAM_OK) rc2 = enqueue_setup(P, dj, ws, cap, nullptr, after_gram);
+    if (rc2 == LINGAM_OK) rc2 = enqueue_steps(P, jobs, ws, cap, tu, nullptr);
+    if (rc2 == LINGAM_OK) rc2 = after();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    if (rc2 != LINGAM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
+    ds.graphs.push_front(GraphEntry{gkey, exec});
+    while (ds.graphs.size() > 8) {
+      (void)hipGraphExecDestroy(ds.graphs.back().exec);
+      ds.graphs.pop_back();
+    }
+  }
+  LG_TRY(hipGraphLaunch(exec, st), "hipGraphLaunch");
+  return finish(P, dj, ws, opts, job_status, st, pf);
+}
+
+int check_opts(const lingam_opts* opts, int64_t d) {
+  if (opts->struct_size != sizeof(lingam_opts))
+    return fail(LINGAM_E_INVALID, "opts->struct_size %u != %zu", opts->struct_size,
+                sizeof(lingam_opts));
+  if (opts->forced_len < 0 || opts->forced_len > d)
+    return fail(LINGAM_E_INVALID, "forced_len %d outside [0, d]", opts->forced_len);
+  if (opts->forced_len > 0 && !opts->forced_order)
+    return fail(LINGAM_E_INVALID, "forced_len > 0 but forced_order is NULL");
+  return LINGAM_OK;
+}
+
+int check_job(const HostJob& j, int k) {
+  if (!j.X || !j.order) return fail(LINGAM_E_INVALID, "job %d: X and order must be non-NULL", k);
+  if (j.n < 2)
+    return fail(LINGAM_E_INVALID, "job %d: need n >= 2 samples (got %lld)", k, (long long)j.n);
+  if (j.d < 1)
+    return fail(LINGAM_E_INVALID, "job %d: need d >= 1 variables (got %lld)", k, (long long)j.d);
+  if (j.ldx < j.d)
+    return fail(LINGAM_E_INVALID, "job %d: ldx (%lld) < d (%lld)", k, (long long)j.ldx,
+                (long long)j.d);
+  if (!j.rows && j.n_src < j.n)
+    return fail(LINGAM_E_INVALID, "job %d: n (%lld) > rows of X (%lld)", k, (long long)j.n,
+                (long long)j.n_src);
+  if (j.n_src < 1) return fail(LINGAM_E_INVALID, "job %d: X has no rows", k);
+  if (j.n > kMaxN || j.d > kMaxD || j.n_src > kMaxN)
+    return fail(LINGAM_E_UNSUPPORTED, "job %d: n <= %lld and d <= %lld supported", k,
+                (long long)kMaxN, (long long)kMaxD);
+  return LINGAM_OK;
+}
+
+int ok_fill() { return LINGAM_OK; }
+hipError_t ok_hip() { return hipSuccess; }
+
 }  // namespace
 
 extern "C" {
@@ -108,14 +588,17 @@ void lingam_opts_init(lingam_opts* o) {
 
 const char* lingam_last_error(void) { return g_err; }
 
-const char* lingam_version(void) { return "lingam-mi355x 0.1 (gfx950)"; }
+const char* lingam_version(void) { return "lingam-mi355x 0.2 (gfx950)"; }
 
 size_t lingam_workspace_size(int64_t n, int64_t d, const lingam_opts* opts) {
   (void)opts;
   if (n < 2 || d < 1 || n > kMaxN || d > kMaxD) return 0;
   int cu = 0;
   if (num_cu_of_current(&cu) != LINGAM_OK) cu = 256;
-  return lg::make_layout(n, d, cu).total;
+  HostJob j{};
+  j.n = n;
+  j.d = d;
+  return make_plan({j}, cu).total;
 }
 
 int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
@@ -130,93 +613,146 @@ int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32
   if (!X || !order) return fail(LINGAM_E_INVALID, "X and order must be non-NULL");
   if (n < 2) return fail(LINGAM_E_INVALID, "need n >= 2 samples (got %lld)", (long long)n);
   if (d < 1) return fail(LINGAM_E_INVALID, "need d >= 1 variables (got %lld)", (long long)d);
-  if (ldx < d) return fail(LINGAM_E_INVALID, "ldx (%lld) < d (%lld)", (long long)ldx, (long long)d);
+  if (ldx < d)
+    return fail(LINGAM_E_INVALID, "ldx (%lld) < d (%lld)", (long long)ldx, (long long)d);
   if (n > kMaxN || d > kMaxD)
     return fail(LINGAM_E_UNSUPPORTED, "n <= %lld and d <= %lld supported", (long long)kMaxN,
                 (long long)kMaxD);
-  if (opts->forced_len < 0 || opts->forced_len > d)
-    return fail(LINGAM_E_INVALID, "forced_len %d outside [0, d]", opts->forced_len);
-  if (opts->forced_len > 0 && !opts->forced_order)
-    return fail(LINGAM_E_INVALID, "forced_len > 0 but forced_order is NULL");
-  int cu = 0;
-  int rc = num_cu_of_current(&cu);
+  int rc = check_opts(opts, d);
   if (rc != LINGAM_OK) return rc;
-  const lg::Layout L = lg::make_layout(n, d, cu);
-  if (!ws || ws_bytes < L.total)
-    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", L.total,
+  int cu = 0;
+  rc = num_cu_of_current(&cu);
+  if (rc != LINGAM_OK) return rc;
+  const HostJob j{X,     nullptr, n, ldx, n, d, order, opts->step_measures, opts->step_gap,
+                  opts->forced_order, opts->forced_len};
+  const std::vector<HostJob> jobs{j};
+  const Plan P = make_plan(jobs, cu);
+  if (!ws || ws_bytes < P.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", P.total,
                 ws ? ws_bytes : (size_t)0);
+  return run_engine(P, jobs, opts, nullptr, (char*)ws, (hipStream_t)stream, ok_fill, ok_hip,
+                    ok_fill);
+}
 
-  hipStream_t st = (hipStream_t)stream;
+static int batch_jobs(const lingam_job* jobs, int32_t n_jobs, std::vector<HostJob>* out) {
+  if (!jobs || n_jobs < 1) return fail(LINGAM_E_INVALID, "need at least one job");
+  if (n_jobs > kMaxJobs) return fail(LINGAM_E_UNSUPPORTED, "at most %d jobs", kMaxJobs);
+  out->clear();
+  for (int k = 0; k < n_jobs; ++k) {
+    const lingam_job& s = jobs[k];
+    const HostJob h{s.X,     s.rows, s.n_rows, s.ldx, s.n, s.d, s.order, s.step_measures,
+                    s.step_gap, nullptr, 0};
+    const int rc = check_job(h, k);
+    if (rc != LINGAM_OK) return rc;
+    out->push_back(h);
+  }
+  return LINGAM_OK;
+}
+
+size_t lingam_batch_workspace_size(const lingam_job* jobs, int32_t n_jobs,
+                                   const lingam_opts* opts) {
+  (void)opts;
+  std::vector<HostJob> hj;
+  if (batch_jobs(jobs, n_jobs, &hj) != LINGAM_OK) return 0;
+  int cu = 0;
+  if (num_cu_of_current(&cu) != LINGAM_OK) cu = 256;
+  return make_plan(hj, cu).total;
+}
+
+int lingam_batch_causal_order(const lingam_job* jobs, int32_t n_jobs, int32_t* job_status,
+                              const lingam_opts* opts, void* ws, size_t ws_bytes,
+                              void* stream) {
+  g_err[0] = 0;
+  lingam_opts dflt;
+  lingam_opts_init(&dflt);
+  if (!opts) opts = &dflt;
+  if (opts->struct_size != sizeof(lingam_opts))
+    return fail(LINGAM_E_INVALID, "opts->struct_size %u != %zu", opts->struct_size,
+                sizeof(lingam_opts));
+  if (opts->forced_len != 0 || opts->step_measures || opts->step_gap || opts->dev_status)
+    return fail(LINGAM_E_INVALID,
+                "batched calls take per-step outputs in lingam_job, status in job_status, and "
+                "no forcing");
+  std::vector<HostJob> hj;
+  int rc = batch_jobs(jobs, n_jobs, &hj);
+  if (rc != LINGAM_OK) return rc;
+  int cu = 0;
+  rc = num_cu_of_current(&cu);
+  if (rc != LINGAM_OK) return rc;
+  const Plan P = make_plan(hj, cu);
+  if (!ws || ws_bytes < P.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", P.total,
+                ws ? ws_bytes : (size_t)0);
+  return run_engine(P, hj, opts, job_status, (char*)ws, (hipStream_t)stream, ok_fill, ok_hip,
+                    ok_fill);
+}
+
+size_t varlingam_workspace_size(int64_t T, int64_t d, int32_t lags, const lingam_opts* opts) {
+  (void)opts;
+  if (d < 1 || lags < 1 || d > kMaxD || T > kMaxN) return 0;
+  if (T - lags < 1 + (int64_t)lags * d + 1) return 0;
+  int cu = 0;
+  if (num_cu_of_current(&cu) != LINGAM_OK) cu = 256;
+  HostJob j{};
+  j.n = T - lags;
+  j.d = d;
+  const Plan P = make_plan({j}, cu);
+  return align256(P.total) + lg::make_var_layout(T, d, lags, cu).total;
+}
+
+int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lags, double* M,
+                  float* resid, int32_t* order, double* B0, const lingam_opts* opts, void* ws,
+                  size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  lingam_opts dflt;
+  lingam_opts_init(&dflt);
+  if (!opts) opts = &dflt;
+  if (opts->struct_size != sizeof(lingam_opts))
+    return fail(LINGAM_E_INVALID, "opts->struct_size %u != %zu", opts->struct_size,
+                sizeof(lingam_opts));
+  if (!X || !order) return fail(LINGAM_E_INVALID, "X and order must be non-NULL");
+  if (d < 1) return fail(LINGAM_E_INVALID, "need d >= 1 variables (got %lld)", (long long)d);
+  if (ldx < d)
+    return fail(LINGAM_E_INVALID, "ldx (%lld) < d (%lld)", (long long)ldx, (long long)d);
+  if (lags < 1) return fail(LINGAM_E_INVALID, "need lags >= 1 (got %d)", lags);
+  if (d > kMaxD || T > kMaxN || (int64_t)lags * d + 1 > 8192)
+    return fail(LINGAM_E_UNSUPPORTED, "d <= %lld, T <= %lld and lags * d < 8192 supported",
+                (long long)kMaxD, (long long)kMaxN);
+  if (T - lags < 1 + (int64_t)lags * d + 1)
+    return fail(LINGAM_E_INVALID, "T - lags (%lld) must exceed the %lld regressors",
+                (long long)(T - lags), (long long)(1 + (int64_t)lags * d));
+  int rc = check_opts(opts, d);
+  if (rc != LINGAM_OK) return rc;
+  if (opts->flags & LINGAM_FLAG_GRAPH)
+    return fail(LINGAM_E_UNSUPPORTED, "varlingam_fit does not take LINGAM_FLAG_GRAPH");
+  int cu = 0;
+  rc = num_cu_of_current(&cu);
+  if (rc != LINGAM_OK) return rc;
+  // the VAR residuals are the job's data rows: no X for the ingest kernel
+  const HostJob j{nullptr, nullptr, T - lags, d, T - lags, d, order, opts->step_measures,
+                  opts->step_gap, opts->forced_order, opts->forced_len};
+  const std::vector<HostJob> jobs{j};
+  const Plan P = make_plan(jobs, cu);
+  const lg::VarLayout V = lg::make_var_layout(T, d, lags, cu);
+  const size_t var_off = align256(P.total);
+  if (!ws || ws_bytes < var_off + V.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)",
+                var_off + V.total, ws ? ws_bytes : (size_t)0);
   char* w = (char*)ws;
-  Timer tm;
-  tm.on = opts->profile != nullptr;
-  int ev_all0 = tm.on ? tm.take(st) : -1;
-  hipError_t e;
-#define LG_TRY(call, what)                    \
-  do {                                        \
-    e = (call);                               \
-    if (e != hipSuccess) return hip_fail(e, what); \
-  } while (0)
-
-  LG_TRY(lg::launch_init(L, w, order, st), "init");
-  LG_TRY(lg::launch_ingest(L, w, X, ldx, st), "ingest");
-  LG_TRY(lg::launch_moments(L, w, st), "moments");
-  int ev_g0 = tm.on ? tm.take(st) : -1;
-  LG_TRY(lg::launch_gram(L, w, st), "gram");
-  int ev_g1 = tm.on ? tm.take(st) : -1;
-  LG_TRY(lg::launch_standardize(L, w, st), "standardize");
-
-  std::vector<int> pair_ev, resid_ev;
-  double pair_evals = 0.0, resid_bytes = 0.0;
-  const int forced_len = opts->forced_len;
-  for (int64_t t = 0; t + 1 < d; ++t) {
-    const int m = (int)(d - t);
-    if (m > lg::kFp64MaxM) {
-      const lg::StepPlan p = lg::plan_step(m, L.n_pad, cu);
-      if (tm.on) pair_ev.push_back(tm.take(st));
-      LG_TRY(lg::launch_pair(L, w, m, p, st), "pair");
-      if (tm.on) pair_ev.push_back(tm.take(st));
-      pair_evals += (double)m * (double)(m - 1) * (double)n;
-      LG_TRY(lg::launch_combine(L, w, m, p, st), "combine");
-    } else {
-      LG_TRY(lg::launch_pair64(L, w, m, st), "pair64");
-    }
-    LG_TRY(lg::launch_rowk(L, w, m, st), "rowk");
-    LG_TRY(lg::launch_select(L, w, m, (int)t, order, opts->forced_order, forced_len,
-                             opts->step_measures, opts->step_gap, st),
-           "select");
-    if (m > 2) {
-      if (tm.on) resid_ev.push_back(tm.take(st));
-      LG_TRY(lg::launch_resid(L, w, m - 1, st), "resid");
-      if (tm.on) resid_ev.push_back(tm.take(st));
-      resid_bytes += 28.0 * (double)n * (double)(m - 1);
-    }
-  }
-  if (opts->dev_status) LG_TRY(lg::launch_copy_status(L, w, opts->dev_status, st), "status");
-  int ev_all1 = tm.on ? tm.take(st) : -1;
-#undef LG_TRY
-
-  const bool sync = !(opts->flags & LINGAM_FLAG_NO_SYNC) || tm.on;
-  if (!sync) return LINGAM_OK;
-  int32_t dev_status = 0;
-  e = hipMemcpyAsync(&dev_status, w + L.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(status)");
-  e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  if (tm.on) {
-    lingam_profile* pr = opts->profile;
-    memset(pr, 0, sizeof(*pr));
-    pr->total_ms = tm.ms(ev_all0, ev_all1);
-    pr->gram_ms = tm.ms(ev_g0, ev_g1);
-    pr->gram_flops = 2.0 * (double)n * (double)d * (double)d;
-    for (size_t k = 0; k + 1 < pair_ev.size(); k += 2) pr->pair_ms += tm.ms(pair_ev[k], pair_ev[k + 1]);
-    pr->pair_launches = (int64_t)(pair_ev.size() / 2);
-    pr->pair_evals = pair_evals;
-    for (size_t k = 0; k + 1 < resid_ev.size(); k += 2)
-      pr->resid_ms += tm.ms(resid_ev[k], resid_ev[k + 1]);
-    pr->resid_bytes = resid_bytes;
-  }
-  return status_from_device(dev_status);
+  char* vw = w + var_off;
+  char* job = w + P.job_off[0];
+  hipStream_t st = (hipStream_t)stream;
+  return run_engine(
+      P, jobs, opts, nullptr, w, st,
+      [&]() -> int {
+        LG_TRY(lg::launch_var_fit(V, vw, job, X, ldx, resid, M, st), "var fit");
+        return LINGAM_OK;
+      },
+      [&] { return B0 ? lg::launch_save_rho(V, vw, job, st) : hipSuccess; },
+      [&]() -> int {
+        if (B0) LG_TRY(lg::launch_b0(V, vw, job, order, B0, st), "b0");
+        return LINGAM_OK;
+      });
 }
 
 size_t lingam_residualize_workspace_size(int64_t n, int64_t d) {
@@ -240,13 +776,12 @@ int lingam_residualize(float* X, int64_t n, int64_t d, int64_t ldx, const int32_
     return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", need,
                 ws ? ws_bytes : (size_t)0);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = lg::launch_residualize_rowmajor(X, n, d, ldx, active, n_active, exo, (char*)ws, st);
-  if (e != hipSuccess) return hip_fail(e, "residualize launch");
+  LG_TRY(lg::launch_residualize_rowmajor(X, n, d, ldx, active, n_active, exo, (char*)ws, st),
+         "residualize launch");
   int32_t s = 0;
-  e = hipMemcpyAsync(&s, ws, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(status)");
-  e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  LG_TRY(hipMemcpyAsync(&s, ws, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
   if (s == LINGAM_E_INVALID) return fail(LINGAM_E_INVALID, "an id in `active` is outside [0, d)");
   if (s != 0) return fail(LINGAM_E_DEGENERATE, "var(x_exo) == 0");
   return LINGAM_OK;

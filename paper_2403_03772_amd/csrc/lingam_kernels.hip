@@ -100,6 +100,11 @@ __device__ inline double logcosh64(double u) {
 }
 __device__ inline double gauss64(double u) { return u * exp(-0.5 * u * u); }
 
+// Pointers read from the job table are generic; the hot loop casts row bases
+// to the global address space so loads use global_load with a scalar base.
+typedef __attribute__((address_space(1))) const char gchar_t;
+typedef __attribute__((address_space(1))) const float gfloat_t;
+
 __device__ __forceinline__ float readlane_f(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -131,51 +136,170 @@ __device__ inline void decode_tile(int tile, int nb, int& bi, int& bj) {
 }
 
 // ---------------------------------------------------------------------------
+// job lookup and schedules
+// ---------------------------------------------------------------------------
+
+// Largest j with pre[j] <= b (pre: exclusive prefix sums, pre[njobs] = total);
+// that job owns workgroup b and has a non-zero count.
+__device__ inline int find_job(const int32_t* __restrict__ pre, int njobs, int b) {
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroup b belongs to job j at local index b - pre[j]; false when b lies
+// beyond the schedule (a grid larger than the device's own totals): the
+// workgroup then has nothing to do.
+__device__ inline bool locate(const int32_t* __restrict__ pre, int njobs, int b, int& j,
+                              int& local) {
+  j = find_job(pre, njobs, b);
+  local = b - pre[j];
+  return local < pre[j + 1] - pre[j];
+}
+
+// out[0..njobs] = exclusive prefix sums of count(j); one block of 1024 threads.
+template <typename F>
+__device__ void block_scan(int njobs, F count, int32_t* out, int32_t* sh) {
+  const int tid = threadIdx.x;
+  const int per = (njobs + 1023) / 1024;
+  const int j0 = tid * per, j1 = min(j0 + per, njobs);
+  int32_t s = 0;
+  for (int j = j0; j < j1; ++j) s += count(j);
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = tid > 0 ? sh[tid - 1] : 0;
+  for (int j = j0; j < j1; ++j) {
+    out[j] = run;
+    run += count(j);
+  }
+  if (tid == 1023) out[njobs] = sh[1023];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_setup_schedule(const JobDev* __restrict__ jobs,
+                                                         int njobs, int32_t* spre) {
+  __shared__ int32_t sh[1024];
+  for (int kind = 0; kind < kNumSetupKinds; ++kind)
+    block_scan(
+        njobs, [&](int j) { return setup_count(jobs[j].n_pad, jobs[j].d, kind); },
+        spre + (int64_t)kind * (njobs + 1), sh);
+}
+
+__global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict__ jobs,
+                                                        int njobs, int t, int num_cu, Tune tu,
+                                                        JobStep* __restrict__ js,
+                                                        int32_t* __restrict__ pre) {
+  __shared__ int32_t sh[1024];
+  __shared__ long long items;
+  const int tid = threadIdx.x;
+  if (tid == 0) items = 0;
+  __syncthreads();
+  long long mine = 0;
+  for (int j = tid; j < njobs; j += 1024) {
+    const JobStep s = job_step_base(jobs[j].d, t);
+    js[j] = s;
+    if (s.m >= 2 && !s.fp64) mine += 2LL * s.ntiles;
+  }
+  if (mine) atomicAdd(reinterpret_cast<unsigned long long*>(&items), (unsigned long long)mine);
+  __syncthreads();
+  for (int j = tid; j < njobs; j += 1024) {
+    JobStep s = js[j];
+    job_split(s, jobs[j].n_pad, items, num_cu, tu);
+    js[j] = s;
+  }
+  __syncthreads();
+  for (int kind = 0; kind < kNumKinds; ++kind)
+    block_scan(
+        njobs, [&](int j) { return kind_count(js[j], kind); }, pre + (int64_t)kind * (njobs + 1),
+        sh);
+}
+
+struct JobPack {
+  JobDev j[kJobsPerLaunch];
+};
+
+__global__ void k_set_jobs(JobDev* table, int first, JobPack pack, int count) {
+  const int k = threadIdx.x;
+  if (k < count) table[first + k] = pack.j[k];
+}
+
+// ---------------------------------------------------------------------------
 // set-up kernels
 // ---------------------------------------------------------------------------
 
-__global__ void k_init(int32_t* act, Ctrl* ctrl, int d, int32_t* order) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < d) act[v] = v;
-  if (v < (int)(sizeof(Ctrl) / sizeof(int32_t))) reinterpret_cast<int32_t*>(ctrl)[v] = 0;
-  if (v == 0 && d == 1) order[0] = 0;
+// Per job: identity active list, zero control block, the trivial order of d = 1.
+__global__ __launch_bounds__(256) void k_init(const JobDev* __restrict__ jobs) {
+  const JobDev& J = jobs[blockIdx.x];
+  for (int v = threadIdx.x; v < J.d; v += 256) J.act[v] = v;
+  if (threadIdx.x < (int)(sizeof(Ctrl) / sizeof(int32_t)))
+    reinterpret_cast<int32_t*>(J.ctrl)[threadIdx.x] = 0;
+  if (threadIdx.x == 0 && J.d == 1) J.order[0] = 0;
 }
 
-// X row-major [n x ldx] -> Zd[v][s] (FP64, exact), zero padding for s >= n and
-// for row v == d; row d of the FP32 copy Z is zeroed as well.
-__global__ __launch_bounds__(256) void k_ingest(const float* __restrict__ X, int64_t ldx, int n,
-                                                int d, int n_pad, double* __restrict__ Zd,
-                                                float* __restrict__ Z, int64_t ldz, Ctrl* ctrl) {
+// Samples (optionally gathered through `rows`) -> Zd[v][s] (FP64, exact), zero
+// padding for s >= n and for row v == d; row d of the FP32 copy Z is zeroed
+// too.  Non-finite input or a row index outside [0, n_src) is reported.
+__global__ __launch_bounds__(256) void k_ingest(const JobDev* __restrict__ jobs, int njobs,
+                                                const int32_t* __restrict__ spre) {
   __shared__ float tile[64][65];
-  const int s0 = blockIdx.x * 64, v0 = blockIdx.y * 64;
+  int j, lb;
+  if (!locate(spre, njobs, blockIdx.x, j, lb)) return;
+  const JobDev& J = jobs[j];
+  if (!J.X) return;  // data rows pre-filled by the caller of the engine
+  const int gx = J.n_pad / 64;
+  const int s0 = (lb % gx) * 64, v0 = (lb / gx) * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  bool bad = false;
+  bool bad = false, badrow = false;
   for (int i = 0; i < 16; ++i) {
     const int sl = ty * 16 + i, s = s0 + sl, v = v0 + tx;
     float val = 0.f;
-    if (s < n && v < d) {
-      val = X[(int64_t)s * ldx + v];
-      bad |= !isfinite(val);
+    if (s < J.n && v < J.d) {
+      int64_t row = s;
+      if (J.rows) {
+        row = J.rows[s];
+        if (row < 0 || row >= J.n_src) {
+          badrow = true;
+          row = -1;
+        }
+      }
+      if (row >= 0) {
+        val = J.X[row * J.ldx + v];
+        bad |= !isfinite(val);
+      }
     }
     tile[sl][tx] = val;
   }
   __syncthreads();
   for (int i = 0; i < 16; ++i) {
     const int vl = ty * 16 + i, v = v0 + vl, s = s0 + tx;
-    if (v <= d && s < n_pad) {
-      Zd[(int64_t)v * ldz + s] = (double)tile[tx][vl];
-      if (v == d) Z[(int64_t)v * ldz + s] = 0.f;
+    if (v <= J.d && s < J.n_pad) {
+      J.zd[(int64_t)v * J.ldz + s] = (double)tile[tx][vl];
+      if (v == J.d) J.z[(int64_t)v * J.ldz + s] = 0.f;
     }
   }
-  if (bad) set_status(ctrl, kStDegenerate);
+  if (bad) set_status(J.ctrl, kStDegenerate);
+  if (badrow) set_status(J.ctrl, kStInvalid);
 }
 
 // Population mean and std (two passes, FP64) of each variable.
-__global__ __launch_bounds__(256) void k_moments(const double* __restrict__ Zd, int64_t ldz,
-                                                 int n, double* mu, double* sig, Ctrl* ctrl) {
+__global__ __launch_bounds__(256) void k_moments(const JobDev* __restrict__ jobs, int njobs,
+                                                 const int32_t* __restrict__ spre) {
   __shared__ double sh[256];
-  const int v = blockIdx.x;
-  const double* z = Zd + (int64_t)v * ldz;
+  int j, v;
+  if (!locate(spre, njobs, blockIdx.x, j, v)) return;
+  const JobDev& J = jobs[j];
+  const int n = J.n;
+  const double* z = J.zd + (int64_t)v * J.ldz;
   double s = 0.0;
   for (int k = threadIdx.x; k < n; k += 256) s += z[k];
   const double m = block_sum_256(s, sh) / (double)n;
@@ -188,11 +312,11 @@ __global__ __launch_bounds__(256) void k_moments(const double* __restrict__ Zd, 
   if (threadIdx.x == 0) {
     double sd = sqrt(var);
     if (!(sd > 0.0) || !isfinite(sd)) {
-      set_status(ctrl, kStDegenerate);
+      set_status(J.ctrl, kStDegenerate);
       sd = 1.0;
     }
-    mu[v] = m;
-    sig[v] = sd;
+    J.mu[v] = m;
+    J.sig[v] = sd;
   }
 }
 
@@ -202,25 +326,28 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // on FP64 MFMA (v_mfma_f64_16x16x4f64).  One workgroup per 32 x 32 tile of the
 // upper triangle, four waves each owning a 16 x 16 block; samples staged
 // through LDS in chunks of 32, centred on the way in.
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Zd, int64_t ldz,
-                                              const double* __restrict__ mu,
-                                              const double* __restrict__ sig, int d, int n,
-                                              int n_pad, int nb, double* __restrict__ rho,
-                                              int64_t ldr, Ctrl* ctrl) {
+__global__ __launch_bounds__(256) void k_gram(const JobDev* __restrict__ jobs, int njobs,
+                                              const int32_t* __restrict__ spre) {
   constexpr int KC = 32;
   __shared__ double As[KC][33];
   __shared__ double Bs[KC][33];
+  int jb, tile;
+  if (!locate(spre + (int64_t)kSGram * (njobs + 1), njobs, blockIdx.x, jb, tile)) return;
+  const JobDev& J = jobs[jb];
+  const int d = J.d, n = J.n, n_pad = J.n_pad;
+  const int64_t ldz = J.ldz, ldr = d;
+  const int nb = cdiv(d, 32);
   int bi, bj;
-  decode_tile(blockIdx.x, nb, bi, bj);
+  decode_tile(tile, nb, bi, bj);
   const int I0 = bi * 32, J0 = bj * 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   // loader mapping: 32 variables x 32 samples, 4 consecutive samples per thread
   const int lv = tid >> 3, ls = (tid & 7) * 4;
   const int va = I0 + lv, vb = J0 + lv;
-  const double* za = Zd + (int64_t)(va < d ? va : d) * ldz;  // row d is all zeros
-  const double* zb = Zd + (int64_t)(vb < d ? vb : d) * ldz;
-  const double mua = va < d ? mu[va] : 0.0, mub = vb < d ? mu[vb] : 0.0;
+  const double* za = J.zd + (int64_t)(va < d ? va : d) * ldz;  // row d is all zeros
+  const double* zb = J.zd + (int64_t)(vb < d ? vb : d) * ldz;
+  const double mua = va < d ? J.mu[va] : 0.0, mub = vb < d ? J.mu[vb] : 0.0;
   double4_t acc = {0.0, 0.0, 0.0, 0.0};
   for (int s0 = 0; s0 < n_pad; s0 += KC) {
     __syncthreads();
@@ -245,32 +372,32 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Zd, int
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = I0 + wi * 16 + 4 * r + (lane >> 4);
-    const int j = J0 + wj * 16 + (lane & 15);
-    if (i < d && j < d && (bi != bj || i <= j)) {
-      double v = acc[r] / ((double)n * sig[i] * sig[j]);
-      if (i == j) v = 1.0;
+    const int jj = J0 + wj * 16 + (lane & 15);
+    if (i < d && jj < d && (bi != bj || i <= jj)) {
+      double v = acc[r] / ((double)n * J.sig[i] * J.sig[jj]);
+      if (i == jj) v = 1.0;
       else if (!(fabs(v) < 1.0 - kCollinear)) degenerate = true;
-      rho[(int64_t)i * ldr + j] = v;
-      rho[(int64_t)j * ldr + i] = v;
+      J.rho[(int64_t)i * ldr + jj] = v;
+      J.rho[(int64_t)jj * ldr + i] = v;
     }
   }
-  if (degenerate) set_status(ctrl, kStDegenerate);
+  if (degenerate) set_status(J.ctrl, kStDegenerate);
 }
 
 // z = (x - mu) / sigma in place in FP64, its FP32 copy, and the marginal
 // entropy H(z) of every variable (FP64).
-__global__ __launch_bounds__(256) void k_standardize(double* __restrict__ Zd,
-                                                     float* __restrict__ Z, int64_t ldz, int n,
-                                                     int n_pad, const double* __restrict__ mu,
-                                                     const double* __restrict__ sig,
-                                                     double* __restrict__ hm) {
+__global__ __launch_bounds__(256) void k_standardize(const JobDev* __restrict__ jobs, int njobs,
+                                                     const int32_t* __restrict__ spre) {
   __shared__ double sh[256];
-  const int v = blockIdx.x;
-  double* zd = Zd + (int64_t)v * ldz;
-  float* zf = Z + (int64_t)v * ldz;
-  const double m = mu[v], is = 1.0 / sig[v];
+  int j, v;
+  if (!locate(spre, njobs, blockIdx.x, j, v)) return;
+  const JobDev& J = jobs[j];
+  double* zd = J.zd + (int64_t)v * J.ldz;
+  float* zf = J.z + (int64_t)v * J.ldz;
+  const double m = J.mu[v], is = 1.0 / J.sig[v];
+  const int n = J.n;
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < n_pad; k += 256) {
+  for (int k = threadIdx.x; k < J.n_pad; k += 256) {
     if (k < n) {
       const double z = (zd[k] - m) * is;
       zd[k] = z;
@@ -283,45 +410,49 @@ __global__ __launch_bounds__(256) void k_standardize(double* __restrict__ Zd,
   }
   const double t1 = block_sum_256(a, sh);
   const double t2 = block_sum_256(b, sh);
-  if (threadIdx.x == 0) hm[v] = entropy_from_moments(t1 / n, t2 / n);
+  if (threadIdx.x == 0) J.hm[v] = entropy_from_moments(t1 / n, t2 / n);
 }
 
 // ---------------------------------------------------------------------------
 // the step kernels
 // ---------------------------------------------------------------------------
 
-// Pair moments.  Grid: ntiles * 2 * nsplit workgroups of 4 waves.  A
-// workgroup owns an 8 x 8 block of (i, j) positions, one residual direction and
-// one range of samples; wave (wi, wj) owns the 4 x 4 sub-block (i in block bi,
-// j in block bj).  Lanes stride over samples (coalesced 256 B loads per
+// Pair moments.  Grid: per job ntiles * 2 * nsplit workgroups of 4 waves.  A
+// workgroup owns an 8 x 8 block of (i, j) positions, one residual direction
+// and one range of samples; wave (wi, wj) owns the 4 x 4 sub-block (i in block
+// bi, j in block bj).  Lanes stride over samples (coalesced 256 B loads per
 // variable row) and every lane keeps 48 running values (16 pairs x {P, S1, S2})
 // for its direction.  The wave ends with an FP64 reduction after which lane
 // L < 32 holds the total of sum L, stored at
-// part[((split * ntiles + tile) * 4 + wave) * 64 + (L / 2) * 4 + dir * 2 + L % 2].
-// Sum index (a * 4 + b) * 2 + which, which 0 = S1 (log cosh, offset as described
-// in the header), 1 = S2; dir 0 = residual of i on j, dir 1 = of j on i.
-__global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64_t ldz,
-                                              const double* __restrict__ rho, int64_t ldr,
-                                              const int32_t* __restrict__ act, int m, int nblk,
-                                              int ntiles, int nsplit, int split_len, int n_pad,
-                                              int zero_slot, double* __restrict__ part) {
+// part[((split * ntiles + tile) * 4 + wave) * 64 + pair * 4 + dir * 2 + which],
+// which 0 = S1 (log cosh, offset as described in the header), 1 = S2;
+// dir 0 = residual of i on j, dir 1 = of j on i.
+__global__ __launch_bounds__(256) void k_pair(const JobDev* __restrict__ jobs, int njobs,
+                                              const JobStep* __restrict__ js,
+                                              const int32_t* __restrict__ pre, int G) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-  // contiguous range of (tile, direction, split) work so that the rows a tile
-  // reads are shared in that XCD's L2.
-  const int per_tile = 2 * nsplit;
-  const int G = ntiles * per_tile;
+  // contiguous range of (job, tile, direction, split) work so that the rows a
+  // tile reads are shared in that XCD's L2.
   const int b = blockIdx.x;
   const int Q = G >> 3, R = G & 7, x = b & 7, idx = b >> 3;
   const int w = x * Q + (x < R ? x : R) + idx;
-  const int tile = w / per_tile, rem = w - tile * per_tile;
+  int jb, local;
+  if (!locate(pre, njobs, w, jb, local)) return;
+  const JobDev& J = jobs[jb];
+  const JobStep S = js[jb];
+  const int m = S.m, nsplit = S.nsplit, ntiles = S.ntiles;
+  const int per_tile = 2 * nsplit;
+  const int tile = local / per_tile, rem = local - tile * per_tile;
   const int dir = rem / nsplit, split = rem - dir * nsplit;
   int bi, bj;
-  decode_tile(tile, nblk, bi, bj);
+  decode_tile(tile, S.nblk, bi, bj);
   const int wi = wave >> 1, wj = wave & 1;
   if (bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)
   const int pi0 = bi * kTileVars + wi * kWaveVars, pj0 = bj * kTileVars + wj * kWaveVars;
+  const int32_t* act = J.act;
+  const int64_t ldz = J.ldz, ldr = J.d;
 
   // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
   // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
@@ -331,7 +462,7 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
     const int q = lane & 15, a = q >> 2, c = q & 3;
     const int pi = pi0 + (dir == 0 ? a : c), pj = pj0 + (dir == 0 ? c : a);
     if (pi < m && pj < m && pi < pj) {
-      double r = rho[(int64_t)act[pi] * ldr + act[pj]];
+      double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
       const double lim = 1.0 - kCollinear;
       r = r > lim ? lim : (r < -lim ? -lim : r);
       const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
@@ -351,17 +482,20 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
   // the scalar-base + vector-offset form.  zr = rows of the regressed
   // variables (the residual's own variable), zx = rows of the regressors.
   const int pr0 = dir == 0 ? pi0 : pj0, px0 = dir == 0 ? pj0 : pi0;
-  const char* zr[4];
-  const char* zx[4];
+  gchar_t* zr[4];
+  gchar_t* zx[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int pr = pr0 + a, px = px0 + a;
-    zr[a] = reinterpret_cast<const char*>(Z + (int64_t)(pr < m ? act[pr] : zero_slot) * ldz);
-    zx[a] = reinterpret_cast<const char*>(Z + (int64_t)(px < m ? act[px] : zero_slot) * ldz);
+    // the row ids are wave-uniform: keep them (and the row bases) in SGPRs
+    const int sr = __builtin_amdgcn_readfirstlane(pr < m ? act[pr] : J.d);
+    const int sx = __builtin_amdgcn_readfirstlane(px < m ? act[px] : J.d);
+    zr[a] = (gchar_t*)(J.z + (int64_t)sr * ldz);
+    zx[a] = (gchar_t*)(J.z + (int64_t)sx * ldz);
   }
 
-  const int s_begin = split * split_len;
-  const int s_end = min(s_begin + split_len, n_pad);
+  const int s_begin = split * S.split_len;
+  const int s_end = min(s_begin + S.split_len, J.n_pad);
   const int nk = (s_end - s_begin) / 64;
 
   float P[16], S1[16], S2[16];
@@ -375,8 +509,8 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
   float xa[4], xb[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    xa[a] = *reinterpret_cast<const float*>(zr[a] + voff);
-    xb[a] = *reinterpret_cast<const float*>(zx[a] + voff);
+    xa[a] = *(gfloat_t*)(zr[a] + voff);
+    xb[a] = *(gfloat_t*)(zx[a] + voff);
   }
   int kb = 0;
   for (int k = 0; k < nk; ++k) {
@@ -387,8 +521,8 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
     float na[4], nb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      na[a] = *reinterpret_cast<const float*>(zr[a] + voff);
-      nb[a] = *reinterpret_cast<const float*>(zx[a] + voff);
+      na[a] = *(gfloat_t*)(zr[a] + voff);
+      nb[a] = *(gfloat_t*)(zx[a] + voff);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -439,57 +573,62 @@ __global__ __launch_bounds__(256) void k_pair(const float* __restrict__ Z, int64
     // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
     const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
     const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
-    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
+    J.part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
   }
 }
 
 // Sum the sample splits (FP64, fixed order), form both residual entropies and
 // the likelihood ratio of every pair, write R by position (antisymmetric).
-// s1_bias undoes the offsets of the S1 sums: nsplit * 64 * kS1Start + 0.5 n_pad.
-__global__ __launch_bounds__(256) void k_combine(const double* __restrict__ part,
-                                                 const double* __restrict__ rho, int64_t ldr,
-                                                 const int32_t* __restrict__ act,
-                                                 const double* __restrict__ hm, int m, int nblk,
-                                                 int ntiles, int nsplit, double s1_bias,
-                                                 double inv_n, double* __restrict__ rmat,
-                                                 int64_t ldm) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= ntiles * 64) return;
+// The S1 sums carry an offset of nsplit * 64 * kS1Start + 0.5 n_pad.
+__global__ __launch_bounds__(256) void k_combine(const JobDev* __restrict__ jobs, int njobs,
+                                                 const JobStep* __restrict__ js,
+                                                 const int32_t* __restrict__ pre) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const JobStep S = js[jb];
+  const int gid = lb * 256 + threadIdx.x;
+  if (gid >= S.ntiles * 64) return;
   const int tile = gid >> 6, wave = (gid >> 4) & 3, q = gid & 15;
   int bi, bj;
-  decode_tile(tile, nblk, bi, bj);
+  decode_tile(tile, S.nblk, bi, bj);
   const int wi = wave >> 1, wj = wave & 1;
+  const int m = S.m;
   const int pi = bi * kTileVars + wi * kWaveVars + (q >> 2);
   const int pj = bj * kTileVars + wj * kWaveVars + (q & 3);
   if (!(pi < m && pj < m && pi < pj)) return;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int sp = 0; sp < nsplit; ++sp) {
-    const double* src = part + (((int64_t)sp * ntiles + tile) * 4 + wave) * 64 + q * 4;
+  for (int sp = 0; sp < S.nsplit; ++sp) {
+    const double* src = J.part + (((int64_t)sp * S.ntiles + tile) * 4 + wave) * 64 + q * 4;
 #pragma unroll
     for (int c = 0; c < 4; ++c) s[c] += src[c];
   }
-  const int si = act[pi], sj = act[pj];
-  double r = rho[(int64_t)si * ldr + sj];
+  const double s1_bias = (double)S.nsplit * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+  const double inv_n = 1.0 / (double)J.n;
+  const int si = J.act[pi], sj = J.act[pj];
+  double r = J.rho[(int64_t)si * J.d + sj];
   const double lim = 1.0 - kCollinear;
   r = r > lim ? lim : (r < -lim ? -lim : r);
   const double al = 1.0 / sqrt(1.0 - r * r);
   const double h_ij = entropy_from_moments(kLn2 * (s[0] + s1_bias) * inv_n, al * s[1] * inv_n);
   const double h_ji = entropy_from_moments(kLn2 * (s[2] + s1_bias) * inv_n, al * s[3] * inv_n);
-  const double R = (hm[sj] + h_ij) - (hm[si] + h_ji);
-  rmat[(int64_t)pi * ldm + pj] = R;
-  rmat[(int64_t)pj * ldm + pi] = -R;
+  const double Rv = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
+  J.rmat[(int64_t)pi * J.d + pj] = Rv;
+  J.rmat[(int64_t)pj * J.d + pi] = -Rv;
 }
 
 // The same measure entirely in FP64 from the FP64 residuals, for steps with few
 // active variables.  One wave per unordered pair (both directions), lanes over
 // samples, FP64 wave reduction; writes R(i,j) and R(j,i) = -R(i,j).
-__global__ __launch_bounds__(256) void k_pair64(const double* __restrict__ Zd, int64_t ldz,
-                                                const double* __restrict__ rho, int64_t ldr,
-                                                const int32_t* __restrict__ act, int m,
-                                                const double* __restrict__ hm, int n,
-                                                double* __restrict__ rmat, int64_t ldm) {
+__global__ __launch_bounds__(256) void k_pair64(const JobDev* __restrict__ jobs, int njobs,
+                                                const JobStep* __restrict__ js,
+                                                const int32_t* __restrict__ pre) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m;
   const int lane = threadIdx.x & 63;
-  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int pair = lb * 4 + (threadIdx.x >> 6);
   const int npairs = m * (m - 1) / 2;
   if (pair >= npairs) return;
   int pi = 0, rem = pair;
@@ -498,15 +637,15 @@ __global__ __launch_bounds__(256) void k_pair64(const double* __restrict__ Zd, i
     ++pi;
   }
   const int pj = pi + 1 + rem;
-  const int si = act[pi], sj = act[pj];
-  double r = rho[(int64_t)si * ldr + sj];
+  const int si = J.act[pi], sj = J.act[pj];
+  double r = J.rho[(int64_t)si * J.d + sj];
   const double lim = 1.0 - kCollinear;
   r = r > lim ? lim : (r < -lim ? -lim : r);
   const double al = 1.0 / sqrt(1.0 - r * r);
-  const double* zi = Zd + (int64_t)si * ldz;
-  const double* zj = Zd + (int64_t)sj * ldz;
+  const double* zi = J.zd + (int64_t)si * J.ldz;
+  const double* zj = J.zd + (int64_t)sj * J.ldz;
   double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
-  for (int s = lane; s < n; s += 64) {
+  for (int s = lane; s < J.n; s += 64) {
     const double xi = zi[s], xj = zj[s];
     const double u = al * (xi - r * xj), w = al * (xj - r * xi);
     a1 += logcosh64(u);
@@ -522,22 +661,27 @@ __global__ __launch_bounds__(256) void k_pair64(const double* __restrict__ Zd, i
     b2 += __shfl_xor(b2, off);
   }
   if (lane == 0) {
-    const double inv_n = 1.0 / (double)n;
+    const double inv_n = 1.0 / (double)J.n;
     const double h_ij = entropy_from_moments(a1 * inv_n, a2 * inv_n);
     const double h_ji = entropy_from_moments(b1 * inv_n, b2 * inv_n);
-    const double R = (hm[sj] + h_ij) - (hm[si] + h_ji);
-    rmat[(int64_t)pi * ldm + pj] = R;
-    rmat[(int64_t)pj * ldm + pi] = -R;
+    const double Rv = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
+    J.rmat[(int64_t)pi * J.d + pj] = Rv;
+    J.rmat[(int64_t)pj * J.d + pi] = -Rv;
   }
 }
 
 // k_p = sum_{q != p} min(0, R(p, q))^2, one wave per row; mvec[p] = -k_p.
-__global__ __launch_bounds__(256) void k_rowk(const double* __restrict__ rmat, int64_t ldm, int m,
-                                              double* __restrict__ mvec) {
+__global__ __launch_bounds__(256) void k_rowk(const JobDev* __restrict__ jobs, int njobs,
+                                              const JobStep* __restrict__ js,
+                                              const int32_t* __restrict__ pre) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p = blockIdx.x * 4 + wave;
+  const int p = lb * 4 + wave;
   if (p >= m) return;
-  const double* row = rmat + (int64_t)p * ldm;
+  const double* row = J.rmat + (int64_t)p * J.d;
   double k = 0.0;
   for (int q = lane; q < m; q += 64) {
     if (q == p) continue;
@@ -547,7 +691,7 @@ __global__ __launch_bounds__(256) void k_rowk(const double* __restrict__ rmat, i
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
-  if (lane == 0) mvec[p] = -k;
+  if (lane == 0) J.mvec[p] = -k;
 }
 
 struct Best {
@@ -574,23 +718,25 @@ __device__ inline Best merge(const Best& a, const Best& b) {
 }
 
 // Argmax with tie-break on the original id, teacher forcing, per-step outputs,
-// swap-remove of the chosen variable.  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ mvec,
-                                                 int32_t* __restrict__ act, int m, int t, int d,
-                                                 Ctrl* ctrl, int32_t* __restrict__ order,
-                                                 const int32_t* __restrict__ forced,
-                                                 int forced_len, double* step_measures,
-                                                 double* step_gap) {
+// swap-remove of the chosen variable.  One workgroup of 1024 threads per job.
+__global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs, int njobs,
+                                                 const JobStep* __restrict__ js,
+                                                 const int32_t* __restrict__ pre, int t) {
   __shared__ Best sh[1024];
   __shared__ int forced_pos;
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m, d = J.d;
+  int32_t* act = J.act;
   const int tid = threadIdx.x;
   if (tid == 0) forced_pos = -1;
   __syncthreads();
   Best b{-INFINITY, 0x7fffffff, -1, -INFINITY};
-  const bool force = t < forced_len;
-  const int want = force ? forced[t] : -1;
+  const bool force = t < J.forced_len;
+  const int want = force ? J.forced[t] : -1;
   for (int p = tid; p < m; p += 1024) {
-    double v = mvec[p];
+    double v = J.mvec[p];
     if (v != v) v = -INFINITY;
     const int sl = act[p];
     Best c{v, sl, p, -INFINITY};
@@ -610,26 +756,26 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ mvec
   int pos = best.pos;
   if (force) {
     if (forced_pos < 0) {
-      if (tid == 0) set_status(ctrl, kStInvalid);
+      if (tid == 0) set_status(J.ctrl, kStInvalid);
     } else {
       pos = forced_pos;
     }
   }
-  if (step_measures) {
-    double* row = step_measures + (int64_t)t * d;
+  if (J.measures) {
+    double* row = J.measures + (int64_t)t * d;
     for (int v = tid; v < d; v += 1024) row[v] = NAN;
     __syncthreads();
-    for (int p = tid; p < m; p += 1024) row[act[p]] = mvec[p];
+    for (int p = tid; p < m; p += 1024) row[act[p]] = J.mvec[p];
   }
   __syncthreads();
   if (tid == 0) {
     const int slot = act[pos];
-    order[t] = slot;
-    ctrl->exo_slot = slot;
-    ctrl->exo_pos = pos;
-    if (step_gap) step_gap[t] = best.v - best.v2;
+    J.order[t] = slot;
+    J.ctrl->exo_slot = slot;
+    J.ctrl->exo_pos = pos;
+    if (J.gaps) J.gaps[t] = best.v - best.v2;
     act[pos] = act[m - 1];
-    if (m == 2) order[t + 1] = act[0];
+    if (m == 2) J.order[t + 1] = act[0];
   }
 }
 
@@ -637,27 +783,30 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ mvec
 // standardized: z_p <- (z_p - rho_pe z_e) / sqrt(1 - rho_pe^2) in FP64, refresh
 // the FP32 copy, recompute H(z_p) in FP64, update row p of the correlation
 // matrix.  One workgroup per remaining variable.
-__global__ __launch_bounds__(256) void k_resid(double* __restrict__ Zd, float* __restrict__ Z,
-                                               int64_t ldz, double* __restrict__ rho,
-                                               int64_t ldr, const int32_t* __restrict__ act,
-                                               int m_after, Ctrl* ctrl,
-                                               double* __restrict__ hm, int n, int n_pad) {
+__global__ __launch_bounds__(256) void k_resid(const JobDev* __restrict__ jobs, int njobs,
+                                               const JobStep* __restrict__ js,
+                                               const int32_t* __restrict__ pre) {
   __shared__ double sh[256];
-  const int p = blockIdx.x;
-  const int sp = act[p], se = ctrl->exo_slot;
-  const double* rho_e = rho + (int64_t)se * ldr;
+  int jb, p;
+  if (!locate(pre, njobs, blockIdx.x, jb, p)) return;
+  const JobDev& J = jobs[jb];
+  const int m_after = js[jb].m - 1;
+  const int64_t ldz = J.ldz, ldr = J.d;
+  const int sp = J.act[p], se = J.ctrl->exo_slot;
+  const double* rho_e = J.rho + (int64_t)se * ldr;
   const double r = rho_e[sp];
   double om = 1.0 - r * r;
   if (!(fabs(r) < 1.0 - kCollinear)) {
-    if (threadIdx.x == 0) set_status(ctrl, kStDegenerate);
+    if (threadIdx.x == 0) set_status(J.ctrl, kStDegenerate);
     om = 1.0;
   }
   const double al = 1.0 / sqrt(om);
-  double* zp = Zd + (int64_t)sp * ldz;
-  const double* ze = Zd + (int64_t)se * ldz;
-  float* zf = Z + (int64_t)sp * ldz;
+  double* zp = J.zd + (int64_t)sp * ldz;
+  const double* ze = J.zd + (int64_t)se * ldz;
+  float* zf = J.z + (int64_t)sp * ldz;
+  const int n = J.n;
   double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < n_pad; k += 256) {
+  for (int k = threadIdx.x; k < J.n_pad; k += 256) {
     const double z = al * (zp[k] - r * ze[k]);  // padded samples stay 0
     zp[k] = z;
     zf[k] = (float)z;
@@ -668,11 +817,11 @@ __global__ __launch_bounds__(256) void k_resid(double* __restrict__ Zd, float* _
   }
   const double t1 = block_sum_256(a, sh);
   const double t2 = block_sum_256(b, sh);
-  if (threadIdx.x == 0) hm[sp] = entropy_from_moments(t1 / n, t2 / n);
-  double* rho_p = rho + (int64_t)sp * ldr;
+  if (threadIdx.x == 0) J.hm[sp] = entropy_from_moments(t1 / n, t2 / n);
+  double* rho_p = J.rho + (int64_t)sp * ldr;
   for (int q = threadIdx.x; q < m_after; q += 256) {
     if (q == p) continue;
-    const int sq = act[q];
+    const int sq = J.act[q];
     const double rq = rho_e[sq];
     double oq = 1.0 - rq * rq;
     if (!(fabs(rq) < 1.0 - kCollinear)) oq = 1.0;  // flagged by q's own workgroup
@@ -680,7 +829,239 @@ __global__ __launch_bounds__(256) void k_resid(double* __restrict__ Zd, float* _
   }
 }
 
-__global__ void k_copy_status(const Ctrl* ctrl, int32_t* dst) { dst[0] = ctrl->status; }
+__global__ void k_gather_status(const JobDev* __restrict__ jobs, int njobs, int32_t* dst) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < njobs) dst[j] = jobs[j].ctrl->status;
+}
+
+// X row-major [n x ldx] -> Zd[v][s] (FP64) for the VAR series: zero padding
+// for s >= n and row d.
+__global__ __launch_bounds__(256) void k_transpose_f64(const float* __restrict__ X, int64_t ldx,
+                                                       int n, int d, int n_pad,
+                                                       double* __restrict__ Zd, int64_t ldz,
+                                                       Ctrl* ctrl) {
+  __shared__ float tile[64][65];
+  const int s0 = blockIdx.x * 64, v0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  bool bad = false;
+  for (int i = 0; i < 16; ++i) {
+    const int sl = ty * 16 + i, s = s0 + sl, v = v0 + tx;
+    float val = 0.f;
+    if (s < n && v < d) {
+      val = X[(int64_t)s * ldx + v];
+      bad |= !isfinite(val);
+    }
+    tile[sl][tx] = val;
+  }
+  __syncthreads();
+  for (int i = 0; i < 16; ++i) {
+    const int vl = ty * 16 + i, v = v0 + vl, s = s0 + tx;
+    if (v <= d && s < n_pad) Zd[(int64_t)v * ldz + s] = (double)tile[tx][vl];
+  }
+  if (bad) set_status(ctrl, kStDegenerate);
+}
+
+// ---------------------------------------------------------------------------
+// VarLiNGAM: least-squares VAR(k) with intercept, residuals, B0
+// ---------------------------------------------------------------------------
+
+// Column q of the lagged design over rows r = 0 .. N-1 (time t = r + lags):
+// q = 0: the intercept (ones); q = 1 + (tau - 1) d + v: x_v(t - tau);
+// q = 1 + lags d + v: the response x_v(t).  Xd is variable-major [d][ldx].
+__device__ inline const double* design_col(int q, const double* Xd, int64_t ldx, int d, int lags,
+                                           const double* ones) {
+  if (q == 0) return ones;
+  const int p = 1 + lags * d;
+  if (q < p) {
+    const int tau = (q - 1) / d + 1, v = (q - 1) - (tau - 1) * d;
+    return Xd + (int64_t)v * ldx + (lags - tau);
+  }
+  return Xd + (int64_t)(q - p) * ldx + lags;
+}
+
+__global__ void k_fill(double* p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// W = D^T D for the lagged design D (N rows, q = 1 + lags d + d columns), FP64
+// MFMA, upper 32 x 32 tiles mirrored.  Same tiling as k_gram, uncentred.
+__global__ __launch_bounds__(256) void k_gram_design(const double* __restrict__ Xd, int64_t ldx,
+                                                     const double* __restrict__ ones, int d,
+                                                     int lags, int N, int q, int nb,
+                                                     double* __restrict__ W, int64_t ldw) {
+  constexpr int KC = 32;
+  __shared__ double As[KC][33];
+  __shared__ double Bs[KC][33];
+  int bi, bj;
+  decode_tile(blockIdx.x, nb, bi, bj);
+  const int I0 = bi * 32, J0 = bj * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lv = tid >> 3, ls = (tid & 7) * 4;
+  const int va = I0 + lv, vb = J0 + lv;
+  const double* za = design_col(va < q ? va : 0, Xd, ldx, d, lags, ones);
+  const double* zb = design_col(vb < q ? vb : 0, Xd, ldx, d, lags, ones);
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < N; s0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + ls + u;
+      As[ls + u][lv] = (s < N && va < q) ? za[s] : 0.0;
+      Bs[ls + u][lv] = (s < N && vb < q) ? zb[s] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const double a = As[kk * 4 + (lane >> 4)][wi * 16 + (lane & 15)];
+      const double b = Bs[kk * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = I0 + wi * 16 + 4 * r + (lane >> 4);
+    const int j = J0 + wj * 16 + (lane & 15);
+    if (i < q && j < q && (bi != bj || i <= j)) {
+      W[(int64_t)i * ldw + j] = acc[r];
+      W[(int64_t)j * ldw + i] = acc[r];
+    }
+  }
+}
+
+// In-place Cholesky A = L L^T of the leading p x p block (lower triangle holds
+// L; the upper triangle is left as it was).  One workgroup, right-looking.
+__device__ void chol_block(double* A, int64_t lda, int p, Ctrl* ctrl) {
+  __shared__ double piv, tol;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < p; ++j) mx = fmax(mx, fabs(A[(int64_t)j * lda + j]));
+    tol = mx * 1e-13;  // pivots below this are rounding noise: the matrix is singular
+  }
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    if (tid == 0) {
+      double a = A[(int64_t)j * lda + j];
+      if (!(a > tol) || !isfinite(a)) {
+        set_status(ctrl, kStDegenerate);
+        a = 1.0;
+      }
+      piv = sqrt(a);
+      A[(int64_t)j * lda + j] = piv;
+    }
+    __syncthreads();
+    const double l = piv;
+    for (int i = j + 1 + tid; i < p; i += nt) A[(int64_t)i * lda + j] /= l;
+    __syncthreads();
+    const int w = p - j - 1;  // trailing block rows/cols j+1 .. p-1, lower part
+    for (int e = tid; e < w * w; e += nt) {
+      const int ii = e / w, kk = e - ii * w;
+      if (kk > ii) continue;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      A[(int64_t)i * lda + k] -= A[(int64_t)i * lda + j] * A[(int64_t)k * lda + j];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_chol(double* A, int64_t lda, int p, Ctrl* ctrl) {
+  chol_block(A, lda, p, ctrl);
+}
+
+// Solve (L L^T) x = c in place for columns c = A[0:p, p + j], j < nrhs.
+// One thread per right-hand side; L is read row-wise (broadcast).
+__global__ __launch_bounds__(64) void k_chol_solve(double* A, int64_t lda, int p, int nrhs) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= nrhs) return;
+  double* c = A + p + j;
+  for (int i = 0; i < p; ++i) {
+    double s = c[(int64_t)i * lda];
+    const double* Li = A + (int64_t)i * lda;
+    for (int k = 0; k < i; ++k) s -= Li[k] * c[(int64_t)k * lda];
+    c[(int64_t)i * lda] = s / Li[i];
+  }
+  for (int i = p - 1; i >= 0; --i) {
+    double s = c[(int64_t)i * lda];
+    for (int k = i + 1; k < p; ++k) s -= A[(int64_t)k * lda + i] * c[(int64_t)k * lda];
+    c[(int64_t)i * lda] = s / A[(int64_t)i * lda + i];
+  }
+}
+
+// Residuals e_v(r) = x_v(r + lags) - sum_q D[r][q] A[q][v] into the ordering's
+// FP64 data rows Zd[v][r]; optional FP32 row-major copy; VAR matrices M.
+__global__ __launch_bounds__(64) void k_var_resid(const double* __restrict__ Xd, int64_t ldx,
+                                                  int d,
+                                                  int lags, int N, const double* __restrict__ W,
+                                                  int64_t ldw, double* __restrict__ Zd,
+                                                  int64_t ldz, float* resid_out,
+                                                  double* M_out) {
+  const int r = blockIdx.x;
+  const int v = blockIdx.y * 64 + threadIdx.x;
+  if (v >= d) return;
+  const int p = 1 + lags * d;
+  const double* A = W + p;  // A[q][v] = W[q][p + v]
+  double e = Xd[(int64_t)v * ldx + r + lags] - A[v];  // response minus intercept
+  for (int tau = 1; tau <= lags; ++tau) {
+    const double* Aq = A + (int64_t)(1 + (tau - 1) * d) * ldw;
+    for (int u = 0; u < d; ++u)
+      e -= Xd[(int64_t)u * ldx + r + lags - tau] * Aq[(int64_t)u * ldw + v];
+  }
+  Zd[(int64_t)v * ldz + r] = e;
+  if (resid_out) resid_out[(int64_t)r * d + v] = (float)e;
+  if (M_out && r == 0) {
+    // M[tau-1][i][j] = coefficient of x_j(t - tau) in the equation of x_i
+    for (int tau = 1; tau <= lags; ++tau)
+      for (int j = 0; j < d; ++j)
+        M_out[((int64_t)(tau - 1) * d + v) * d + j] = A[(int64_t)(1 + (tau - 1) * d + j) * ldw + v];
+  }
+}
+
+// Zero the sample padding of Zd rows 0..d-1 and all of row d of Zd and Z.
+__global__ void k_zero_pad(double* Zd, float* Z, int64_t ldz, int d, int n, int n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tail = (int64_t)(n_pad - n);
+  if (i < (int64_t)d * tail) {
+    const int v = (int)(i / tail), r = n + (int)(i - (int64_t)v * tail);
+    Zd[(int64_t)v * ldz + r] = 0.0;
+  }
+  if (i < n_pad) {
+    Zd[(int64_t)d * ldz + i] = 0.0;
+    Z[(int64_t)d * ldz + i] = 0.f;
+  }
+}
+
+// B0 by least squares of every variable on its order predecessors, from the
+// covariance of the residuals S = diag(sig) rho0 diag(sig): with the order-
+// permuted S = L L^T, the coefficients b of variable o_i on o_0 .. o_{i-1}
+// solve L[0:i, 0:i]^T b = L[i, 0:i]^T.  One workgroup; `scr` holds d x d.
+__global__ __launch_bounds__(1024) void k_b0(const double* __restrict__ rho0, int64_t ldr,
+                                             const double* __restrict__ sig,
+                                             const int32_t* __restrict__ order, int d,
+                                             double* __restrict__ scr, double* __restrict__ B0,
+                                             Ctrl* ctrl) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < d * d; e += 1024) {
+    const int a = e / d, b = e - a * d;
+    const int oa = order[a], ob = order[b];
+    scr[e] = sig[oa] * sig[ob] * rho0[(int64_t)oa * ldr + ob];
+    B0[e] = 0.0;
+  }
+  __syncthreads();
+  chol_block(scr, d, d, ctrl);
+  // row i: back substitution with the leading i x i block of L; the solution is
+  // written straight into row order[i] of B0 (entries needed later are final)
+  for (int i = 1 + tid; i < d; i += 1024) {
+    const double* Li = scr + (int64_t)i * d;
+    for (int k = i - 1; k >= 0; --k) {
+      double s = Li[k];
+      for (int q = k + 1; q < i; ++q) s -= scr[(int64_t)q * d + k] * B0[(int64_t)order[i] * d + order[q]];
+      B0[(int64_t)order[i] * d + order[k]] = s / scr[(int64_t)k * d + k];
+    }
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 // standalone residualisation on a row-major matrix
@@ -754,31 +1135,10 @@ __global__ void k_zero_i32(int32_t* p) { p[0] = 0; }
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// host side: plans, layout, launchers
+// host side: layouts, schedules, launchers
 // ---------------------------------------------------------------------------
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-StepPlan plan_step(int64_t m, int64_t n_pad, int num_cu) {
-  StepPlan p;
-  p.nblk = (int)((m + kTileVars - 1) / kTileVars);
-  p.ntiles = p.nblk * (p.nblk + 1) / 2;
-  const int64_t iters = n_pad / kSampleQuantum;
-  // Enough workgroups (two per tile, one per residual direction) to fill every
-  // CU several times over: when the pair triangle is small, split the sample
-  // range (partials are combined in FP64), keeping at least kMinIters sample
-  // iterations per split so the per-workgroup set-up and reduction stay small.
-  constexpr int64_t kMinIters = 8;
-  const int64_t target = (int64_t)num_cu * 16;
-  int64_t ns = (target + 2 * p.ntiles - 1) / (2 * p.ntiles);
-  const int64_t cap = iters >= kMinIters ? iters / kMinIters : 1;
-  if (ns > cap) ns = cap;
-  if (ns < 1) ns = 1;
-  const int64_t per = (iters + ns - 1) / ns;
-  p.split_len = (int)(per * kSampleQuantum);
-  p.nsplit = (int)((iters + per - 1) / per);
-  return p;
-}
 
 Layout make_layout(int64_t n, int64_t d, int num_cu) {
   Layout L{};
@@ -800,10 +1160,14 @@ Layout make_layout(int64_t n, int64_t d, int num_cu) {
   L.hm = take(sizeof(double) * (size_t)d);
   L.act = take(sizeof(int32_t) * (size_t)d);
   L.ctrl = take(sizeof(Ctrl));
+  // partial sums: the most splits any policy in range can give a job alone
+  // (a batch only ever splits less)
+  const Tune worst{kMaxTargetPerCu, kMinMinIters};
   size_t pe = 0;
-  for (int64_t m = d; m > kFp64MaxM; --m) {
-    const StepPlan p = plan_step(m, L.n_pad, num_cu);
-    const size_t need = (size_t)p.ntiles * (size_t)p.nsplit * 256;
+  for (int64_t t = 0; t + kFp64MaxM < d; ++t) {
+    JobStep s = job_step_base((int32_t)d, (int32_t)t);
+    job_split(s, (int32_t)L.n_pad, 2LL * s.ntiles, num_cu, worst);
+    const size_t need = (size_t)s.ntiles * (size_t)s.nsplit * 256;
     if (need > pe) pe = need;
   }
   L.part_elems = pe;
@@ -814,98 +1178,128 @@ Layout make_layout(int64_t n, int64_t d, int num_cu) {
   return L;
 }
 
-hipError_t launch_init(const Layout& L, char* ws, int32_t* order, hipStream_t st) {
-  const int threads = 256;
-  const int64_t cnt = L.d > 64 ? L.d : 64;
-  hipLaunchKernelGGL(k_init, dim3((unsigned)((cnt + threads - 1) / threads)), dim3(threads), 0,
-                     st, at<int32_t>(ws, L.act), at<Ctrl>(ws, L.ctrl), (int)L.d, order);
+size_t sched_bytes(int njobs) {
+  return align256(sizeof(JobStep) * (size_t)njobs) +
+         align256(sizeof(int32_t) * (size_t)kNumKinds * (size_t)(njobs + 1)) +
+         align256(sizeof(int32_t) * (size_t)kNumSetupKinds * (size_t)(njobs + 1));
+}
+
+SchedDev sched_at(char* base, int njobs) {
+  SchedDev s;
+  s.js = reinterpret_cast<JobStep*>(base);
+  char* p = base + align256(sizeof(JobStep) * (size_t)njobs);
+  s.pre = reinterpret_cast<int32_t*>(p);
+  p += align256(sizeof(int32_t) * (size_t)kNumKinds * (size_t)(njobs + 1));
+  s.spre = reinterpret_cast<int32_t*>(p);
+  return s;
+}
+
+static inline const int32_t* pre_of(SchedDev sc, int njobs, int kind) {
+  return sc.pre + (int64_t)kind * (njobs + 1);
+}
+static inline const int32_t* spre_of(SchedDev sc, int njobs, int kind) {
+  return sc.spre + (int64_t)kind * (njobs + 1);
+}
+
+hipError_t launch_set_jobs(JobDev* table, int first, const JobDev* host_jobs, int count,
+                           hipStream_t st) {
+  JobPack pack{};
+  for (int k = 0; k < count && k < kJobsPerLaunch; ++k) pack.j[k] = host_jobs[k];
+  hipLaunchKernelGGL(k_set_jobs, dim3(1), dim3(kJobsPerLaunch), 0, st, table, first, pack, count);
   return hipGetLastError();
 }
 
-hipError_t launch_ingest(const Layout& L, char* ws, const float* X, int64_t ldx,
+hipError_t launch_setup_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, sc.spre);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const JobDev* jobs, int njobs, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3((unsigned)njobs), dim3(256), 0, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ingest, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     spre_of(sc, njobs, kSIngest));
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_moments, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     spre_of(sc, njobs, kSCols));
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs, sc.spre);
+  return hipGetLastError();
+}
+
+hipError_t launch_standardize(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+                              hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_standardize, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     spre_of(sc, njobs, kSCols));
+  return hipGetLastError();
+}
+
+hipError_t launch_step_schedule(const JobDev* jobs, int njobs, int t, int num_cu, Tune tu,
+                                SchedDev sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, t, num_cu, tu,
+                     sc.js, sc.pre);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_of(sc, njobs, kKPair), grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_of(sc, njobs, kKComb));
+  return hipGetLastError();
+}
+
+hipError_t launch_pair64(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair64, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_of(sc, njobs, kKP64));
+  return hipGetLastError();
+}
+
+hipError_t launch_rowk(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rowk, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_of(sc, njobs, kKRowk));
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const JobDev* jobs, int njobs, int t, SchedDev sc, int grid,
                          hipStream_t st) {
-  dim3 grid((unsigned)(L.n_pad / 64), (unsigned)((L.d + 1 + 63) / 64));
-  hipLaunchKernelGGL(k_ingest, grid, dim3(256), 0, st, X, ldx, (int)L.n, (int)L.d,
-                     (int)L.n_pad, at<double>(ws, L.zd), at<float>(ws, L.z), L.ldz,
-                     at<Ctrl>(ws, L.ctrl));
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select, dim3((unsigned)grid), dim3(1024), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_of(sc, njobs, kKSel), t);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const Layout& L, char* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_moments, dim3((unsigned)L.d), dim3(256), 0, st, at<double>(ws, L.zd),
-                     L.ldz, (int)L.n, at<double>(ws, L.mu), at<double>(ws, L.sig),
-                     at<Ctrl>(ws, L.ctrl));
+hipError_t launch_resid(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resid, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_of(sc, njobs, kKRes));
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const Layout& L, char* ws, hipStream_t st) {
-  const int nb = (int)((L.d + 31) / 32);
-  const int tiles = nb * (nb + 1) / 2;
-  hipLaunchKernelGGL(k_gram, dim3((unsigned)tiles), dim3(256), 0, st, at<double>(ws, L.zd),
-                     L.ldz, at<double>(ws, L.mu), at<double>(ws, L.sig), (int)L.d, (int)L.n,
-                     (int)L.n_pad, nb, at<double>(ws, L.rho), L.d, at<Ctrl>(ws, L.ctrl));
-  return hipGetLastError();
-}
-
-hipError_t launch_standardize(const Layout& L, char* ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_standardize, dim3((unsigned)L.d), dim3(256), 0, st,
-                     at<double>(ws, L.zd), at<float>(ws, L.z), L.ldz, (int)L.n, (int)L.n_pad,
-                     at<double>(ws, L.mu), at<double>(ws, L.sig), at<double>(ws, L.hm));
-  return hipGetLastError();
-}
-
-hipError_t launch_pair(const Layout& L, char* ws, int m, const StepPlan& p, hipStream_t st) {
-  const int G = p.ntiles * 2 * p.nsplit;
-  hipLaunchKernelGGL(k_pair, dim3((unsigned)G), dim3(256), 0, st, at<float>(ws, L.z), L.ldz,
-                     at<double>(ws, L.rho), L.d, at<int32_t>(ws, L.act), m, p.nblk, p.ntiles,
-                     p.nsplit, p.split_len, (int)L.n_pad, (int)L.d, at<double>(ws, L.part));
-  return hipGetLastError();
-}
-
-hipError_t launch_combine(const Layout& L, char* ws, int m, const StepPlan& p, hipStream_t st) {
-  const int64_t threads = (int64_t)p.ntiles * 64;
-  const double s1_bias = (double)p.nsplit * 64.0 * (double)kS1Start + 0.5 * (double)L.n_pad;
-  hipLaunchKernelGGL(k_combine, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st,
-                     at<double>(ws, L.part), at<double>(ws, L.rho), L.d,
-                     at<int32_t>(ws, L.act), at<double>(ws, L.hm), m, p.nblk, p.ntiles,
-                     p.nsplit, s1_bias, 1.0 / (double)L.n, at<double>(ws, L.rmat), L.d);
-  return hipGetLastError();
-}
-
-hipError_t launch_pair64(const Layout& L, char* ws, int m, hipStream_t st) {
-  const int npairs = m * (m - 1) / 2;
-  hipLaunchKernelGGL(k_pair64, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st,
-                     at<double>(ws, L.zd), L.ldz, at<double>(ws, L.rho), L.d,
-                     at<int32_t>(ws, L.act), m, at<double>(ws, L.hm), (int)L.n,
-                     at<double>(ws, L.rmat), L.d);
-  return hipGetLastError();
-}
-
-hipError_t launch_rowk(const Layout& L, char* ws, int m, hipStream_t st) {
-  hipLaunchKernelGGL(k_rowk, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st,
-                     at<double>(ws, L.rmat), L.d, m, at<double>(ws, L.mvec));
-  return hipGetLastError();
-}
-
-hipError_t launch_select(const Layout& L, char* ws, int m, int t, int32_t* order,
-                         const int32_t* forced, int forced_len, double* step_measures,
-                         double* step_gap, hipStream_t st) {
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st, at<double>(ws, L.mvec),
-                     at<int32_t>(ws, L.act), m, t, (int)L.d, at<Ctrl>(ws, L.ctrl), order, forced,
-                     forced_len, step_measures, step_gap);
-  return hipGetLastError();
-}
-
-hipError_t launch_resid(const Layout& L, char* ws, int m_after, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid, dim3((unsigned)m_after), dim3(256), 0, st, at<double>(ws, L.zd),
-                     at<float>(ws, L.z), L.ldz, at<double>(ws, L.rho), L.d,
-                     at<int32_t>(ws, L.act), m_after, at<Ctrl>(ws, L.ctrl),
-                     at<double>(ws, L.hm), (int)L.n, (int)L.n_pad);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_status(const Layout& L, char* ws, int32_t* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, st, at<Ctrl>(ws, L.ctrl), dst);
+hipError_t launch_gather_status(const JobDev* jobs, int njobs, int32_t* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_status, dim3((unsigned)((njobs + 255) / 256)), dim3(256), 0, st,
+                     jobs, njobs, dst);
   return hipGetLastError();
 }
 
@@ -940,6 +1334,73 @@ hipError_t launch_residualize_rowmajor(float* X, int64_t n, int64_t d, int64_t l
   dim3 grid((unsigned)(gx < 64 ? gx : 64), (unsigned)n_active);
   hipLaunchKernelGGL(k_rr_apply, grid, dim3(256), 0, st, X, ldx, (int)n, (int)d, active,
                      n_active, exo, cov, status);
+  return hipGetLastError();
+}
+
+VarLayout make_var_layout(int64_t T, int64_t d, int lags, int num_cu) {
+  VarLayout V{};
+  V.T = T;
+  V.d = d;
+  V.lags = lags;
+  V.N = T - lags;
+  V.p = 1 + (int64_t)lags * d;
+  V.q = V.p + d;
+  V.ord = make_layout(V.N, d, num_cu);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  V.ldx = (T + 63) / 64 * 64;
+  V.xd = take(sizeof(double) * (size_t)(d + 1) * (size_t)V.ldx);
+  V.ones = take(sizeof(double) * (size_t)V.N);
+  V.w = take(sizeof(double) * (size_t)V.q * (size_t)V.q);
+  V.rho0 = take(sizeof(double) * (size_t)d * (size_t)d);
+  V.scr = take(sizeof(double) * (size_t)d * (size_t)d);
+  V.total = off;
+  return V;
+}
+
+hipError_t launch_var_fit(const VarLayout& V, char* ws, char* job, const float* X,
+                          int64_t ldx_in, float* resid_out, double* M_out, hipStream_t st) {
+  const Layout& L = V.ord;
+  Ctrl* ctrl = at<Ctrl>(job, L.ctrl);
+  double* Xd = at<double>(ws, V.xd);
+  double* ones = at<double>(ws, V.ones);
+  double* W = at<double>(ws, V.w);
+  // series -> variable-major FP64 (padding beyond T is zero)
+  dim3 g1((unsigned)(V.ldx / 64), (unsigned)((V.d + 1 + 63) / 64));
+  hipLaunchKernelGGL(k_transpose_f64, g1, dim3(256), 0, st, X, ldx_in, (int)V.T, (int)V.d,
+                     (int)V.ldx, Xd, V.ldx, ctrl);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((V.N + 255) / 256)), dim3(256), 0, st, ones,
+                     (int)V.N, 1.0);
+  const int nb = (int)((V.q + 31) / 32);
+  hipLaunchKernelGGL(k_gram_design, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, st, Xd,
+                     V.ldx, ones, (int)V.d, V.lags, (int)V.N, (int)V.q, nb, W, V.q);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, W, V.q, (int)V.p, ctrl);
+  hipLaunchKernelGGL(k_chol_solve, dim3((unsigned)((V.d + 63) / 64)), dim3(64), 0, st, W, V.q,
+                     (int)V.p, (int)V.d);
+  dim3 g2((unsigned)V.N, (unsigned)((V.d + 63) / 64));
+  hipLaunchKernelGGL(k_var_resid, g2, dim3(64), 0, st, Xd, V.ldx, (int)V.d, V.lags, (int)V.N,
+                     W, V.q, at<double>(job, L.zd), L.ldz, resid_out, M_out);
+  const int64_t zn = (L.d * (L.n_pad - L.n) > L.n_pad) ? L.d * (L.n_pad - L.n) : L.n_pad;
+  hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((zn + 255) / 256)), dim3(256), 0, st,
+                     at<double>(job, L.zd), at<float>(job, L.z), L.ldz, (int)L.d, (int)L.n,
+                     (int)L.n_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_save_rho(const VarLayout& V, char* ws, char* job, hipStream_t st) {
+  return hipMemcpyAsync(ws + V.rho0, job + V.ord.rho, sizeof(double) * (size_t)(V.d * V.d),
+                        hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t launch_b0(const VarLayout& V, char* ws, char* job, const int32_t* order, double* B0,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_b0, dim3(1), dim3(1024), 0, st, at<double>(ws, V.rho0), V.d,
+                     at<double>(job, V.ord.sig), order, (int)V.d, at<double>(ws, V.scr), B0,
+                     at<Ctrl>(job, V.ord.ctrl));
   return hipGetLastError();
 }
 

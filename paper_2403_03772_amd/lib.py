@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblingam_mi355x.so")
 
 OK, E_INVALID, E_DEGENERATE, E_HIP, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-FLAG_NO_SYNC = 1
+FLAG_NO_SYNC, FLAG_GRAPH, FLAG_AUTOTUNE = 1, 2, 4
 
 _lock = threading.Lock()
 _lib = None
@@ -55,6 +55,20 @@ class _Opts(ctypes.Structure):
     ]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("n_rows", ctypes.c_int64),
+        ("ldx", ctypes.c_int64),
+        ("rows", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int64),
+        ("order", ctypes.c_void_p),
+        ("step_measures", ctypes.c_void_p),
+        ("step_gap", ctypes.c_void_p),
+    ]
+
+
 @dataclass
 class Profile:
     total_ms: float
@@ -88,6 +102,17 @@ def load():
         lib.lingam_residualize_workspace_size.restype = sz
         lib.lingam_residualize.argtypes = [P, i64, i64, i64, P, i32, i32, P, sz, P]
         lib.lingam_residualize.restype = ctypes.c_int
+        lib.varlingam_workspace_size.argtypes = [i64, i64, i32, ctypes.POINTER(_Opts)]
+        lib.varlingam_workspace_size.restype = sz
+        lib.varlingam_fit.argtypes = [P, i64, i64, i64, i32, P, P, P, P, ctypes.POINTER(_Opts),
+                                      P, sz, P]
+        lib.varlingam_fit.restype = ctypes.c_int
+        lib.lingam_batch_workspace_size.argtypes = [ctypes.POINTER(_Job), i32,
+                                                    ctypes.POINTER(_Opts)]
+        lib.lingam_batch_workspace_size.restype = sz
+        lib.lingam_batch_causal_order.argtypes = [ctypes.POINTER(_Job), i32, P,
+                                                  ctypes.POINTER(_Opts), P, sz, P]
+        lib.lingam_batch_causal_order.restype = ctypes.c_int
         lib.lingam_last_error.argtypes = []
         lib.lingam_last_error.restype = ctypes.c_char_p
         lib.lingam_version.argtypes = []
@@ -126,7 +151,8 @@ def _ptr(t):
 
 
 def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool = False,
-                 workspace=None, sync: bool = True):
+                 workspace=None, sync: bool = True, graph: bool = False,
+                 autotune: bool = False):
     """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
 
     Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
@@ -150,6 +176,10 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     lib.lingam_opts_init(ctypes.byref(opts))
     if not sync:
         opts.flags |= FLAG_NO_SYNC
+    if graph:
+        opts.flags |= FLAG_GRAPH
+    if autotune:
+        opts.flags |= FLAG_AUTOTUNE
     keep = []
     if forced is not None:
         f = torch.as_tensor(forced, dtype=torch.int32).to(dev).contiguous()
@@ -198,3 +228,128 @@ def residualize(X, active, exo: int):
                                   _ptr(ws), ws.numel(), _stream_ptr(torch, X.device))
     _check(code)
     return X
+
+
+def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
+                  profile: bool = False):
+    """VarLiNGAM on a CUDA float32 series ``X`` (T x d, time in rows).
+
+    Returns a dict: ``M`` (lags x d x d float64), ``resid`` ((T-lags) x d
+    float32), ``order`` (int32), ``B0`` (d x d float64), plus ``measures`` /
+    ``gaps`` / ``profile`` when asked.
+    """
+    import torch
+
+    lib = load()
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
+        raise TypeError("X must be a CUDA float32 tensor")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D with unit column stride")
+    T, d = X.shape
+    dev = X.device
+    opts = _Opts()
+    lib.lingam_opts_init(ctypes.byref(opts))
+    keep = []
+    if forced is not None:
+        f = torch.as_tensor(forced, dtype=torch.int32).to(dev).contiguous()
+        keep.append(f)
+        opts.forced_order = f.data_ptr()
+        opts.forced_len = f.numel()
+    out = {
+        "M": torch.empty((lags, d, d), dtype=torch.float64, device=dev),
+        "resid": torch.empty((T - lags, d), dtype=torch.float32, device=dev),
+        "order": torch.empty(d, dtype=torch.int32, device=dev),
+        "B0": torch.empty((d, d), dtype=torch.float64, device=dev),
+    }
+    if with_measures and d > 1:
+        out["measures"] = torch.empty((d - 1, d), dtype=torch.float64, device=dev)
+        out["gaps"] = torch.empty(d - 1, dtype=torch.float64, device=dev)
+        opts.step_measures = out["measures"].data_ptr()
+        opts.step_gap = out["gaps"].data_ptr()
+    prof = _Profile() if profile else None
+    if prof is not None:
+        opts.profile = ctypes.pointer(prof)
+    need = int(lib.varlingam_workspace_size(T, d, int(lags), ctypes.byref(opts)))
+    if need == 0:
+        raise LingamError(E_INVALID, f"unsupported size T={T} d={d} lags={lags}")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    code = lib.varlingam_fit(_ptr(X), T, d, X.stride(0), int(lags), _ptr(out["M"]),
+                             _ptr(out["resid"]), _ptr(out["order"]), _ptr(out["B0"]),
+                             ctypes.byref(opts), _ptr(ws), ws.numel(), _stream_ptr(torch, dev))
+    _check(code)
+    if prof is not None:
+        out["profile"] = Profile(**{k: getattr(prof, k) for k, _ in _Profile._fields_})
+    return out
+
+
+def batch_causal_order(jobs, *, graph: bool = False, autotune: bool = False,
+                       profile: bool = False, workspace=None, with_measures: bool = False,
+                       raise_on_error: bool = True):
+    """Causal orders of many jobs in one batched run.
+
+    ``jobs``: sequence of dicts with ``X`` (CUDA float32, rows x d; jobs may
+    share one tensor) and optionally ``rows`` (int32 CUDA tensor of row
+    indices, bootstrap resampling) or ``n`` (use the first n rows).  Returns a
+    dict with ``orders`` (list of int32 tensors), ``status`` (int32 tensor per
+    job), ``measures`` (list, when asked) and ``profile``.
+    """
+    import torch
+
+    lib = load()
+    njobs = len(jobs)
+    arr = (_Job * njobs)()
+    orders, meas, keep = [], [], []
+    dev = None
+    for k, j in enumerate(jobs):
+        X = j["X"]
+        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
+            raise TypeError("X must be a CUDA float32 tensor")
+        if X.dim() != 2 or X.stride(1) != 1:
+            raise ValueError("X must be 2-D with unit column stride")
+        dev = X.device
+        rows = j.get("rows")
+        if rows is not None:
+            rows = torch.as_tensor(rows, dtype=torch.int32).to(dev).contiguous()
+            keep.append(rows)
+            n = rows.numel()
+        else:
+            n = int(j.get("n", X.shape[0]))
+        d = X.shape[1]
+        o = torch.empty(d, dtype=torch.int32, device=dev)
+        orders.append(o)
+        a = arr[k]
+        a.X, a.n_rows, a.ldx = X.data_ptr(), X.shape[0], X.stride(0)
+        a.rows = rows.data_ptr() if rows is not None else None
+        a.n, a.d, a.order = n, d, o.data_ptr()
+        if with_measures and d > 1:
+            m = torch.empty((d - 1, d), dtype=torch.float64, device=dev)
+            meas.append(m)
+            a.step_measures = m.data_ptr()
+        else:
+            meas.append(None)
+    opts = _Opts()
+    lib.lingam_opts_init(ctypes.byref(opts))
+    if graph:
+        opts.flags |= FLAG_GRAPH
+    if autotune:
+        opts.flags |= FLAG_AUTOTUNE
+    prof = _Profile() if profile else None
+    if prof is not None:
+        opts.profile = ctypes.pointer(prof)
+    need = int(lib.lingam_batch_workspace_size(arr, njobs, ctypes.byref(opts)))
+    if need == 0:
+        raise LingamError(E_INVALID, last_error() or "invalid batch")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    status = torch.zeros(njobs, dtype=torch.int32, device=dev)
+    code = lib.lingam_batch_causal_order(arr, njobs, _ptr(status), ctypes.byref(opts),
+                                         _ptr(workspace), workspace.numel(),
+                                         _stream_ptr(torch, dev))
+    if raise_on_error:
+        _check(code)
+    out = {"orders": orders, "status": status, "code": code, "workspace": workspace}
+    if with_measures:
+        out["measures"] = meas
+    if prof is not None:
+        out["profile"] = Profile(**{k: getattr(prof, k) for k, _ in _Profile._fields_})
+    return out

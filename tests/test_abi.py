@@ -126,3 +126,22 @@ def test_product_path_has_no_oracle_dependency():
     assert "oracle" not in src.replace("# ", "")
     out = subprocess.run(["ldd", pkg.LIB_PATH], capture_output=True, text=True).stdout
     assert "oracle" not in out
+
+
+def test_batch_argument_errors():
+    lib = pkg.load()
+    J = (L._Job * 2)()
+    for k in range(2):
+        J[k].X, J[k].n_rows, J[k].ldx, J[k].n, J[k].d, J[k].order = 1, 100, 5, 100, 5, 1
+    assert lib.lingam_batch_workspace_size(J, 0, None) == 0
+    J[1].n = 200                      # more samples than rows, no row map
+    assert lib.lingam_batch_workspace_size(J, 2, None) == 0
+    assert lib.lingam_batch_causal_order(J, 2, None, None, ctypes.c_void_p(1), 1 << 30, None) \
+        == L.E_INVALID
+    assert "job 1" in pkg.last_error()
+    J[1].n = 100
+    o = _opts()
+    o.forced_len = 1
+    o.forced_order = 1
+    assert lib.lingam_batch_causal_order(J, 2, None, ctypes.byref(o), ctypes.c_void_p(1),
+                                         1 << 30, None) == L.E_INVALID

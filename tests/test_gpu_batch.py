@@ -1,0 +1,119 @@
+"""Batched orderings (many jobs in one run) through the C ABI.
+
+Every job of a batch must give what a single-job call gives on the same data
+(orders identical, measures equal up to the rounding of a different split of
+the sample sums), bootstrap row gathers must equal ordering the gathered
+matrix, graph replays must repeat the eager result, and a failing job must
+not disturb the others.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_03772_amd import synth
+from gpu_helpers import check_step, measure_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _uneven_jobs(seed=0, count=7):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for k in range(count):
+        d = int(rng.integers(3, 150))
+        n = int(rng.integers(100, 1500))
+        s = synth.er_sem(d, n, indeg=2.0, noise_family=("uniform", "laplace", "exp"),
+                         seed=100 + k)
+        jobs.append(s.X)
+    return jobs
+
+
+def test_batch_equals_single_jobs(lib):
+    Xs = _uneven_jobs()
+    out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], with_measures=True)
+    assert int(out["status"].abs().sum()) == 0
+    for k, X in enumerate(Xs):
+        single = lib.causal_order(_t(X), with_measures=True)
+        assert np.array_equal(out["orders"][k].cpu().numpy(), single["order"].cpu().numpy()), k
+        if X.shape[1] > 1:
+            mb = out["measures"][k].cpu().numpy()
+            ms = single["measures"].cpu().numpy()
+            fin = np.isfinite(ms)
+            assert np.array_equal(fin, np.isfinite(mb))
+            assert np.all(np.abs(mb[fin] - ms[fin]) <= 1e-9 * np.maximum(np.abs(ms[fin]), 1e-9))
+
+
+def test_batch_jobs_match_oracle(lib):
+    Xs = _uneven_jobs(seed=1, count=4)
+    out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], with_measures=True)
+    for k, X in enumerate(Xs):
+        order = out["orders"][k].cpu().numpy()
+        d = X.shape[1]
+        if d < 2:
+            continue
+        _, mr, _ = oracle.causal_order(X, forced=order, mode="table", with_measures=True)
+        mg = out["measures"][k].cpu().numpy()
+        for t in range(d - 1):
+            bad, ok = check_step(mg[t], mr[t], order[t])
+            assert bad == 0 and ok, (k, t)
+
+
+def test_bootstrap_rows(lib):
+    import torch
+    base = synth.er_sem(40, 2000, indeg=2.0, noise_family="laplace", seed=5).X
+    Xb = _t(base)
+    idx = [synth.bootstrap_indices(2000, n, seed=s) for s, n in ((1, 700), (2, 1500), (3, 2000))]
+    out = lib.batch_causal_order([{"X": Xb, "rows": torch.as_tensor(i).cuda()} for i in idx],
+                                 with_measures=True)
+    for k, i in enumerate(idx):
+        ref = lib.causal_order(_t(base[i]), with_measures=True)
+        assert np.array_equal(out["orders"][k].cpu().numpy(), ref["order"].cpu().numpy())
+        mr = ref["measures"].cpu().numpy()
+        mb = out["measures"][k].cpu().numpy()
+        fin = np.isfinite(mr)
+        assert np.all(np.abs(mb[fin] - mr[fin]) <= 1e-9 * np.maximum(np.abs(mr[fin]), 1e-9))
+
+
+def test_graph_replay_matches_eager(lib):
+    Xs = _uneven_jobs(seed=2, count=5)
+    jobs = [{"X": _t(X)} for X in Xs]
+    eager = lib.batch_causal_order(jobs)
+    ws = eager["workspace"]
+    for rep in range(3):
+        g = lib.batch_causal_order(jobs, graph=True, workspace=ws)
+        for k in range(len(Xs)):
+            assert np.array_equal(g["orders"][k].cpu().numpy(),
+                                  eager["orders"][k].cpu().numpy()), (rep, k)
+        # eager work and a sync between replays
+        lib.causal_order(_t(Xs[0]))
+
+
+def test_single_graph_and_autotune(lib):
+    s = synth.er_sem(200, 3000, indeg=3.0, noise_family=("uniform", "exp"), seed=9)
+    X = _t(s.X)
+    ref = lib.causal_order(X).cpu().numpy()
+    for _ in range(2):
+        assert np.array_equal(lib.causal_order(X, graph=True).cpu().numpy(), ref)
+    tuned = lib.causal_order(X, autotune=True).cpu().numpy()
+    assert np.array_equal(tuned, ref)
+
+
+def test_failing_job_is_isolated(lib):
+    import torch
+    good = synth.er_sem(12, 500, seed=3).X
+    bad = good.copy()
+    bad[:, 4] = 2.0                                   # constant column
+    rows_bad = torch.as_tensor(np.array([0, 1, 5000, 3], dtype=np.int32)).cuda()
+    out = lib.batch_causal_order([{"X": _t(good)}, {"X": _t(bad)},
+                                  {"X": _t(good), "rows": rows_bad}],
+                                 raise_on_error=False)
+    st = out["status"].cpu().numpy()
+    assert st[0] == 0 and st[1] == -2 and st[2] == -1
+    assert out["code"] == -2
+    ref = lib.causal_order(_t(good)).cpu().numpy()
+    assert np.array_equal(out["orders"][0].cpu().numpy(), ref)
