@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -41,6 +43,28 @@ PEAK_EVALS = N_CU * CLOCK_HZ / (VALU_PER_EVAL / 128.0 + TRANS_PER_EVAL / 32.0)
 
 def evals_per_ordering(n: int, d: int) -> float:
     return float(n) * (d ** 3 - d) / 3.0
+
+
+def measured_traffic(d: int, n: int):
+    """HBM bytes per k_pair launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel), or None when the
+    summary is for another shape or the kernel sources changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_pair_d{d}_n{n}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2403_03772_amd", "csrc")
+    h = hashlib.sha256(open(os.path.join(src, "lingam_kernels.hip"), "rb").read()
+                       + open(os.path.join(src, "lingam_internal.h"), "rb").read()).hexdigest()
+    if fields.get("kernel_sources_sha256") != h or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(X32, n: int, d: int, target_s: float = 15.0) -> dict:
@@ -66,6 +90,38 @@ def cpu_baseline(X32, n: int, d: int, target_s: float = 15.0) -> dict:
                       f"workload (literal Algorithm 1, FP64, {dt:.1f} s)"}
 
 
+def bench_batch(steps: int, warmup: int, seed: int) -> dict:
+    """Batched orderings: 256 bootstrap resamples of one d = 200 base sample
+    (n ~ U[500, 5000] rows each, gathered on the device) plus 64 independent
+    SEMs with d ~ U[50, 400], n ~ U[500, 5000], all in one graph-captured run."""
+    import torch
+
+    import paper_2403_03772_amd as lg
+    from paper_2403_03772_amd import synth
+
+    wl = synth.workload_bootstrap_batch(seed=seed)
+    base = torch.as_tensor(np.ascontiguousarray(wl.base.X, dtype=np.float32), device="cuda:0")
+    jobs = [{"X": base, "rows": torch.as_tensor(r, device="cuda:0")} for r in wl.rows]
+    jobs += [{"X": torch.as_tensor(np.ascontiguousarray(s.X, dtype=np.float32),
+                                   device="cuda:0")} for s in wl.sems]
+    evals = sum(evals_per_ordering(r.size, wl.base.X.shape[1]) for r in wl.rows)
+    evals += sum(evals_per_ordering(*s.X.shape) for s in wl.sems)
+    ws = None
+    for _ in range(max(warmup, 1)):  # the first graph call captures
+        ws = lg.batch_causal_order(jobs, graph=True, workspace=ws)["workspace"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = lg.batch_causal_order(jobs, graph=True, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    assert int(out["status"].abs().sum()) == 0
+    return {"workload": "256 bootstrap resamples (d=200, n~U[500,5000]) + 64 SEMs "
+                        "(d~U[50,400], n~U[500,5000]), one graph-captured batch",
+            "jobs": len(jobs), "evals": evals, "ms": dt * 1e3, "value": evals / dt,
+            "unit": "sample-pair evals/s", "workspace_bytes": int(ws.numel())}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,8 +131,10 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched bootstrap workload")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the run, copy 256 MiB device-to-device with a plain copy "
+                    help="after the run, copy 1 GiB device-to-device with a plain copy "
                          "kernel (reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -150,7 +208,8 @@ def main() -> int:
             "peak": PEAK_EVALS / 1e9,
             "unit": "Geval/s",
             "frac": achieved / PEAK_EVALS,
-            "traffic": None,
+            "traffic": measured_traffic(d, n),
+            "traffic_unit": "HBM bytes per launch",
             "avg_launch_ms": pair_ms / max(pair_launches, 1),
             "launches": pair_launches,
             "share_of_step": pair_ms / (dt * 1e3),
@@ -163,8 +222,10 @@ def main() -> int:
                   "peak": 8000.0, "unit": "GB/s"},
         "learned": None,
     }
+    if not args.no_batch:
+        rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed)
     if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        src = torch.ones(256 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)

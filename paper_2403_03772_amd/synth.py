@@ -181,3 +181,33 @@ def workload_gene_scale(seed: int = 0, d: int = 1024, n: int = 8192,
     per-variable noise family from {uniform, Laplace, exponential - 1}."""
     return er_sem(d, n, indeg=4.0, wlo=0.5, whi=2.0,
                   noise_family=("uniform", "laplace", "exp"), seed=seed, rescale=rescale)
+
+
+@dataclass
+class BootstrapBatch:
+    base: SEM                 # the shared base sample (n_base x d_base)
+    rows: list                # int32 row-index arrays, one per bootstrap resample
+    sems: list                # independent SEMs of uneven size
+
+
+def workload_bootstrap_batch(seed: int = 0, n_resamples: int = 256, d_base: int = 200,
+                             n_base: int = 5000, n_sems: int = 64, n_lo: int = 500,
+                             n_hi: int = 5000, d_lo: int = 50, d_hi: int = 400
+                             ) -> BootstrapBatch:
+    """Many independent orderings in one batch: bootstrap resamples of one base
+    sample (d_base variables, n_base rows; each resample draws n ~ U[n_lo, n_hi]
+    rows with replacement) plus independent SEMs with d ~ U[d_lo, d_hi] and
+    n ~ U[n_lo, n_hi].  All SEMs use the gene-expression-scale family."""
+    rng = np.random.default_rng(seed)
+    fam = ("uniform", "laplace", "exp")
+    base = er_sem(d_base, n_base, indeg=4.0, wlo=0.5, whi=2.0, noise_family=fam,
+                  seed=int(rng.integers(1 << 31)))
+    rows = [bootstrap_indices(n_base, int(rng.integers(n_lo, n_hi + 1)),
+                              seed=int(rng.integers(1 << 31))) for _ in range(n_resamples)]
+    sems = []
+    for _ in range(n_sems):
+        d = int(rng.integers(d_lo, d_hi + 1))
+        n = int(rng.integers(n_lo, n_hi + 1))
+        sems.append(er_sem(d, n, indeg=4.0, wlo=0.5, whi=2.0, noise_family=fam,
+                           seed=int(rng.integers(1 << 31))))
+    return BootstrapBatch(base=base, rows=rows, sems=sems)
