@@ -19,12 +19,17 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
   Algorithm 1, in literal or memoised ("table") mode, with optional teacher
   forcing.
 * :func:`step_measures_rows` -- k_list entries of chosen rows at one step.
+* :func:`pair_matrix` -- the whole measure matrix between active columns.
 * :func:`residualize` -- least-squares removal of one variable's effect.
 * :func:`var_fit` -- least-squares VAR fit with intercept (Section 3.3, the
   first stage of VarLiNGAM).
 * :func:`ols_adjacency` -- least-squares regression of every variable on its
   order predecessors (the instantaneous matrix B0 of VarLiNGAM).
 * :func:`varlingam` -- the three stages of VarLiNGAM together.
+
+The learned-proposal form of the search (features, the scoring network with
+its gradients and optimiser, the certified / margin / audit decisions) is in
+:mod:`oracle.proposer`.
 """
 from __future__ import annotations
 
@@ -77,6 +82,8 @@ def _load():
         lib.lo_entropy_moments.restype = None
         lib.lo_entropy_constants.argtypes = [P, P, P, P]
         lib.lo_entropy_constants.restype = None
+        lib.lo_pair_matrix.argtypes = [P, i64, P, i32, P]
+        lib.lo_pair_matrix.restype = ctypes.c_int
         lib.lo_pair_measure.argtypes = [P, P, i64, P]
         lib.lo_pair_measure.restype = ctypes.c_int
         lib.lo_causal_order.argtypes = [P, i64, i64, i64, P, i32, i32, P, P, P]
@@ -140,6 +147,17 @@ def pair_measure(xi, xj) -> float:
     _check(_load().lo_pair_measure(_ptr(xi), _ptr(xj), xi.size, ctypes.byref(out)),
            "pair_measure")
     return out.value
+
+
+def pair_matrix(X, active) -> np.ndarray:
+    """D[p, q] = diff(active[p], active[q]) (Algorithm 1's measure, R1) between
+    the columns ``active`` of the FP64 matrix X (n x d); D[p, p] = 0."""
+    Xc = np.ascontiguousarray(np.asarray(X, dtype=np.float64).T)
+    n = Xc.shape[1]
+    U = np.ascontiguousarray(active, dtype=np.int32)
+    D = np.empty((U.size, U.size), dtype=np.float64)
+    _check(_load().lo_pair_matrix(_ptr(Xc), n, _ptr(U), U.size, _ptr(D)), "pair_matrix")
+    return D
 
 
 def causal_order(X, forced=None, mode: str = "literal", with_measures: bool = False):

@@ -242,19 +242,17 @@ static int lo_step_literal(const double* Xc, int64_t n, const int32_t* U, int32_
   return status;
 }
 
-/* Table mode: the same numbers, memoised.  Each column is standardized once,
- * each marginal entropy and each ordered residual entropy is computed once,
- * and diff(j, i) is taken as -diff(i, j) (which the formula of R1 gives
- * exactly).  `want` is ignored (all rows are computed). */
-static int lo_step_table(const double* Xc, int64_t n, const int32_t* U, int32_t m,
-                         double* k_list) {
+/* The matrix of the likelihood-ratio measure between the active columns:
+ * D[p * m + q] = diff(U[p], U[q]) of R1, D[p * m + p] = 0.  Each column is
+ * standardized once, each marginal entropy and each ordered residual entropy
+ * is computed once, and diff(j, i) is taken as -diff(i, j) (which the formula
+ * of R1 gives exactly).  Xc is column-major (column v at Xc + v * n). */
+int lo_pair_matrix(const double* Xc, int64_t n, const int32_t* U, int32_t m, double* D) {
   double* Z = (double*)malloc(sizeof(double) * (size_t)m * (size_t)n);
   double* Hm = (double*)malloc(sizeof(double) * (size_t)m);
-  double* D = (double*)malloc(sizeof(double) * (size_t)m * (size_t)m);
-  if (!Z || !Hm || !D) {
+  if (!Z || !Hm) {
     free(Z);
     free(Hm);
-    free(D);
     return LO_NOMEM;
   }
   int status = LO_OK;
@@ -281,6 +279,7 @@ static int lo_step_table(const double* Xc, int64_t n, const int32_t* U, int32_t 
       }
       double *ri_j = buf, *rj_i = buf + n, *tmp = buf + 2 * n;
       const double* zi = Z + (int64_t)p * n;
+      D[(int64_t)p * m + p] = 0.0;
       for (int32_t q = p + 1; q < m; ++q) {
         const double* zj = Z + (int64_t)q * n;
         double h1 = 0.0, h2 = 0.0;
@@ -301,20 +300,31 @@ static int lo_step_table(const double* Xc, int64_t n, const int32_t* U, int32_t 
     }
     free(buf);
   }
-  if (status) goto done;
-  for (int32_t p = 0; p < m; ++p) {
-    double k = 0.0;
-    for (int32_t q = 0; q < m; ++q) {
-      if (q == p) continue;
-      const double v = D[(int64_t)p * m + q];
-      const double neg = v < 0.0 ? v : 0.0;
-      k += neg * neg;
-    }
-    k_list[p] = -k;
-  }
 done:
   free(Z);
   free(Hm);
+  return status;
+}
+
+/* Table mode: k_list from the memoised measure matrix.  `want` is ignored
+ * (all rows are computed). */
+static int lo_step_table(const double* Xc, int64_t n, const int32_t* U, int32_t m,
+                         double* k_list) {
+  double* D = (double*)malloc(sizeof(double) * (size_t)m * (size_t)m);
+  if (!D) return LO_NOMEM;
+  const int status = lo_pair_matrix(Xc, n, U, m, D);
+  if (!status) {
+    for (int32_t p = 0; p < m; ++p) {
+      double k = 0.0;
+      for (int32_t q = 0; q < m; ++q) {
+        if (q == p) continue;
+        const double v = D[(int64_t)p * m + q];
+        const double neg = v < 0.0 ? v : 0.0;
+        k += neg * neg;
+      }
+      k_list[p] = -k;
+    }
+  }
   free(D);
   return status;
 }

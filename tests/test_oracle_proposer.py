@@ -1,0 +1,208 @@
+"""Pins of the proposer oracle (CPU): every part is checked against something
+other than itself -- a library routine, a closed form, finite differences, or
+the plain search it must reduce to."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from oracle import proposer as P
+from paper_2403_03772_amd import synth
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=5000) * 10.0 ** rng.integers(-8, 8, 5000),
+                        # exact halfway cases between two BF16 values (ties to even)
+                        np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -1.0 - 2.0 ** -8])])
+    ref = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(P.bf16(x), ref)
+
+
+def _grid(dist, n=200001):
+    q = (np.arange(n) + 0.5) / n
+    return dist.ppf(q)
+
+
+@pytest.mark.parametrize("name,dist,e_lc,H,e3,ex4,eabs", [
+    ("gauss", stats.norm(), 0.3745672075, 1.4189385326, 0.0, 0.0, np.sqrt(2 / np.pi)),
+    ("uniform", stats.uniform(-np.sqrt(3), 2 * np.sqrt(3)), 0.4013378931, 1.3622997688, 0.0,
+     -1.2, np.sqrt(3) / 2),
+    ("laplace", stats.laplace(scale=1 / np.sqrt(2)), 0.3382367723, 1.3145883171, 0.0, 3.0,
+     1 / np.sqrt(2)),
+    ("exp", stats.expon(loc=-1.0), 0.3301432991, 1.0879312472, 2.0, 6.0, 2 / np.e),
+])
+def test_moment_features_closed_forms(name, dist, e_lc, H, e3, ex4, eabs):
+    """Features 1-7 of one column drawn on a quantile grid equal the
+    distribution's moments (closed forms; the grid error is far below the
+    tolerances, which allow for the truncated tails of the 4th moment)."""
+    x = _grid(dist)
+    F = P.features(x[:, None], [0], t=0, d=1)[0]
+    assert abs(F[0] - e_lc) < 2e-5
+    assert abs(F[2] - H) < 1e-4
+    assert abs(F[3] - e3) < 2e-3 * max(1.0, abs(e3))
+    assert abs(F[4] - ex4) < 5e-3 * max(1.0, abs(ex4))
+    assert abs(F[5] - eabs) < 3e-5
+    assert abs(F[6] - F[3] ** 2) < 1e-15
+    assert F[12] == 0.0 and F[13] == 1.0 and abs(F[14] - np.log(x.size)) < 1e-12
+
+
+def test_correlation_features_brute_force():
+    """Features 3, 8-12 and 16 against np.corrcoef, the C oracle's entropy and
+    scipy's ordinal ranks."""
+    s = synth.er_sem(7, 300, indeg=2.0, noise_family=("uniform", "laplace", "exp"), seed=4)
+    X = s.X.astype(np.float64)
+    U = [0, 2, 3, 5, 6]
+    F = P.features(X, U, t=2, d=7)
+    rho = np.corrcoef(X[:, U].T)
+    H = np.array([oracle.entropy((X[:, v] - X[:, v].mean()) / X[:, v].std()) for v in U])
+    m = len(U)
+    ranks = stats.rankdata(H, method="ordinal") - 1
+    for p in range(m):
+        r = np.delete(rho[p], p)
+        Ho = np.delete(H, p)
+        assert abs(F[p, 2] - H[p]) < 1e-12
+        assert abs(F[p, 7] - np.abs(r).max()) < 1e-12
+        assert abs(F[p, 8] - (r ** 2).sum() / m) < 1e-12
+        assert abs(F[p, 9] - np.abs(r).mean()) < 1e-12
+        assert F[p, 10] == np.mean(np.abs(r) > 0.5)
+        assert F[p, 11] == ranks[p] / m
+        assert abs(F[p, 15] - (r ** 2 * Ho).sum() / (r ** 2).sum()) < 1e-12
+        assert F[p, 12] == 2 / 7 and F[p, 13] == m / 7
+
+
+def _lists(rng, sizes):
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    tg = np.array([offs[L] + rng.integers(sizes[L]) for L in range(len(sizes))])
+    return offs, tg
+
+
+def test_gradient_central_differences():
+    rng = np.random.default_rng(1)
+    flat = P.init_params(3) + rng.normal(scale=0.01, size=P.N_PARAMS)
+    offs, tg = _lists(rng, [9, 15, 6])
+    Xn = rng.normal(size=(offs[-1], P.N_FEAT))
+
+    def loss(f):
+        s, _ = P.forward(f, Xn)
+        return P.listwise_ce(s, offs, tg)[0]
+
+    s, cache = P.forward(flat, Xn)
+    _, ds = P.listwise_ce(s, offs, tg)
+    g = P.backward(flat, cache, ds)
+    idx = np.concatenate([rng.choice(P.N_PARAMS, 300, replace=False),
+                          [P.N_PARAMS - 1, 2048, 18560, 18700]])  # every block
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(P.N_PARAMS)
+        e[i] = h
+        fd = (loss(flat + e) - loss(flat - e)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])), (i, fd, g[i])
+
+
+def test_listwise_ce_closed_forms():
+    rng = np.random.default_rng(2)
+    sizes = [5, 8, 3]
+    offs, tg = _lists(rng, sizes)
+    loss, ds = P.listwise_ce(np.zeros(offs[-1]), offs, tg)
+    assert abs(loss - np.mean(np.log(sizes))) < 1e-15
+    for L, m in enumerate(sizes):
+        seg = ds[offs[L]:offs[L + 1]]
+        assert abs(seg.sum()) < 1e-15
+        assert abs(ds[tg[L]] - (1 / m - 1) / 3) < 1e-15
+    # a dominant target score gives a loss near 0
+    s = np.zeros(offs[-1])
+    s[tg] = 50.0
+    assert P.listwise_ce(s, offs, tg)[0] < 1e-20
+
+
+def test_adam_first_step_and_convergence():
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=50)
+    g = rng.normal(size=50)
+    opt = P.Adam(lr=0.01)
+    x1 = opt.step(x, g)
+    # bias-corrected first step: -lr * g / (|g| + eps)
+    assert np.allclose(x1 - x, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    # minimises a convex quadratic
+    c = rng.normal(size=50)
+    opt = P.Adam(lr=0.05)
+    y = np.zeros(50)
+    for _ in range(3000):
+        y = opt.step(y, 2 * (y - c))
+    assert np.max(np.abs(y - c)) < 5e-3  # from O(1) at the start
+
+
+def test_topk_brute_force():
+    rng = np.random.default_rng(4)
+    s = rng.integers(0, 20, 200).astype(np.float64)  # many ties
+    slots = rng.permutation(200)
+    C = P.topk(s, slots, 37)
+    ref = sorted(range(200), key=lambda p: (-s[p], slots[p]))[:37]
+    assert list(C) == ref
+
+
+def test_certificate_is_sound():
+    """LB_l <= k_l for every excluded l, and a certified best candidate is the
+    plain choice (checked on the full measure matrix at several steps)."""
+    s = synth.er_sem(14, 1500, indeg=2.0, noise_family=("uniform", "laplace", "exp"), seed=7)
+    X = s.X.astype(np.float64)
+    rng = np.random.default_rng(5)
+    U = list(range(14))
+    checked = 0
+    for step in range(6):
+        D = oracle.pair_matrix(X, U)
+        k = np.sum(np.minimum(D, 0) ** 2, axis=1)
+        for trial in range(20):
+            C = rng.choice(len(U), 4, replace=False)
+            excl = np.setdiff1d(np.arange(len(U)), C)
+            lb = np.sum(np.maximum(D[C], 0) ** 2, axis=0)
+            assert np.all(lb[excl] <= k[excl] + 1e-15)
+            best = C[np.argmin(k[C])]
+            if np.all(lb[excl] > k[best]):
+                assert best == int(np.argmin(k))
+                checked += 1
+        e = U[int(np.argmin(k))]
+        X = oracle.residualize(X, U, e)
+        U.remove(e)
+    assert checked > 0
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_learned_order_reduces_to_plain(seed):
+    """With every uncertified step deferred (delta = +inf), or with an audit at
+    every step, the learned form must give exactly the plain order."""
+    s = synth.er_sem(12, 1000, indeg=2.0, noise_family=("uniform", "laplace", "exp"),
+                     seed=20 + seed)
+    plain = oracle.causal_order(s.X, mode="table")
+    prop = np.concatenate([np.zeros(16), np.ones(16), P.init_params(seed)])
+    o1, info1 = P.learned_order(s.X, prop, K=3, delta=np.inf, audit_every=0, min_m=3)
+    assert np.array_equal(o1, plain)
+    kinds = {i.kind for i in info1}
+    assert "learned" in kinds or "fallback" in kinds
+    o2, info2 = P.learned_order(s.X, prop, K=3, delta=-np.inf, audit_every=1, min_m=3)
+    assert np.array_equal(o2, plain)
+    o3, info3 = P.learned_order(s.X, prop, K=3, delta=-np.inf, audit_every=0, min_m=3)
+    assert sorted(o3) == list(range(12))
+    assert all(i.kind in ("learned", "plain") for i in info3)
+    # every certified learned step agrees with the plain choice of that step
+    assert all(i.learned_choice == i.plain_choice for i in info3 if i.certified)
+
+
+def test_kendall_tau_matches_scipy():
+    rng = np.random.default_rng(6)
+    n = 300
+    a = rng.permutation(n)
+    assert P.kendall_tau(a, a) == 1.0
+    assert P.kendall_tau(a, a[::-1]) == -1.0
+    for _ in range(5):
+        b = a.copy()
+        sw = rng.choice(n - 1, 30)
+        for i in sw:
+            b[i], b[i + 1] = b[i + 1], b[i]
+        pa = np.empty(n)
+        pb = np.empty(n)
+        pa[a] = np.arange(n)
+        pb[b] = np.arange(n)
+        assert abs(P.kendall_tau(a, b) - stats.kendalltau(pa, pb)[0]) < 1e-12
