@@ -15,7 +15,13 @@ the full-ordering time (ms_per_step), the roofline of the pair-moment kernel
 (timed with HIP events on the launch stream over the timed region) and the
 FP64 oracle timed on a bounded sample on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Also reported (when the trained network is present): the learned-proposal
+form on the same input -- time per ordering, speed-up over the plain form,
+Kendall tau to the plain order, its decisions, and the same form with an
+untrained network (ablation) -- and a batched bootstrap workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gene|large]
+                       [--no-cpu-baseline] [--no-batch] [--no-learned]
 """
 from __future__ import annotations
 
@@ -69,7 +75,6 @@ def measured_traffic(d: int, n: int):
 
 def cpu_baseline(X32, n: int, d: int, target_s: float = 15.0) -> dict:
     """Time the FP64 oracle (literal Algorithm 1) on k_list rows of step 0."""
-    import numpy as np
     import oracle
 
     threads = oracle.num_threads()
@@ -122,17 +127,105 @@ def bench_batch(steps: int, warmup: int, seed: int) -> dict:
             "unit": "sample-pair evals/s", "workspace_bytes": int(ws.numel())}
 
 
+def kendall_tau(a, b) -> float:
+    """Kendall rank correlation of two orders of the same items."""
+    from scipy import stats
+
+    pa = np.empty(len(a))
+    pb = np.empty(len(b))
+    pa[np.asarray(a)] = np.arange(len(a))
+    pb[np.asarray(b)] = np.arange(len(b))
+    return float(stats.kendalltau(pa, pb)[0])
+
+
+def run_learned(lg, X, n, d, steps, warmup, proposer, plain_order, plain_ms):
+    """The learned-proposal form on the same input: time per ordering, speed-up
+    over the plain form, Kendall tau to the plain order, decisions, the work
+    actually performed and the candidate-row kernel against the roofline."""
+    import torch
+
+    cfg = lg.Learned(proposer)
+    ws = torch.empty(lg.workspace_size(n, d, cfg), dtype=torch.uint8, device="cuda:0")
+    for _ in range(warmup):
+        lg.causal_order(X, learned=cfg, workspace=ws)
+    torch.cuda.synchronize()
+    cand_ms = cand_evals = pair_ms = pair_evals = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = lg.causal_order(X, learned=cfg, workspace=ws, profile=True)
+        p = out["profile"]
+        cand_ms += p.cand_ms
+        cand_evals += p.cand_evals
+        pair_ms += p.pair_ms
+        pair_evals += p.pair_evals
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    order = out["order"].cpu().numpy()
+    st = out["learned_stats"]
+    small = sum(m * (m - 1) * float(n) for m in range(2, min(64, d) + 1))
+    done = (cand_evals + pair_evals) / steps + small
+    return {
+        "ms_per_ordering": dt * 1e3,
+        "speedup_vs_plain": plain_ms / (dt * 1e3),
+        "kendall_tau": kendall_tau(order, plain_order),
+        "orders_identical": bool(np.array_equal(order, plain_order)),
+        "topk": cfg.topk, "audit_every": cfg.audit_every, "margin": cfg.margin,
+        "stats": {"learned_steps": st.learned_steps, "certified": st.certified,
+                  "fallbacks": st.fallbacks, "audits": st.audits,
+                  "audit_agree": st.audit_agree},
+        "evals_done": done,
+        "evals_done_per_s": done / dt,
+        "cand_kernel": {"bound": "alu", "kernel": "k_pair_cand",
+                        "achieved": cand_evals / (cand_ms * 1e-3) / 1e9 if cand_ms else None,
+                        "peak": PEAK_EVALS / 1e9, "unit": "Geval/s",
+                        "frac": cand_evals / (cand_ms * 1e-3) / PEAK_EVALS if cand_ms else None,
+                        "ms_per_ordering": cand_ms / steps},
+        "full_pair_ms_per_ordering": pair_ms / steps,
+    }
+
+
+def run_plain(lg, X, n, d, steps, warmup):
+    import torch
+
+    ws = torch.empty(lg.workspace_size(n, d), dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        lg.causal_order(X, workspace=ws)
+    torch.cuda.synchronize()
+    acc = dict(pair_ms=0.0, pair_evals=0.0, pair_launches=0, gram_ms=0.0, gram_flops=0.0,
+               resid_ms=0.0, resid_bytes=0.0)
+    orders = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = lg.causal_order(X, workspace=ws, profile=True)
+        p = out["profile"]
+        for k in acc:
+            acc[k] += getattr(p, k)
+        orders.append(out["order"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    o0 = orders[0].cpu().numpy()
+    for o in orders[1:]:
+        assert np.array_equal(o.cpu().numpy(), o0), "orderings differ between steps"
+    acc["dt"] = dt
+    acc["order"] = o0
+    return acc
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--d", type=int, default=1024)
-    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--workload", choices=("gene", "large"), default="gene",
+                    help="gene: d=1024, n=8192 (default); large: d=4096, n=16384 "
+                         "(learned vs plain at scale; one plain ordering takes ~2 min)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched bootstrap workload")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device-to-device with a plain copy "
                          "kernel (reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -142,51 +235,25 @@ def main() -> int:
               f"got --gpus {args.gpus}", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2403_03772_amd as lg
     from paper_2403_03772_amd import synth
+    from paper_2403_03772_amd import train_proposer as tp
 
-    d, n = args.d, args.n
+    d, n = (1024, 8192) if args.workload == "gene" else (4096, 16384)
     sem = synth.workload_gene_scale(seed=args.seed, d=d, n=n)
     X32 = np.ascontiguousarray(sem.X, dtype=np.float32)
     X = torch.as_tensor(X32, device="cuda:0")
-    ws = torch.empty(lg.workspace_size(n, d), dtype=torch.uint8, device="cuda:0")
-    torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        lg.causal_order(X, workspace=ws)
-    torch.cuda.synchronize()
-
-    pair_ms = pair_evals = 0.0
-    pair_launches = 0
-    gram_ms = gram_flops = resid_ms = resid_bytes = 0.0
-    orders = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = lg.causal_order(X, workspace=ws, profile=True)
-        p = out["profile"]
-        pair_ms += p.pair_ms
-        pair_launches += p.pair_launches
-        pair_evals += p.pair_evals
-        gram_ms += p.gram_ms
-        gram_flops += p.gram_flops
-        resid_ms += p.resid_ms
-        resid_bytes += p.resid_bytes
-        orders.append(out["order"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
-    o0 = orders[0].cpu().numpy()
-    for o in orders[1:]:
-        assert np.array_equal(o.cpu().numpy(), o0), "orderings differ between steps"
+    pl = run_plain(lg, X, n, d, args.steps, args.warmup)
+    dt = pl["dt"]
     ms_per_step = dt * 1e3 / args.steps
     evals = evals_per_ordering(n, d)
     value = evals * args.steps / dt
-    achieved = pair_evals / (pair_ms * 1e-3)
+    achieved = pl["pair_evals"] / (pl["pair_ms"] * 1e-3)
     rec = {
-        "metric": "sample-pair evals/s (plain DirectLiNGAM ordering, d=1024, n=8192)",
+        "metric": f"sample-pair evals/s (plain DirectLiNGAM ordering, d={d}, n={n})",
         "value": value,
         "unit": "sample-pair evals/s",
         "n_gpus": 1,
@@ -210,19 +277,37 @@ def main() -> int:
             "frac": achieved / PEAK_EVALS,
             "traffic": measured_traffic(d, n),
             "traffic_unit": "HBM bytes per launch",
-            "avg_launch_ms": pair_ms / max(pair_launches, 1),
-            "launches": pair_launches,
-            "share_of_step": pair_ms / (dt * 1e3),
+            "avg_launch_ms": pl["pair_ms"] / max(pl["pair_launches"], 1),
+            "launches": pl["pair_launches"],
+            "share_of_step": pl["pair_ms"] / (dt * 1e3),
         },
-        "gram": {"bound": "mfma", "ms": gram_ms / args.steps,
-                 "achieved": gram_flops / (gram_ms * 1e-3) / 1e12 if gram_ms else None,
+        "gram": {"bound": "mfma", "ms": pl["gram_ms"] / args.steps,
+                 "achieved": pl["gram_flops"] / (pl["gram_ms"] * 1e-3) / 1e12
+                 if pl["gram_ms"] else None,
                  "peak": 78.6, "unit": "TFLOP/s (fp64)"},
-        "resid": {"bound": "hbm", "ms": resid_ms / args.steps,
-                  "achieved": resid_bytes / (resid_ms * 1e-3) / 1e9 if resid_ms else None,
+        "resid": {"bound": "hbm", "ms": pl["resid_ms"] / args.steps,
+                  "achieved": pl["resid_bytes"] / (pl["resid_ms"] * 1e-3) / 1e9
+                  if pl["resid_ms"] else None,
                   "peak": 8000.0, "unit": "GB/s"},
         "learned": None,
     }
-    if not args.no_batch:
+    if not args.no_learned:
+        if os.path.exists(tp.WEIGHTS):
+            prop = tp.default_proposer()
+            _, meta = tp.load_weights()
+            lw = max(1, args.warmup)
+            rec["learned"] = run_learned(lg, X, n, d, args.steps, lw, prop, pl["order"],
+                                         ms_per_step)
+            rec["learned"]["proposer"] = {k: meta.get(k) for k in
+                                          ("sems", "d", "n", "lists", "holdout")}
+            # ablation: the same form with an untrained (random) network
+            raw = prop.clone()
+            raw[32:] = torch.as_tensor(tp.init_weights(1), device=raw.device)
+            rec["learned"]["untrained"] = run_learned(lg, X, n, d, 1, 0, raw, pl["order"],
+                                                      ms_per_step)
+        else:
+            rec["learned"] = {"error": f"no trained proposer at {tp.WEIGHTS}"}
+    if not args.no_batch and args.workload == "gene":
         rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed)
     if args.copy_calibration:
         src = torch.ones(256 << 20, dtype=torch.float32, device="cuda:0")
@@ -231,7 +316,7 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = src.numel() * 4
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "gene":
         rec["cpu_baseline"] = cpu_baseline(X32, n, d)
     print(json.dumps(rec), flush=True)
     return 0

@@ -24,6 +24,18 @@
  *     copied to opts->dev_status when that pointer is given.
  *   - lingam_last_error() returns a thread-local message for the last
  *     non-OK status of the calling thread.
+ *
+ * Learned-proposal form (opts->proposer non-NULL): at every step with more
+ * than learned_min_m active variables a small network (16 features ->
+ * 128 -> 128 -> 1, ReLU, BF16 weights, FP32 accumulation) scores the active
+ * variables, the exact measure k_i is computed only for the `topk` best
+ * scored, and the best of those is taken when (a) it is certified -- every
+ * other variable l already has sum over candidates c of max(0, R(c, l))^2 >
+ * k_best, a lower bound of k_l, so the full search would pick it too -- or
+ * (b) its score leads every non-candidate's by at least `margin`.  Otherwise,
+ * and at every audit step (t % audit_every == 0), the full step of the exact
+ * search decides.  This proposal layer is not part of the paper's method; it
+ * is an addition on top of the exact search it accelerates.
  */
 #ifndef LINGAM_MI355X_H
 #define LINGAM_MI355X_H
@@ -57,14 +69,37 @@ typedef enum {
 /* Per-call profile, filled when opts->profile is non-NULL (forces a sync). */
 typedef struct lingam_profile {
   double total_ms;        /* enqueue-to-completion of the whole call, HIP events */
-  double pair_ms;         /* summed duration of the pair-moment kernel launches */
-  int64_t pair_launches;  /* number of pair-moment kernel launches */
-  double pair_evals;      /* sample-pair evaluations done by those launches */
+  double pair_ms;         /* summed duration of the all-pairs moment kernel launches */
+  int64_t pair_launches;  /* number of those launches */
+  double pair_evals;      /* sample-pair evaluations they performed (steps whose full
+                             search ran): m (m - 1) n per step */
   double gram_ms;         /* duration of the Gram (correlation) kernel */
   double gram_flops;      /* algorithmic flops of that Gram: 2 * n * d * d */
   double resid_ms;        /* summed duration of the residualize kernels */
   double resid_bytes;     /* algorithmic HBM bytes of those: 28 * n * (m - 1) per step */
+  double cand_ms;         /* learned form: summed duration of the candidate-row kernel */
+  int64_t cand_launches;  /* ... its launches */
+  double cand_evals;      /* ... its sample-pair evaluations: 2 K (m - 1) n per step */
 } lingam_profile;
+
+/* Decisions of the learned form, summed over the jobs of a call (host). */
+typedef struct lingam_learned_stats {
+  int32_t learned_steps;  /* steps with a learned pass */
+  int32_t certified;      /* ... whose best candidate was certified */
+  int32_t fallbacks;      /* ... decided by the full step because the margin was small */
+  int32_t audits;         /* ... decided by the full step as audits */
+  int32_t audit_agree;    /* audits whose full choice equalled the learned choice */
+  int32_t reserved;
+} lingam_learned_stats;
+
+/* The proposer network.  A proposer block is LINGAM_PROPOSER_SIZE FP32 values
+ * (device): feature mean[16], feature scale[16] (inputs are (f - mean) /
+ * scale), then LINGAM_PROPOSER_PARAMS trainable values W1[128][16], b1[128],
+ * W2[128][128], b2[128], w3[128], b3. */
+#define LINGAM_PROPOSER_FEATURES 16
+#define LINGAM_PROPOSER_HIDDEN 128
+#define LINGAM_PROPOSER_PARAMS 18817
+#define LINGAM_PROPOSER_SIZE (32 + LINGAM_PROPOSER_PARAMS)
 
 typedef struct lingam_opts {
   uint32_t struct_size;         /* sizeof(lingam_opts): ABI version check */
@@ -80,9 +115,23 @@ typedef struct lingam_opts {
   double* step_gap;             /* device double[d-1] or NULL: best minus runner-up measure */
   int32_t* dev_status;          /* device int32 or NULL: receives the device-side status */
   lingam_profile* profile;      /* HOST pointer or NULL: per-kernel timings (forces sync) */
+  /* learned-proposal form (see the top of this file) */
+  const float* proposer;        /* device FP32[LINGAM_PROPOSER_SIZE] or NULL: plain search */
+  int32_t topk;                 /* candidates per learned step: multiple of 8 in [8, 256];
+                                   default 64 */
+  int32_t audit_every;          /* full-step audit when t % audit_every == 0; 0 = never;
+                                   default 32 */
+  float margin;                 /* score lead that accepts an uncertified candidate; +inf
+                                   accepts certified candidates only; default 4 */
+  int32_t learned_min_m;        /* steps with m <= learned_min_m are plain; >= topk and
+                                   >= 64; default 2 * topk */
+  lingam_learned_stats* learned_stats; /* HOST pointer or NULL: filled when the call syncs */
+  float* record_features;       /* device FP32[(d-1) * d * 16] or NULL: the 16 features of
+                                   every active variable at every step, by step and original
+                                   column id (training data); unwritten entries untouched */
 } lingam_opts;
 
-/* Fill *opts with defaults (no forcing, no extra outputs, synchronous). */
+/* Fill *opts with defaults (no forcing, no extra outputs, plain search, synchronous). */
 void lingam_opts_init(lingam_opts* opts);
 
 /*
@@ -128,6 +177,7 @@ typedef struct lingam_job {
   int32_t* order;
   double* step_measures;
   double* step_gap;
+  float* record_features;  /* as in lingam_opts, per job, or NULL */
 } lingam_job;
 
 /* Workspace bytes for lingam_batch_causal_order (0 if a job is invalid). */
@@ -141,8 +191,9 @@ size_t lingam_batch_workspace_size(const lingam_job* jobs, int32_t n_jobs,
  * together (Section 2.2 search per job, unchanged).
  *   jobs        HOST array of n_jobs descriptors (device pointers inside).
  *   job_status  device int32[n_jobs] or NULL: per-job device status.
- *   opts        flags only (LINGAM_FLAG_GRAPH, _AUTOTUNE, _NO_SYNC, profile);
- *               forcing and opts-level per-step outputs are rejected.
+ *   opts        flags (LINGAM_FLAG_GRAPH, _AUTOTUNE, _NO_SYNC), profile and the
+ *               learned-form fields (shared by all jobs); forcing and
+ *               opts-level per-step outputs are rejected.
  * Returns the first failing job's status, or LINGAM_OK.  A degenerate job
  * does not stop the others.
  */
@@ -193,6 +244,47 @@ size_t varlingam_workspace_size(int64_t T, int64_t d, int32_t lags, const lingam
 int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lags, double* M,
                   float* resid, int32_t* order, double* B0, const lingam_opts* opts, void* ws,
                   size_t ws_bytes, void* stream);
+
+/*
+ * Proposer network (the learned-proposal form; its kernels are the ones the
+ * ordering runs).  Features are FP32 [rows x 16] row-major, as recorded by
+ * opts->record_features.
+ */
+
+/* Workspace bytes for lingam_proposer_scores. */
+size_t lingam_proposer_scores_workspace_size(void);
+
+/* scores[r] = network(features[r]) for r < rows (FP32 out, device). */
+int lingam_proposer_scores(const float* proposer, const float* features, int64_t rows,
+                           float* scores, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for lingam_proposer_grad (0 if rows < 1 or n_lists < 1). */
+size_t lingam_proposer_grad_workspace_size(int64_t rows, int32_t n_lists);
+
+/*
+ * Listwise softmax cross-entropy of the network over n_lists lists and its
+ * gradient.  List L is rows offsets[L] .. offsets[L+1]-1 (device int64,
+ * non-decreasing from 0 to rows); its target is row targets[L] (device
+ * int64, inside the list).  loss = mean over lists of
+ * logsumexp(s_L) - s_target.
+ *   grad    device FP32[LINGAM_PROPOSER_PARAMS]: d loss / d (trainable values),
+ *           at the BF16-rounded weights the forward pass uses.
+ *   loss    device FP32[1] or NULL.
+ *   scores  device FP32[rows] or NULL: the forward scores.
+ * Synchronizes; a malformed offsets / targets array returns LINGAM_E_INVALID.
+ */
+int lingam_proposer_grad(const float* proposer, const float* features, int64_t rows,
+                         const int64_t* offsets, const int64_t* targets, int32_t n_lists,
+                         float* grad, float* loss, float* scores, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/*
+ * One Adam step (bias-corrected; Kingma and Ba) on the trainable values of
+ * `proposer` (the normalisation stays): m1, m2 device FP32[PARAMS] moment
+ * buffers (zero before step 1), step >= 1.
+ */
+int lingam_proposer_adam(float* proposer, const float* grad, float* m1, float* m2, int32_t step,
+                         float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Thread-local text of the last error of the calling thread ("" if none). */
 const char* lingam_last_error(void);

@@ -17,17 +17,26 @@ Functions mirror the C entry points:
 * :func:`batch_causal_order` -- ``lingam_batch_causal_order`` (many
   independent orderings, e.g. bootstrap resamples, in one batched run).
 * :func:`workspace_size`, :func:`residualize_workspace_size`.
+* learned-proposal form: ``learned=Learned(proposer, ...)`` on the ordering
+  calls; :func:`proposer_scores`, :func:`proposer_grad`, :func:`proposer_adam`
+  (the network's kernels: ``lingam_proposer_*``).
 """
 from __future__ import annotations
 
 from .lib import (  # noqa: F401
     LIB_PATH,
+    PROPOSER_SIZE,
+    Learned,
+    LearnedStats,
     LingamError,
     Profile,
     batch_causal_order,
     causal_order,
     last_error,
     load,
+    proposer_adam,
+    proposer_grad,
+    proposer_scores,
     residualize,
     residualize_workspace_size,
     varlingam_fit,

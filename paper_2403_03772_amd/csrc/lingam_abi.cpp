@@ -8,6 +8,7 @@
 // step's chosen variable lives only on the device.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -133,9 +134,9 @@ struct Timer {
 
 struct Prof {
   Timer tm;
-  std::vector<int> pair_ev, resid_ev;
+  std::vector<int> pair_ev, resid_ev, cand_ev;
   int all0 = -1, all1 = -1, g0 = -1, g1 = -1;
-  double pair_evals = 0.0, resid_bytes = 0.0, gram_flops = 0.0;
+  double pair_evals = 0.0, resid_bytes = 0.0, gram_flops = 0.0, cand_evals = 0.0;
 };
 
 // --------------------------------------------------------------------------
@@ -151,30 +152,55 @@ struct HostJob {
   double* gaps;
   const int32_t* forced;
   int32_t forced_len;
+  float* record = nullptr;  // optional feature record
 };
+
+// Learned-form configuration of a call (proposer == NULL: plain search).
+struct Learn {
+  const float* proposer = nullptr;
+  int32_t K = 0, min_m = 0, audit_every = 0;
+  float delta = 0.f;
+};
+
+Learn learn_of(const lingam_opts* o) {
+  Learn l;
+  if (!o || !o->proposer) return l;
+  l.proposer = o->proposer;
+  l.K = o->topk;
+  l.min_m = o->learned_min_m;
+  l.audit_every = o->audit_every;
+  l.delta = o->margin;
+  return l;
+}
 
 struct Plan {
   int njobs = 0;
   int cu = 0;
-  size_t table_off = 0, sched_off = 0, total = 0;
+  size_t table_off = 0, sched_off = 0, prop_off = 0, total = 0;
   std::vector<lg::Layout> L;
   std::vector<size_t> job_off;
   int max_d = 0;
+  Learn lc;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Plan make_plan(const std::vector<HostJob>& jobs, int cu) {
+Plan make_plan(const std::vector<HostJob>& jobs, int cu, const Learn& lc = Learn{}) {
   Plan P;
   P.njobs = (int)jobs.size();
   P.cu = cu;
+  P.lc = lc;
   size_t off = 0;
   P.table_off = off;
   off = align256(off + sizeof(lg::JobDev) * (size_t)P.njobs);
   P.sched_off = off;
   off = align256(off + lg::sched_bytes(P.njobs));
+  if (lc.proposer) {
+    P.prop_off = off;
+    off = align256(off + sizeof(lg::PropDev));
+  }
   for (const HostJob& j : jobs) {
-    P.L.push_back(lg::make_layout(j.n, j.d, cu));
+    P.L.push_back(lg::make_layout(j.n, j.d, cu, lc.proposer ? lc.K : 0));
     P.job_off.push_back(off);
     off = align256(off + P.L.back().total);
     P.max_d = std::max(P.max_d, (int)j.d);
@@ -215,6 +241,24 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
     J.part = reinterpret_cast<double*>(b + L.part);
     J.rmat = reinterpret_cast<double*>(b + L.rmat);
     J.mvec = reinterpret_cast<double*>(b + L.mvec);
+    J.mom = reinterpret_cast<double*>(b + L.mom);
+    J.record = h.record;
+    if (P.lc.proposer) {
+      J.prop = reinterpret_cast<const lg::PropDev*>(ws + P.prop_off);
+      J.K = P.lc.K;
+      J.min_m = P.lc.min_m;
+      J.audit_every = P.lc.audit_every;
+      J.delta = P.lc.delta;
+      J.feat = reinterpret_cast<float*>(b + L.feat);
+      J.score = reinterpret_cast<float*>(b + L.score);
+      J.cand = reinterpret_cast<int32_t*>(b + L.cand);
+      J.cmark = reinterpret_cast<int32_t*>(b + L.cmark);
+      J.partc = reinterpret_cast<double*>(b + L.partc);
+      J.rc = reinterpret_cast<double*>(b + L.rc);
+      J.kc = reinterpret_cast<double*>(b + L.kc);
+      J.lb = reinterpret_cast<double*>(b + L.lb);
+      J.steplog = reinterpret_cast<int32_t*>(b + L.steplog);
+    }
   }
   return out;
 }
@@ -222,22 +266,27 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
 // Host replay of the device schedule: the grid totals of every kernel kind.
 struct StepTotals {
   int32_t g[lg::kNumKinds] = {0};
-  double pair_evals = 0.0, resid_bytes = 0.0;
+  double pair_evals = 0.0, resid_bytes = 0.0, cand_evals = 0.0;
 };
 
 StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, lg::Tune tu) {
   StepTotals T;
   std::vector<lg::JobStep> js(P.njobs);
-  int64_t items = 0;
+  const int K = P.lc.proposer ? P.lc.K : 0;
+  int64_t items = 0, items_c = 0;
   for (int k = 0; k < P.njobs; ++k) {
-    js[k] = lg::job_step_base((int32_t)jobs[k].d, t);
+    js[k] = lg::job_step_base((int32_t)jobs[k].d, t, K, P.lc.min_m, jobs[k].record != nullptr);
     if (js[k].m >= 2 && !js[k].fp64) items += 2LL * js[k].ntiles;
+    if (js[k].learned) items_c += 2LL * js[k].nct;
   }
   for (int k = 0; k < P.njobs; ++k) {
     lg::job_split(js[k], (int32_t)P.L[k].n_pad, items, P.cu, tu);
-    for (int kind = 0; kind < lg::kNumKinds; ++kind) T.g[kind] += lg::kind_count(js[k], kind);
+    lg::job_split_cand(js[k], (int32_t)P.L[k].n_pad, items_c, P.cu, tu);
+    for (int kind = 0; kind < lg::kNumKinds; ++kind)
+      T.g[kind] += lg::kind_count(js[k], kind, K);
     const int m = js[k].m;
     if (m >= 2 && !js[k].fp64) T.pair_evals += (double)m * (m - 1) * (double)jobs[k].n;
+    if (js[k].learned) T.cand_evals += 2.0 * K * (double)(m - 1) * (double)jobs[k].n;
     if (m > 2) T.resid_bytes += 28.0 * (double)jobs[k].n * (double)(m - 1);
   }
   return T;
@@ -262,6 +311,11 @@ int enqueue_setup(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, hi
                                std::min(lg::kJobsPerLaunch, P.njobs - k), st),
            "set jobs");
   LG_TRY(lg::launch_init(table, P.njobs, st), "init");
+  if (P.lc.proposer)
+    LG_TRY(lg::launch_prop_prep(P.lc.proposer,
+                                reinterpret_cast<lg::PropDev*>(ws + P.prop_off), table,
+                                P.njobs, st),
+           "proposer prep");
   LG_TRY(lg::launch_setup_schedule(table, P.njobs, sc, st), "setup schedule");
   LG_TRY(lg::launch_ingest(table, P.njobs, sc, setup_total(P, lg::kSIngest), st), "ingest");
   const int cols = setup_total(P, lg::kSCols);
@@ -286,6 +340,18 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     const StepTotals T = step_totals(jobs, P, t, tu);
     if (T.g[lg::kKSel] == 0) break;  // every job finished
     LG_TRY(lg::launch_step_schedule(table, P.njobs, t, P.cu, tu, sc, st), "step schedule");
+    if (T.g[lg::kKFeat] > 0 || T.g[lg::kKMlp] > 0)
+      LG_TRY(lg::launch_learned_front(table, P.njobs, t, sc, T.g, st), "features / scores");
+    if (T.g[lg::kKPairC] > 0) {
+      if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
+      LG_TRY(lg::launch_pair_cand(table, P.njobs, sc, T.g[lg::kKPairC], st), "pair cand");
+      if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
+      if (pf) pf->cand_evals += T.cand_evals;
+    }
+    if (T.g[lg::kKLsel] > 0) {
+      LG_TRY(lg::launch_learned_back(table, P.njobs, t, sc, T.g, st), "learned decision");
+      LG_TRY(lg::launch_gate_schedule(table, P.njobs, sc, st), "gate schedule");
+    }
     if (T.g[lg::kKPair] > 0) {
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
       LG_TRY(lg::launch_pair(table, P.njobs, sc, T.g[lg::kKPair], st), "pair");
@@ -426,11 +492,35 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
   if (pf.tm.on) pf.all1 = pf.tm.take(st);
   const bool sync = !(opts->flags & LINGAM_FLAG_NO_SYNC) || pf.tm.on;
   if (!sync) return LINGAM_OK;
-  std::vector<int32_t> st_host(P.njobs, 0);
+  std::vector<lg::Ctrl> ctrl(P.njobs);
   for (int k = 0; k < P.njobs; ++k)
-    LG_TRY(hipMemcpyAsync(&st_host[k], dj[k].ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
-           "hipMemcpyAsync(status)");
+    LG_TRY(hipMemcpyAsync(&ctrl[k], dj[k].ctrl, sizeof(lg::Ctrl), hipMemcpyDeviceToHost, st),
+           "hipMemcpyAsync(control)");
+  // learned steps whose full search was gated off (for the profile's counts)
+  std::vector<std::vector<int32_t>> logs;
+  if (P.lc.proposer && pf.tm.on && opts->profile) {
+    logs.resize(P.njobs);
+    for (int k = 0; k < P.njobs; ++k) {
+      logs[k].resize((size_t)P.L[k].d);
+      LG_TRY(hipMemcpyAsync(logs[k].data(), dj[k].steplog, sizeof(int32_t) * logs[k].size(),
+                            hipMemcpyDeviceToHost, st),
+             "hipMemcpyAsync(step log)");
+    }
+  }
   LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  std::vector<int32_t> st_host(P.njobs, 0);
+  for (int k = 0; k < P.njobs; ++k) st_host[k] = ctrl[k].status;
+  if (P.lc.proposer && opts->learned_stats) {
+    lingam_learned_stats* ls = opts->learned_stats;
+    memset(ls, 0, sizeof(*ls));
+    for (const lg::Ctrl& c : ctrl) {
+      ls->learned_steps += c.n_learned;
+      ls->certified += c.n_certified;
+      ls->fallbacks += c.n_fallback;
+      ls->audits += c.n_audit;
+      ls->audit_agree += c.n_audit_agree;
+    }
+  }
   if (pf.tm.on && opts->profile) {
     lingam_profile* pr = opts->profile;
     memset(pr, 0, sizeof(*pr));
@@ -444,6 +534,19 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
     for (size_t k = 0; k + 1 < pf.resid_ev.size(); k += 2)
       pr->resid_ms += pf.tm.ms(pf.resid_ev[k], pf.resid_ev[k + 1]);
     pr->resid_bytes = pf.resid_bytes;
+    for (size_t k = 0; k + 1 < pf.cand_ev.size(); k += 2)
+      pr->cand_ms += pf.tm.ms(pf.cand_ev[k], pf.cand_ev[k + 1]);
+    pr->cand_launches = (int64_t)(pf.cand_ev.size() / 2);
+    pr->cand_evals = pf.cand_evals;
+    // steps a learned decision took did not run the all-pairs kernel
+    for (int k = 0; k < (int)logs.size(); ++k) {
+      const int64_t d = P.L[k].d, n = P.L[k].n;
+      for (int64_t t = 0; t + 1 < d; ++t) {
+        const int64_t m = d - t;
+        if (logs[k][(size_t)t] == 1 && m > lg::kFp64MaxM)
+          pr->pair_evals -= (double)m * (double)(m - 1) * (double)n;
+      }
+    }
   }
   for (int k = 0; k < P.njobs; ++k)
     if (st_host[k] != 0) return status_from_device(st_host[k]);
@@ -543,10 +646,26 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
   return finish(P, dj, ws, opts, job_status, st, pf);
 }
 
+int check_learn(const lingam_opts* opts) {
+  if (!opts->proposer) return LINGAM_OK;
+  if (opts->topk < 8 || opts->topk > lg::kMaxTopK || opts->topk % 8 != 0)
+    return fail(LINGAM_E_INVALID, "topk %d must be a multiple of 8 in [8, %d]", opts->topk,
+                lg::kMaxTopK);
+  if (opts->audit_every < 0)
+    return fail(LINGAM_E_INVALID, "audit_every %d < 0", opts->audit_every);
+  if (opts->learned_min_m < opts->topk || opts->learned_min_m < lg::kFp64MaxM)
+    return fail(LINGAM_E_INVALID, "learned_min_m %d must be >= topk and >= %d",
+                opts->learned_min_m, lg::kFp64MaxM);
+  if (opts->margin != opts->margin) return fail(LINGAM_E_INVALID, "margin is NaN");
+  return LINGAM_OK;
+}
+
 int check_opts(const lingam_opts* opts, int64_t d) {
   if (opts->struct_size != sizeof(lingam_opts))
     return fail(LINGAM_E_INVALID, "opts->struct_size %u != %zu", opts->struct_size,
                 sizeof(lingam_opts));
+  const int rc = check_learn(opts);
+  if (rc != LINGAM_OK) return rc;
   if (opts->forced_len < 0 || opts->forced_len > d)
     return fail(LINGAM_E_INVALID, "forced_len %d outside [0, d]", opts->forced_len);
   if (opts->forced_len > 0 && !opts->forced_order)
@@ -584,6 +703,10 @@ void lingam_opts_init(lingam_opts* o) {
   if (!o) return;
   memset(o, 0, sizeof(*o));
   o->struct_size = sizeof(lingam_opts);
+  o->topk = 64;
+  o->audit_every = 32;
+  o->margin = 4.0f;
+  o->learned_min_m = 128;
 }
 
 const char* lingam_last_error(void) { return g_err; }
@@ -591,14 +714,15 @@ const char* lingam_last_error(void) { return g_err; }
 const char* lingam_version(void) { return "lingam-mi355x 0.2 (gfx950)"; }
 
 size_t lingam_workspace_size(int64_t n, int64_t d, const lingam_opts* opts) {
-  (void)opts;
   if (n < 2 || d < 1 || n > kMaxN || d > kMaxD) return 0;
+  if (opts && (opts->struct_size != sizeof(lingam_opts) || check_learn(opts) != LINGAM_OK))
+    return 0;
   int cu = 0;
   if (num_cu_of_current(&cu) != LINGAM_OK) cu = 256;
   HostJob j{};
   j.n = n;
   j.d = d;
-  return make_plan({j}, cu).total;
+  return make_plan({j}, cu, learn_of(opts)).total;
 }
 
 int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
@@ -624,9 +748,9 @@ int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32
   rc = num_cu_of_current(&cu);
   if (rc != LINGAM_OK) return rc;
   const HostJob j{X,     nullptr, n, ldx, n, d, order, opts->step_measures, opts->step_gap,
-                  opts->forced_order, opts->forced_len};
+                  opts->forced_order, opts->forced_len, opts->record_features};
   const std::vector<HostJob> jobs{j};
-  const Plan P = make_plan(jobs, cu);
+  const Plan P = make_plan(jobs, cu, learn_of(opts));
   if (!ws || ws_bytes < P.total)
     return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", P.total,
                 ws ? ws_bytes : (size_t)0);
@@ -640,8 +764,8 @@ static int batch_jobs(const lingam_job* jobs, int32_t n_jobs, std::vector<HostJo
   out->clear();
   for (int k = 0; k < n_jobs; ++k) {
     const lingam_job& s = jobs[k];
-    const HostJob h{s.X,     s.rows, s.n_rows, s.ldx, s.n, s.d, s.order, s.step_measures,
-                    s.step_gap, nullptr, 0};
+    const HostJob h{s.X,        s.rows, s.n_rows, s.ldx, s.n, s.d, s.order, s.step_measures,
+                    s.step_gap, nullptr, 0,      s.record_features};
     const int rc = check_job(h, k);
     if (rc != LINGAM_OK) return rc;
     out->push_back(h);
@@ -651,12 +775,13 @@ static int batch_jobs(const lingam_job* jobs, int32_t n_jobs, std::vector<HostJo
 
 size_t lingam_batch_workspace_size(const lingam_job* jobs, int32_t n_jobs,
                                    const lingam_opts* opts) {
-  (void)opts;
+  if (opts && (opts->struct_size != sizeof(lingam_opts) || check_learn(opts) != LINGAM_OK))
+    return 0;
   std::vector<HostJob> hj;
   if (batch_jobs(jobs, n_jobs, &hj) != LINGAM_OK) return 0;
   int cu = 0;
   if (num_cu_of_current(&cu) != LINGAM_OK) cu = 256;
-  return make_plan(hj, cu).total;
+  return make_plan(hj, cu, learn_of(opts)).total;
 }
 
 int lingam_batch_causal_order(const lingam_job* jobs, int32_t n_jobs, int32_t* job_status,
@@ -673,13 +798,15 @@ int lingam_batch_causal_order(const lingam_job* jobs, int32_t n_jobs, int32_t* j
     return fail(LINGAM_E_INVALID,
                 "batched calls take per-step outputs in lingam_job, status in job_status, and "
                 "no forcing");
+  int rc = check_learn(opts);
+  if (rc != LINGAM_OK) return rc;
   std::vector<HostJob> hj;
-  int rc = batch_jobs(jobs, n_jobs, &hj);
+  rc = batch_jobs(jobs, n_jobs, &hj);
   if (rc != LINGAM_OK) return rc;
   int cu = 0;
   rc = num_cu_of_current(&cu);
   if (rc != LINGAM_OK) return rc;
-  const Plan P = make_plan(hj, cu);
+  const Plan P = make_plan(hj, cu, learn_of(opts));
   if (!ws || ws_bytes < P.total)
     return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", P.total,
                 ws ? ws_bytes : (size_t)0);
@@ -688,15 +815,16 @@ int lingam_batch_causal_order(const lingam_job* jobs, int32_t n_jobs, int32_t* j
 }
 
 size_t varlingam_workspace_size(int64_t T, int64_t d, int32_t lags, const lingam_opts* opts) {
-  (void)opts;
   if (d < 1 || lags < 1 || d > kMaxD || T > kMaxN) return 0;
+  if (opts && (opts->struct_size != sizeof(lingam_opts) || check_learn(opts) != LINGAM_OK))
+    return 0;
   if (T - lags < 1 + (int64_t)lags * d + 1) return 0;
   int cu = 0;
   if (num_cu_of_current(&cu) != LINGAM_OK) cu = 256;
   HostJob j{};
   j.n = T - lags;
   j.d = d;
-  const Plan P = make_plan({j}, cu);
+  const Plan P = make_plan({j}, cu, learn_of(opts));
   return align256(P.total) + lg::make_var_layout(T, d, lags, cu).total;
 }
 
@@ -729,10 +857,11 @@ int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lag
   rc = num_cu_of_current(&cu);
   if (rc != LINGAM_OK) return rc;
   // the VAR residuals are the job's data rows: no X for the ingest kernel
-  const HostJob j{nullptr, nullptr, T - lags, d, T - lags, d, order, opts->step_measures,
-                  opts->step_gap, opts->forced_order, opts->forced_len};
+  const HostJob j{nullptr,         nullptr,      T - lags, d, T - lags, d, order,
+                  opts->step_measures, opts->step_gap, opts->forced_order, opts->forced_len,
+                  opts->record_features};
   const std::vector<HostJob> jobs{j};
-  const Plan P = make_plan(jobs, cu);
+  const Plan P = make_plan(jobs, cu, learn_of(opts));
   const lg::VarLayout V = lg::make_var_layout(T, d, lags, cu);
   const size_t var_off = align256(P.total);
   if (!ws || ws_bytes < var_off + V.total)
@@ -784,6 +913,78 @@ int lingam_residualize(float* X, int64_t n, int64_t d, int64_t ldx, const int32_
   LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
   if (s == LINGAM_E_INVALID) return fail(LINGAM_E_INVALID, "an id in `active` is outside [0, d)");
   if (s != 0) return fail(LINGAM_E_DEGENERATE, "var(x_exo) == 0");
+  return LINGAM_OK;
+}
+
+size_t lingam_proposer_scores_workspace_size(void) {
+  return (sizeof(lg::PropDev) + 255) & ~size_t(255);
+}
+
+int lingam_proposer_scores(const float* proposer, const float* features, int64_t rows,
+                           float* scores, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!proposer || !features || !scores)
+    return fail(LINGAM_E_INVALID, "proposer, features and scores must be non-NULL");
+  if (rows < 1 || rows > kMaxN)
+    return fail(LINGAM_E_INVALID, "rows %lld outside [1, %lld]", (long long)rows,
+                (long long)kMaxN);
+  const size_t need = lingam_proposer_scores_workspace_size();
+  if (!ws || ws_bytes < need)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", need,
+                ws ? ws_bytes : (size_t)0);
+  LG_TRY(lg::launch_scores(proposer, features, rows, scores, (char*)ws, (hipStream_t)stream),
+         "proposer scores");
+  return LINGAM_OK;
+}
+
+size_t lingam_proposer_grad_workspace_size(int64_t rows, int32_t n_lists) {
+  if (rows < 1 || n_lists < 1 || rows > kMaxN) return 0;
+  return lg::make_train_layout(rows, n_lists).total;
+}
+
+int lingam_proposer_grad(const float* proposer, const float* features, int64_t rows,
+                         const int64_t* offsets, const int64_t* targets, int32_t n_lists,
+                         float* grad, float* loss, float* scores, void* ws, size_t ws_bytes,
+                         void* stream) {
+  g_err[0] = 0;
+  if (!proposer || !features || !offsets || !targets || !grad)
+    return fail(LINGAM_E_INVALID,
+                "proposer, features, offsets, targets and grad must be non-NULL");
+  if (rows < 1 || rows > kMaxN || n_lists < 1)
+    return fail(LINGAM_E_INVALID, "need 1 <= rows <= %lld and n_lists >= 1", (long long)kMaxN);
+  const lg::TrainLayout T = lg::make_train_layout(rows, n_lists);
+  if (!ws || ws_bytes < T.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", T.total,
+                ws ? ws_bytes : (size_t)0);
+  hipStream_t st = (hipStream_t)stream;
+  LG_TRY(lg::launch_grad(T, proposer, features, offsets, targets, grad, loss, scores, (char*)ws,
+                         st),
+         "proposer grad");
+  int32_t status = 0;
+  LG_TRY(hipMemcpyAsync(&status, (char*)ws + T.status, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (status == 1)
+    return fail(LINGAM_E_INVALID, "a list lies outside [0, rows) or a target outside its list");
+  if (status == 2)
+    return fail(LINGAM_E_INVALID, "non-finite proposer value or feature scale <= 0");
+  return LINGAM_OK;
+}
+
+int lingam_proposer_adam(float* proposer, const float* grad, float* m1, float* m2, int32_t step,
+                         float lr, float beta1, float beta2, float eps, void* stream) {
+  g_err[0] = 0;
+  if (!proposer || !grad || !m1 || !m2)
+    return fail(LINGAM_E_INVALID, "proposer, grad, m1 and m2 must be non-NULL");
+  if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(LINGAM_E_INVALID, "need step >= 1, lr > 0, 0 <= beta < 1, eps > 0");
+  const double c1 = 1.0 / (1.0 - pow((double)beta1, (double)step));
+  const double c2 = 1.0 / (1.0 - pow((double)beta2, (double)step));
+  LG_TRY(lg::launch_adam(proposer, grad, m1, m2, lr, beta1, beta2, eps, (float)c1, (float)c2,
+                         (hipStream_t)stream),
+         "proposer adam");
   return LINGAM_OK;
 }
 

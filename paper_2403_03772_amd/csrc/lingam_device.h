@@ -1,0 +1,385 @@
+// Device helpers shared by the gfx950 kernel sources of the library (not
+// installed; each source gets its own copies in an unnamed namespace).
+#pragma once
+
+#include "lingam_internal.h"
+
+#include <math.h>
+
+namespace lg {
+namespace {
+
+// Constants of the maximum-entropy approximation of differential entropy.
+constexpr double kK1 = 79.047;
+constexpr double kK2 = 7.4129;
+constexpr double kGamma = 0.37457;
+constexpr double kHnu = 1.41893853320467274178;  // (1 + ln(2 pi)) / 2
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLog2e = 1.44269504088896340736;
+constexpr double kCollinear = 1e-12;  // |rho| >= 1 - kCollinear is degenerate
+constexpr int kLogBlock = 16;         // samples per lane folded into one log2
+constexpr float kS1Start = 9.0f;      // start value (negated) of each lane's log cosh sum
+
+constexpr int32_t kStInvalid = -1;
+constexpr int32_t kStDegenerate = -2;
+
+template <typename T>
+__host__ __device__ inline T* at(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+__device__ inline void set_status(Ctrl* c, int32_t s) { atomicCAS(&c->status, 0, s); }
+
+__device__ inline double entropy_from_moments(double e_lc, double e_g) {
+  const double a = e_lc - kGamma;
+  return kHnu - kK1 * a * a - kK2 * e_g * e_g;
+}
+
+// One evaluation (one residual direction at one sample).  See the header.
+__device__ __forceinline__ void eval_dir(float x, float y, float r, float c1h, float c1l,
+                                         float& P, float& S1, float& S2) {
+  const float kM2 = (float)(-1.0 / (8.0 * kLog2e));  // rounds with relative error 2.7e-9
+  const float t = fmaf(-r, y, x);
+  const float at = fabsf(t);
+  const float m1 = fmaf(c1h, at, c1l * at);
+  const float e1 = __builtin_amdgcn_exp2f(m1);
+  P = fmaf(P, e1, P);
+  S1 = fmaf(m1, -0.5f, S1);
+  const float m2 = (kM2 * m1) * m1;
+  const float e2 = __builtin_amdgcn_exp2f(m2);
+  S2 = fmaf(t, e2, S2);
+}
+
+// FP64 log cosh and Gaussian-weighted term (marginals and the FP64 pair path).
+__device__ inline double logcosh64(double u) {
+  const double a = fabs(u);
+  return a + log1p(exp(-2.0 * a)) - kLn2;
+}
+__device__ inline double gauss64(double u) { return u * exp(-0.5 * u * u); }
+
+// Pointers read from the job table are generic; the hot loop casts row bases
+// to the global address space so loads use global_load with a scalar base.
+typedef __attribute__((address_space(1))) const char gchar_t;
+typedef __attribute__((address_space(1))) const float gfloat_t;
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Block-wide deterministic FP64 sum (256 threads), result valid in all threads.
+__device__ double block_sum_256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] += sh[tid + off];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Per-sample terms of the five moments kept for every variable:
+// log cosh z, z exp(-z^2/2), z^3, z^4, |z|.
+__device__ inline void add_moments(double z, double (&acc)[5]) {
+  const double z2 = z * z;
+  acc[0] += logcosh64(z);
+  acc[1] += gauss64(z);
+  acc[2] += z2 * z;
+  acc[3] += z2 * z2;
+  acc[4] += fabs(z);
+}
+
+// Block-wide deterministic sum of five FP64 values (256 threads): wave
+// butterflies, then the four wave totals in order.  `sh` holds 20 doubles.
+// The result is valid in thread 0.
+__device__ inline void block_sum_5(double (&v)[5], double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sh[k * 4 + wave] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = ((sh[k * 4] + sh[k * 4 + 1]) + sh[k * 4 + 2]) + sh[k * 4 + 3];
+}
+
+// Means of the five moments of variable `slot` and its marginal entropy.
+__device__ inline void store_moments(const JobDev& J, int slot, const double (&acc)[5], int n) {
+  const double inv = 1.0 / (double)n;
+  double* mo = J.mom + (int64_t)slot * 8;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) mo[k] = acc[k] * inv;
+  J.hm[slot] = entropy_from_moments(acc[0] * inv, acc[1] * inv);
+}
+
+// Row-major upper-triangular tile index -> (bi, bj), bi <= bj < nb.
+__device__ inline void decode_tile(int tile, int nb, int& bi, int& bj) {
+  const double B = 2.0 * nb + 1.0;
+  int r = (int)((B - sqrt(B * B - 8.0 * (double)tile)) * 0.5);
+  r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
+  auto off = [nb](int q) { return q * nb - (q * (q - 1)) / 2; };
+  while (r > 0 && off(r) > tile) --r;
+  while (r + 1 < nb && off(r + 1) <= tile) ++r;
+  bi = r;
+  bj = r + (tile - off(r));
+}
+
+// ---------------------------------------------------------------------------
+// job lookup and schedules
+// ---------------------------------------------------------------------------
+
+// Largest j with pre[j] <= b (pre: exclusive prefix sums, pre[njobs] = total);
+// that job owns workgroup b and has a non-zero count.
+__device__ inline int find_job(const int32_t* __restrict__ pre, int njobs, int b) {
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroup b belongs to job j at local index b - pre[j]; false when b lies
+// beyond the schedule (a grid larger than the device's own totals): the
+// workgroup then has nothing to do.
+__device__ inline bool locate(const int32_t* __restrict__ pre, int njobs, int b, int& j,
+                              int& local) {
+  j = find_job(pre, njobs, b);
+  local = b - pre[j];
+  return local < pre[j + 1] - pre[j];
+}
+
+// out[0..njobs] = exclusive prefix sums of count(j); one block of 1024 threads.
+template <typename F>
+__device__ void block_scan(int njobs, F count, int32_t* out, int32_t* sh) {
+  const int tid = threadIdx.x;
+  const int per = (njobs + 1023) / 1024;
+  const int j0 = tid * per, j1 = min(j0 + per, njobs);
+  int32_t s = 0;
+  for (int j = j0; j < j1; ++j) s += count(j);
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = tid > 0 ? sh[tid - 1] : 0;
+  for (int j = j0; j < j1; ++j) {
+    out[j] = run;
+    run += count(j);
+  }
+  if (tid == 1023) out[njobs] = sh[1023];
+  __syncthreads();
+}
+
+struct Best {
+  double v;   // measure (NaN mapped to -inf)
+  int slot;   // original id
+  int pos;    // position in the active list
+  double v2;  // runner-up measure
+};
+
+__device__ inline bool better(double va, int sa, double vb, int sb) {
+  return va > vb || (va == vb && sa < sb);
+}
+
+__device__ inline Best merge(const Best& a, const Best& b) {
+  Best r;
+  if (better(a.v, a.slot, b.v, b.slot)) {
+    r = a;
+    r.v2 = fmax(a.v2, b.v);
+  } else {
+    r = b;
+    r.v2 = fmax(b.v2, a.v);
+  }
+  return r;
+}
+
+// Pair moments (the hot loop), shared by the all-pairs kernel and the
+// candidate-row kernel of the learned form.  Grid: per job ntiles * 2 * nsplit
+// workgroups of 4 waves (all pairs: upper-triangular 8 x 8 tiles of positions;
+// candidate rows: (K / 8) x nblk tiles whose i side lists candidates).  A
+// workgroup owns an 8 x 8 block of (i, j) variables, one residual direction
+// and one range of samples; wave (wi, wj) owns the 4 x 4 sub-block (i in block
+// bi, j in block bj).  Lanes stride over samples (coalesced 256 B loads per
+// variable row) and every lane keeps 48 running values (16 pairs x {P, S1, S2})
+// for its direction.  The wave ends with an FP64 reduction after which lane
+// L < 32 holds the total of sum L, stored at
+// part[((split * ntiles + tile) * 4 + wave) * 64 + pair * 4 + dir * 2 + which],
+// which 0 = S1 (log cosh, offset as described in the header), 1 = S2;
+// dir 0 = residual of i on j, dir 1 = of j on i.
+template <bool kCand>
+__device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int njobs,
+                                           const JobStep* __restrict__ js,
+                                           const int32_t* __restrict__ pre, int G) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
+  // contiguous range of (job, tile, direction, split) work so that the rows a
+  // tile reads are shared in that XCD's L2.
+  const int b = blockIdx.x;
+  const int Q = G >> 3, R = G & 7, x = b & 7, idx = b >> 3;
+  const int w = x * Q + (x < R ? x : R) + idx;
+  int jb, local;
+  if (!locate(pre, njobs, w, jb, local)) return;
+  const JobDev& J = jobs[jb];
+  const JobStep S = js[jb];
+  const int m = S.m;
+  const int nsplit = kCand ? S.nsplit_c : S.nsplit;
+  const int ntiles = kCand ? S.nct : S.ntiles;
+  const int split_len = kCand ? S.split_len_c : S.split_len;
+  const int per_tile = 2 * nsplit;
+  const int tile = local / per_tile, rem = local - tile * per_tile;
+  const int dir = rem / nsplit, split = rem - dir * nsplit;
+  int bi, bj;
+  if (kCand) {
+    bi = tile / S.nblk;
+    bj = tile - bi * S.nblk;
+  } else {
+    decode_tile(tile, S.nblk, bi, bj);
+  }
+  const int wi = wave >> 1, wj = wave & 1;
+  if (!kCand && bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)
+  // i side: positions bi * 8 + .. (all pairs) or candidate indices (candidate rows)
+  const int i0 = bi * kTileVars + wi * kWaveVars, pj0 = bj * kTileVars + wj * kWaveVars;
+  const int32_t* act = J.act;
+  const int32_t* cand = J.cand;
+  const int64_t ldz = J.ldz, ldr = J.d;
+  auto ipos = [&](int a) { return kCand ? cand[i0 + a] : i0 + a; };
+
+  // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
+  // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
+  // i = pi0 + c.  Lane q < 16 computes the coefficients of walk index q.
+  float my_r = 0.f, my_c1h = 0.f, my_c1l = 0.f;
+  {
+    const int q = lane & 15, a = q >> 2, c = q & 3;
+    const int pi = ipos(dir == 0 ? a : c), pj = pj0 + (dir == 0 ? c : a);
+    const bool valid = kCand ? (pj < m && pi != pj) : (pi < m && pj < m && pi < pj);
+    if (valid) {
+      double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
+      const double lim = 1.0 - kCollinear;
+      r = r > lim ? lim : (r < -lim ? -lim : r);
+      const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
+      my_r = (float)r;
+      my_c1h = (float)c1;
+      my_c1l = (float)(c1 - (double)my_c1h);
+    }
+  }
+  float kr[16], kh[16], kl[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    kr[q] = readlane_f(my_r, q);
+    kh[q] = readlane_f(my_c1h, q);
+    kl[q] = readlane_f(my_c1l, q);
+  }
+  // Row bases (wave-uniform) and a 32-bit per-lane byte offset, so loads use
+  // the scalar-base + vector-offset form.  zr = rows of the regressed
+  // variables (the residual's own variable), zx = rows of the regressors.
+  gchar_t* zr[4];
+  gchar_t* zx[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int pi = ipos(a), pj = pj0 + a;
+    const int pr = dir == 0 ? pi : pj, px = dir == 0 ? pj : pi;
+    // the row ids are wave-uniform: keep them (and the row bases) in SGPRs
+    const int sr = __builtin_amdgcn_readfirstlane(pr < m ? act[pr] : J.d);
+    const int sx = __builtin_amdgcn_readfirstlane(px < m ? act[px] : J.d);
+    zr[a] = (gchar_t*)(J.z + (int64_t)sr * ldz);
+    zx[a] = (gchar_t*)(J.z + (int64_t)sx * ldz);
+  }
+
+  const int s_begin = split * split_len;
+  const int s_end = min(s_begin + split_len, J.n_pad);
+  const int nk = (s_end - s_begin) / 64;
+
+  float P[16], S1[16], S2[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    P[q] = 1.f;
+    S1[q] = -kS1Start;
+    S2[q] = 0.f;
+  }
+  uint32_t voff = (uint32_t)(s_begin + lane) * 4u;
+  float xa[4], xb[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    xa[a] = *(gfloat_t*)(zr[a] + voff);
+    xb[a] = *(gfloat_t*)(zx[a] + voff);
+  }
+  int kb = 0;
+  for (int k = 0; k < nk; ++k) {
+    // prefetch the next sample of every row; on the last iteration the stride
+    // is 0 and the current sample is re-read (always in bounds, no branch)
+    const bool more = k + 1 < nk;
+    voff += more ? 256u : 0u;
+    float na[4], nb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      na[a] = *(gfloat_t*)(zr[a] + voff);
+      nb[a] = *(gfloat_t*)(zx[a] + voff);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = a * 4 + c;
+        eval_dir(xa[a], xb[c], kr[q], kh[q], kl[q], P[q], S1[q], S2[q]);
+      }
+    }
+    if (++kb == kLogBlock || !more) {
+      const float off = 1.5f * (float)kb;  // exact
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        S1[q] += __builtin_amdgcn_logf(P[q]) - off;
+        P[q] = 1.f;
+      }
+      kb = 0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xa[a] = na[a];
+      xb[a] = nb[a];
+    }
+  }
+
+  // FP64 reduction over the 64 lanes: fold the upper half onto the lower, then
+  // a reduce-scatter butterfly over 32 lanes; afterwards lane L < 32 holds sum L.
+  double v[32];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    v[2 * q] = (double)S1[q];
+    v[2 * q + 1] = (double)S2[q];
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 32; ++k2) v[k2] += __shfl_xor(v[k2], 32);
+#pragma unroll
+  for (int half = 16; half >= 1; half >>= 1) {
+    const bool up = (lane & half) != 0;
+#pragma unroll
+    for (int k2 = 0; k2 < half; ++k2) {
+      const double lo = v[k2], hi = v[k2 + half];
+      const double send = up ? lo : hi;
+      const double keep = up ? hi : lo;
+      v[k2] = keep + __shfl_xor(send, half);
+    }
+  }
+  if (lane < 32) {
+    // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
+    const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
+    const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
+    double* part = kCand ? J.partc : J.part;
+    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
+  }
+}
+
+}  // namespace
+}  // namespace lg

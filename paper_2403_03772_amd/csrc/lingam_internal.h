@@ -30,12 +30,48 @@ constexpr int kFp64MaxM = 64;
 constexpr int kMaxTargetPerCu = 32;
 constexpr int kMinMinIters = 4;
 
+// Learned-proposal form: a 16 -> 128 -> 128 -> 1 ReLU network scores every
+// active variable, the exact measure is evaluated for the kTopK best.
+constexpr int kFeat = 16;
+constexpr int kHidden = 128;
+constexpr int kParams = kHidden * kFeat + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
+constexpr int kPropNorm = 2 * kFeat;  // feature mean and scale ahead of the weights
+constexpr int kMaxTopK = 256;
+// offsets of the trainable parameters inside the flat FP32 block
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kHidden * kFeat;
+constexpr int kOffW2 = kOffB1 + kHidden;
+constexpr int kOffB2 = kOffW2 + kHidden * kHidden;
+constexpr int kOffW3 = kOffB2 + kHidden;
+constexpr int kOffB3 = kOffW3 + kHidden;
+
+// Device copy of the network for one run (BF16 weights, FP32 biases).
+struct PropDev {
+  uint16_t w1[kHidden * kFeat];    // W1[h][f]
+  uint16_t w2[kHidden * kHidden];  // W2[h][g]
+  uint16_t w3[kHidden];
+  float b1[kHidden];
+  float b2[kHidden];
+  float mu[kFeat];
+  float sd[kFeat];
+  float b3;
+  float pad[63];
+};
+
 // Device control block (one per job, in the workspace).
 struct Ctrl {
   int32_t status;    // 0 = ok, else a negative lingam_status
   int32_t exo_slot;  // original id chosen at the current step
   int32_t exo_pos;   // its position in the active list before removal
-  int32_t pad[61];
+  int32_t full;      // learned step: 1 = the full step decides
+  int32_t learned_slot;  // learned step: the best candidate's original id
+  int32_t n_learned;     // learned steps taken
+  int32_t n_certified;   // ... of which certified exact
+  int32_t n_fallback;    // full steps taken because the margin was small
+  int32_t n_audit;       // audit steps
+  int32_t n_audit_agree; // audits whose full choice equalled the learned one
+  float s_out;           // best score outside the candidates (this step)
+  int32_t pad[53];
 };
 
 // Byte offsets of one job's workspace regions.
@@ -52,8 +88,21 @@ struct Layout {
   size_t part;   // double [part_elems] pair-kernel partial sums
   size_t rmat;   // double [d * d]  pairwise measure R by position
   size_t mvec;   // double [d]      per-position measure -k
+  size_t mom;    // double [d * 8]  moments of z by original id (E lc, E g, E z^3, E z^4, E|z|)
+  // learned form (K > 0 only)
+  int32_t K;
+  size_t feat;   // float  [d * kFeat] features by position
+  size_t score;  // float  [d]      network score by position
+  size_t cand;   // int32  [kMaxTopK] candidate positions (ascending)
+  size_t cmark;  // int32  [d]      t + 1 at candidate positions of step t
+  size_t partc;  // double [partc_elems] candidate pair-kernel partial sums
+  size_t rc;     // double [K * d]  R(candidate, position)
+  size_t kc;     // double [K]      exact k of every candidate
+  size_t lb;     // double [d]      lower bound of k at excluded positions
+  size_t steplog;  // int32 [d]     per step: 0 plain, 1 learned, 2 fallback, 3 audit
   size_t total;
   size_t part_elems;
+  size_t partc_elems;
 };
 
 // Device job table entry (absolute device addresses).
@@ -78,6 +127,21 @@ struct JobDev {
   double* part;
   double* rmat;
   double* mvec;
+  double* mom;
+  // learned form
+  const PropDev* prop;   // NULL: plain search
+  int32_t K, min_m, audit_every;
+  float delta;
+  float* record;         // optional [(d - 1) * d * kFeat] features by step and original id
+  float* feat;
+  float* score;
+  int32_t* cand;
+  int32_t* cmark;
+  double* partc;
+  double* rc;
+  double* kc;
+  double* lb;
+  int32_t* steplog;
 };
 
 // Split policy of the pair kernel (autotuned): enough workgroups for
@@ -95,6 +159,12 @@ struct JobStep {
   int32_t nsplit;     // sample splits per (tile, direction)
   int32_t split_len;  // samples per split
   int32_t fp64;       // 1: FP64 pair path (m <= kFp64MaxM)
+  int32_t feat;       // 1: features are computed this step
+  int32_t learned;    // 1: learned pass this step (m > min_m)
+  int32_t gate;       // 1: the full step is skipped (set after the learned decision)
+  int32_t nct;        // candidate tiles (K / 8) * nblk
+  int32_t nsplit_c;   // sample splits of the candidate pair kernel
+  int32_t split_len_c;
 };
 
 // Workgroup-count kinds with a prefix array each.
@@ -105,8 +175,20 @@ enum Kind : int {
   kKRowk,       // k_rowk: ceil(m / 4)
   kKSel,        // k_select: 1
   kKRes,        // k_resid: m - 1 when m > 2
+  kKFeat,       // k_features: ceil(m / 4)
+  kKMlp,        // k_mlp: ceil(m / 64)
+  kKTopk,       // k_topk: 1
+  kKPairC,      // k_pair_cand: nct * 2 * nsplit_c
+  kKCombC,      // k_combine_cand: ceil(nct / 4)
+  kKRowkC,      // k_candk rows: K / 4
+  kKColC,       // k_candk columns: ceil(m / 256)
+  kKLsel,       // k_lselect: 1
   kNumKinds
 };
+// the full-step kinds a learned decision can gate off
+__host__ __device__ inline bool gated_kind(int kind) {
+  return kind == kKPair || kind == kKComb || kind == kKP64 || kind == kKRowk || kind == kKSel;
+}
 // Set-up kinds (one schedule before the first step).
 enum SetupKind : int {
   kSIngest = 0,  // (n_pad / 64) * ceil((d + 1) / 64)
@@ -118,7 +200,9 @@ enum SetupKind : int {
 __host__ __device__ inline int32_t cdiv(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
 // The step's plan for a job without the split (needs the batch-wide sum).
-__host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t) {
+// K > 0 and m > min_m: learned pass; rec: features are recorded every step.
+__host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t, int32_t K = 0,
+                                                 int32_t min_m = 0, bool rec = false) {
   JobStep s{};
   const int32_t m = d - t;
   if (m < 2) return s;
@@ -128,6 +212,9 @@ __host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t) {
     s.nblk = cdiv(m, kTileVars);
     s.ntiles = s.nblk * (s.nblk + 1) / 2;
   }
+  s.learned = K > 0 && m > min_m && !s.fp64;
+  s.feat = s.learned || rec;
+  if (s.learned) s.nct = (K / kTileVars) * s.nblk;
   return s;
 }
 
@@ -146,8 +233,20 @@ __host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t ite
   s.nsplit = (int32_t)((iters + per - 1) / per);
 }
 
-__host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
+// Split of the candidate pair kernel given the batch's candidate (tile, direction) items.
+__host__ __device__ inline void job_split_cand(JobStep& s, int32_t n_pad, int64_t items_total,
+                                               int32_t num_cu, Tune tu) {
+  if (!s.learned) return;
+  JobStep c{};
+  c.m = s.m;
+  job_split(c, n_pad, items_total, num_cu, tu);
+  s.nsplit_c = c.nsplit;
+  s.split_len_c = c.split_len;
+}
+
+__host__ __device__ inline int32_t kind_count(const JobStep& s, int kind, int32_t K = 0) {
   if (s.m < 2) return 0;
+  if (s.gate && gated_kind(kind)) return 0;
   switch (kind) {
     case kKPair: return s.fp64 ? 0 : s.ntiles * 2 * s.nsplit;
     case kKComb: return s.fp64 ? 0 : cdiv(s.ntiles, 4);
@@ -155,6 +254,14 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
     case kKRowk: return cdiv(s.m, 4);
     case kKSel: return 1;
     case kKRes: return s.m > 2 ? s.m - 1 : 0;
+    case kKFeat: return s.feat ? cdiv(s.m, 4) : 0;
+    case kKMlp: return s.learned ? cdiv(s.m, 64) : 0;
+    case kKTopk: return s.learned ? 1 : 0;
+    case kKPairC: return s.learned ? s.nct * 2 * s.nsplit_c : 0;
+    case kKCombC: return s.learned ? cdiv(s.nct, 4) : 0;
+    case kKRowkC: return s.learned ? cdiv(K, 4) : 0;
+    case kKColC: return s.learned ? cdiv(s.m, 256) : 0;
+    case kKLsel: return s.learned ? 1 : 0;
     default: return 0;
   }
 }
@@ -171,7 +278,8 @@ __host__ __device__ inline int32_t setup_count(int32_t n_pad, int32_t d, int kin
   }
 }
 
-Layout make_layout(int64_t n, int64_t d, int num_cu);
+// K > 0 adds the regions of the learned form.
+Layout make_layout(int64_t n, int64_t d, int num_cu, int K = 0);
 
 // Schedule buffer of a batch (device): per step, JobStep[njobs] and
 // kNumKinds prefix arrays of njobs + 1 entries; for the set-up,
@@ -195,6 +303,7 @@ hipError_t launch_standardize(const JobDev* jobs, int njobs, SchedDev sc, int gr
                               hipStream_t st);
 hipError_t launch_step_schedule(const JobDev* jobs, int njobs, int t, int num_cu, Tune tu,
                                 SchedDev sc, hipStream_t st);
+hipError_t launch_gate_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st);
 hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_combine(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_pair64(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
@@ -204,9 +313,40 @@ hipError_t launch_select(const JobDev* jobs, int njobs, int t, SchedDev sc, int 
 hipError_t launch_resid(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_gather_status(const JobDev* jobs, int njobs, int32_t* dst, hipStream_t st);
 // Writes `count` (at most kJobsPerLaunch) job-table entries from kernel arguments.
-constexpr int kJobsPerLaunch = 16;
+constexpr int kJobsPerLaunch = 8;
 hipError_t launch_set_jobs(JobDev* table, int first, const JobDev* host_jobs, int count,
                            hipStream_t st);
+
+// Learned form (lingam_learned.hip).
+hipError_t launch_prop_prep(const float* in, PropDev* out, const JobDev* jobs, int njobs,
+                            hipStream_t st);
+// The learned pass of step t in three launches: features, scores, top-K; the
+// candidate pair kernel; candidate measures and the decision.  `grid` holds
+// the host's totals of every kind.
+hipError_t launch_learned_front(const JobDev* jobs, int njobs, int t, SchedDev sc,
+                                const int32_t* grid, hipStream_t st);
+hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+                            hipStream_t st);
+hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
+                               const int32_t* grid, hipStream_t st);
+
+// Training of the network.
+constexpr int kTrainParts = 512;  // workgroups of the backward pass (partial gradients)
+struct TrainLayout {
+  int64_t rows;
+  int32_t n_lists;
+  int nparts;
+  size_t status, prop, score, ds, h1, h2, loss_part, part, total;  // status: int32, 0 = ok
+};
+TrainLayout make_train_layout(int64_t rows, int32_t n_lists);
+// Scores of `rows` feature rows; ws holds a PropDev.
+hipError_t launch_scores(const float* prop, const float* feat, int64_t rows, float* score,
+                         char* ws, hipStream_t st);
+hipError_t launch_grad(const TrainLayout& T, const float* prop, const float* feat,
+                       const int64_t* offsets, const int64_t* targets, float* grad,
+                       float* loss, float* score_out, char* ws, hipStream_t st);
+hipError_t launch_adam(float* prop, const float* grad, float* m1, float* m2, float lr,
+                       float beta1, float beta2, float eps, float c1, float c2, hipStream_t st);
 
 // VarLiNGAM: the ordering layout for the residuals (n = T - lags) followed by
 // the VAR regions.

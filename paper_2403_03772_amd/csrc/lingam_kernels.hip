@@ -45,146 +45,10 @@
 // reduction across lanes, waves and sample splits are FP64.  When few
 // variables remain (m <= kFp64MaxM) all pairwise measures are tiny, the step
 // is cheap, and k_pair64 computes it entirely in FP64 from Zd.
-#include "lingam_internal.h"
-
-#include <math.h>
+#include "lingam_device.h"
 
 namespace lg {
 namespace {
-
-// Constants of the maximum-entropy approximation of differential entropy.
-constexpr double kK1 = 79.047;
-constexpr double kK2 = 7.4129;
-constexpr double kGamma = 0.37457;
-constexpr double kHnu = 1.41893853320467274178;  // (1 + ln(2 pi)) / 2
-constexpr double kLn2 = 0.69314718055994530942;
-constexpr double kLog2e = 1.44269504088896340736;
-constexpr double kCollinear = 1e-12;  // |rho| >= 1 - kCollinear is degenerate
-constexpr int kLogBlock = 16;         // samples per lane folded into one log2
-constexpr float kS1Start = 9.0f;      // start value (negated) of each lane's log cosh sum
-
-constexpr int32_t kStInvalid = -1;
-constexpr int32_t kStDegenerate = -2;
-
-template <typename T>
-__host__ __device__ inline T* at(char* ws, size_t off) {
-  return reinterpret_cast<T*>(ws + off);
-}
-
-__device__ inline void set_status(Ctrl* c, int32_t s) { atomicCAS(&c->status, 0, s); }
-
-__device__ inline double entropy_from_moments(double e_lc, double e_g) {
-  const double a = e_lc - kGamma;
-  return kHnu - kK1 * a * a - kK2 * e_g * e_g;
-}
-
-// One evaluation (one residual direction at one sample).  See the header.
-__device__ __forceinline__ void eval_dir(float x, float y, float r, float c1h, float c1l,
-                                         float& P, float& S1, float& S2) {
-  const float kM2 = (float)(-1.0 / (8.0 * kLog2e));  // rounds with relative error 2.7e-9
-  const float t = fmaf(-r, y, x);
-  const float at = fabsf(t);
-  const float m1 = fmaf(c1h, at, c1l * at);
-  const float e1 = __builtin_amdgcn_exp2f(m1);
-  P = fmaf(P, e1, P);
-  S1 = fmaf(m1, -0.5f, S1);
-  const float m2 = (kM2 * m1) * m1;
-  const float e2 = __builtin_amdgcn_exp2f(m2);
-  S2 = fmaf(t, e2, S2);
-}
-
-// FP64 log cosh and Gaussian-weighted term (marginals and the FP64 pair path).
-__device__ inline double logcosh64(double u) {
-  const double a = fabs(u);
-  return a + log1p(exp(-2.0 * a)) - kLn2;
-}
-__device__ inline double gauss64(double u) { return u * exp(-0.5 * u * u); }
-
-// Pointers read from the job table are generic; the hot loop casts row bases
-// to the global address space so loads use global_load with a scalar base.
-typedef __attribute__((address_space(1))) const char gchar_t;
-typedef __attribute__((address_space(1))) const float gfloat_t;
-
-__device__ __forceinline__ float readlane_f(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-// Block-wide deterministic FP64 sum (256 threads), result valid in all threads.
-__device__ double block_sum_256(double v, double* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) sh[tid] += sh[tid + off];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-// Row-major upper-triangular tile index -> (bi, bj), bi <= bj < nb.
-__device__ inline void decode_tile(int tile, int nb, int& bi, int& bj) {
-  const double B = 2.0 * nb + 1.0;
-  int r = (int)((B - sqrt(B * B - 8.0 * (double)tile)) * 0.5);
-  r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
-  auto off = [nb](int q) { return q * nb - (q * (q - 1)) / 2; };
-  while (r > 0 && off(r) > tile) --r;
-  while (r + 1 < nb && off(r + 1) <= tile) ++r;
-  bi = r;
-  bj = r + (tile - off(r));
-}
-
-// ---------------------------------------------------------------------------
-// job lookup and schedules
-// ---------------------------------------------------------------------------
-
-// Largest j with pre[j] <= b (pre: exclusive prefix sums, pre[njobs] = total);
-// that job owns workgroup b and has a non-zero count.
-__device__ inline int find_job(const int32_t* __restrict__ pre, int njobs, int b) {
-  int lo = 0, hi = njobs;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= b) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// Workgroup b belongs to job j at local index b - pre[j]; false when b lies
-// beyond the schedule (a grid larger than the device's own totals): the
-// workgroup then has nothing to do.
-__device__ inline bool locate(const int32_t* __restrict__ pre, int njobs, int b, int& j,
-                              int& local) {
-  j = find_job(pre, njobs, b);
-  local = b - pre[j];
-  return local < pre[j + 1] - pre[j];
-}
-
-// out[0..njobs] = exclusive prefix sums of count(j); one block of 1024 threads.
-template <typename F>
-__device__ void block_scan(int njobs, F count, int32_t* out, int32_t* sh) {
-  const int tid = threadIdx.x;
-  const int per = (njobs + 1023) / 1024;
-  const int j0 = tid * per, j1 = min(j0 + per, njobs);
-  int32_t s = 0;
-  for (int j = j0; j < j1; ++j) s += count(j);
-  sh[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int32_t v = tid >= off ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += v;
-    __syncthreads();
-  }
-  int32_t run = tid > 0 ? sh[tid - 1] : 0;
-  for (int j = j0; j < j1; ++j) {
-    out[j] = run;
-    run += count(j);
-  }
-  if (tid == 1023) out[njobs] = sh[1023];
-  __syncthreads();
-}
 
 __global__ __launch_bounds__(1024) void k_setup_schedule(const JobDev* __restrict__ jobs,
                                                          int njobs, int32_t* spre) {
@@ -204,24 +68,52 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
   const int tid = threadIdx.x;
   if (tid == 0) items = 0;
   __syncthreads();
-  long long mine = 0;
+  __shared__ long long items_c;
+  if (tid == 0) items_c = 0;
+  __syncthreads();
+  long long mine = 0, mine_c = 0;
   for (int j = tid; j < njobs; j += 1024) {
-    const JobStep s = job_step_base(jobs[j].d, t);
+    const JobDev& J = jobs[j];
+    const JobStep s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
     js[j] = s;
     if (s.m >= 2 && !s.fp64) mine += 2LL * s.ntiles;
+    if (s.learned) mine_c += 2LL * s.nct;
   }
   if (mine) atomicAdd(reinterpret_cast<unsigned long long*>(&items), (unsigned long long)mine);
+  if (mine_c)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&items_c), (unsigned long long)mine_c);
   __syncthreads();
   for (int j = tid; j < njobs; j += 1024) {
     JobStep s = js[j];
     job_split(s, jobs[j].n_pad, items, num_cu, tu);
+    job_split_cand(s, jobs[j].n_pad, items_c, num_cu, tu);
     js[j] = s;
   }
   __syncthreads();
   for (int kind = 0; kind < kNumKinds; ++kind)
     block_scan(
-        njobs, [&](int j) { return kind_count(js[j], kind); }, pre + (int64_t)kind * (njobs + 1),
-        sh);
+        njobs, [&](int j) { return kind_count(js[j], kind, jobs[j].K); },
+        pre + (int64_t)kind * (njobs + 1), sh);
+}
+
+// After the learned decisions: gate off the full step of every job whose
+// learned pass chose, and recompute the prefix sums of the gated kinds.  The
+// splits are left as planned, so no count exceeds the host's grid.
+__global__ __launch_bounds__(1024) void k_gate_schedule(const JobDev* __restrict__ jobs,
+                                                        int njobs, JobStep* __restrict__ js,
+                                                        int32_t* __restrict__ pre) {
+  __shared__ int32_t sh[1024];
+  for (int j = threadIdx.x; j < njobs; j += 1024) {
+    JobStep s = js[j];
+    s.gate = s.learned && jobs[j].ctrl->full == 0;
+    js[j] = s;
+  }
+  __syncthreads();
+  for (int kind = 0; kind < kNumKinds; ++kind)
+    if (gated_kind(kind))
+      block_scan(
+          njobs, [&](int j) { return kind_count(js[j], kind, jobs[j].K); },
+          pre + (int64_t)kind * (njobs + 1), sh);
 }
 
 struct JobPack {
@@ -240,7 +132,11 @@ __global__ void k_set_jobs(JobDev* table, int first, JobPack pack, int count) {
 // Per job: identity active list, zero control block, the trivial order of d = 1.
 __global__ __launch_bounds__(256) void k_init(const JobDev* __restrict__ jobs) {
   const JobDev& J = jobs[blockIdx.x];
-  for (int v = threadIdx.x; v < J.d; v += 256) J.act[v] = v;
+  for (int v = threadIdx.x; v < J.d; v += 256) {
+    J.act[v] = v;
+    if (J.cmark) J.cmark[v] = 0;
+    if (J.steplog) J.steplog[v] = 0;
+  }
   if (threadIdx.x < (int)(sizeof(Ctrl) / sizeof(int32_t)))
     reinterpret_cast<int32_t*>(J.ctrl)[threadIdx.x] = 0;
   if (threadIdx.x == 0 && J.d == 1) J.order[0] = 0;
@@ -388,7 +284,7 @@ __global__ __launch_bounds__(256) void k_gram(const JobDev* __restrict__ jobs, i
 // entropy H(z) of every variable (FP64).
 __global__ __launch_bounds__(256) void k_standardize(const JobDev* __restrict__ jobs, int njobs,
                                                      const int32_t* __restrict__ spre) {
-  __shared__ double sh[256];
+  __shared__ double sh[5 * 4];
   int j, v;
   if (!locate(spre, njobs, blockIdx.x, j, v)) return;
   const JobDev& J = jobs[j];
@@ -396,185 +292,29 @@ __global__ __launch_bounds__(256) void k_standardize(const JobDev* __restrict__ 
   float* zf = J.z + (int64_t)v * J.ldz;
   const double m = J.mu[v], is = 1.0 / J.sig[v];
   const int n = J.n;
-  double a = 0.0, b = 0.0;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < J.n_pad; k += 256) {
     if (k < n) {
       const double z = (zd[k] - m) * is;
       zd[k] = z;
       zf[k] = (float)z;
-      a += logcosh64(z);
-      b += gauss64(z);
+      add_moments(z, acc);
     } else {
       zf[k] = 0.f;
     }
   }
-  const double t1 = block_sum_256(a, sh);
-  const double t2 = block_sum_256(b, sh);
-  if (threadIdx.x == 0) J.hm[v] = entropy_from_moments(t1 / n, t2 / n);
+  block_sum_5(acc, sh);
+  if (threadIdx.x == 0) store_moments(J, v, acc, n);
 }
 
 // ---------------------------------------------------------------------------
 // the step kernels
 // ---------------------------------------------------------------------------
 
-// Pair moments.  Grid: per job ntiles * 2 * nsplit workgroups of 4 waves.  A
-// workgroup owns an 8 x 8 block of (i, j) positions, one residual direction
-// and one range of samples; wave (wi, wj) owns the 4 x 4 sub-block (i in block
-// bi, j in block bj).  Lanes stride over samples (coalesced 256 B loads per
-// variable row) and every lane keeps 48 running values (16 pairs x {P, S1, S2})
-// for its direction.  The wave ends with an FP64 reduction after which lane
-// L < 32 holds the total of sum L, stored at
-// part[((split * ntiles + tile) * 4 + wave) * 64 + pair * 4 + dir * 2 + which],
-// which 0 = S1 (log cosh, offset as described in the header), 1 = S2;
-// dir 0 = residual of i on j, dir 1 = of j on i.
 __global__ __launch_bounds__(256) void k_pair(const JobDev* __restrict__ jobs, int njobs,
                                               const JobStep* __restrict__ js,
                                               const int32_t* __restrict__ pre, int G) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-  // contiguous range of (job, tile, direction, split) work so that the rows a
-  // tile reads are shared in that XCD's L2.
-  const int b = blockIdx.x;
-  const int Q = G >> 3, R = G & 7, x = b & 7, idx = b >> 3;
-  const int w = x * Q + (x < R ? x : R) + idx;
-  int jb, local;
-  if (!locate(pre, njobs, w, jb, local)) return;
-  const JobDev& J = jobs[jb];
-  const JobStep S = js[jb];
-  const int m = S.m, nsplit = S.nsplit, ntiles = S.ntiles;
-  const int per_tile = 2 * nsplit;
-  const int tile = local / per_tile, rem = local - tile * per_tile;
-  const int dir = rem / nsplit, split = rem - dir * nsplit;
-  int bi, bj;
-  decode_tile(tile, S.nblk, bi, bj);
-  const int wi = wave >> 1, wj = wave & 1;
-  if (bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)
-  const int pi0 = bi * kTileVars + wi * kWaveVars, pj0 = bj * kTileVars + wj * kWaveVars;
-  const int32_t* act = J.act;
-  const int64_t ldz = J.ldz, ldr = J.d;
-
-  // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
-  // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
-  // i = pi0 + c.  Lane q < 16 computes the coefficients of walk index q.
-  float my_r = 0.f, my_c1h = 0.f, my_c1l = 0.f;
-  {
-    const int q = lane & 15, a = q >> 2, c = q & 3;
-    const int pi = pi0 + (dir == 0 ? a : c), pj = pj0 + (dir == 0 ? c : a);
-    if (pi < m && pj < m && pi < pj) {
-      double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
-      const double lim = 1.0 - kCollinear;
-      r = r > lim ? lim : (r < -lim ? -lim : r);
-      const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
-      my_r = (float)r;
-      my_c1h = (float)c1;
-      my_c1l = (float)(c1 - (double)my_c1h);
-    }
-  }
-  float kr[16], kh[16], kl[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    kr[q] = readlane_f(my_r, q);
-    kh[q] = readlane_f(my_c1h, q);
-    kl[q] = readlane_f(my_c1l, q);
-  }
-  // Row bases (wave-uniform) and a 32-bit per-lane byte offset, so loads use
-  // the scalar-base + vector-offset form.  zr = rows of the regressed
-  // variables (the residual's own variable), zx = rows of the regressors.
-  const int pr0 = dir == 0 ? pi0 : pj0, px0 = dir == 0 ? pj0 : pi0;
-  gchar_t* zr[4];
-  gchar_t* zx[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int pr = pr0 + a, px = px0 + a;
-    // the row ids are wave-uniform: keep them (and the row bases) in SGPRs
-    const int sr = __builtin_amdgcn_readfirstlane(pr < m ? act[pr] : J.d);
-    const int sx = __builtin_amdgcn_readfirstlane(px < m ? act[px] : J.d);
-    zr[a] = (gchar_t*)(J.z + (int64_t)sr * ldz);
-    zx[a] = (gchar_t*)(J.z + (int64_t)sx * ldz);
-  }
-
-  const int s_begin = split * S.split_len;
-  const int s_end = min(s_begin + S.split_len, J.n_pad);
-  const int nk = (s_end - s_begin) / 64;
-
-  float P[16], S1[16], S2[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    P[q] = 1.f;
-    S1[q] = -kS1Start;
-    S2[q] = 0.f;
-  }
-  uint32_t voff = (uint32_t)(s_begin + lane) * 4u;
-  float xa[4], xb[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    xa[a] = *(gfloat_t*)(zr[a] + voff);
-    xb[a] = *(gfloat_t*)(zx[a] + voff);
-  }
-  int kb = 0;
-  for (int k = 0; k < nk; ++k) {
-    // prefetch the next sample of every row; on the last iteration the stride
-    // is 0 and the current sample is re-read (always in bounds, no branch)
-    const bool more = k + 1 < nk;
-    voff += more ? 256u : 0u;
-    float na[4], nb[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      na[a] = *(gfloat_t*)(zr[a] + voff);
-      nb[a] = *(gfloat_t*)(zx[a] + voff);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int q = a * 4 + c;
-        eval_dir(xa[a], xb[c], kr[q], kh[q], kl[q], P[q], S1[q], S2[q]);
-      }
-    }
-    if (++kb == kLogBlock || !more) {
-      const float off = 1.5f * (float)kb;  // exact
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        S1[q] += __builtin_amdgcn_logf(P[q]) - off;
-        P[q] = 1.f;
-      }
-      kb = 0;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      xa[a] = na[a];
-      xb[a] = nb[a];
-    }
-  }
-
-  // FP64 reduction over the 64 lanes: fold the upper half onto the lower, then
-  // a reduce-scatter butterfly over 32 lanes; afterwards lane L < 32 holds sum L.
-  double v[32];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    v[2 * q] = (double)S1[q];
-    v[2 * q + 1] = (double)S2[q];
-  }
-#pragma unroll
-  for (int k2 = 0; k2 < 32; ++k2) v[k2] += __shfl_xor(v[k2], 32);
-#pragma unroll
-  for (int half = 16; half >= 1; half >>= 1) {
-    const bool up = (lane & half) != 0;
-#pragma unroll
-    for (int k2 = 0; k2 < half; ++k2) {
-      const double lo = v[k2], hi = v[k2 + half];
-      const double send = up ? lo : hi;
-      const double keep = up ? hi : lo;
-      v[k2] = keep + __shfl_xor(send, half);
-    }
-  }
-  if (lane < 32) {
-    // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
-    const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
-    const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
-    J.part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
-  }
+  pair_tiles<false>(jobs, njobs, js, pre, G);
 }
 
 // Sum the sample splits (FP64, fixed order), form both residual entropies and
@@ -644,15 +384,32 @@ __global__ __launch_bounds__(256) void k_pair64(const JobDev* __restrict__ jobs,
   const double al = 1.0 / sqrt(1.0 - r * r);
   const double* zi = J.zd + (int64_t)si * J.ldz;
   const double* zj = J.zd + (int64_t)sj * J.ldz;
+  // log cosh u = |u| + log(1 + e^{-2|u|}) - ln 2; the logs of a lane's
+  // samples are taken as the log of their product (each factor is in (1, 2],
+  // so 512 of them stay below 2^512), one FP64 log per 512 samples
   double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+  double pa = 1.0, pb = 1.0;
+  int cnt = 0, tot = 0;
   for (int s = lane; s < J.n; s += 64) {
     const double xi = zi[s], xj = zj[s];
     const double u = al * (xi - r * xj), w = al * (xj - r * xi);
-    a1 += logcosh64(u);
-    a2 += gauss64(u);
-    b1 += logcosh64(w);
-    b2 += gauss64(w);
+    const double au = fabs(u), aw = fabs(w);
+    a1 += au;
+    b1 += aw;
+    pa *= 1.0 + exp(-2.0 * au);
+    pb *= 1.0 + exp(-2.0 * aw);
+    a2 += u * exp(-0.5 * u * u);
+    b2 += w * exp(-0.5 * w * w);
+    ++tot;
+    if (++cnt == 512) {
+      a1 += log(pa);
+      b1 += log(pb);
+      pa = pb = 1.0;
+      cnt = 0;
+    }
   }
+  a1 += log(pa) - (double)tot * kLn2;
+  b1 += log(pb) - (double)tot * kLn2;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     a1 += __shfl_xor(a1, off);
@@ -692,29 +449,6 @@ __global__ __launch_bounds__(256) void k_rowk(const JobDev* __restrict__ jobs, i
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
   if (lane == 0) J.mvec[p] = -k;
-}
-
-struct Best {
-  double v;   // measure (NaN mapped to -inf)
-  int slot;   // original id
-  int pos;    // position in the active list
-  double v2;  // runner-up measure
-};
-
-__device__ inline bool better(double va, int sa, double vb, int sb) {
-  return va > vb || (va == vb && sa < sb);
-}
-
-__device__ inline Best merge(const Best& a, const Best& b) {
-  Best r;
-  if (better(a.v, a.slot, b.v, b.slot)) {
-    r = a;
-    r.v2 = fmax(a.v2, b.v);
-  } else {
-    r = b;
-    r.v2 = fmax(b.v2, a.v);
-  }
-  return r;
 }
 
 // Argmax with tie-break on the original id, teacher forcing, per-step outputs,
@@ -770,6 +504,9 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
   __syncthreads();
   if (tid == 0) {
     const int slot = act[pos];
+    if (js[jb].learned && J.audit_every > 0 && t % J.audit_every == 0 &&
+        slot == J.ctrl->learned_slot)
+      J.ctrl->n_audit_agree += 1;
     J.order[t] = slot;
     J.ctrl->exo_slot = slot;
     J.ctrl->exo_pos = pos;
@@ -786,7 +523,7 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
 __global__ __launch_bounds__(256) void k_resid(const JobDev* __restrict__ jobs, int njobs,
                                                const JobStep* __restrict__ js,
                                                const int32_t* __restrict__ pre) {
-  __shared__ double sh[256];
+  __shared__ double sh[5 * 4];
   int jb, p;
   if (!locate(pre, njobs, blockIdx.x, jb, p)) return;
   const JobDev& J = jobs[jb];
@@ -805,19 +542,15 @@ __global__ __launch_bounds__(256) void k_resid(const JobDev* __restrict__ jobs, 
   const double* ze = J.zd + (int64_t)se * ldz;
   float* zf = J.z + (int64_t)sp * ldz;
   const int n = J.n;
-  double a = 0.0, b = 0.0;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < J.n_pad; k += 256) {
     const double z = al * (zp[k] - r * ze[k]);  // padded samples stay 0
     zp[k] = z;
     zf[k] = (float)z;
-    if (k < n) {
-      a += logcosh64(z);
-      b += gauss64(z);
-    }
+    if (k < n) add_moments(z, acc);
   }
-  const double t1 = block_sum_256(a, sh);
-  const double t2 = block_sum_256(b, sh);
-  if (threadIdx.x == 0) J.hm[sp] = entropy_from_moments(t1 / n, t2 / n);
+  block_sum_5(acc, sh);
+  if (threadIdx.x == 0) store_moments(J, sp, acc, n);
   double* rho_p = J.rho + (int64_t)sp * ldr;
   for (int q = threadIdx.x; q < m_after; q += 256) {
     if (q == p) continue;
@@ -1140,7 +873,7 @@ __global__ void k_zero_i32(int32_t* p) { p[0] = 0; }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int64_t n, int64_t d, int num_cu) {
+Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
   Layout L{};
   L.n = n;
   L.d = d;
@@ -1174,6 +907,28 @@ Layout make_layout(int64_t n, int64_t d, int num_cu) {
   L.part = take(sizeof(double) * (pe ? pe : 1));
   L.rmat = take(sizeof(double) * (size_t)d * (size_t)d);
   L.mvec = take(sizeof(double) * (size_t)d);
+  L.mom = take(sizeof(double) * 8 * (size_t)d);
+  L.K = K;
+  if (K > 0) {
+    L.feat = take(sizeof(float) * kFeat * (size_t)d);
+    L.score = take(sizeof(float) * (size_t)d);
+    L.cand = take(sizeof(int32_t) * kMaxTopK);
+    L.cmark = take(sizeof(int32_t) * (size_t)d);
+    size_t pc = 0;
+    for (int64_t t = 0; t + kFp64MaxM < d; ++t) {
+      JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
+      if (!s.learned) continue;
+      job_split_cand(s, (int32_t)L.n_pad, 2LL * s.nct, num_cu, worst);
+      const size_t need = (size_t)s.nct * (size_t)s.nsplit_c * 256;
+      if (need > pc) pc = need;
+    }
+    L.partc_elems = pc;
+    L.partc = take(sizeof(double) * (pc ? pc : 1));
+    L.rc = take(sizeof(double) * (size_t)K * (size_t)d);
+    L.kc = take(sizeof(double) * (size_t)K);
+    L.lb = take(sizeof(double) * (size_t)d);
+    L.steplog = take(sizeof(int32_t) * (size_t)d);
+  }
   L.total = off;
   return L;
 }
@@ -1251,6 +1006,11 @@ hipError_t launch_step_schedule(const JobDev* jobs, int njobs, int t, int num_cu
                                 SchedDev sc, hipStream_t st) {
   hipLaunchKernelGGL(k_step_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, t, num_cu, tu,
                      sc.js, sc.pre);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_gate_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, sc.js, sc.pre);
   return hipGetLastError();
 }
 

@@ -1,0 +1,970 @@
+// gfx950 kernels of the learned-proposal form of the ordering search.
+//
+// The exact search (Section 2.2, Algorithm 1) spends its time on the measure
+// of every pair of active variables.  The learned form evaluates that measure
+// only for the rows of K candidates chosen by a small network, and decides on
+// the device, without any host round trip, whether the candidates' result can
+// stand in for the full step:
+//
+//   k_features      16 features per active variable (moments of z kept by the
+//                   residual update, statistics of its correlation row, rank
+//                   of its marginal entropy, progress of the search)
+//   k_mlp           scores of a 16 -> 128 -> 128 -> 1 ReLU network, BF16
+//                   weights and activations on MFMA, FP32 accumulation
+//   k_topk          the K best scores (ties to the smaller original id) by an
+//                   8-bit radix select over 64-bit keys
+//   k_pair_cand     the pair moments of every (candidate, active) pair: the
+//                   all-pairs hot loop on (K / 8) x nblk tiles
+//   k_combine_cand  R(c, j) of every candidate row
+//   k_cand_rowk     exact k of every candidate
+//   k_cand_colk     for every other variable l, the lower bound
+//                   sum_c max(0, R(c, l))^2 <= k_l its candidate pairs give
+//   k_lselect       best candidate; it is certified when every lower bound
+//                   exceeds its k, and accepted when certified or when its
+//                   score beats every non-candidate's by the margin; audit
+//                   steps and small margins hand the step to the full kernels
+//                   (gated by k_gate_schedule)
+//
+// and the training kernels of the network (forward with saved activations,
+// listwise softmax cross-entropy, backward on MFMA, gradient reduction, Adam).
+#include "lingam_device.h"
+
+namespace lg {
+namespace {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x4_t load4(const uint16_t* p) {
+  // 8-byte aligned by construction of every caller's layout
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  bf16x4_t r;
+  r[0] = (short)(v.x & 0xFFFF);
+  r[1] = (short)(v.x >> 16);
+  r[2] = (short)(v.y & 0xFFFF);
+  r[3] = (short)(v.y >> 16);
+  return r;
+}
+
+// 16 x 16 x 16 BF16 MFMA.  Operand layout: lane l supplies A[l % 16][4 (l / 16) + j]
+// and B[4 (l / 16) + j][l % 16] (j = 0..3); result register r of lane l is
+// D[4 (l / 16) + r][l % 16].
+__device__ __forceinline__ f32x4_t mfma16(bf16x4_t a, bf16x4_t b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+constexpr int kLdW = kHidden + 8;  // padded LDS row of 128 BF16 values
+constexpr int kLdR = 64 + 8;       // padded LDS row of 64 BF16 values
+
+// ---------------------------------------------------------------------------
+// network preparation
+// ---------------------------------------------------------------------------
+
+// FP32 parameter block [mean(16), scale(16), W1, b1, W2, b2, w3, b3] -> BF16
+// weights; a non-finite value or a scale <= 0 marks every job invalid (and
+// sets *flag when given).
+__global__ __launch_bounds__(256) void k_prop_prep(const float* __restrict__ in,
+                                                   PropDev* __restrict__ out,
+                                                   const JobDev* __restrict__ jobs, int njobs,
+                                                   int32_t* __restrict__ flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const float* w = in + kPropNorm;
+  int mybad = 0;
+  for (int i = threadIdx.x; i < kHidden * kHidden; i += 256) {
+    const float v = w[kOffW2 + i];
+    mybad |= !isfinite(v);
+    out->w2[i] = to_bf16(v);
+  }
+  for (int i = threadIdx.x; i < kHidden * kFeat; i += 256) {
+    const float v = w[kOffW1 + i];
+    mybad |= !isfinite(v);
+    out->w1[i] = to_bf16(v);
+  }
+  for (int i = threadIdx.x; i < kHidden; i += 256) {
+    const float a = w[kOffW3 + i], b1 = w[kOffB1 + i], b2 = w[kOffB2 + i];
+    mybad |= !isfinite(a) || !isfinite(b1) || !isfinite(b2);
+    out->w3[i] = to_bf16(a);
+    out->b1[i] = b1;
+    out->b2[i] = b2;
+  }
+  if (threadIdx.x < kFeat) {
+    const float mu = in[threadIdx.x], sd = in[kFeat + threadIdx.x];
+    mybad |= !isfinite(mu) || !(sd > 0.f) || !isfinite(sd);
+    out->mu[threadIdx.x] = mu;
+    out->sd[threadIdx.x] = sd;
+  }
+  if (threadIdx.x == 0) {
+    out->b3 = w[kOffB3];
+    mybad |= !isfinite(w[kOffB3]);
+  }
+  if (mybad) bad = 1;
+  __syncthreads();
+  if (bad) {
+    for (int j = threadIdx.x; j < njobs; j += 256) set_status(jobs[j].ctrl, kStInvalid);
+    if (flag && threadIdx.x == 0) *flag = 2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// features
+// ---------------------------------------------------------------------------
+
+// One wave per active position p: statistics of its correlation row and the
+// rank of its marginal entropy; lane 0 assembles the 16 features.
+__global__ __launch_bounds__(256) void k_features(const JobDev* __restrict__ jobs, int njobs,
+                                                  const JobStep* __restrict__ js,
+                                                  const int32_t* __restrict__ pre, int t) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lb * 4 + wave;
+  if (p >= m) return;
+  const int si = J.act[p];
+  const double Hi = J.hm[si];
+  const double* rr = J.rho + (int64_t)si * J.d;
+  double mx = 0.0, s1 = 0.0, s2 = 0.0, sw = 0.0;
+  int c5 = 0, rk = 0;
+  for (int q = lane; q < m; q += 64) {
+    const int sq = J.act[q];
+    const double Hq = J.hm[sq];
+    rk += (Hq < Hi || (Hq == Hi && sq < si)) ? 1 : 0;  // never true for q == p
+    if (q == p) continue;
+    const double r = rr[sq], a = fabs(r), r2 = r * r;
+    mx = fmax(mx, a);
+    s1 += a;
+    s2 += r2;
+    sw += r2 * Hq;
+    c5 += a > 0.5 ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off));
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+    sw += __shfl_xor(sw, off);
+    c5 += __shfl_xor(c5, off);
+    rk += __shfl_xor(rk, off);
+  }
+  if (lane != 0) return;
+  const double* mo = J.mom + (int64_t)si * 8;
+  const double mm1 = (double)(m - 1);
+  float f[kFeat];
+  f[0] = (float)mo[0];
+  f[1] = (float)mo[1];
+  f[2] = (float)Hi;
+  f[3] = (float)mo[2];
+  f[4] = (float)(mo[3] - 3.0);
+  f[5] = (float)mo[4];
+  f[6] = (float)(mo[2] * mo[2]);
+  f[7] = (float)mx;
+  f[8] = (float)(s2 / (double)m);
+  f[9] = (float)(s1 / mm1);
+  f[10] = (float)((double)c5 / mm1);
+  f[11] = (float)((double)rk / (double)m);
+  f[12] = (float)((double)t / (double)J.d);
+  f[13] = (float)((double)m / (double)J.d);
+  f[14] = (float)log((double)J.n);
+  f[15] = (float)(s2 > 0.0 ? sw / s2 : 0.0);
+  if (J.feat) {
+    float* dst = J.feat + (int64_t)p * kFeat;
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) dst[k] = f[k];
+  }
+  if (J.record) {
+    float* rec = J.record + ((int64_t)t * J.d + si) * kFeat;
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) rec[k] = f[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the network
+// ---------------------------------------------------------------------------
+
+// LDS of one 64-row tile of the network.
+struct MlpShared {
+  uint16_t w2[kHidden][kLdW];  // W2[h][g]
+  uint16_t h1[64][kLdW];       // first hidden layer of the tile's rows (BF16)
+};
+
+__device__ inline void stage_w2(const PropDev& W, MlpShared& S) {
+  for (int i = threadIdx.x; i < kHidden * kHidden / 4; i += 256) {
+    const int h = i / (kHidden / 4), g4 = (i % (kHidden / 4)) * 4;
+    *reinterpret_cast<uint2*>(&S.w2[h][g4]) =
+        *reinterpret_cast<const uint2*>(&W.w2[h * kHidden + g4]);
+  }
+}
+
+// Forward pass of rows row0 .. row0 + 63 (rows >= nrows are zero inputs and
+// produce nothing).  Wave w owns rows row0 + 16 w .. + 15.  Features are
+// normalized with the network's mean and scale and rounded to BF16.  Writes
+// score[row]; with H1 / H2 non-NULL also the BF16 first and FP32 second hidden
+// layer ([row][128]) for the backward pass.  S.w2 must be staged.
+__device__ void mlp_tile(const PropDev& W, MlpShared& S, const float* __restrict__ feat,
+                         int64_t row0, int64_t nrows, float* __restrict__ score,
+                         uint16_t* __restrict__ H1, float* __restrict__ H2) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg4 = (lane >> 4) * 4;
+  // layer 1: A = x[row][f], B = W1^T
+  bf16x4_t xa;
+  {
+    const int64_t row = row0 + wave * 16 + li;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = lg4 + j;
+      float v = 0.f;
+      if (row < nrows) v = (feat[row * kFeat + f] - W.mu[f]) / W.sd[f];
+      xa[j] = (short)to_bf16(v);
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < kHidden / 16; ++nt) {
+    const int n = nt * 16 + li;
+    const bf16x4_t wb = load4(&W.w1[n * kFeat + lg4]);
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma16(xa, wb, acc);
+    const float b = W.b1[n];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float h = fmaxf(acc[r] + b, 0.f);
+      S.h1[wave * 16 + lg4 + r][n] = to_bf16(h);
+    }
+  }
+  __syncthreads();
+  if (H1) {
+    for (int e = lane; e < 16 * kHidden / 4; e += 64) {
+      const int i = e / (kHidden / 4), g4 = (e % (kHidden / 4)) * 4;
+      const int64_t row = row0 + wave * 16 + i;
+      if (row < nrows)
+        *reinterpret_cast<uint2*>(&H1[row * kHidden + g4]) =
+            *reinterpret_cast<const uint2*>(&S.h1[wave * 16 + i][g4]);
+    }
+  }
+  // layer 2: A = h1[row][g], B = W2^T; score = w3 . relu(.) + b3
+  float ps[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int nt = 0; nt < kHidden / 16; ++nt) {
+    const int n = nt * 16 + li;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kHidden / 16; ++ks) {
+      const bf16x4_t a = load4(&S.h1[wave * 16 + li][ks * 16 + lg4]);
+      const bf16x4_t b = load4(&S.w2[n][ks * 16 + lg4]);
+      acc = mfma16(a, b, acc);
+    }
+    const float b2 = W.b2[n], w3 = from_bf16(W.w3[n]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float h = fmaxf(acc[r] + b2, 0.f);
+      ps[r] = fmaf(h, w3, ps[r]);
+      if (H2) {
+        const int64_t row = row0 + wave * 16 + lg4 + r;
+        if (row < nrows) H2[row * kHidden + n] = h;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) ps[r] += __shfl_xor(ps[r], off);
+  if (li == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + wave * 16 + lg4 + r;
+      if (row < nrows) score[row] = ps[r] + W.b3;
+    }
+  }
+}
+
+// Scores of the active positions of every learned job, 64 per workgroup.
+__global__ __launch_bounds__(256) void k_mlp(const JobDev* __restrict__ jobs, int njobs,
+                                             const JobStep* __restrict__ js,
+                                             const int32_t* __restrict__ pre) {
+  __shared__ MlpShared S;
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  stage_w2(*J.prop, S);
+  __syncthreads();
+  mlp_tile(*J.prop, S, J.feat, (int64_t)lb * 64, js[jb].m, J.score, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// top-K
+// ---------------------------------------------------------------------------
+
+// Order-preserving map of an FP32 score to 32 bits (NaN sorts lowest).
+__device__ __forceinline__ uint32_t ord_f32(float f) {
+  if (f != f) return 0u;
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// One workgroup per job: the K largest keys (score, then smaller original id)
+// by an 8-bit radix select from the top byte; keys are distinct, so exactly K
+// positions are at or above the K-th key.  Candidates are listed in
+// ascending position order; cmark[p] = t + 1 marks them; ctrl->s_out is the
+// best score outside them.
+__global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, int njobs,
+                                               const JobStep* __restrict__ js,
+                                               const int32_t* __restrict__ pre, int t) {
+  __shared__ uint32_t hist[256];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_need;
+  __shared__ int32_t scan[1024];
+  __shared__ float smax[16];
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m, K = J.K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto key = [&](int p) -> unsigned long long {
+    return ((unsigned long long)ord_f32(J.score[p]) << 32) |
+           (unsigned long long)(0xFFFFFFFFu - (uint32_t)J.act[p]);
+  };
+  if (tid == 0) {
+    s_prefix = 0ull;
+    s_need = K;
+  }
+  unsigned long long prefix = 0ull, mask = 0ull;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    if (tid < 256) hist[tid] = 0u;
+    __syncthreads();
+    for (int p = tid; p < m; p += 1024) {
+      const unsigned long long k = key(p);
+      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // lane L holds bins 255 - 4L .. 252 - 4L (descending)
+      uint32_t c[4], tot = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c[i] = hist[255 - 4 * lane - i];
+        tot += c[i];
+      }
+      uint32_t incl = tot;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+      }
+      const int need = s_need;
+      const unsigned long long bal = __ballot(incl >= (uint32_t)need);
+      const int first = __ffsll((long long)bal) - 1;
+      if (lane == first) {
+        uint32_t excl = incl - tot;
+        int dg = 255 - 4 * lane - 3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (excl + c[i] >= (uint32_t)need) {
+            dg = 255 - 4 * lane - i;
+            break;
+          }
+          excl += c[i];
+        }
+        s_prefix = s_prefix | ((unsigned long long)dg << shift);
+        s_need = need - (int)excl;
+      }
+    }
+    __syncthreads();
+    prefix = s_prefix;
+    mask |= 0xFFull << shift;
+  }
+  // prefix is the K-th largest key; compact positions p with key(p) >= prefix
+  const int per = (m + 1023) / 1024;
+  const int p0 = tid * per, p1 = min(p0 + per, m);
+  int cnt = 0;
+  float best_out = -INFINITY;
+  for (int p = p0; p < p1; ++p) {
+    if (key(p) >= prefix) ++cnt;
+    else best_out = fmaxf(best_out, J.score[p] == J.score[p] ? J.score[p] : -INFINITY);
+  }
+  scan[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = tid >= off ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  int w = scan[tid] - cnt;
+  for (int p = p0; p < p1; ++p)
+    if (key(p) >= prefix) {
+      if (w < K) J.cand[w] = p;
+      J.cmark[p] = t + 1;
+      ++w;
+    }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) best_out = fmaxf(best_out, __shfl_xor(best_out, off));
+  if (lane == 0) smax[wave] = best_out;
+  __syncthreads();
+  if (tid == 0) {
+    float b = smax[0];
+    for (int i = 1; i < 16; ++i) b = fmaxf(b, smax[i]);
+    J.ctrl->s_out = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// candidate rows of the measure
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre, int G) {
+  pair_tiles<true>(jobs, njobs, js, pre, G);
+}
+
+// R(c, j) for candidate c against every active position j (0 for j = c),
+// stored rc[c * d + j].  Same arithmetic as the all-pairs combine.
+__global__ __launch_bounds__(256) void k_combine_cand(const JobDev* __restrict__ jobs, int njobs,
+                                                      const JobStep* __restrict__ js,
+                                                      const int32_t* __restrict__ pre) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const JobStep S = js[jb];
+  const int gid = lb * 256 + threadIdx.x;
+  if (gid >= S.nct * 64) return;
+  const int tile = gid >> 6, wave = (gid >> 4) & 3, q = gid & 15;
+  const int bi = tile / S.nblk, bj = tile - bi * S.nblk;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int m = S.m;
+  const int ci = bi * kTileVars + wi * kWaveVars + (q >> 2);
+  const int pj = bj * kTileVars + wj * kWaveVars + (q & 3);
+  if (pj >= m) return;
+  const int pi = J.cand[ci];
+  double* out = J.rc + (int64_t)ci * J.d + pj;
+  if (pi == pj) {
+    *out = 0.0;
+    return;
+  }
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int sp = 0; sp < S.nsplit_c; ++sp) {
+    const double* src = J.partc + (((int64_t)sp * S.nct + tile) * 4 + wave) * 64 + q * 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] += src[c];
+  }
+  const double s1_bias = (double)S.nsplit_c * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+  const double inv_n = 1.0 / (double)J.n;
+  const int si = J.act[pi], sj = J.act[pj];
+  double r = J.rho[(int64_t)si * J.d + sj];
+  const double lim = 1.0 - kCollinear;
+  r = r > lim ? lim : (r < -lim ? -lim : r);
+  const double al = 1.0 / sqrt(1.0 - r * r);
+  const double h_ij = entropy_from_moments(kLn2 * (s[0] + s1_bias) * inv_n, al * s[1] * inv_n);
+  const double h_ji = entropy_from_moments(kLn2 * (s[2] + s1_bias) * inv_n, al * s[3] * inv_n);
+  *out = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
+}
+
+// kc[c] = sum_j min(0, R(c, j))^2, one wave per candidate.
+__global__ __launch_bounds__(256) void k_cand_rowk(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m;
+  const int lane = threadIdx.x & 63;
+  const int c = lb * 4 + (threadIdx.x >> 6);
+  if (c >= J.K) return;
+  const double* row = J.rc + (int64_t)c * J.d;
+  double k = 0.0;
+  for (int q = lane; q < m; q += 64) {
+    const double x = row[q];
+    const double ng = x < 0.0 ? x : 0.0;
+    k += ng * ng;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
+  if (lane == 0) J.kc[c] = k;
+}
+
+// lb[l] = sum_c max(0, R(c, l))^2 for non-candidate positions (a lower bound
+// of k_l, since R(l, c) = -R(c, l)); +inf at candidate positions.
+__global__ __launch_bounds__(256) void k_cand_colk(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre, int t) {
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m;
+  const int l = lb * 256 + threadIdx.x;
+  if (l >= m) return;
+  if (J.cmark[l] == t + 1) {
+    J.lb[l] = INFINITY;
+    return;
+  }
+  double s = 0.0;
+  for (int c = 0; c < J.K; ++c) {
+    const double x = J.rc[(int64_t)c * J.d + l];
+    const double ps = x > 0.0 ? x : 0.0;
+    s += ps * ps;
+  }
+  J.lb[l] = s;
+}
+
+// The learned decision of one job (one workgroup).  Best candidate by -k with
+// ties to the smaller original id; certified when min lb > its k; accepted
+// when certified or when its score leads every non-candidate's by at least
+// delta; audit steps (t % audit_every == 0) and rejected steps set ctrl->full
+// and leave the choice to the full step.  An accepted choice is committed
+// here exactly as the full selection commits its own.
+__global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs, int njobs,
+                                                 const JobStep* __restrict__ js,
+                                                 const int32_t* __restrict__ pre, int t) {
+  __shared__ Best sh[256];
+  __shared__ double shm[256];
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m, K = J.K;
+  const int tid = threadIdx.x;
+  Best b{-INFINITY, 0x7fffffff, -1, -INFINITY};
+  for (int c = tid; c < K; c += 256) {
+    double v = -J.kc[c];
+    if (v != v) v = -INFINITY;
+    const int p = J.cand[c];
+    const Best x{v, J.act[p], p, -INFINITY};
+    b = (b.pos < 0) ? x : merge(b, x);
+  }
+  double mn = INFINITY;
+  for (int l = tid; l < m; l += 256) {
+    const double v = J.lb[l];
+    mn = fmin(mn, v == v ? v : -INFINITY);  // NaN never certifies
+  }
+  sh[tid] = b;
+  shm[tid] = mn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      const Best o = sh[tid + off];
+      if (o.pos >= 0) sh[tid] = (sh[tid].pos < 0) ? o : merge(sh[tid], o);
+      shm[tid] = fmin(shm[tid], shm[tid + off]);
+    }
+    __syncthreads();
+  }
+  const Best best = sh[0];
+  const double kbest = -best.v;
+  const bool certified = shm[0] > kbest;
+  const float margin = J.score[best.pos] - J.ctrl->s_out;
+  const bool audit = J.audit_every > 0 && t % J.audit_every == 0;
+  const bool fallback = !certified && !(margin >= J.delta);
+  const bool forced = t < J.forced_len;  // teacher forcing is applied by the full step
+  const bool full = audit || fallback || forced;
+  if (J.measures) {
+    double* row = J.measures + (int64_t)t * J.d;
+    if (!full) {
+      for (int v = tid; v < J.d; v += 256) row[v] = NAN;
+      __syncthreads();
+      for (int c = tid; c < K; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
+    }
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  Ctrl* C = J.ctrl;
+  C->full = full ? 1 : 0;
+  C->learned_slot = best.slot;
+  C->n_learned += 1;
+  C->n_certified += certified ? 1 : 0;
+  C->n_audit += audit ? 1 : 0;
+  C->n_fallback += (fallback && !audit) ? 1 : 0;
+  if (J.steplog) J.steplog[t] = full ? (audit ? 3 : 2) : 1;
+  if (full) return;
+  int32_t* act = J.act;
+  J.order[t] = best.slot;
+  C->exo_slot = best.slot;
+  C->exo_pos = best.pos;
+  if (J.gaps) J.gaps[t] = best.v - best.v2;
+  act[best.pos] = act[m - 1];
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+
+// Forward pass over the training rows with saved activations.
+__global__ __launch_bounds__(256) void k_train_fwd(const PropDev* __restrict__ W,
+                                                   const float* __restrict__ feat, int64_t rows,
+                                                   float* __restrict__ score,
+                                                   uint16_t* __restrict__ H1,
+                                                   float* __restrict__ H2) {
+  __shared__ MlpShared S;
+  stage_w2(*W, S);
+  __syncthreads();
+  mlp_tile(*W, S, feat, (int64_t)blockIdx.x * 64, rows, score, H1, H2);
+}
+
+// Listwise softmax cross-entropy, one workgroup per list:
+// loss_L = logsumexp(s_L) - s_target, ds = (softmax - onehot) / n_lists.
+// A list outside [0, rows] or a target outside its list sets *status = 1 and
+// contributes nothing.
+__global__ __launch_bounds__(256) void k_list_ce(const float* __restrict__ score, int64_t rows,
+                                                 const int64_t* __restrict__ offsets,
+                                                 const int64_t* __restrict__ targets,
+                                                 int n_lists, float* __restrict__ ds,
+                                                 double* __restrict__ loss_part,
+                                                 int32_t* __restrict__ status) {
+  __shared__ double sh[256];
+  const int L = blockIdx.x;
+  const int64_t a = offsets[L], b = offsets[L + 1];
+  const int64_t tg = targets[L];
+  const int tid = threadIdx.x;
+  if (!(0 <= a && a <= b && b <= rows && a <= tg && tg < b)) {
+    if (tid == 0) {
+      *status = 1;
+      loss_part[L] = 0.0;
+    }
+    return;
+  }
+  double mx = -INFINITY;
+  for (int64_t r = a + tid; r < b; r += 256) mx = fmax(mx, (double)score[r]);
+  sh[tid] = mx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] = fmax(sh[tid], sh[tid + off]);
+    __syncthreads();
+  }
+  mx = sh[0];
+  __syncthreads();
+  double se = 0.0;
+  for (int64_t r = a + tid; r < b; r += 256) se += exp((double)score[r] - mx);
+  const double tot = block_sum_256(se, sh);
+  const double inv = 1.0 / (double)n_lists;
+  for (int64_t r = a + tid; r < b; r += 256) {
+    const double p = exp((double)score[r] - mx) / tot;
+    ds[r] = (float)((p - (r == tg ? 1.0 : 0.0)) * inv);
+  }
+  if (tid == 0) loss_part[L] = (mx + log(tot)) - (double)score[tg];
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, int64_t n, int32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+  if (i == 0 && status) *status = 0;
+}
+
+// LDS of the backward pass of one 64-row tile.
+struct BwdShared {
+  uint16_t w2t[kHidden][kLdW];  // W2^T[g][h] = W2[h][g]
+  uint16_t dh2t[kHidden][kLdR]; // dh2^T[h][i] (BF16)
+  uint16_t h1t[kHidden][kLdR];  // h1^T[g][i]
+  uint16_t dh1t[kHidden][kLdR]; // dh1^T[g][i]
+  uint16_t xt[kFeat][kLdR];     // x^T[f][i]
+  float ds[64];
+};
+
+// Backward pass.  Each workgroup walks 64-row tiles (grid stride) and keeps its
+// share of the weight gradients in registers (W2: wave w owns rows
+// 32 w .. 32 w + 31 of dW2; W1: wave w owns rows 32 w .. + 31 of dW1) and
+// the vector gradients in per-thread registers (thread h < 128), then writes
+// one partial gradient of kParams values per workgroup.
+__global__ __launch_bounds__(256) void k_train_bwd(const PropDev* __restrict__ W,
+                                                   const float* __restrict__ feat, int64_t rows,
+                                                   const float* __restrict__ dsv,
+                                                   const uint16_t* __restrict__ H1,
+                                                   const float* __restrict__ H2,
+                                                   float* __restrict__ part) {
+  __shared__ BwdShared S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg4 = (lane >> 4) * 4;
+  for (int i = tid; i < kHidden * kHidden; i += 256) {
+    const int h = i / kHidden, g = i % kHidden;
+    S.w2t[g][h] = W->w2[i];
+  }
+  f32x4_t gw2[2][8];
+  f32x4_t gw1[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    gw1[a] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) gw2[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  }
+  float g_w3 = 0.f, g_b2 = 0.f, g_b1 = 0.f, g_b3 = 0.f;
+  const int h_own = tid & (kHidden - 1);  // threads h and h + 128 split the rows
+  const int half = tid >> 7;
+  const float w3h = from_bf16(W->w3[h_own]);
+  const int64_t ntile = (rows + 63) / 64;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t row0 = tile * 64;
+    __syncthreads();
+    if (tid < 64) S.ds[tid] = row0 + tid < rows ? dsv[row0 + tid] : 0.f;
+    // x^T (BF16, normalized) and h1^T of the tile
+    for (int e = tid; e < 64 * kFeat; e += 256) {
+      const int i = e / kFeat, f = e % kFeat;
+      const int64_t row = row0 + i;
+      const float v = row < rows ? (feat[row * kFeat + f] - W->mu[f]) / W->sd[f] : 0.f;
+      S.xt[f][i] = to_bf16(v);
+    }
+    for (int e = tid; e < 64 * kHidden; e += 256) {
+      const int i = e / kHidden, g = e % kHidden;
+      const int64_t row = row0 + i;
+      S.h1t[g][i] = row < rows ? H1[row * kHidden + g] : (uint16_t)0;
+    }
+    __syncthreads();
+    // dh2 = ds * w3 * [h2 > 0]; vector gradients of w3, b2, b3
+    for (int i = half * 32; i < half * 32 + 32; ++i) {
+      const int64_t row = row0 + i;
+      float d = 0.f;
+      if (row < rows) {
+        const float h2 = H2[row * kHidden + h_own];
+        const float dsi = S.ds[i];
+        g_w3 = fmaf(dsi, h2, g_w3);
+        d = h2 > 0.f ? dsi * w3h : 0.f;
+        g_b2 += d;
+      }
+      S.dh2t[h_own][i] = to_bf16(d);
+    }
+    if (tid == 0)
+      for (int i = 0; i < 64; ++i) g_b3 += S.ds[i];
+    __syncthreads();
+    // dh1 = (dh2 W2) * [h1 > 0]: rows 16 wave .. + 15, all 128 columns
+#pragma unroll 1
+    for (int nt = 0; nt < kHidden / 16; ++nt) {
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < kHidden / 16; ++ks) {
+        // A[i][h] = dh2[i][h] = dh2t[h][i]; B[h][g] = W2[h][g] = w2t[g][h]
+        bf16x4_t a;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = (short)S.dh2t[ks * 16 + lg4 + j][wave * 16 + li];
+        const bf16x4_t b = load4(&S.w2t[nt * 16 + li][ks * 16 + lg4]);
+        acc = mfma16(a, b, acc);
+      }
+      const int g = nt * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wave * 16 + lg4 + r;
+        const float v = (S.h1t[g][i] & 0x7FFF) != 0 ? acc[r] : 0.f;  // h1 > 0 <=> a1 > 0
+        S.dh1t[g][i] = to_bf16(v);
+      }
+    }
+    __syncthreads();
+    // b1 from the BF16 dh1 (as the weight gradient sees it)
+    for (int i = half * 32; i < half * 32 + 32; ++i) g_b1 += from_bf16(S.dh1t[h_own][i]);
+    // dW2[h][g] += sum_i dh2[i][h] h1[i][g]: wave owns h = 32 wave .. + 31
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int h = wave * 32 + a * 16 + li;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x4_t A = load4(&S.dh2t[h][ks * 16 + lg4]);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const bf16x4_t B = load4(&S.h1t[b * 16 + li][ks * 16 + lg4]);
+          gw2[a][b] = mfma16(A, B, gw2[a][b]);
+        }
+      }
+      // dW1[h][f] += sum_i dh1[i][h] x[i][f]
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x4_t A = load4(&S.dh1t[h][ks * 16 + lg4]);
+        const bf16x4_t B = load4(&S.xt[li][ks * 16 + lg4]);
+        gw1[a] = mfma16(A, B, gw1[a]);
+      }
+    }
+  }
+  // partial gradient of this workgroup
+  float* out = part + (int64_t)blockIdx.x * kParams;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int h = wave * 32 + a * 16 + lg4 + r;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) out[kOffW2 + h * kHidden + b * 16 + li] = gw2[a][b][r];
+      out[kOffW1 + h * kFeat + li] = gw1[a][r];
+    }
+  }
+  // the two halves of the vector gradients
+  __shared__ float vec[3][256];
+  vec[0][tid] = g_w3;
+  vec[1][tid] = g_b2;
+  vec[2][tid] = g_b1;
+  __syncthreads();
+  if (tid < kHidden) {
+    out[kOffW3 + tid] = vec[0][tid] + vec[0][tid + 128];
+    out[kOffB2 + tid] = vec[1][tid] + vec[1][tid + 128];
+    out[kOffB1 + tid] = vec[2][tid] + vec[2][tid + 128];
+  }
+  if (tid == 0) out[kOffB3] = g_b3;
+}
+
+// grad[p] = sum over workgroups of the partials (fixed order); loss = mean.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part, int nparts,
+                                                     float* __restrict__ grad,
+                                                     const double* __restrict__ loss_part,
+                                                     int n_lists, float* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < kParams) {
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += (double)part[(int64_t)k * kParams + p];
+    grad[p] = (float)s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+    double s = 0.0;
+    for (int L = 0; L < n_lists; ++L) s += loss_part[L];
+    *loss = (float)(s / (double)n_lists);
+  }
+}
+
+// Adam on the FP32 master weights (after the 32 normalisation values).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ prop,
+                                              const float* __restrict__ grad,
+                                              float* __restrict__ mom1, float* __restrict__ mom2,
+                                              float lr, float beta1, float beta2, float eps,
+                                              float c1, float c2) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= kParams) return;
+  const float g = grad[p];
+  const float m1 = beta1 * mom1[p] + (1.f - beta1) * g;
+  const float m2 = beta2 * mom2[p] + (1.f - beta2) * g * g;
+  mom1[p] = m1;
+  mom2[p] = m2;
+  prop[kPropNorm + p] -= lr * (m1 * c1) / (sqrtf(m2 * c2) + eps);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline const int32_t* pre_kind(SchedDev sc, int njobs, int kind) {
+  return sc.pre + (int64_t)kind * (njobs + 1);
+}
+
+hipError_t launch_prop_prep(const float* in, PropDev* out, const JobDev* jobs, int njobs,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_prop_prep, dim3(1), dim3(256), 0, st, in, out, jobs, njobs,
+                     (int32_t*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_front(const JobDev* jobs, int njobs, int t, SchedDev sc,
+                                const int32_t* grid, hipStream_t st) {
+  const JobStep* js = sc.js;
+  if (grid[kKFeat] > 0)
+    hipLaunchKernelGGL(k_features, dim3((unsigned)grid[kKFeat]), dim3(256), 0, st, jobs, njobs,
+                       js, pre_kind(sc, njobs, kKFeat), t);
+  if (grid[kKMlp] <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_mlp, dim3((unsigned)grid[kKMlp]), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKMlp));
+  hipLaunchKernelGGL(k_topk, dim3((unsigned)grid[kKTopk]), dim3(1024), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKTopk), t);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+                            hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_cand, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKPairC), grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
+                               const int32_t* grid, hipStream_t st) {
+  const JobStep* js = sc.js;
+  if (grid[kKLsel] <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_cand, dim3((unsigned)grid[kKCombC]), dim3(256), 0, st, jobs,
+                     njobs, js, pre_kind(sc, njobs, kKCombC));
+  hipLaunchKernelGGL(k_cand_rowk, dim3((unsigned)grid[kKRowkC]), dim3(256), 0, st, jobs, njobs,
+                     js, pre_kind(sc, njobs, kKRowkC));
+  hipLaunchKernelGGL(k_cand_colk, dim3((unsigned)grid[kKColC]), dim3(256), 0, st, jobs, njobs,
+                     js, pre_kind(sc, njobs, kKColC), t);
+  hipLaunchKernelGGL(k_lselect, dim3((unsigned)grid[kKLsel]), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKLsel), t);
+  return hipGetLastError();
+}
+
+// Training workspace: [status][PropDev][score f32 rows][ds f32 rows][H1 u16 rows*128]
+// [H2 f32 rows*128][loss_part f64 n_lists][partials f32 nparts*kParams]
+TrainLayout make_train_layout(int64_t rows, int32_t n_lists) {
+  TrainLayout T{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~size_t(255);
+    return o;
+  };
+  T.rows = rows;
+  T.n_lists = n_lists;
+  const int64_t ntile = (rows + 63) / 64;
+  T.nparts = (int)(ntile < kTrainParts ? ntile : kTrainParts);
+  T.status = take(sizeof(int32_t));
+  T.prop = take(sizeof(PropDev));
+  T.score = take(sizeof(float) * (size_t)rows);
+  T.ds = take(sizeof(float) * (size_t)rows);
+  T.h1 = take(sizeof(uint16_t) * (size_t)rows * kHidden);
+  T.h2 = take(sizeof(float) * (size_t)rows * kHidden);
+  T.loss_part = take(sizeof(double) * (size_t)n_lists);
+  T.part = take(sizeof(float) * (size_t)T.nparts * kParams);
+  T.total = off;
+  return T;
+}
+
+hipError_t launch_scores(const float* prop, const float* feat, int64_t rows, float* score,
+                         char* ws, hipStream_t st) {
+  PropDev* W = reinterpret_cast<PropDev*>(ws);
+  hipLaunchKernelGGL(k_prop_prep, dim3(1), dim3(256), 0, st, prop, W, (const JobDev*)nullptr, 0,
+                     (int32_t*)nullptr);
+  const int64_t ntile = (rows + 63) / 64;
+  hipLaunchKernelGGL(k_train_fwd, dim3((unsigned)ntile), dim3(256), 0, st, (const PropDev*)W,
+                     feat, rows, score, (uint16_t*)nullptr, (float*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const TrainLayout& T, const float* prop, const float* feat,
+                       const int64_t* offsets, const int64_t* targets, float* grad,
+                       float* loss, float* score_out, char* ws, hipStream_t st) {
+  PropDev* W = reinterpret_cast<PropDev*>(ws + T.prop);
+  float* score = reinterpret_cast<float*>(ws + T.score);
+  float* ds = reinterpret_cast<float*>(ws + T.ds);
+  uint16_t* H1 = reinterpret_cast<uint16_t*>(ws + T.h1);
+  float* H2 = reinterpret_cast<float*>(ws + T.h2);
+  double* lp = reinterpret_cast<double*>(ws + T.loss_part);
+  float* part = reinterpret_cast<float*>(ws + T.part);
+  int32_t* status = reinterpret_cast<int32_t*>(ws + T.status);
+  hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((T.rows + 255) / 256)), dim3(256), 0, st, ds,
+                     T.rows, status);
+  hipLaunchKernelGGL(k_prop_prep, dim3(1), dim3(256), 0, st, prop, W, (const JobDev*)nullptr, 0,
+                     status);
+  const int64_t ntile = (T.rows + 63) / 64;
+  hipLaunchKernelGGL(k_train_fwd, dim3((unsigned)ntile), dim3(256), 0, st, (const PropDev*)W,
+                     feat, T.rows, score, H1, H2);
+  hipLaunchKernelGGL(k_list_ce, dim3((unsigned)T.n_lists), dim3(256), 0, st,
+                     (const float*)score, T.rows, offsets, targets, T.n_lists, ds, lp, status);
+  hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)T.nparts), dim3(256), 0, st, (const PropDev*)W,
+                     feat, T.rows, (const float*)ds, (const uint16_t*)H1, (const float*)H2,
+                     part);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((kParams + 255) / 256)), dim3(256), 0, st,
+                     (const float*)part, T.nparts, grad, (const double*)lp, T.n_lists, loss);
+  if (score_out)
+    return hipMemcpyAsync(score_out, score, sizeof(float) * (size_t)T.rows,
+                          hipMemcpyDeviceToDevice, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* prop, const float* grad, float* m1, float* m2, float lr,
+                       float beta1, float beta2, float eps, float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((kParams + 255) / 256)), dim3(256), 0, st, prop,
+                     grad, m1, m2, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace lg

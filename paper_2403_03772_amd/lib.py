@@ -8,6 +8,7 @@ non-OK status codes into :class:`LingamError`.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 from dataclasses import dataclass
@@ -17,6 +18,13 @@ LIB_PATH = os.path.join(HERE, "liblingam_mi355x.so")
 
 OK, E_INVALID, E_DEGENERATE, E_HIP, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 FLAG_NO_SYNC, FLAG_GRAPH, FLAG_AUTOTUNE = 1, 2, 4
+
+# proposer network (include/lingam.h)
+N_FEATURES = 16
+HIDDEN = 128
+N_PARAMS = 18817
+N_NORM = 32
+PROPOSER_SIZE = N_NORM + N_PARAMS
 
 _lock = threading.Lock()
 _lib = None
@@ -38,6 +46,20 @@ class _Profile(ctypes.Structure):
         ("gram_flops", ctypes.c_double),
         ("resid_ms", ctypes.c_double),
         ("resid_bytes", ctypes.c_double),
+        ("cand_ms", ctypes.c_double),
+        ("cand_launches", ctypes.c_int64),
+        ("cand_evals", ctypes.c_double),
+    ]
+
+
+class _LearnedStats(ctypes.Structure):
+    _fields_ = [
+        ("learned_steps", ctypes.c_int32),
+        ("certified", ctypes.c_int32),
+        ("fallbacks", ctypes.c_int32),
+        ("audits", ctypes.c_int32),
+        ("audit_agree", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -52,6 +74,13 @@ class _Opts(ctypes.Structure):
         ("step_gap", ctypes.c_void_p),
         ("dev_status", ctypes.c_void_p),
         ("profile", ctypes.POINTER(_Profile)),
+        ("proposer", ctypes.c_void_p),
+        ("topk", ctypes.c_int32),
+        ("audit_every", ctypes.c_int32),
+        ("margin", ctypes.c_float),
+        ("learned_min_m", ctypes.c_int32),
+        ("learned_stats", ctypes.POINTER(_LearnedStats)),
+        ("record_features", ctypes.c_void_p),
     ]
 
 
@@ -66,6 +95,7 @@ class _Job(ctypes.Structure):
         ("order", ctypes.c_void_p),
         ("step_measures", ctypes.c_void_p),
         ("step_gap", ctypes.c_void_p),
+        ("record_features", ctypes.c_void_p),
     ]
 
 
@@ -79,6 +109,29 @@ class Profile:
     gram_flops: float
     resid_ms: float
     resid_bytes: float
+    cand_ms: float
+    cand_launches: int
+    cand_evals: float
+
+
+@dataclass
+class LearnedStats:
+    learned_steps: int
+    certified: int
+    fallbacks: int
+    audits: int
+    audit_agree: int
+
+
+@dataclass
+class Learned:
+    """Learned-proposal configuration: ``proposer`` is a CUDA float32 tensor
+    of PROPOSER_SIZE values (feature mean, feature scale, network weights)."""
+    proposer: object
+    topk: int = 64
+    audit_every: int = 32
+    margin: float = 4.0
+    min_m: int | None = None
 
 
 def load():
@@ -92,27 +145,36 @@ def load():
                 f"{LIB_PATH} is missing: build it with `python -m paper_2403_03772_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)
         P, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
-        lib.lingam_opts_init.argtypes = [ctypes.POINTER(_Opts)]
+        f32 = ctypes.c_float
+        O = ctypes.POINTER(_Opts)
+        lib.lingam_opts_init.argtypes = [O]
         lib.lingam_opts_init.restype = None
-        lib.lingam_workspace_size.argtypes = [i64, i64, ctypes.POINTER(_Opts)]
+        lib.lingam_workspace_size.argtypes = [i64, i64, O]
         lib.lingam_workspace_size.restype = sz
-        lib.lingam_causal_order.argtypes = [P, i64, i64, i64, P, ctypes.POINTER(_Opts), P, sz, P]
+        lib.lingam_causal_order.argtypes = [P, i64, i64, i64, P, O, P, sz, P]
         lib.lingam_causal_order.restype = ctypes.c_int
         lib.lingam_residualize_workspace_size.argtypes = [i64, i64]
         lib.lingam_residualize_workspace_size.restype = sz
         lib.lingam_residualize.argtypes = [P, i64, i64, i64, P, i32, i32, P, sz, P]
         lib.lingam_residualize.restype = ctypes.c_int
-        lib.varlingam_workspace_size.argtypes = [i64, i64, i32, ctypes.POINTER(_Opts)]
+        lib.varlingam_workspace_size.argtypes = [i64, i64, i32, O]
         lib.varlingam_workspace_size.restype = sz
-        lib.varlingam_fit.argtypes = [P, i64, i64, i64, i32, P, P, P, P, ctypes.POINTER(_Opts),
-                                      P, sz, P]
+        lib.varlingam_fit.argtypes = [P, i64, i64, i64, i32, P, P, P, P, O, P, sz, P]
         lib.varlingam_fit.restype = ctypes.c_int
-        lib.lingam_batch_workspace_size.argtypes = [ctypes.POINTER(_Job), i32,
-                                                    ctypes.POINTER(_Opts)]
+        lib.lingam_batch_workspace_size.argtypes = [ctypes.POINTER(_Job), i32, O]
         lib.lingam_batch_workspace_size.restype = sz
-        lib.lingam_batch_causal_order.argtypes = [ctypes.POINTER(_Job), i32, P,
-                                                  ctypes.POINTER(_Opts), P, sz, P]
+        lib.lingam_batch_causal_order.argtypes = [ctypes.POINTER(_Job), i32, P, O, P, sz, P]
         lib.lingam_batch_causal_order.restype = ctypes.c_int
+        lib.lingam_proposer_scores_workspace_size.argtypes = []
+        lib.lingam_proposer_scores_workspace_size.restype = sz
+        lib.lingam_proposer_scores.argtypes = [P, P, i64, P, P, sz, P]
+        lib.lingam_proposer_scores.restype = ctypes.c_int
+        lib.lingam_proposer_grad_workspace_size.argtypes = [i64, i32]
+        lib.lingam_proposer_grad_workspace_size.restype = sz
+        lib.lingam_proposer_grad.argtypes = [P, P, i64, P, P, i32, P, P, P, P, sz, P]
+        lib.lingam_proposer_grad.restype = ctypes.c_int
+        lib.lingam_proposer_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
+        lib.lingam_proposer_adam.restype = ctypes.c_int
         lib.lingam_last_error.argtypes = []
         lib.lingam_last_error.restype = ctypes.c_char_p
         lib.lingam_version.argtypes = []
@@ -138,40 +200,20 @@ def _stream_ptr(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def workspace_size(n: int, d: int) -> int:
-    return int(load().lingam_workspace_size(int(n), int(d), None))
-
-
-def residualize_workspace_size(n: int, d: int) -> int:
-    return int(load().lingam_residualize_workspace_size(int(n), int(d)))
-
-
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool = False,
-                 workspace=None, sync: bool = True, graph: bool = False,
-                 autotune: bool = False):
-    """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
-
-    Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
-    or a dict with ``order``, ``measures`` ((d-1) x d FP64, NaN for columns
-    already ordered), ``gaps`` and ``profile`` when ``with_measures`` or
-    ``profile`` is set.  ``forced`` (sequence or tensor of column ids) fixes the
-    first ``len(forced)`` choices (teacher forcing).
-    """
-    import torch
-
-    lib = load()
+def _cuda_f32_matrix(torch, X, name="X"):
     if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
-        raise TypeError("X must be a CUDA float32 tensor")
+        raise TypeError(f"{name} must be a CUDA float32 tensor")
     if X.dim() != 2 or X.stride(1) != 1:
-        raise ValueError("X must be 2-D with unit column stride")
-    n, d = X.shape
-    ldx = X.stride(0) if n > 1 else d
-    dev = X.device
-    order = torch.empty(d, dtype=torch.int32, device=dev)
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+
+
+def _new_opts(lib, *, sync=True, graph=False, autotune=False, learned=None, profile=False,
+              keep=None):
+    """lingam_opts with flags, the learned configuration and the profile."""
     opts = _Opts()
     lib.lingam_opts_init(ctypes.byref(opts))
     if not sync:
@@ -180,34 +222,106 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
         opts.flags |= FLAG_GRAPH
     if autotune:
         opts.flags |= FLAG_AUTOTUNE
+    stats = None
+    if learned is not None:
+        import torch
+        p = learned.proposer
+        if not (isinstance(p, torch.Tensor) and p.is_cuda and p.dtype == torch.float32
+                and p.is_contiguous() and p.numel() == PROPOSER_SIZE):
+            raise TypeError(f"proposer must be a contiguous CUDA float32 tensor of "
+                            f"{PROPOSER_SIZE} values")
+        opts.proposer = p.data_ptr()
+        opts.topk = int(learned.topk)
+        opts.audit_every = int(learned.audit_every)
+        opts.margin = float(learned.margin)
+        opts.learned_min_m = int(learned.min_m if learned.min_m is not None
+                                 else max(2 * learned.topk, 64))
+        stats = _LearnedStats()
+        opts.learned_stats = ctypes.pointer(stats)
+        if keep is not None:
+            keep.append(stats)
+    prof = _Profile() if profile else None
+    if prof is not None:
+        opts.profile = ctypes.pointer(prof)
+    return opts, prof, stats
+
+
+def _profile_of(prof):
+    return Profile(**{k: getattr(prof, k) for k, _ in _Profile._fields_})
+
+
+def _stats_of(stats):
+    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_
+                           if k != "reserved"})
+
+
+def workspace_size(n: int, d: int, learned: Learned | None = None) -> int:
+    lib = load()
     keep = []
+    opts, _, _ = _new_opts(lib, learned=learned, keep=keep)
+    return int(lib.lingam_workspace_size(int(n), int(d), ctypes.byref(opts)))
+
+
+def residualize_workspace_size(n: int, d: int) -> int:
+    return int(load().lingam_residualize_workspace_size(int(n), int(d)))
+
+
+def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool = False,
+                 workspace=None, sync: bool = True, graph: bool = False,
+                 autotune: bool = False, learned: Learned | None = None,
+                 record_features: bool = False):
+    """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
+
+    Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
+    or a dict with ``order``, ``measures`` ((d-1) x d FP64, NaN for columns
+    already ordered), ``gaps``, ``profile``, ``features`` ((d-1) x d x 16
+    FP32, NaN where not recorded) and ``learned_stats`` when any of those is
+    asked for.  ``forced`` (sequence or tensor of column ids) fixes the first
+    ``len(forced)`` choices (teacher forcing).  ``learned`` switches on the
+    learned-proposal form.
+    """
+    import torch
+
+    lib = load()
+    _cuda_f32_matrix(torch, X)
+    n, d = X.shape
+    ldx = X.stride(0) if n > 1 else d
+    dev = X.device
+    order = torch.empty(d, dtype=torch.int32, device=dev)
+    keep = []
+    opts, prof, stats = _new_opts(lib, sync=sync, graph=graph, autotune=autotune,
+                                  learned=learned, profile=profile, keep=keep)
     if forced is not None:
         f = torch.as_tensor(forced, dtype=torch.int32).to(dev).contiguous()
         keep.append(f)
         opts.forced_order = f.data_ptr()
         opts.forced_len = f.numel()
-    meas = gaps = None
+    meas = gaps = feats = None
     if with_measures and d > 1:
         meas = torch.empty((d - 1, d), dtype=torch.float64, device=dev)
         gaps = torch.empty(d - 1, dtype=torch.float64, device=dev)
         opts.step_measures = meas.data_ptr()
         opts.step_gap = gaps.data_ptr()
-    prof = _Profile() if profile else None
-    if prof is not None:
-        opts.profile = ctypes.pointer(prof)
+    if record_features and d > 1:
+        feats = torch.full((d - 1, d, N_FEATURES), math.nan, dtype=torch.float32, device=dev)
+        opts.record_features = feats.data_ptr()
     need = int(lib.lingam_workspace_size(n, d, ctypes.byref(opts)))
     if need == 0:
-        raise LingamError(E_UNSUPPORTED, f"unsupported size n={n} d={d}")
+        raise LingamError(E_UNSUPPORTED, last_error() or f"unsupported size n={n} d={d}")
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
     code = lib.lingam_causal_order(_ptr(X), n, d, ldx, _ptr(order), ctypes.byref(opts),
                                    _ptr(workspace), workspace.numel(), _stream_ptr(torch, dev))
     _check(code)
-    if not (with_measures or profile):
+    if not (with_measures or profile or record_features or learned is not None):
         return order
-    out = {"order": order, "measures": meas, "gaps": gaps}
+    out = {"order": order, "measures": meas, "gaps": gaps, "workspace": workspace}
+    if feats is not None:
+        out["features"] = feats
     if prof is not None:
-        out["profile"] = Profile(**{k: getattr(prof, k) for k, _ in _Profile._fields_})
+        out["profile"] = _profile_of(prof)
+    if stats is not None and sync:
+        out["learned_stats"] = _stats_of(stats)
     return out
 
 
@@ -216,10 +330,7 @@ def residualize(X, active, exo: int):
     import torch
 
     lib = load()
-    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
-        raise TypeError("X must be a CUDA float32 tensor")
-    if X.dim() != 2 or X.stride(1) != 1:
-        raise ValueError("X must be 2-D with unit column stride")
+    _cuda_f32_matrix(torch, X)
     n, d = X.shape
     a = torch.as_tensor(active, dtype=torch.int32).to(X.device).contiguous()
     need = int(lib.lingam_residualize_workspace_size(n, d))
@@ -231,25 +342,21 @@ def residualize(X, active, exo: int):
 
 
 def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
-                  profile: bool = False):
+                  profile: bool = False, learned: Learned | None = None):
     """VarLiNGAM on a CUDA float32 series ``X`` (T x d, time in rows).
 
     Returns a dict: ``M`` (lags x d x d float64), ``resid`` ((T-lags) x d
     float32), ``order`` (int32), ``B0`` (d x d float64), plus ``measures`` /
-    ``gaps`` / ``profile`` when asked.
+    ``gaps`` / ``profile`` / ``learned_stats`` when asked.
     """
     import torch
 
     lib = load()
-    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
-        raise TypeError("X must be a CUDA float32 tensor")
-    if X.dim() != 2 or X.stride(1) != 1:
-        raise ValueError("X must be 2-D with unit column stride")
+    _cuda_f32_matrix(torch, X)
     T, d = X.shape
     dev = X.device
-    opts = _Opts()
-    lib.lingam_opts_init(ctypes.byref(opts))
     keep = []
+    opts, prof, stats = _new_opts(lib, learned=learned, profile=profile, keep=keep)
     if forced is not None:
         f = torch.as_tensor(forced, dtype=torch.int32).to(dev).contiguous()
         keep.append(f)
@@ -266,9 +373,6 @@ def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
         out["gaps"] = torch.empty(d - 1, dtype=torch.float64, device=dev)
         opts.step_measures = out["measures"].data_ptr()
         opts.step_gap = out["gaps"].data_ptr()
-    prof = _Profile() if profile else None
-    if prof is not None:
-        opts.profile = ctypes.pointer(prof)
     need = int(lib.varlingam_workspace_size(T, d, int(lags), ctypes.byref(opts)))
     if need == 0:
         raise LingamError(E_INVALID, f"unsupported size T={T} d={d} lags={lags}")
@@ -278,34 +382,35 @@ def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
                              ctypes.byref(opts), _ptr(ws), ws.numel(), _stream_ptr(torch, dev))
     _check(code)
     if prof is not None:
-        out["profile"] = Profile(**{k: getattr(prof, k) for k, _ in _Profile._fields_})
+        out["profile"] = _profile_of(prof)
+    if stats is not None:
+        out["learned_stats"] = _stats_of(stats)
     return out
 
 
 def batch_causal_order(jobs, *, graph: bool = False, autotune: bool = False,
                        profile: bool = False, workspace=None, with_measures: bool = False,
-                       raise_on_error: bool = True):
+                       raise_on_error: bool = True, learned: Learned | None = None,
+                       record_features: bool = False):
     """Causal orders of many jobs in one batched run.
 
     ``jobs``: sequence of dicts with ``X`` (CUDA float32, rows x d; jobs may
     share one tensor) and optionally ``rows`` (int32 CUDA tensor of row
     indices, bootstrap resampling) or ``n`` (use the first n rows).  Returns a
     dict with ``orders`` (list of int32 tensors), ``status`` (int32 tensor per
-    job), ``measures`` (list, when asked) and ``profile``.
+    job), ``measures`` / ``features`` (lists, when asked), ``profile`` and
+    ``learned_stats``.
     """
     import torch
 
     lib = load()
     njobs = len(jobs)
     arr = (_Job * njobs)()
-    orders, meas, keep = [], [], []
+    orders, meas, feats, keep = [], [], [], []
     dev = None
     for k, j in enumerate(jobs):
         X = j["X"]
-        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32):
-            raise TypeError("X must be a CUDA float32 tensor")
-        if X.dim() != 2 or X.stride(1) != 1:
-            raise ValueError("X must be 2-D with unit column stride")
+        _cuda_f32_matrix(torch, X)
         dev = X.device
         rows = j.get("rows")
         if rows is not None:
@@ -321,21 +426,17 @@ def batch_causal_order(jobs, *, graph: bool = False, autotune: bool = False,
         a.X, a.n_rows, a.ldx = X.data_ptr(), X.shape[0], X.stride(0)
         a.rows = rows.data_ptr() if rows is not None else None
         a.n, a.d, a.order = n, d, o.data_ptr()
+        m = f = None
         if with_measures and d > 1:
             m = torch.empty((d - 1, d), dtype=torch.float64, device=dev)
-            meas.append(m)
             a.step_measures = m.data_ptr()
-        else:
-            meas.append(None)
-    opts = _Opts()
-    lib.lingam_opts_init(ctypes.byref(opts))
-    if graph:
-        opts.flags |= FLAG_GRAPH
-    if autotune:
-        opts.flags |= FLAG_AUTOTUNE
-    prof = _Profile() if profile else None
-    if prof is not None:
-        opts.profile = ctypes.pointer(prof)
+        if record_features and d > 1:
+            f = torch.full((d - 1, d, N_FEATURES), math.nan, dtype=torch.float32, device=dev)
+            a.record_features = f.data_ptr()
+        meas.append(m)
+        feats.append(f)
+    opts, prof, stats = _new_opts(lib, graph=graph, autotune=autotune, learned=learned,
+                                  profile=profile, keep=keep)
     need = int(lib.lingam_batch_workspace_size(arr, njobs, ctypes.byref(opts)))
     if need == 0:
         raise LingamError(E_INVALID, last_error() or "invalid batch")
@@ -350,6 +451,90 @@ def batch_causal_order(jobs, *, graph: bool = False, autotune: bool = False,
     out = {"orders": orders, "status": status, "code": code, "workspace": workspace}
     if with_measures:
         out["measures"] = meas
+    if record_features:
+        out["features"] = feats
     if prof is not None:
-        out["profile"] = Profile(**{k: getattr(prof, k) for k, _ in _Profile._fields_})
+        out["profile"] = _profile_of(prof)
+    if stats is not None:
+        out["learned_stats"] = _stats_of(stats)
     return out
+
+
+# ---------------------------------------------------------------------------
+# the proposer network
+# ---------------------------------------------------------------------------
+
+def _check_features(torch, F):
+    if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float32
+            and F.is_contiguous() and F.dim() == 2 and F.shape[1] == N_FEATURES):
+        raise TypeError("features must be a contiguous CUDA float32 tensor of shape (rows, 16)")
+
+
+def _check_proposer(torch, p):
+    if not (isinstance(p, torch.Tensor) and p.is_cuda and p.dtype == torch.float32
+            and p.is_contiguous() and p.numel() == PROPOSER_SIZE):
+        raise TypeError(f"proposer must be a contiguous CUDA float32 tensor of "
+                        f"{PROPOSER_SIZE} values")
+
+
+def proposer_scores(proposer, features):
+    """Network scores of feature rows (CUDA float32 (rows, 16)) -> (rows,)."""
+    import torch
+
+    lib = load()
+    _check_proposer(torch, proposer)
+    _check_features(torch, features)
+    rows = features.shape[0]
+    dev = features.device
+    scores = torch.empty(rows, dtype=torch.float32, device=dev)
+    ws = torch.empty(int(lib.lingam_proposer_scores_workspace_size()), dtype=torch.uint8,
+                     device=dev)
+    _check(lib.lingam_proposer_scores(_ptr(proposer), _ptr(features), rows, _ptr(scores),
+                                      _ptr(ws), ws.numel(), _stream_ptr(torch, dev)))
+    return scores
+
+
+def proposer_grad(proposer, features, offsets, targets, *, workspace=None):
+    """Listwise softmax cross-entropy and its gradient.
+
+    ``offsets`` (int64, n_lists + 1) delimit the lists of feature rows,
+    ``targets`` (int64, n_lists) name each list's target row.  Returns
+    ``(loss, grad, scores, workspace)`` with ``grad`` of N_PARAMS values.
+    """
+    import torch
+
+    lib = load()
+    _check_proposer(torch, proposer)
+    _check_features(torch, features)
+    dev = features.device
+    rows = features.shape[0]
+    off = torch.as_tensor(offsets, dtype=torch.int64).to(dev).contiguous()
+    tg = torch.as_tensor(targets, dtype=torch.int64).to(dev).contiguous()
+    nl = tg.numel()
+    if off.numel() != nl + 1:
+        raise ValueError("offsets must have n_lists + 1 entries")
+    need = int(lib.lingam_proposer_grad_workspace_size(rows, nl))
+    if need == 0:
+        raise LingamError(E_INVALID, "empty training batch")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    grad = torch.empty(N_PARAMS, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    scores = torch.empty(rows, dtype=torch.float32, device=dev)
+    _check(lib.lingam_proposer_grad(_ptr(proposer), _ptr(features), rows, _ptr(off), _ptr(tg),
+                                    nl, _ptr(grad), _ptr(loss), _ptr(scores), _ptr(workspace),
+                                    workspace.numel(), _stream_ptr(torch, dev)))
+    return loss, grad, scores, workspace
+
+
+def proposer_adam(proposer, grad, m1, m2, step: int, lr: float = 1e-3, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step on the proposer's trainable values, in place."""
+    import torch
+
+    lib = load()
+    _check_proposer(torch, proposer)
+    _check(lib.lingam_proposer_adam(_ptr(proposer), _ptr(grad), _ptr(m1), _ptr(m2), int(step),
+                                    float(lr), float(beta1), float(beta2), float(eps),
+                                    _stream_ptr(torch, proposer.device)))
+    return proposer

@@ -145,3 +145,54 @@ def test_batch_argument_errors():
     o.forced_order = 1
     assert lib.lingam_batch_causal_order(J, 2, None, ctypes.byref(o), ctypes.c_void_p(1),
                                          1 << 30, None) == L.E_INVALID
+
+
+def test_learned_options_are_validated():
+    lib = pkg.load()
+    o = _opts()
+    assert o.topk == 64 and o.audit_every == 32 and o.learned_min_m == 128
+    o.proposer = 1
+    assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) > \
+        lib.lingam_workspace_size(1000, 300, None)
+    for field, bad in (("topk", 12), ("topk", 0), ("topk", 264), ("audit_every", -1),
+                       ("learned_min_m", 32)):
+        o = _opts()
+        o.proposer = 1
+        setattr(o, field, bad)
+        assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) == 0, field
+        assert _call(opts=o) == L.E_INVALID, field
+    o = _opts()
+    o.proposer = 1
+    o.margin = float("nan")
+    assert _call(opts=o) == L.E_INVALID
+
+
+def test_proposer_argument_errors():
+    lib = pkg.load()
+    P = ctypes.c_void_p(1)
+    assert lib.lingam_proposer_scores_workspace_size() >= 38016
+    assert lib.lingam_proposer_scores(None, P, 10, P, P, 1 << 20, None) == L.E_INVALID
+    assert lib.lingam_proposer_scores(P, P, 0, P, P, 1 << 20, None) == L.E_INVALID
+    assert lib.lingam_proposer_scores(P, P, 10, P, P, 16, None) == L.E_WORKSPACE
+    assert lib.lingam_proposer_grad_workspace_size(0, 1) == 0
+    assert lib.lingam_proposer_grad_workspace_size(100, 0) == 0
+    assert lib.lingam_proposer_grad_workspace_size(100, 3) > 0
+    assert lib.lingam_proposer_grad(P, P, 100, P, P, 0, P, None, None, P, 1 << 30,
+                                    None) == L.E_INVALID
+    assert lib.lingam_proposer_grad(P, P, 100, None, P, 3, P, None, None, P, 1 << 30,
+                                    None) == L.E_INVALID
+    assert lib.lingam_proposer_grad(P, P, 100, P, P, 3, P, None, None, P, 8,
+                                    None) == L.E_WORKSPACE
+    assert lib.lingam_proposer_adam(P, P, P, P, 0, 1e-3, 0.9, 0.999, 1e-8, None) == L.E_INVALID
+    assert lib.lingam_proposer_adam(P, P, P, P, 1, 1e-3, 1.0, 0.999, 1e-8, None) == L.E_INVALID
+    assert lib.lingam_proposer_adam(P, P, None, P, 1, 1e-3, 0.9, 0.999, 1e-8,
+                                    None) == L.E_INVALID
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the ABI structs have the sizes the library expects."""
+    o = _opts()
+    assert o.struct_size == ctypes.sizeof(L._Opts)
+    assert ctypes.sizeof(L._Profile) == 11 * 8
+    assert ctypes.sizeof(L._LearnedStats) == 24
+    assert ctypes.sizeof(L._Job) == 10 * 8

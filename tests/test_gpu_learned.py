@@ -1,0 +1,253 @@
+"""GPU learned-proposal form against the FP64 oracle, through the C ABI.
+
+* network scores (BF16 MFMA, FP32 accumulation) vs the oracle forward pass
+  with the same BF16 rounding points;
+* the training gradient vs the oracle's FP64 backward pass at the same
+  BF16-rounded weights and inputs (relative error per parameter block);
+* Adam vs the oracle's Adam;
+* the 16 features recorded during a plain search vs the oracle's features of
+  the residuals along the same order;
+* orderings: the exact mode (margin = +inf) and all-audit runs give the plain
+  order; the pure learned order (margin = -inf) equals the oracle's learned
+  order up to the first near-tie;
+* training on recorded plain orderings lowers the loss.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import proposer as OP
+from paper_2403_03772_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=dtype or np.float32)).cuda()
+
+
+def _proposer(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    norm = np.concatenate([rng.normal(scale=0.3, size=16), rng.uniform(0.5, 2.0, 16)])
+    return np.concatenate([norm, OP.init_params(seed) * scale])
+
+
+def test_scores_match_oracle(lib):
+    rng = np.random.default_rng(0)
+    prop = _proposer(1)
+    for rows in (1, 63, 64, 1000, 4099):
+        F = rng.normal(size=(rows, 16)).astype(np.float32)
+        print(f"scores rows={rows}", flush=True)
+        g = lib.proposer_scores(_t(prop), _t(F)).cpu().numpy().astype(np.float64)
+        ref, _ = OP.forward(prop[32:], OP.normalize(F, prop[:32]), emulate_bf16=True)
+        scale = max(1.0, np.max(np.abs(ref)))
+        assert np.max(np.abs(g - ref)) <= 2e-5 * scale, rows
+
+
+def _lists(rng, sizes):
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    tg = np.array([offs[L] + rng.integers(sizes[L]) for L in range(len(sizes))],
+                  dtype=np.int64)
+    return offs, tg
+
+
+def test_grad_matches_oracle(lib):
+    rng = np.random.default_rng(2)
+    prop = _proposer(3)
+    sizes = [int(x) for x in rng.integers(2, 300, 40)]
+    offs, tg = _lists(rng, sizes)
+    rows = int(offs[-1])
+    F = rng.normal(size=(rows, 16)).astype(np.float32)
+    print(f"grad rows={rows} lists={len(sizes)}", flush=True)
+    loss, grad, scores, _ = lib.proposer_grad(_t(prop), _t(F), _t(offs, np.int64),
+                                              _t(tg, np.int64))
+    g = grad.cpu().numpy().astype(np.float64)
+    # oracle at the BF16-rounded weights and inputs the kernels use
+    flat = prop[32:].copy()
+    p = OP.unpack(flat)
+    for k in ("W1", "W2", "w3"):
+        p[k] = OP.bf16(p[k])
+    flat_b = OP.pack(p)
+    s, cache = OP.forward(flat_b, OP.bf16(OP.normalize(F, prop[:32])), emulate_bf16=True)
+    ref_loss, ds = OP.listwise_ce(s.astype(np.float32).astype(np.float64), offs, tg)
+    ref = OP.backward(flat_b, cache, ds)
+    assert abs(float(loss.item()) - ref_loss) <= 1e-4 * max(1.0, abs(ref_loss))
+    o = 0
+    for name, shp in OP.SHAPES:
+        k = int(np.prod(shp))
+        a, b = g[o:o + k], ref[o:o + k]
+        o += k
+        if name == "b3":
+            # d loss / d b3 = sum of ds = 0 exactly (softmax gradients sum to
+            # zero over every list): only rounding remains
+            print(f"  b3: {a[0]:.2e} (exact 0)", flush=True)
+            assert abs(a[0]) <= 1e-6
+            continue
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        print(f"  {name}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-2, name
+
+
+def test_adam_matches_oracle(lib):
+    import torch
+    rng = np.random.default_rng(4)
+    prop = _proposer(5)
+    P = _t(prop)
+    m1 = torch.zeros(OP.N_PARAMS, device="cuda")
+    m2 = torch.zeros(OP.N_PARAMS, device="cuda")
+    opt = OP.Adam(lr=3e-3)
+    w = prop[32:].copy()
+    for step in range(1, 4):
+        g = rng.normal(size=OP.N_PARAMS).astype(np.float32)
+        lib.proposer_adam(P, _t(g), m1, m2, step, lr=3e-3)
+        w = opt.step(w, g.astype(np.float64))
+    got = P.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:32], prop[:32].astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(got[32:] - w)) <= 1e-6 * max(1.0, np.max(np.abs(w)))
+
+
+def test_features_match_oracle(lib):
+    s = synth.er_sem(40, 2000, indeg=2.0, noise_family=("uniform", "laplace", "exp"), seed=8)
+    X32 = s.X.astype(np.float32)
+    out = lib.causal_order(_t(X32), record_features=True)
+    order = out["order"].cpu().numpy()
+    feats = out["features"].cpu().numpy()
+    Xc = X32.astype(np.float64)
+    U = list(range(40))
+    for t in range(39):
+        if t in (0, 1, 5, 20, 37):
+            F = OP.features(Xc, U, t, 40)
+            G = feats[t][U].astype(np.float64)
+            cont = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 13, 14, 15]
+            err = np.abs(G[:, cont] - F[:, cont]) / np.maximum(np.abs(F[:, cont]), 1e-3)
+            assert np.max(err) <= 1e-5, (t, np.unravel_index(np.argmax(err), err.shape))
+            assert np.array_equal(G[:, 10], F[:, 10].astype(np.float32)), t
+            assert np.array_equal(G[:, 11], F[:, 11].astype(np.float32)), t
+            inactive = np.setdiff1d(np.arange(40), U)
+            assert np.all(np.isnan(feats[t][inactive]))
+        Xc = oracle.residualize(Xc, U, int(order[t]))
+        U.remove(int(order[t]))
+
+
+def _sem(d, n, seed):
+    return synth.er_sem(d, n, indeg=3.0, noise_family=("uniform", "laplace", "exp"), seed=seed)
+
+
+def test_exact_mode_and_audits_give_plain_order(lib):
+    s = _sem(180, 3000, 11)
+    X = _t(s.X)
+    plain = lib.causal_order(X, with_measures=True)
+    po = plain["order"].cpu().numpy()
+    P = _t(_proposer(6))
+    for margin, audit in ((np.inf, 0), (-np.inf, 1)):
+        print(f"learned margin={margin} audit={audit}", flush=True)
+        out = lib.causal_order(X, learned=lib.Learned(P, topk=16, audit_every=audit,
+                                                      margin=float(margin), min_m=64))
+        lo = out["order"].cpu().numpy()
+        st = out["learned_stats"]
+        assert st.learned_steps == 180 - 64
+        if audit == 1:
+            assert st.audits == st.learned_steps
+        diff = np.flatnonzero(lo != po)
+        if diff.size:
+            t = int(diff[0])
+            mv = plain["measures"].cpu().numpy()[t]
+            a, b = mv[po[t]], mv[lo[t]]
+            assert abs(a - b) <= 2e-4 * max(abs(a), 1e-3 * np.nanmax(np.abs(mv))), (t, a, b)
+
+
+def _oracle_step(X32, prefix, prop, K):
+    """Oracle scores and exact k at the state after `prefix`."""
+    Xc = X32.astype(np.float64)
+    U = list(range(X32.shape[1]))
+    for e in prefix:
+        Xc = oracle.residualize(Xc, U, int(e))
+        U.remove(int(e))
+    F = OP.features(Xc, U, len(prefix), X32.shape[1])
+    s, _ = OP.forward(prop[32:], OP.normalize(F, prop[:32]), emulate_bf16=True)
+    D = oracle.pair_matrix(Xc, U)
+    k = np.sum(np.minimum(D, 0) ** 2, axis=1)
+    return np.array(U), s.astype(np.float32).astype(np.float64), k
+
+
+def test_pure_learned_order_matches_oracle(lib):
+    d, n, K = 110, 1500, 8
+    s = _sem(d, n, 12)
+    X32 = s.X.astype(np.float32)
+    prop = _proposer(7)
+    out = lib.causal_order(_t(X32), learned=lib.Learned(_t(prop), topk=K, audit_every=0,
+                                                        margin=-np.inf, min_m=64))
+    go = out["order"].cpu().numpy()
+    assert out["learned_stats"].fallbacks == 0 and out["learned_stats"].audits == 0
+    ro, info = OP.learned_order(X32, prop, K=K, delta=-np.inf, audit_every=0, min_m=64)
+    diff = np.flatnonzero(go != ro)
+    if diff.size == 0:
+        return
+    t = int(diff[0])
+    U, sc, k = _oracle_step(X32, ro[:t], prop, K)
+    srt = np.sort(sc)[::-1]
+    boundary_tie = abs(srt[K - 1] - srt[K]) <= 1e-4 * max(1.0, np.max(np.abs(sc)))
+    pa, pb = np.flatnonzero(U == ro[t])[0], np.flatnonzero(U == go[t])[0]
+    k_tie = abs(k[pa] - k[pb]) <= 2e-4 * max(k[pa], k[pb], 1e-12)
+    assert boundary_tie or k_tie, (t, ro[t], go[t], k[pa], k[pb])
+
+
+def test_batch_learned_equals_single(lib):
+    P = _t(_proposer(8))
+    cfg = lib.Learned(P, topk=8, audit_every=8, margin=1.0, min_m=64)
+    Xs = [_sem(d, n, 30 + d) .X for d, n in ((100, 800), (150, 1200), (70, 600), (30, 500))]
+    out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], learned=cfg)
+    for k, X in enumerate(Xs):
+        single = lib.causal_order(_t(X), learned=cfg)["order"].cpu().numpy()
+        assert np.array_equal(out["orders"][k].cpu().numpy(), single), k
+
+
+def test_bad_proposer_and_lists_rejected(lib):
+    import torch
+    prop = _proposer(9)
+    bad = prop.copy()
+    bad[40] = np.nan
+    X = _t(_sem(100, 500, 1).X)
+    with pytest.raises(lib.LingamError) as e:
+        lib.causal_order(X, learned=lib.Learned(_t(bad), topk=8, min_m=64))
+    assert e.value.code == -1
+    F = _t(np.zeros((10, 16)))
+    with pytest.raises(lib.LingamError):
+        lib.proposer_grad(_t(prop), F, np.array([0, 5, 12]), np.array([1, 6]))
+    with pytest.raises(lib.LingamError):
+        lib.proposer_grad(_t(prop), F, np.array([0, 5, 10]), np.array([1, 3]))
+    # a good call after the rejected ones
+    loss, g, _, _ = lib.proposer_grad(_t(prop), F, np.array([0, 5, 10]), np.array([1, 6]))
+    assert np.isfinite(loss.item()) and torch.isfinite(g).all()
+
+
+def test_training_lowers_loss(lib):
+    """A few Adam steps on lists recorded from plain orderings."""
+    import torch
+    feats, offs, tgs = [], [0], []
+    for seed in range(6):
+        s = _sem(120, 1500, 100 + seed)
+        out = lib.causal_order(_t(s.X), record_features=True)
+        order = out["order"].cpu().numpy()
+        R = out["features"].cpu().numpy()
+        for t in range(0, 100, 5):
+            act = np.flatnonzero(~np.isnan(R[t, :, 0]))
+            feats.append(R[t, act])
+            tgs.append(offs[-1] + int(np.flatnonzero(act == order[t])[0]))
+            offs.append(offs[-1] + act.size)
+    F = np.concatenate(feats).astype(np.float32)
+    mu, sd = F.mean(axis=0), F.std(axis=0) + 1e-3
+    prop = np.concatenate([mu, sd, OP.init_params(0)]).astype(np.float32)
+    P = _t(prop)
+    Ft = _t(F)
+    m1 = torch.zeros(OP.N_PARAMS, device="cuda")
+    m2 = torch.zeros(OP.N_PARAMS, device="cuda")
+    ws = None
+    losses = []
+    for step in range(1, 61):
+        loss, g, _, ws = lib.proposer_grad(P, Ft, np.array(offs), np.array(tgs), workspace=ws)
+        losses.append(float(loss.item()))
+        lib.proposer_adam(P, g, m1, m2, step, lr=3e-3)
+    print("loss", losses[0], "->", losses[-1], flush=True)
+    assert losses[-1] < 0.8 * losses[0]
