@@ -245,7 +245,7 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
     bi = tile / S.nblk;
     bj = tile - bi * S.nblk;
   } else {
-    decode_tile(tile, S.nblk, bi, bj);
+    decode_tile_st(tile, S.nblk, bi, bj);
   }
   const int wi = wave >> 1, wj = wave & 1;
   if (!kCand && bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)

@@ -199,6 +199,48 @@ enum SetupKind : int {
 
 __host__ __device__ inline int32_t cdiv(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
 
+// Tile order of the all-pairs kernel: the upper triangle of nb x nb blocks
+// (bi <= bj) is walked in super-blocks of kSuperTile x kSuperTile blocks --
+// super-rows in order; in each, the diagonal triangle, then the full-height
+// blocks to its right -- so the tiles that run at the same time on one XCD
+// read few distinct rows.  Bijective from [0, nb (nb + 1) / 2).
+constexpr int kSuperTile = 8;
+__host__ __device__ inline void decode_tile_st(int tile, int nb, int& bi, int& bj) {
+  constexpr int64_t S = kSuperTile;
+  const int ns = (nb + kSuperTile - 1) / kSuperTile;
+  // tiles before full super-row q: q S (S + 1) / 2 + S (q nb - S q (q + 1) / 2)
+  auto pre = [nb](int64_t q) -> int64_t {
+    return q * S * (S + 1) / 2 + S * (q * nb - S * q * (q + 1) / 2);
+  };
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre(mid) <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t r0 = (int64_t)lo * S;
+  const int64_t h = (int64_t)nb - r0 < S ? (int64_t)nb - r0 : S;
+  int64_t r = tile - pre(lo);
+  const int64_t diag = h * (h + 1) / 2;
+  if (r < diag) {
+    int a = 0;
+    while (r >= h - a) {
+      r -= h - a;
+      ++a;
+    }
+    bi = (int)(r0 + a);
+    bj = (int)(r0 + a + r);
+    return;
+  }
+  r -= diag;
+  const int64_t blk = r / (h * S);
+  const int64_t rem = r - blk * h * S;
+  const int64_t c0 = r0 + S * (blk + 1);
+  const int64_t w = (int64_t)nb - c0 < S ? (int64_t)nb - c0 : S;
+  bi = (int)(r0 + rem / w);
+  bj = (int)(c0 + rem % w);
+}
+
 // The step's plan for a job without the split (needs the batch-wide sum).
 // K > 0 and m > min_m: learned pass; rec: features are recorded every step.
 __host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t, int32_t K = 0,

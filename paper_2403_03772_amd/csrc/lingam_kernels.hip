@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_combine(const JobDev* __restrict__ jobs
   if (gid >= S.ntiles * 64) return;
   const int tile = gid >> 6, wave = (gid >> 4) & 3, q = gid & 15;
   int bi, bj;
-  decode_tile(tile, S.nblk, bi, bj);
+  decode_tile_st(tile, S.nblk, bi, bj);
   const int wi = wave >> 1, wj = wave & 1;
   const int m = S.m;
   const int pi = bi * kTileVars + wi * kWaveVars + (q >> 2);

@@ -30,33 +30,49 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "proposer_weights.npz")
 
 
+def _gen(spec):
+    d, n, seed = spec
+    s = synth.er_sem(d, n, indeg=4.0, wlo=0.5, whi=2.0,
+                     noise_family=("uniform", "laplace", "exp"), seed=seed)
+    return s.X.astype(np.float32)
+
+
 def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n: int = 4096,
             steps_per_sem: int = 32, m_floor: int = 64, seed: int = 0, batch: int = 16,
-            log=print):
+            workers: int = 8, log=print):
     """Training lists from plain GPU orderings of ``n_sems`` SEMs (d ~ U[d_lo,
     d_hi], gene-expression-scale family, n samples).  At up to
     ``steps_per_sem`` steps with at least ``m_floor`` active variables, a list
     holds the features of the active variables; its target is the plain
-    choice.  Returns (features float32 [rows, 16], offsets int64, targets
+    choice.  SEMs are drawn by a pool of ``workers`` processes ahead of the
+    GPU.  Returns (features float32 [rows, 16], offsets int64, targets
     int64)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
     import torch
 
     rng = np.random.default_rng(seed)
-    fam = ("uniform", "laplace", "exp")
+    specs = [(int(rng.integers(d_lo, d_hi + 1)), n, int(rng.integers(1 << 31)))
+             for _ in range(n_sems)]
     feats, offs, tgs = [], [0], []
     done = 0
     t0 = time.time()
+    pool = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+    futs = [pool.submit(_gen, sp) for sp in specs[:2 * batch]]
+    nxt = len(futs)
     while done < n_sems:
         cnt = min(batch, n_sems - done)
-        sems = []
+        Xs = [futs[done + k].result() for k in range(cnt)]
         for _ in range(cnt):
-            d = int(rng.integers(d_lo, d_hi + 1))
-            sems.append(synth.er_sem(d, n, indeg=4.0, wlo=0.5, whi=2.0, noise_family=fam,
-                                     seed=int(rng.integers(1 << 31))))
-        jobs = [{"X": torch.as_tensor(s.X.astype(np.float32), device="cuda")} for s in sems]
+            if nxt < n_sems:
+                futs.append(pool.submit(_gen, specs[nxt]))
+                nxt += 1
+        jobs = [{"X": torch.as_tensor(X, device="cuda")} for X in Xs]
         out = L.batch_causal_order(jobs, record_features=True)
-        for k, s in enumerate(sems):
-            d = s.X.shape[1]
+        for k, X in enumerate(Xs):
+            d = X.shape[1]
+            futs[done + k] = None
             order = out["orders"][k].cpu().numpy()
             R = out["features"][k]
             last = d - m_floor  # steps t <= last have m >= m_floor
@@ -73,6 +89,7 @@ def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n: int = 4096,
         del out, jobs
         log(f"collect: {done}/{n_sems} SEMs, {len(tgs)} lists, {offs[-1]} rows, "
             f"{time.time() - t0:.0f} s")
+    pool.shutdown()
     return (np.concatenate(feats).astype(np.float32), np.asarray(offs, np.int64),
             np.asarray(tgs, np.int64))
 
@@ -111,7 +128,6 @@ def train(F, offs, tgs, *, epochs: int = 20, lr: float = 2e-3, lists_per_batch: 
     prop = np.concatenate([normalization(F), init_weights(seed)])
     P = torch.as_tensor(prop, device="cuda")
     Fd = torch.as_tensor(F, device="cuda")
-    offs_d = torch.as_tensor(offs, device="cuda")
     m1 = torch.zeros(L.N_PARAMS, device="cuda")
     m2 = torch.zeros(L.N_PARAMS, device="cuda")
     sizes = np.diff(offs)
@@ -185,11 +201,13 @@ def main(argv=None) -> int:
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--holdout", type=float, default=0.1)
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", default=WEIGHTS)
     a = ap.parse_args(argv)
     log = lambda msg: print(msg, flush=True)  # noqa: E731
     t0 = time.time()
-    F, offs, tgs = collect(a.sems, a.d_lo, a.d_hi, a.n, a.steps_per_sem, seed=a.seed, log=log)
+    F, offs, tgs = collect(a.sems, a.d_lo, a.d_hi, a.n, a.steps_per_sem, seed=a.seed,
+                           workers=a.workers, log=log)
     nl = len(tgs)
     nh = int(nl * a.holdout)
     # hold out the last lists (whole SEMs, since lists are in SEM order)
