@@ -151,9 +151,10 @@ def run_learned(lg, X, n, d, steps, warmup, proposer, plain_order, plain_ms):
     torch.cuda.synchronize()
     cand_ms = cand_evals = pair_ms = pair_evals = 0.0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         out = lg.causal_order(X, learned=cfg, workspace=ws, profile=True)
         p = out["profile"]
+        progress(f"learned ordering {i + 1}/{steps}: {p.total_ms:.0f} ms")
         cand_ms += p.cand_ms
         cand_evals += p.cand_evals
         pair_ms += p.pair_ms
@@ -184,6 +185,10 @@ def run_learned(lg, X, n, d, steps, warmup, proposer, plain_order, plain_ms):
     }
 
 
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_plain(lg, X, n, d, steps, warmup):
     import torch
 
@@ -196,12 +201,13 @@ def run_plain(lg, X, n, d, steps, warmup):
                resid_ms=0.0, resid_bytes=0.0)
     orders = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         out = lg.causal_order(X, workspace=ws, profile=True)
         p = out["profile"]
         for k in acc:
             acc[k] += getattr(p, k)
         orders.append(out["order"])
+        progress(f"plain ordering {i + 1}/{steps}: {p.total_ms:.0f} ms")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     o0 = orders[0].cpu().numpy()
@@ -242,6 +248,8 @@ def main() -> int:
     from paper_2403_03772_amd import train_proposer as tp
 
     d, n = (1024, 8192) if args.workload == "gene" else (4096, 16384)
+    if args.workload == "large" and args.steps == 3 and args.warmup == 1:
+        args.steps, args.warmup = 1, 0  # one plain ordering takes about two minutes
     sem = synth.workload_gene_scale(seed=args.seed, d=d, n=n)
     X32 = np.ascontiguousarray(sem.X, dtype=np.float32)
     X = torch.as_tensor(X32, device="cuda:0")

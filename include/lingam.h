@@ -89,7 +89,9 @@ typedef struct lingam_learned_stats {
   int32_t fallbacks;      /* ... decided by the full step because the margin was small */
   int32_t audits;         /* ... decided by the full step as audits */
   int32_t audit_agree;    /* audits whose full choice equalled the learned choice */
-  int32_t reserved;
+  int32_t suspects_max;   /* most non-candidates in one step whose lower bound did not
+                             exceed the best candidate's k (0 = certified) */
+  int64_t suspects_sum;   /* ... summed over learned steps */
 } lingam_learned_stats;
 
 /* The proposer network.  A proposer block is LINGAM_PROPOSER_SIZE FP32 values

@@ -519,6 +519,8 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
       ls->fallbacks += c.n_fallback;
       ls->audits += c.n_audit;
       ls->audit_agree += c.n_audit_agree;
+      ls->suspects_max = std::max(ls->suspects_max, c.n_suspects_max);
+      ls->suspects_sum += c.n_suspects_sum;
     }
   }
   if (pf.tm.on && opts->profile) {

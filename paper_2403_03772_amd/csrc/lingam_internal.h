@@ -71,8 +71,11 @@ struct Ctrl {
   int32_t n_audit;       // audit steps
   int32_t n_audit_agree; // audits whose full choice equalled the learned one
   float s_out;           // best score outside the candidates (this step)
-  int32_t pad[53];
+  int32_t n_suspects_max;  // largest count of non-candidates whose bound <= k_best
+  long long n_suspects_sum;
+  int32_t pad[50];
 };
+static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 
 // Byte offsets of one job's workspace regions.
 struct Layout {
@@ -180,8 +183,8 @@ enum Kind : int {
   kKTopk,       // k_topk: 1
   kKPairC,      // k_pair_cand: nct * 2 * nsplit_c
   kKCombC,      // k_combine_cand: ceil(nct / 4)
-  kKRowkC,      // k_candk rows: K / 4
-  kKColC,       // k_candk columns: ceil(m / 256)
+  kKRowkC,      // k_cand_rowk: K / 4
+  kKColC,       // k_cand_colk: ceil(m / 64)
   kKLsel,       // k_lselect: 1
   kNumKinds
 };
@@ -302,7 +305,7 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind, int32_
     case kKPairC: return s.learned ? s.nct * 2 * s.nsplit_c : 0;
     case kKCombC: return s.learned ? cdiv(s.nct, 4) : 0;
     case kKRowkC: return s.learned ? cdiv(K, 4) : 0;
-    case kKColC: return s.learned ? cdiv(s.m, 256) : 0;
+    case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
     default: return 0;
   }

@@ -59,10 +59,65 @@ __global__ __launch_bounds__(1024) void k_setup_schedule(const JobDev* __restric
         spre + (int64_t)kind * (njobs + 1), sh);
 }
 
+// Exclusive prefix sums of one value per lane over the first `count` lanes
+// of a wave (inclusive in the return value's last lane).
+__device__ inline int32_t wave_excl_scan(int32_t v, int32_t& total) {
+  const int lane = threadIdx.x & 63;
+  int32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
+  }
+  total = __shfl(incl, 63);
+  return incl - v;
+}
+
+// Schedule of a batch of at most 64 jobs: one wave, lane j plans job j, no
+// barriers.  Same arithmetic as the block path below.
+__device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, int t,
+                                   int num_cu, Tune tu, JobStep* __restrict__ js,
+                                   int32_t* __restrict__ pre) {
+  const int lane = threadIdx.x & 63;
+  JobStep s{};
+  long long mine = 0, mine_c = 0;
+  int K = 0;
+  if (lane < njobs) {
+    const JobDev& J = jobs[lane];
+    K = J.K;
+    s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
+    if (s.m >= 2 && !s.fp64) mine = 2LL * s.ntiles;
+    if (s.learned) mine_c = 2LL * s.nct;
+  }
+  long long items = mine, items_c = mine_c;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    items += __shfl_xor(items, off);
+    items_c += __shfl_xor(items_c, off);
+  }
+  if (lane < njobs) {
+    job_split(s, jobs[lane].n_pad, items, num_cu, tu);
+    job_split_cand(s, jobs[lane].n_pad, items_c, num_cu, tu);
+    js[lane] = s;
+  }
+  for (int kind = 0; kind < kNumKinds; ++kind) {
+    const int32_t c = lane < njobs ? kind_count(s, kind, K) : 0;
+    int32_t total;
+    const int32_t ex = wave_excl_scan(c, total);
+    int32_t* out = pre + (int64_t)kind * (njobs + 1);
+    if (lane < njobs) out[lane] = ex;
+    if (lane == 0) out[njobs] = total;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict__ jobs,
                                                         int njobs, int t, int num_cu, Tune tu,
                                                         JobStep* __restrict__ js,
                                                         int32_t* __restrict__ pre) {
+  if (njobs <= 64) {  // uniform over the block
+    if (threadIdx.x < 64) step_schedule_wave(jobs, njobs, t, num_cu, tu, js, pre);
+    return;
+  }
   __shared__ int32_t sh[1024];
   __shared__ long long items;
   const int tid = threadIdx.x;
@@ -102,6 +157,28 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
 __global__ __launch_bounds__(1024) void k_gate_schedule(const JobDev* __restrict__ jobs,
                                                         int njobs, JobStep* __restrict__ js,
                                                         int32_t* __restrict__ pre) {
+  if (njobs <= 64) {  // one wave, no barriers
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    JobStep s{};
+    int K = 0;
+    if (lane < njobs) {
+      s = js[lane];
+      s.gate = s.learned && jobs[lane].ctrl->full == 0;
+      js[lane] = s;
+      K = jobs[lane].K;
+    }
+    for (int kind = 0; kind < kNumKinds; ++kind) {
+      if (!gated_kind(kind)) continue;
+      const int32_t c = lane < njobs ? kind_count(s, kind, K) : 0;
+      int32_t total;
+      const int32_t ex = wave_excl_scan(c, total);
+      int32_t* out = pre + (int64_t)kind * (njobs + 1);
+      if (lane < njobs) out[lane] = ex;
+      if (lane == 0) out[njobs] = total;
+    }
+    return;
+  }
   __shared__ int32_t sh[1024];
   for (int j = threadIdx.x; j < njobs; j += 1024) {
     JobStep s = js[j];

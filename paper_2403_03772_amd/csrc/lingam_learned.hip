@@ -495,27 +495,31 @@ __global__ __launch_bounds__(256) void k_cand_rowk(const JobDev* __restrict__ jo
 }
 
 // lb[l] = sum_c max(0, R(c, l))^2 for non-candidate positions (a lower bound
-// of k_l, since R(l, c) = -R(c, l)); +inf at candidate positions.
+// of k_l, since R(l, c) = -R(c, l)); +inf at candidate positions.  A
+// workgroup covers 64 positions; wave w sums candidates c = w, w + 4, ...,
+// and the four partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_cand_colk(const JobDev* __restrict__ jobs, int njobs,
                                                    const JobStep* __restrict__ js,
                                                    const int32_t* __restrict__ pre, int t) {
+  __shared__ double part[4][64];
   int jb, lb;
   if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
   const JobDev& J = jobs[jb];
   const int m = js[jb].m;
-  const int l = lb * 256 + threadIdx.x;
-  if (l >= m) return;
-  if (J.cmark[l] == t + 1) {
-    J.lb[l] = INFINITY;
-    return;
-  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l = lb * 64 + lane;
   double s = 0.0;
-  for (int c = 0; c < J.K; ++c) {
-    const double x = J.rc[(int64_t)c * J.d + l];
-    const double ps = x > 0.0 ? x : 0.0;
-    s += ps * ps;
-  }
-  J.lb[l] = s;
+  if (l < m)
+    for (int c = wave; c < J.K; c += 4) {
+      const double x = J.rc[(int64_t)c * J.d + l];
+      const double ps = x > 0.0 ? x : 0.0;
+      s += ps * ps;
+    }
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && l < m)
+    J.lb[l] = J.cmark[l] == t + 1 ? INFINITY
+                                  : ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // The learned decision of one job (one workgroup).  Best candidate by -k with
@@ -528,7 +532,6 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
                                                  const JobStep* __restrict__ js,
                                                  const int32_t* __restrict__ pre, int t) {
   __shared__ Best sh[256];
-  __shared__ double shm[256];
   int jb, lb;
   if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
   const JobDev& J = jobs[jb];
@@ -542,25 +545,32 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
     const Best x{v, J.act[p], p, -INFINITY};
     b = (b.pos < 0) ? x : merge(b, x);
   }
-  double mn = INFINITY;
-  for (int l = tid; l < m; l += 256) {
-    const double v = J.lb[l];
-    mn = fmin(mn, v == v ? v : -INFINITY);  // NaN never certifies
-  }
   sh[tid] = b;
-  shm[tid] = mn;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (tid < off) {
       const Best o = sh[tid + off];
       if (o.pos >= 0) sh[tid] = (sh[tid].pos < 0) ? o : merge(sh[tid], o);
-      shm[tid] = fmin(shm[tid], shm[tid + off]);
     }
     __syncthreads();
   }
   const Best best = sh[0];
   const double kbest = -best.v;
-  const bool certified = shm[0] > kbest;
+  // non-candidates whose lower bound does not exceed k_best could still win
+  int nsus = 0;
+  for (int l = tid; l < m; l += 256) {
+    const double v = J.lb[l];
+    nsus += (v == v && v > kbest) ? 0 : 1;  // NaN bounds count as suspects
+  }
+  __shared__ int shs[256];
+  shs[tid] = nsus;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) shs[tid] += shs[tid + off];
+    __syncthreads();
+  }
+  nsus = shs[0];
+  const bool certified = nsus == 0;
   const float margin = J.score[best.pos] - J.ctrl->s_out;
   const bool audit = J.audit_every > 0 && t % J.audit_every == 0;
   const bool fallback = !certified && !(margin >= J.delta);
@@ -583,6 +593,8 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
   C->n_certified += certified ? 1 : 0;
   C->n_audit += audit ? 1 : 0;
   C->n_fallback += (fallback && !audit) ? 1 : 0;
+  C->n_suspects_sum += nsus;
+  if (nsus > C->n_suspects_max) C->n_suspects_max = nsus;
   if (J.steplog) J.steplog[t] = full ? (audit ? 3 : 2) : 1;
   if (full) return;
   int32_t* act = J.act;

@@ -59,7 +59,8 @@ class _LearnedStats(ctypes.Structure):
         ("fallbacks", ctypes.c_int32),
         ("audits", ctypes.c_int32),
         ("audit_agree", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("suspects_max", ctypes.c_int32),
+        ("suspects_sum", ctypes.c_int64),
     ]
 
 
@@ -121,6 +122,8 @@ class LearnedStats:
     fallbacks: int
     audits: int
     audit_agree: int
+    suspects_max: int
+    suspects_sum: int
 
 
 @dataclass
@@ -251,8 +254,7 @@ def _profile_of(prof):
 
 
 def _stats_of(stats):
-    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_
-                           if k != "reserved"})
+    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_})
 
 
 def workspace_size(n: int, d: int, learned: Learned | None = None) -> int:

@@ -37,11 +37,11 @@ def _gen(spec):
     return s.X.astype(np.float32)
 
 
-def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n: int = 4096,
-            steps_per_sem: int = 32, m_floor: int = 64, seed: int = 0, batch: int = 16,
-            workers: int = 8, log=print):
+def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n_lo: int = 2048,
+            n_hi: int = 16384, steps_per_sem: int = 32, m_floor: int = 64, seed: int = 0,
+            batch: int = 16, workers: int = 8, log=print):
     """Training lists from plain GPU orderings of ``n_sems`` SEMs (d ~ U[d_lo,
-    d_hi], gene-expression-scale family, n samples).  At up to
+    d_hi], n log-uniform in [n_lo, n_hi], gene-expression-scale family).  At up to
     ``steps_per_sem`` steps with at least ``m_floor`` active variables, a list
     holds the features of the active variables; its target is the plain
     choice.  SEMs are drawn by a pool of ``workers`` processes ahead of the
@@ -53,8 +53,9 @@ def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n: int = 4096,
     import torch
 
     rng = np.random.default_rng(seed)
-    specs = [(int(rng.integers(d_lo, d_hi + 1)), n, int(rng.integers(1 << 31)))
-             for _ in range(n_sems)]
+    specs = [(int(rng.integers(d_lo, d_hi + 1)),
+              int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))),
+              int(rng.integers(1 << 31))) for _ in range(n_sems)]
     feats, offs, tgs = [], [0], []
     done = 0
     t0 = time.time()
@@ -98,7 +99,7 @@ def normalization(F) -> np.ndarray:
     """Feature mean and scale (std, floored) of the training rows."""
     mu = F.mean(axis=0, dtype=np.float64)
     sd = F.std(axis=0, dtype=np.float64)
-    sd = np.maximum(sd, 1e-3 * np.maximum(1.0, np.abs(mu)))
+    sd = np.maximum(sd, 1e-2 * np.maximum(1.0, np.abs(mu)))
     return np.concatenate([mu, sd]).astype(np.float32)
 
 
@@ -195,7 +196,8 @@ def main(argv=None) -> int:
     ap.add_argument("--sems", type=int, default=1000)
     ap.add_argument("--d-lo", type=int, default=100)
     ap.add_argument("--d-hi", type=int, default=1000)
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--n-lo", type=int, default=2048)
+    ap.add_argument("--n-hi", type=int, default=16384)
     ap.add_argument("--steps-per-sem", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -206,8 +208,8 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     log = lambda msg: print(msg, flush=True)  # noqa: E731
     t0 = time.time()
-    F, offs, tgs = collect(a.sems, a.d_lo, a.d_hi, a.n, a.steps_per_sem, seed=a.seed,
-                           workers=a.workers, log=log)
+    F, offs, tgs = collect(a.sems, a.d_lo, a.d_hi, a.n_lo, a.n_hi, a.steps_per_sem,
+                           seed=a.seed, workers=a.workers, log=log)
     nl = len(tgs)
     nh = int(nl * a.holdout)
     # hold out the last lists (whole SEMs, since lists are in SEM order)
@@ -217,7 +219,8 @@ def main(argv=None) -> int:
     prop, hist = train(Ftr, otr, ttr, epochs=a.epochs, lr=a.lr, seed=a.seed, log=log)
     ev_tr = evaluate(prop, Ftr, otr, ttr)
     ev_te = evaluate(prop, Fte, ote, tte) if nh else {}
-    meta = {"sems": a.sems, "d": [a.d_lo, a.d_hi], "n": a.n, "steps_per_sem": a.steps_per_sem,
+    meta = {"sems": a.sems, "d": [a.d_lo, a.d_hi], "n": [a.n_lo, a.n_hi],
+            "steps_per_sem": a.steps_per_sem,
             "epochs": a.epochs, "lr": a.lr, "seed": a.seed, "lists": nl,
             "rows": int(offs[-1]), "loss": hist, "train": ev_tr, "holdout": ev_te,
             "seconds": round(time.time() - t0, 1)}
