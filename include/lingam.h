@@ -29,12 +29,16 @@
  * than learned_min_m active variables a small network (16 features ->
  * 128 -> 128 -> 1, ReLU, BF16 weights, FP32 accumulation) scores the active
  * variables, the exact measure k_i is computed only for the `topk` best
- * scored, and the best of those is taken when (a) it is certified -- every
- * other variable l already has sum over candidates c of max(0, R(c, l))^2 >
- * k_best, a lower bound of k_l, so the full search would pick it too -- or
- * (b) its score leads every non-candidate's by at least `margin`.  Otherwise,
- * and at every audit step (t % audit_every == 0), the full step of the exact
- * search decides.  This proposal layer is not part of the paper's method; it
+ * scored, and the choice is made as follows.  The candidates' rows bound every
+ * other variable's k from below (sum over candidates c of max(0, R(c, l))^2);
+ * the "suspects" are the variables whose bound does not exceed the best
+ * candidate's k.  (a) No suspect: the best candidate is the plain search's
+ * choice (certified).  (b) At most min(1024, m/2 - topk) suspects: their rows
+ * are evaluated exactly in a second pass and the best of candidates and
+ * suspects is the plain choice.  (c) More: the best candidate is taken when
+ * its score leads every non-candidate's by at least `margin`.  Otherwise, and
+ * at every audit step (t % audit_every == 0), the full step of the exact
+ * search decides.  With margin = +inf the order is the plain order.  This proposal layer is not part of the paper's method; it
  * is an addition on top of the exact search it accelerates.
  */
 #ifndef LINGAM_MI355X_H
@@ -92,6 +96,8 @@ typedef struct lingam_learned_stats {
   int32_t suspects_max;   /* most non-candidates in one step whose lower bound did not
                              exceed the best candidate's k (0 = certified) */
   int64_t suspects_sum;   /* ... summed over learned steps */
+  int32_t expanded;       /* steps decided exactly by evaluating the suspects' rows */
+  int32_t reserved;
 } lingam_learned_stats;
 
 /* The proposer network.  A proposer block is LINGAM_PROPOSER_SIZE FP32 values
@@ -123,8 +129,9 @@ typedef struct lingam_opts {
                                    default 64 */
   int32_t audit_every;          /* full-step audit when t % audit_every == 0; 0 = never;
                                    default 32 */
-  float margin;                 /* score lead that accepts an uncertified candidate; +inf
-                                   accepts certified candidates only; default 4 */
+  float margin;                 /* score lead that accepts the best candidate when the
+                                   suspects are too many for the second pass; +inf never
+                                   does (exact); default +inf */
   int32_t learned_min_m;        /* steps with m <= learned_min_m are plain; >= topk and
                                    >= 64; default 2 * topk */
   lingam_learned_stats* learned_stats; /* HOST pointer or NULL: filled when the call syncs */

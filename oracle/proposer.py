@@ -16,15 +16,15 @@ matrix of the C oracle:
   (forward, backward, listwise softmax cross-entropy against the plain
   search's choice, Adam);
 * one learned step: the K best-scored variables are the candidates, their
-  exact k_i = sum_j min(0, R(i, j))^2 is taken from the measure, and the best
-  candidate is accepted when a certificate proves no other variable can beat
-  it, or else when its score beats every excluded variable's by at least a
-  margin delta; otherwise (and at every audit step) the full plain step
-  decides.
-
-The certificate: for an excluded variable l the candidates' rows already give
-R(l, c) = -R(c, l), so k_l >= LB_l = sum_{c in C} max(0, R(c, l))^2.  If
-LB_l > k_best for every excluded l, the plain argmax is the best candidate.
+  exact k_i = sum_j min(0, R(i, j))^2 is taken from the measure.  For an
+  excluded variable l the candidates' rows already give R(l, c) = -R(c, l),
+  so k_l >= LB_l = sum_{c in C} max(0, R(c, l))^2.  The suspects are the
+  excluded variables with LB_l <= k_best.  No suspect: the best candidate is
+  the plain choice (certified).  At most cap(m) = min(1024, m/2 - K) (rounded
+  down to a multiple of 8) suspects: their exact k is evaluated and the best
+  of candidates and suspects is the plain choice.  More: the best candidate
+  is taken when its score beats every excluded variable's by at least a
+  margin delta, else (and at every audit step) the full plain step decides.
 
 Where the library rounds to BF16 (network inputs, weights, first hidden
 layer) ``emulate_bf16=True`` applies the same rounding (round to nearest
@@ -238,16 +238,23 @@ def topk(scores, slots, K: int) -> np.ndarray:
     return np.array(idx[:K], dtype=np.int64)
 
 
+def suspect_cap(m: int, K: int, cap: int = 1024) -> int:
+    """Most suspects the second pass evaluates at a step with m variables."""
+    c = min(m // 2 - K, cap)
+    return c // 8 * 8 if c > 0 else 0
+
+
 @dataclass
 class StepInfo:
     t: int
-    kind: str            # "plain" (small m), "learned", "fallback", "audit"
+    kind: str            # "plain" (small m), "learned", "expanded", "fallback", "audit"
     chosen: int
     plain_choice: int
     learned_choice: int = -1
     certified: bool = False
     margin: float = float("nan")
     candidates: np.ndarray = None
+    suspects: int = 0
 
 
 def _plain_choice(k, U):
@@ -259,16 +266,17 @@ def _plain_choice(k, U):
     return best
 
 
-def learned_order(X, proposer, K: int = 64, delta: float = 0.0, audit_every: int = 32,
-                  min_m: int | None = None, emulate_bf16: bool = True):
+def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: int = 32,
+                  min_m: int | None = None, emulate_bf16: bool = True,
+                  max_suspects: int = 1024):
     """Causal order by the learned-proposal form.
 
     X: n x d samples (cast to FP32 first, like the library's input).
     proposer: flat [norm(32), params(18817)].
-    delta: score margin under which an uncertified candidate defers to the
-    full step (+inf: every uncertified step is a full step, so the order is
-    the plain order).  audit_every: full step at t % audit_every == 0 (0: no
-    audits).  Steps with m <= min_m (default 2K) are plain steps.
+    delta: score margin that accepts the best candidate when the suspects
+    are too many for the second pass (+inf: never, so the order is the plain
+    order).  audit_every: full step at t % audit_every == 0 (0: no audits).
+    Steps with m <= min_m (default 2K) are plain steps.
     Returns (order, [StepInfo]).
     """
     X = np.asarray(np.asarray(X, dtype=np.float32), dtype=np.float64).copy()
@@ -304,18 +312,30 @@ def learned_order(X, proposer, K: int = 64, delta: float = 0.0, audit_every: int
             pos = np.maximum(D[C], 0.0)            # R(c, l) > 0 -> k_l contribution
             lb = np.sum(pos * pos, axis=0)
             excl = ~inC
-            certified = bool(np.all(lb[excl] > k[best])) if excl.any() else True
+            sus = np.flatnonzero(excl & ~(lb > k[best]))
+            certified = sus.size == 0
             s_out = np.max(s[excl]) if excl.any() else -np.inf
             margin = s[best] - s_out
             audit = audit_every > 0 and t % audit_every == 0
-            fallback = (not certified) and not (margin >= delta)
-            if audit or fallback:
-                p = pc
-                kind = "audit" if audit else "fallback"
-            else:
+            expand = (not audit) and (not certified) and \
+                sus.size <= suspect_cap(m, K, max_suspects)
+            if audit:
+                p, kind = pc, "audit"
+            elif certified:
+                p, kind = best, "learned"
+            elif expand:
+                # exact k of the suspects; the best of candidates and suspects
                 p = best
-                kind = "learned"
-            info.append(StepInfo(t, kind, U[p], U[pc], U[best], certified, float(margin), C))
+                for c in sus:
+                    if k[c] < k[p] or (k[c] == k[p] and U[c] < U[p]):
+                        p = c
+                kind = "expanded"
+            elif margin >= delta:
+                p, kind = best, "learned"
+            else:
+                p, kind = pc, "fallback"
+            info.append(StepInfo(t, kind, U[p], U[pc], U[best], certified, float(margin), C,
+                                 int(sus.size)))
         e = U[p]
         order.append(e)
         xe = X[:, e]

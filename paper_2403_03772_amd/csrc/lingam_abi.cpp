@@ -258,6 +258,11 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
       J.kc = reinterpret_cast<double*>(b + L.kc);
       J.lb = reinterpret_cast<double*>(b + L.lb);
       J.steplog = reinterpret_cast<int32_t*>(b + L.steplog);
+      J.cap_s = L.cap_s;
+      J.cand2 = reinterpret_cast<int32_t*>(b + L.cand2);
+      J.parts = reinterpret_cast<double*>(b + L.parts);
+      J.rc2 = reinterpret_cast<double*>(b + L.rc2);
+      J.kc2 = reinterpret_cast<double*>(b + L.kc2);
     }
   }
   return out;
@@ -286,7 +291,15 @@ StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, l
       T.g[kind] += lg::kind_count(js[k], kind, K);
     const int m = js[k].m;
     if (m >= 2 && !js[k].fp64) T.pair_evals += (double)m * (m - 1) * (double)jobs[k].n;
-    if (js[k].learned) T.cand_evals += 2.0 * K * (double)(m - 1) * (double)jobs[k].n;
+    if (js[k].learned) {
+      T.cand_evals += 2.0 * K * (double)(m - 1) * (double)jobs[k].n;
+      // bounds of the suspect pass (its size is decided on the device)
+      lg::JobStep b = js[k];
+      b.nsus = lg::suspect_cap(m, K, P.L[k].cap_s);
+      b.nct2 = lg::cdiv(b.nsus, lg::kTileVars) * b.nblk;
+      for (int kind = lg::kKPairS; kind <= lg::kKLsel2; ++kind)
+        T.g[kind] += lg::kind_count(b, kind, K);
+    }
     if (m > 2) T.resid_bytes += 28.0 * (double)jobs[k].n * (double)(m - 1);
   }
   return T;
@@ -348,19 +361,40 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
       if (pf) pf->cand_evals += T.cand_evals;
     }
-    if (T.g[lg::kKLsel] > 0) {
+    // learned steps: the full-step kernels are gated on the device, so their
+    // host grids are only bounds; bounded grids walk the items instead
+    const bool gated = T.g[lg::kKLsel] > 0;
+    auto capped = [&](int32_t g, int per_cu) {
+      return gated ? std::min<int32_t>(g, P.cu * per_cu) : g;
+    };
+    if (gated) {
       LG_TRY(lg::launch_learned_back(table, P.njobs, t, sc, T.g, st), "learned decision");
+      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, st), "suspect schedule");
+      if (T.g[lg::kKPairS] > 0) {
+        if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
+        LG_TRY(lg::launch_pair_susp(table, P.njobs, sc,
+                                    std::min<int32_t>(T.g[lg::kKPairS], P.cu * 8), st),
+               "pair susp");
+        if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
+      }
+      LG_TRY(lg::launch_susp_back(table, P.njobs, t, sc,
+                                  std::min<int32_t>(T.g[lg::kKCombS], P.cu * 8),
+                                  std::min<int32_t>(T.g[lg::kKRowkS], P.cu * 4),
+                                  std::min<int32_t>(T.g[lg::kKLsel2], P.njobs), st),
+             "suspect decision");
       LG_TRY(lg::launch_gate_schedule(table, P.njobs, sc, st), "gate schedule");
     }
     if (T.g[lg::kKPair] > 0) {
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
-      LG_TRY(lg::launch_pair(table, P.njobs, sc, T.g[lg::kKPair], st), "pair");
+      LG_TRY(lg::launch_pair(table, P.njobs, sc, capped(T.g[lg::kKPair], 8), st, gated),
+             "pair");
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
       if (pf) pf->pair_evals += T.pair_evals;
-      LG_TRY(lg::launch_combine(table, P.njobs, sc, T.g[lg::kKComb], st), "combine");
+      LG_TRY(lg::launch_combine(table, P.njobs, sc, capped(T.g[lg::kKComb], 8), st),
+             "combine");
     }
     LG_TRY(lg::launch_pair64(table, P.njobs, sc, T.g[lg::kKP64], st), "pair64");
-    LG_TRY(lg::launch_rowk(table, P.njobs, sc, T.g[lg::kKRowk], st), "rowk");
+    LG_TRY(lg::launch_rowk(table, P.njobs, sc, capped(T.g[lg::kKRowk], 8), st), "rowk");
     LG_TRY(lg::launch_select(table, P.njobs, t, sc, T.g[lg::kKSel], st), "select");
     if (T.g[lg::kKRes] > 0) {
       if (pf && pf->tm.on) pf->resid_ev.push_back(pf->tm.take(st));
@@ -521,6 +555,7 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
       ls->audit_agree += c.n_audit_agree;
       ls->suspects_max = std::max(ls->suspects_max, c.n_suspects_max);
       ls->suspects_sum += c.n_suspects_sum;
+      ls->expanded += c.n_expanded;
     }
   }
   if (pf.tm.on && opts->profile) {
@@ -540,13 +575,16 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
       pr->cand_ms += pf.tm.ms(pf.cand_ev[k], pf.cand_ev[k + 1]);
     pr->cand_launches = (int64_t)(pf.cand_ev.size() / 2);
     pr->cand_evals = pf.cand_evals;
-    // steps a learned decision took did not run the all-pairs kernel
+    // steps a learned decision took did not run the all-pairs kernel; steps
+    // decided by the second pass evaluated their suspects' rows
     for (int k = 0; k < (int)logs.size(); ++k) {
       const int64_t d = P.L[k].d, n = P.L[k].n;
       for (int64_t t = 0; t + 1 < d; ++t) {
         const int64_t m = d - t;
-        if (logs[k][(size_t)t] == 1 && m > lg::kFp64MaxM)
+        const int32_t kind = logs[k][(size_t)t] & 15, nsus = logs[k][(size_t)t] >> 4;
+        if ((kind == 1 || kind == 4) && m > lg::kFp64MaxM)
           pr->pair_evals -= (double)m * (double)(m - 1) * (double)n;
+        if (kind == 4) pr->cand_evals += 2.0 * nsus * (double)(m - 1) * (double)n;
       }
     }
   }
@@ -707,7 +745,7 @@ void lingam_opts_init(lingam_opts* o) {
   o->struct_size = sizeof(lingam_opts);
   o->topk = 64;
   o->audit_every = 32;
-  o->margin = 4.0f;
+  o->margin = INFINITY;
   o->learned_min_m = 128;
 }
 

@@ -204,6 +204,19 @@ __device__ inline Best merge(const Best& a, const Best& b) {
   return r;
 }
 
+// Grid-stride walk over the workgroup items of a schedule: f(job, local
+// index) for items blockIdx.x, blockIdx.x + gridDim.x, ...  (uniform over
+// the workgroup, so f may use barriers).
+template <typename F>
+__device__ __forceinline__ void for_blocks(const int32_t* __restrict__ pre, int njobs, F f) {
+  const int total = pre[njobs];
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    int jb, lb;
+    if (!locate(pre, njobs, b, jb, lb)) break;
+    f(jb, lb);
+  }
+}
+
 // Pair moments (the hot loop), shared by the all-pairs kernel and the
 // candidate-row kernel of the learned form.  Grid: per job ntiles * 2 * nsplit
 // workgroups of 4 waves (all pairs: upper-triangular 8 x 8 tiles of positions;
@@ -217,7 +230,19 @@ __device__ inline Best merge(const Best& a, const Best& b) {
 // part[((split * ntiles + tile) * 4 + wave) * 64 + pair * 4 + dir * 2 + which],
 // which 0 = S1 (log cosh, offset as described in the header), 1 = S2;
 // dir 0 = residual of i on j, dir 1 = of j on i.
-template <bool kCand>
+// Work items of the pair kernels.  With kLoop false the grid is the schedule
+// and workgroup p (after the XCD remap) takes item p.  With kLoop true (gated
+// launches whose size the host only bounds) a smaller grid walks the items:
+// workgroup p takes items p * chunk .. p * chunk + chunk - 1, chunk =
+// ceil(total / G), so a gated-off step costs a few thousand empty workgroups
+// instead of the bound.
+enum PairMode : int { kModeAll = 0, kModeCand = 1, kModeSusp = 2 };
+
+template <int kMode>
+__device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int local,
+                                          int wave, int lane);
+
+template <int kMode, bool kLoop>
 __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int njobs,
                                            const JobStep* __restrict__ js,
                                            const int32_t* __restrict__ pre, int G) {
@@ -228,14 +253,28 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
   // tile reads are shared in that XCD's L2.
   const int b = blockIdx.x;
   const int Q = G >> 3, R = G & 7, x = b & 7, idx = b >> 3;
-  const int w = x * Q + (x < R ? x : R) + idx;
+  const int p = x * Q + (x < R ? x : R) + idx;
   int jb, local;
-  if (!locate(pre, njobs, w, jb, local)) return;
-  const JobDev& J = jobs[jb];
-  const JobStep S = js[jb];
+  if (!kLoop) {  // the grid is the schedule: one item per workgroup
+    if (locate(pre, njobs, p, jb, local)) pair_item<kMode>(jobs[jb], js[jb], local, wave, lane);
+    return;
+  }
+  const int total = pre[njobs];
+  const int chunk = (total + G - 1) / G;
+  for (int it = 0; it < chunk; ++it) {
+    const int w = p * chunk + it;
+    if (w >= total || !locate(pre, njobs, w, jb, local)) break;
+    pair_item<kMode>(jobs[jb], js[jb], local, wave, lane);
+  }
+}
+
+template <int kMode>
+__device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int local,
+                                          int wave, int lane) {
+  constexpr bool kCand = kMode != kModeAll;
   const int m = S.m;
   const int nsplit = kCand ? S.nsplit_c : S.nsplit;
-  const int ntiles = kCand ? S.nct : S.ntiles;
+  const int ntiles = kMode == kModeAll ? S.ntiles : (kMode == kModeCand ? S.nct : S.nct2);
   const int split_len = kCand ? S.split_len_c : S.split_len;
   const int per_tile = 2 * nsplit;
   const int tile = local / per_tile, rem = local - tile * per_tile;
@@ -249,12 +288,13 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
   }
   const int wi = wave >> 1, wj = wave & 1;
   if (!kCand && bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)
-  // i side: positions bi * 8 + .. (all pairs) or candidate indices (candidate rows)
+  // i side: positions bi * 8 + .. (all pairs) or list entries (candidate /
+  // suspect rows; list padding holds position m)
   const int i0 = bi * kTileVars + wi * kWaveVars, pj0 = bj * kTileVars + wj * kWaveVars;
   const int32_t* act = J.act;
-  const int32_t* cand = J.cand;
+  const int32_t* list = kMode == kModeCand ? J.cand : J.cand2;
   const int64_t ldz = J.ldz, ldr = J.d;
-  auto ipos = [&](int a) { return kCand ? cand[i0 + a] : i0 + a; };
+  auto ipos = [&](int a) { return kCand ? list[i0 + a] : i0 + a; };
 
   // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
   // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
@@ -263,7 +303,7 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
   {
     const int q = lane & 15, a = q >> 2, c = q & 3;
     const int pi = ipos(dir == 0 ? a : c), pj = pj0 + (dir == 0 ? c : a);
-    const bool valid = kCand ? (pj < m && pi != pj) : (pi < m && pj < m && pi < pj);
+    const bool valid = kCand ? (pi < m && pj < m && pi != pj) : (pi < m && pj < m && pi < pj);
     if (valid) {
       double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
       const double lim = 1.0 - kCollinear;
@@ -376,7 +416,7 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
     // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
     const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
     const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
-    double* part = kCand ? J.partc : J.part;
+    double* part = kMode == kModeAll ? J.part : (kMode == kModeCand ? J.partc : J.parts);
     part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
   }
 }

@@ -37,6 +37,9 @@ constexpr int kHidden = 128;
 constexpr int kParams = kHidden * kFeat + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
 constexpr int kPropNorm = 2 * kFeat;  // feature mean and scale ahead of the weights
 constexpr int kMaxTopK = 256;
+// Most suspects (non-candidates whose lower bound does not exceed the best
+// candidate's k) a second candidate pass evaluates in one step.
+constexpr int kMaxSuspects = 1024;
 // offsets of the trainable parameters inside the flat FP32 block
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kHidden * kFeat;
@@ -73,7 +76,9 @@ struct Ctrl {
   float s_out;           // best score outside the candidates (this step)
   int32_t n_suspects_max;  // largest count of non-candidates whose bound <= k_best
   long long n_suspects_sum;
-  int32_t pad[50];
+  int32_t nsus;            // this step: suspects listed for the second pass (0: none)
+  int32_t n_expanded;      // learned steps decided exactly by the second pass
+  int32_t pad[48];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 
@@ -103,9 +108,16 @@ struct Layout {
   size_t kc;     // double [K]      exact k of every candidate
   size_t lb;     // double [d]      lower bound of k at excluded positions
   size_t steplog;  // int32 [d]     per step: 0 plain, 1 learned, 2 fallback, 3 audit
+  // second candidate pass over the suspects
+  int32_t cap_s;   // most suspects listed (kMaxSuspects or less, multiple of 8)
+  size_t cand2;    // int32  [cap_s] suspect positions (ascending; padding = m)
+  size_t parts;    // double [parts_elems] partial sums
+  size_t rc2;      // double [cap_s * d] R(suspect, position)
+  size_t kc2;      // double [cap_s] exact k of every suspect
   size_t total;
   size_t part_elems;
   size_t partc_elems;
+  size_t parts_elems;
 };
 
 // Device job table entry (absolute device addresses).
@@ -145,6 +157,11 @@ struct JobDev {
   double* kc;
   double* lb;
   int32_t* steplog;
+  int32_t cap_s;
+  int32_t* cand2;
+  double* parts;
+  double* rc2;
+  double* kc2;
 };
 
 // Split policy of the pair kernel (autotuned): enough workgroups for
@@ -168,6 +185,8 @@ struct JobStep {
   int32_t nct;        // candidate tiles (K / 8) * nblk
   int32_t nsplit_c;   // sample splits of the candidate pair kernel
   int32_t split_len_c;
+  int32_t nsus;       // suspects of the second pass (set after the learned decision)
+  int32_t nct2;       // suspect tiles ceil(nsus / 8) * nblk
 };
 
 // Workgroup-count kinds with a prefix array each.
@@ -186,6 +205,10 @@ enum Kind : int {
   kKRowkC,      // k_cand_rowk: K / 4
   kKColC,       // k_cand_colk: ceil(m / 64)
   kKLsel,       // k_lselect: 1
+  kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c (after the learned decision)
+  kKCombS,      // k_combine_susp: ceil(nct2 / 4)
+  kKRowkS,      // k_susp_rowk: ceil(nsus / 4)
+  kKLsel2,      // k_lselect2: 1 when nsus > 0
   kNumKinds
 };
 // the full-step kinds a learned decision can gate off
@@ -278,6 +301,15 @@ __host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t ite
   s.nsplit = (int32_t)((iters + per - 1) / per);
 }
 
+// Most suspects a job with m active variables and K candidates lists: the
+// second pass must cost less than the full step (2 (K + S) < m rows), and at
+// most cap_s (the layout's room); a multiple of 8.
+__host__ __device__ inline int32_t suspect_cap(int32_t m, int32_t K, int32_t cap_s) {
+  int32_t c = m / 2 - K;
+  c = c < cap_s ? c : cap_s;
+  return c > 0 ? c / 8 * 8 : 0;
+}
+
 // Split of the candidate pair kernel given the batch's candidate (tile, direction) items.
 __host__ __device__ inline void job_split_cand(JobStep& s, int32_t n_pad, int64_t items_total,
                                                int32_t num_cu, Tune tu) {
@@ -307,6 +339,10 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind, int32_
     case kKRowkC: return s.learned ? cdiv(K, 4) : 0;
     case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
+    case kKPairS: return s.nct2 * 2 * s.nsplit_c;
+    case kKCombS: return cdiv(s.nct2, 4);
+    case kKRowkS: return cdiv(s.nsus, 4);
+    case kKLsel2: return s.nsus > 0 ? 1 : 0;
     default: return 0;
   }
 }
@@ -349,7 +385,9 @@ hipError_t launch_standardize(const JobDev* jobs, int njobs, SchedDev sc, int gr
 hipError_t launch_step_schedule(const JobDev* jobs, int njobs, int t, int num_cu, Tune tu,
                                 SchedDev sc, hipStream_t st);
 hipError_t launch_gate_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st);
-hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
+// loop: grid smaller than the schedule (gated launches), workgroups walk items
+hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st,
+                       bool loop = false);
 hipError_t launch_combine(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_pair64(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_rowk(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
@@ -374,6 +412,13 @@ hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid
                             hipStream_t st);
 hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                const int32_t* grid, hipStream_t st);
+// The second (suspect) pass: its schedule, its pair kernel (a bounded grid that
+// walks the items), and combine / row k / exact decision (grid-stride).
+hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st);
+hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+                            hipStream_t st);
+hipError_t launch_susp_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_comb,
+                            int g_rowk, int g_sel, hipStream_t st);
 
 // Training of the network.
 constexpr int kTrainParts = 512;  // workgroups of the backward pass (partial gradients)

@@ -391,7 +391,15 @@ __global__ __launch_bounds__(256) void k_standardize(const JobDev* __restrict__ 
 __global__ __launch_bounds__(256) void k_pair(const JobDev* __restrict__ jobs, int njobs,
                                               const JobStep* __restrict__ js,
                                               const int32_t* __restrict__ pre, int G) {
-  pair_tiles<false>(jobs, njobs, js, pre, G);
+  pair_tiles<kModeAll, false>(jobs, njobs, js, pre, G);
+}
+
+// The same kernel for gated launches (learned form): a bounded grid walks the
+// step's items.
+__global__ __launch_bounds__(256) void k_pair_loop(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre, int G) {
+  pair_tiles<kModeAll, true>(jobs, njobs, js, pre, G);
 }
 
 // Sum the sample splits (FP64, fixed order), form both residual entropies and
@@ -400,8 +408,7 @@ __global__ __launch_bounds__(256) void k_pair(const JobDev* __restrict__ jobs, i
 __global__ __launch_bounds__(256) void k_combine(const JobDev* __restrict__ jobs, int njobs,
                                                  const JobStep* __restrict__ js,
                                                  const int32_t* __restrict__ pre) {
-  int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  for_blocks(pre, njobs, [&](int jb, int lb) {
   const JobDev& J = jobs[jb];
   const JobStep S = js[jb];
   const int gid = lb * 256 + threadIdx.x;
@@ -432,6 +439,7 @@ __global__ __launch_bounds__(256) void k_combine(const JobDev* __restrict__ jobs
   const double Rv = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
   J.rmat[(int64_t)pi * J.d + pj] = Rv;
   J.rmat[(int64_t)pj * J.d + pi] = -Rv;
+  });
 }
 
 // The same measure entirely in FP64 from the FP64 residuals, for steps with few
@@ -440,8 +448,7 @@ __global__ __launch_bounds__(256) void k_combine(const JobDev* __restrict__ jobs
 __global__ __launch_bounds__(256) void k_pair64(const JobDev* __restrict__ jobs, int njobs,
                                                 const JobStep* __restrict__ js,
                                                 const int32_t* __restrict__ pre) {
-  int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  for_blocks(pre, njobs, [&](int jb, int lb) {
   const JobDev& J = jobs[jb];
   const int m = js[jb].m;
   const int lane = threadIdx.x & 63;
@@ -502,14 +509,14 @@ __global__ __launch_bounds__(256) void k_pair64(const JobDev* __restrict__ jobs,
     J.rmat[(int64_t)pi * J.d + pj] = Rv;
     J.rmat[(int64_t)pj * J.d + pi] = -Rv;
   }
+  });
 }
 
 // k_p = sum_{q != p} min(0, R(p, q))^2, one wave per row; mvec[p] = -k_p.
 __global__ __launch_bounds__(256) void k_rowk(const JobDev* __restrict__ jobs, int njobs,
                                               const JobStep* __restrict__ js,
                                               const int32_t* __restrict__ pre) {
-  int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  for_blocks(pre, njobs, [&](int jb, int lb) {
   const JobDev& J = jobs[jb];
   const int m = js[jb].m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -526,6 +533,7 @@ __global__ __launch_bounds__(256) void k_rowk(const JobDev* __restrict__ jobs, i
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
   if (lane == 0) J.mvec[p] = -k;
+  });
 }
 
 // Argmax with tie-break on the original id, teacher forcing, per-step outputs,
@@ -535,8 +543,7 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
                                                  const int32_t* __restrict__ pre, int t) {
   __shared__ Best sh[1024];
   __shared__ int forced_pos;
-  int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  for_blocks(pre, njobs, [&](int jb, int) {
   const JobDev& J = jobs[jb];
   const int m = js[jb].m, d = J.d;
   int32_t* act = J.act;
@@ -591,6 +598,8 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
     act[pos] = act[m - 1];
     if (m == 2) J.order[t + 1] = act[0];
   }
+  __syncthreads();  // the next job's item reuses the shared arrays
+  });
 }
 
 // Remove the chosen variable e from every remaining variable p and keep p
@@ -1005,6 +1014,23 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
     L.kc = take(sizeof(double) * (size_t)K);
     L.lb = take(sizeof(double) * (size_t)d);
     L.steplog = take(sizeof(int32_t) * (size_t)d);
+    int64_t cap = d / 2 - K;
+    cap = cap < kMaxSuspects ? cap : kMaxSuspects;
+    L.cap_s = cap > 0 ? (int32_t)(cap / 8 * 8) : 0;
+    size_t ps = 0;
+    for (int64_t t = 0; t + kFp64MaxM < d && L.cap_s > 0; ++t) {
+      JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
+      if (!s.learned) continue;
+      job_split_cand(s, (int32_t)L.n_pad, 2LL * s.nct, num_cu, worst);
+      const int32_t cs = suspect_cap(s.m, K, L.cap_s);
+      const size_t need = (size_t)cdiv(cs, kTileVars) * s.nblk * (size_t)s.nsplit_c * 256;
+      if (need > ps) ps = need;
+    }
+    L.parts_elems = ps;
+    L.cand2 = take(sizeof(int32_t) * (size_t)(L.cap_s > 0 ? L.cap_s : 1));
+    L.parts = take(sizeof(double) * (ps ? ps : 1));
+    L.rc2 = take(sizeof(double) * (size_t)(L.cap_s > 0 ? L.cap_s : 1) * (size_t)d);
+    L.kc2 = take(sizeof(double) * (size_t)(L.cap_s > 0 ? L.cap_s : 1));
   }
   L.total = off;
   return L;
@@ -1091,10 +1117,15 @@ hipError_t launch_gate_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st,
+                       bool loop) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
-                     (const JobStep*)sc.js, pre_of(sc, njobs, kKPair), grid);
+  if (loop)
+    hipLaunchKernelGGL(k_pair_loop, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                       (const JobStep*)sc.js, pre_of(sc, njobs, kKPair), grid);
+  else
+    hipLaunchKernelGGL(k_pair, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                       (const JobStep*)sc.js, pre_of(sc, njobs, kKPair), grid);
   return hipGetLastError();
 }
 

@@ -426,7 +426,7 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
 __global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jobs, int njobs,
                                                    const JobStep* __restrict__ js,
                                                    const int32_t* __restrict__ pre, int G) {
-  pair_tiles<true>(jobs, njobs, js, pre, G);
+  pair_tiles<kModeCand, false>(jobs, njobs, js, pre, G);
 }
 
 // R(c, j) for candidate c against every active position j (0 for j = c),
@@ -522,27 +522,19 @@ __global__ __launch_bounds__(256) void k_cand_colk(const JobDev* __restrict__ jo
                                   : ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
-// The learned decision of one job (one workgroup).  Best candidate by -k with
-// ties to the smaller original id; certified when min lb > its k; accepted
-// when certified or when its score leads every non-candidate's by at least
-// delta; audit steps (t % audit_every == 0) and rejected steps set ctrl->full
-// and leave the choice to the full step.  An accepted choice is committed
-// here exactly as the full selection commits its own.
-__global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs, int njobs,
-                                                 const JobStep* __restrict__ js,
-                                                 const int32_t* __restrict__ pre, int t) {
-  __shared__ Best sh[256];
-  int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
-  const JobDev& J = jobs[jb];
-  const int m = js[jb].m, K = J.K;
+// Best of a list of measured rows (-k, ties to the smaller original id),
+// merged with `seed` (thread 0's value) and reduced over the 256 threads of a
+// workgroup; valid in every thread.
+__device__ inline Best best_of_rows(const double* __restrict__ kvals,
+                                    const int32_t* __restrict__ pos, int count,
+                                    const int32_t* __restrict__ act, Best seed, Best* sh) {
   const int tid = threadIdx.x;
-  Best b{-INFINITY, 0x7fffffff, -1, -INFINITY};
-  for (int c = tid; c < K; c += 256) {
-    double v = -J.kc[c];
+  Best b = tid == 0 ? seed : Best{-INFINITY, 0x7fffffff, -1, -INFINITY};
+  for (int c = tid; c < count; c += 256) {
+    double v = -kvals[c];
     if (v != v) v = -INFINITY;
-    const int p = J.cand[c];
-    const Best x{v, J.act[p], p, -INFINITY};
+    const int p = pos[c];
+    const Best x{v, act[p], p, -INFINITY};
     b = (b.pos < 0) ? x : merge(b, x);
   }
   sh[tid] = b;
@@ -554,55 +546,239 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
     }
     __syncthreads();
   }
-  const Best best = sh[0];
-  const double kbest = -best.v;
-  // non-candidates whose lower bound does not exceed k_best could still win
-  int nsus = 0;
-  for (int l = tid; l < m; l += 256) {
-    const double v = J.lb[l];
-    nsus += (v == v && v > kbest) ? 0 : 1;  // NaN bounds count as suspects
-  }
-  __shared__ int shs[256];
-  shs[tid] = nsus;
+  const Best r = sh[0];
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) shs[tid] += shs[tid + off];
+  return r;
+}
+
+// Commit the choice of a learned step exactly as the full selection does.
+__device__ inline void commit_choice(const JobDev& J, int t, int m, const Best& best) {
+  J.order[t] = best.slot;
+  J.ctrl->exo_slot = best.slot;
+  J.ctrl->exo_pos = best.pos;
+  J.ctrl->full = 0;
+  if (J.gaps) J.gaps[t] = best.v - best.v2;
+  J.act[best.pos] = J.act[m - 1];
+}
+
+// The learned decision of one job (one workgroup).  Best candidate by -k with
+// ties to the smaller original id.  Suspects: non-candidates whose lower bound
+// does not exceed its k (only they could still win).  No suspect: certified,
+// the choice is the plain one.  At most suspect_cap suspects: they are listed
+// (ascending position, padded to a multiple of 8 with position m) for the
+// second pass, which decides exactly.  More: accepted when its score leads
+// every non-candidate's by at least delta, else the full step decides.  Audit
+// and teacher-forced steps always hand the step to the full kernels.
+__global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs, int njobs,
+                                                 const JobStep* __restrict__ js,
+                                                 const int32_t* __restrict__ pre, int t) {
+  __shared__ Best sh[256];
+  __shared__ int shs[256];
+  int jb, lb;
+  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m, K = J.K;
+  const int tid = threadIdx.x;
+  const Best best =
+      best_of_rows(J.kc, J.cand, K, J.act, Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
+  const double kbest = -best.v;
+  auto suspect = [&](int l) {
+    const double v = J.lb[l];
+    return !(v == v && v > kbest);  // NaN bounds count as suspects
+  };
+  // count, then (if listed) write in ascending position order: thread chunks
+  const int per = (m + 255) / 256;
+  const int p0 = tid * per, p1 = min(p0 + per, m);
+  int mine = 0;
+  for (int l = p0; l < p1; ++l) mine += suspect(l) ? 1 : 0;
+  shs[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? shs[tid - off] : 0;
+    __syncthreads();
+    shs[tid] += v;
     __syncthreads();
   }
-  nsus = shs[0];
+  const int nsus = shs[255];
   const bool certified = nsus == 0;
   const float margin = J.score[best.pos] - J.ctrl->s_out;
   const bool audit = J.audit_every > 0 && t % J.audit_every == 0;
-  const bool fallback = !certified && !(margin >= J.delta);
   const bool forced = t < J.forced_len;  // teacher forcing is applied by the full step
-  const bool full = audit || fallback || forced;
-  if (J.measures) {
+  const bool handover = audit || forced;
+  const bool expand = !handover && !certified && nsus <= suspect_cap(m, K, J.cap_s);
+  const bool take = !handover && (certified || (!expand && margin >= J.delta));
+  const bool fallback = !handover && !take && !expand;
+  if (expand) {
+    int w = shs[tid] - mine;
+    for (int l = p0; l < p1; ++l)
+      if (suspect(l)) J.cand2[w++] = l;
+    const int padded = (nsus + kTileVars - 1) / kTileVars * kTileVars;
+    for (int c = nsus + tid; c < padded; c += 256) J.cand2[c] = m;
+  }
+  if (J.measures && take) {
     double* row = J.measures + (int64_t)t * J.d;
-    if (!full) {
-      for (int v = tid; v < J.d; v += 256) row[v] = NAN;
-      __syncthreads();
-      for (int c = tid; c < K; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
-    }
+    for (int v = tid; v < J.d; v += 256) row[v] = NAN;
+    __syncthreads();
+    for (int c = tid; c < K; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
   }
   __syncthreads();
   if (tid != 0) return;
   Ctrl* C = J.ctrl;
-  C->full = full ? 1 : 0;
+  C->full = 1;
+  C->nsus = expand ? nsus : 0;
   C->learned_slot = best.slot;
   C->n_learned += 1;
   C->n_certified += certified ? 1 : 0;
   C->n_audit += audit ? 1 : 0;
-  C->n_fallback += (fallback && !audit) ? 1 : 0;
+  C->n_fallback += fallback ? 1 : 0;
   C->n_suspects_sum += nsus;
   if (nsus > C->n_suspects_max) C->n_suspects_max = nsus;
-  if (J.steplog) J.steplog[t] = full ? (audit ? 3 : 2) : 1;
-  if (full) return;
-  int32_t* act = J.act;
-  J.order[t] = best.slot;
-  C->exo_slot = best.slot;
-  C->exo_pos = best.pos;
-  if (J.gaps) J.gaps[t] = best.v - best.v2;
-  act[best.pos] = act[m - 1];
+  if (J.steplog)
+    J.steplog[t] = take ? 1 : (expand ? (4 | (nsus << 4)) : (audit ? 3 : 2));
+  if (take) commit_choice(J, t, m, best);
+}
+
+// Plan of the second pass: per job, the suspects listed at this step (0 for
+// jobs without a listing) and the prefix sums of the suspect kinds.
+__global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict__ jobs,
+                                                        int njobs, JobStep* __restrict__ js,
+                                                        int32_t* __restrict__ pre) {
+  auto plan = [&](int j) {
+    JobStep s = js[j];
+    s.nsus = s.learned ? jobs[j].ctrl->nsus : 0;
+    s.nct2 = cdiv(s.nsus, kTileVars) * s.nblk;
+    js[j] = s;
+    return s;
+  };
+  if (njobs <= 64) {  // one wave, no barriers
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    JobStep s{};
+    if (lane < njobs) s = plan(lane);
+    for (int kind = kKPairS; kind <= kKLsel2; ++kind) {
+      const int32_t c = lane < njobs ? kind_count(s, kind) : 0;
+      int32_t incl = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+      }
+      int32_t* out = pre + (int64_t)kind * (njobs + 1);
+      if (lane < njobs) out[lane] = incl - c;
+      if (lane == 63) out[njobs] = incl;
+    }
+    return;
+  }
+  __shared__ int32_t sh[1024];
+  for (int j = threadIdx.x; j < njobs; j += 1024) plan(j);
+  __syncthreads();
+  for (int kind = kKPairS; kind <= kKLsel2; ++kind)
+    block_scan(
+        njobs, [&](int j) { return kind_count(js[j], kind); },
+        pre + (int64_t)kind * (njobs + 1), sh);
+}
+
+__global__ __launch_bounds__(256) void k_pair_susp(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre, int G) {
+  pair_tiles<kModeSusp, true>(jobs, njobs, js, pre, G);
+}
+
+// R(s, j) of every listed suspect against every active position (0 for j = s).
+__global__ __launch_bounds__(256) void k_combine_susp(const JobDev* __restrict__ jobs, int njobs,
+                                                      const JobStep* __restrict__ js,
+                                                      const int32_t* __restrict__ pre) {
+  for_blocks(pre, njobs, [&](int jb, int lb) {
+    const JobDev& J = jobs[jb];
+    const JobStep S = js[jb];
+    const int gid = lb * 256 + threadIdx.x;
+    if (gid >= S.nct2 * 64) return;
+    const int tile = gid >> 6, wave = (gid >> 4) & 3, q = gid & 15;
+    const int bi = tile / S.nblk, bj = tile - bi * S.nblk;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int m = S.m;
+    const int ci = bi * kTileVars + wi * kWaveVars + (q >> 2);
+    const int pj = bj * kTileVars + wj * kWaveVars + (q & 3);
+    if (ci >= S.nsus || pj >= m) return;
+    const int pi = J.cand2[ci];
+    double* out = J.rc2 + (int64_t)ci * J.d + pj;
+    if (pi == pj) {
+      *out = 0.0;
+      return;
+    }
+    double sm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int sp = 0; sp < S.nsplit_c; ++sp) {
+      const double* src = J.parts + (((int64_t)sp * S.nct2 + tile) * 4 + wave) * 64 + q * 4;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sm[c] += src[c];
+    }
+    const double s1_bias =
+        (double)S.nsplit_c * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+    const double inv_n = 1.0 / (double)J.n;
+    const int si = J.act[pi], sj = J.act[pj];
+    double r = J.rho[(int64_t)si * J.d + sj];
+    const double lim = 1.0 - kCollinear;
+    r = r > lim ? lim : (r < -lim ? -lim : r);
+    const double al = 1.0 / sqrt(1.0 - r * r);
+    const double h_ij =
+        entropy_from_moments(kLn2 * (sm[0] + s1_bias) * inv_n, al * sm[1] * inv_n);
+    const double h_ji =
+        entropy_from_moments(kLn2 * (sm[2] + s1_bias) * inv_n, al * sm[3] * inv_n);
+    *out = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
+  });
+}
+
+// kc2[s] = sum_j min(0, R(s, j))^2, one wave per listed suspect.
+__global__ __launch_bounds__(256) void k_susp_rowk(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre) {
+  for_blocks(pre, njobs, [&](int jb, int lb) {
+    const JobDev& J = jobs[jb];
+    const JobStep S = js[jb];
+    const int lane = threadIdx.x & 63;
+    const int c = lb * 4 + (threadIdx.x >> 6);
+    if (c >= S.nsus) return;
+    const double* row = J.rc2 + (int64_t)c * J.d;
+    double k = 0.0;
+    for (int q = lane; q < S.m; q += 64) {
+      const double x = row[q];
+      const double ng = x < 0.0 ? x : 0.0;
+      k += ng * ng;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
+    if (lane == 0) J.kc2[c] = k;
+  });
+}
+
+// The exact decision after the second pass: the best of candidates and
+// suspects is the plain choice (every other variable's bound exceeds the
+// best candidate's k, which is at least the new best's).
+__global__ __launch_bounds__(256) void k_lselect2(const JobDev* __restrict__ jobs, int njobs,
+                                                  const JobStep* __restrict__ js,
+                                                  const int32_t* __restrict__ pre, int t) {
+  __shared__ Best sh[256];
+  for_blocks(pre, njobs, [&](int jb, int) {
+    const JobDev& J = jobs[jb];
+    const JobStep S = js[jb];
+    const int tid = threadIdx.x;
+    Best b = best_of_rows(J.kc, J.cand, J.K, J.act,
+                          Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
+    b = best_of_rows(J.kc2, J.cand2, S.nsus, J.act, b, sh);
+    if (J.measures) {
+      double* row = J.measures + (int64_t)t * J.d;
+      for (int v = tid; v < J.d; v += 256) row[v] = NAN;
+      __syncthreads();
+      for (int c = tid; c < J.K; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
+      for (int c = tid; c < S.nsus; c += 256) row[J.act[J.cand2[c]]] = -J.kc2[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      J.ctrl->n_expanded += 1;
+      commit_choice(J, t, S.m, b);
+    }
+    __syncthreads();
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -901,6 +1077,32 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
                      js, pre_kind(sc, njobs, kKColC), t);
   hipLaunchKernelGGL(k_lselect, dim3((unsigned)grid[kKLsel]), dim3(256), 0, st, jobs, njobs, js,
                      pre_kind(sc, njobs, kKLsel), t);
+  return hipGetLastError();
+}
+
+hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_susp_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, sc.js, sc.pre);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+                            hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_susp, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKPairS), grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_susp_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_comb,
+                            int g_rowk, int g_sel, hipStream_t st) {
+  const JobStep* js = sc.js;
+  if (g_sel <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_susp, dim3((unsigned)g_comb), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKCombS));
+  hipLaunchKernelGGL(k_susp_rowk, dim3((unsigned)g_rowk), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKRowkS));
+  hipLaunchKernelGGL(k_lselect2, dim3((unsigned)g_sel), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKLsel2), t);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ class _LearnedStats(ctypes.Structure):
         ("audit_agree", ctypes.c_int32),
         ("suspects_max", ctypes.c_int32),
         ("suspects_sum", ctypes.c_int64),
+        ("expanded", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -124,6 +126,7 @@ class LearnedStats:
     audit_agree: int
     suspects_max: int
     suspects_sum: int
+    expanded: int
 
 
 @dataclass
@@ -133,7 +136,7 @@ class Learned:
     proposer: object
     topk: int = 64
     audit_every: int = 32
-    margin: float = 4.0
+    margin: float = math.inf
     min_m: int | None = None
 
 
@@ -254,7 +257,8 @@ def _profile_of(prof):
 
 
 def _stats_of(stats):
-    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_})
+    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_
+                           if k != "reserved"})
 
 
 def workspace_size(n: int, d: int, learned: Learned | None = None) -> int:

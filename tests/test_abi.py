@@ -194,5 +194,5 @@ def test_struct_layouts_match_header():
     o = _opts()
     assert o.struct_size == ctypes.sizeof(L._Opts)
     assert ctypes.sizeof(L._Profile) == 11 * 8
-    assert ctypes.sizeof(L._LearnedStats) == 32
+    assert ctypes.sizeof(L._LearnedStats) == 40
     assert ctypes.sizeof(L._Job) == 10 * 8

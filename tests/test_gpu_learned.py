@@ -146,9 +146,12 @@ def test_exact_mode_and_audits_give_plain_order(lib):
                                                       margin=float(margin), min_m=64))
         lo = out["order"].cpu().numpy()
         st = out["learned_stats"]
+        print(st, flush=True)
         assert st.learned_steps == 180 - 64
         if audit == 1:
             assert st.audits == st.learned_steps
+        else:  # every step certified, decided by the suspect pass, or a full step
+            assert st.certified + st.expanded + st.fallbacks == st.learned_steps
         diff = np.flatnonzero(lo != po)
         if diff.size:
             t = int(diff[0])

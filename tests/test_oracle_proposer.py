@@ -169,10 +169,17 @@ def test_certificate_is_sound():
     assert checked > 0
 
 
+def test_suspect_cap():
+    assert P.suspect_cap(200, 64) == 32
+    assert P.suspect_cap(130, 64) == 0
+    assert P.suspect_cap(4096, 64) == 1024
+    assert P.suspect_cap(1000, 8) == 488
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_learned_order_reduces_to_plain(seed):
-    """With every uncertified step deferred (delta = +inf), or with an audit at
-    every step, the learned form must give exactly the plain order."""
+    """With delta = +inf (suspects evaluated, or the full step), or with an
+    audit at every step, the learned form must give exactly the plain order."""
     s = synth.er_sem(12, 1000, indeg=2.0, noise_family=("uniform", "laplace", "exp"),
                      seed=20 + seed)
     plain = oracle.causal_order(s.X, mode="table")
@@ -185,9 +192,15 @@ def test_learned_order_reduces_to_plain(seed):
     assert np.array_equal(o2, plain)
     o3, info3 = P.learned_order(s.X, prop, K=3, delta=-np.inf, audit_every=0, min_m=3)
     assert sorted(o3) == list(range(12))
-    assert all(i.kind in ("learned", "plain") for i in info3)
-    # every certified learned step agrees with the plain choice of that step
+    assert all(i.kind in ("learned", "plain", "expanded") for i in info3)
+    # certified and expanded steps take the plain choice of that step
     assert all(i.learned_choice == i.plain_choice for i in info3 if i.certified)
+    assert all(i.chosen == i.plain_choice for i in info3 if i.kind == "expanded")
+    # without the second pass (cap 0) uncertified steps follow the margin rule
+    o4, info4 = P.learned_order(s.X, prop, K=3, delta=np.inf, audit_every=0, min_m=3,
+                                max_suspects=0)
+    assert np.array_equal(o4, plain)
+    assert not any(i.kind == "expanded" for i in info4)
 
 
 def test_kendall_tau_matches_scipy():
