@@ -138,13 +138,21 @@ def kendall_tau(a, b) -> float:
     return float(stats.kendalltau(pa, pb)[0])
 
 
-def run_learned(lg, X, n, d, steps, warmup, proposer, plain_order, plain_ms):
+def reversed_edges(order, B) -> int:
+    """Edges of the generating DAG (B[child, parent] != 0) that `order` places
+    child first."""
+    pos = np.empty(len(order), dtype=np.int64)
+    pos[np.asarray(order)] = np.arange(len(order))
+    child, parent = np.nonzero(B)
+    return int(np.sum(pos[parent] > pos[child]))
+
+
+def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None):
     """The learned-proposal form on the same input: time per ordering, speed-up
     over the plain form, Kendall tau to the plain order, decisions, the work
-    actually performed and the candidate-row kernel against the roofline."""
+    actually performed and the candidate-row kernels against the roofline."""
     import torch
 
-    cfg = lg.Learned(proposer)
     ws = torch.empty(lg.workspace_size(n, d, cfg), dtype=torch.uint8, device="cuda:0")
     for _ in range(warmup):
         lg.causal_order(X, learned=cfg, workspace=ws)
@@ -170,13 +178,17 @@ def run_learned(lg, X, n, d, steps, warmup, proposer, plain_order, plain_ms):
         "speedup_vs_plain": plain_ms / (dt * 1e3),
         "kendall_tau": kendall_tau(order, plain_order),
         "orders_identical": bool(np.array_equal(order, plain_order)),
-        "topk": cfg.topk, "audit_every": cfg.audit_every, "margin": cfg.margin,
+        "reversed_edges": reversed_edges(order, B) if B is not None else None,
+        "topk": cfg.topk, "audit_every": cfg.audit_every,
+        "margin": cfg.margin if np.isfinite(cfg.margin) else str(cfg.margin),
+        "max_suspects": cfg.max_suspects,
         "stats": {"learned_steps": st.learned_steps, "certified": st.certified,
-                  "fallbacks": st.fallbacks, "audits": st.audits,
-                  "audit_agree": st.audit_agree},
+                  "expanded": st.expanded, "fallbacks": st.fallbacks, "audits": st.audits,
+                  "audit_agree": st.audit_agree,
+                  "suspects_mean": st.suspects_sum / max(st.learned_steps, 1)},
         "evals_done": done,
         "evals_done_per_s": done / dt,
-        "cand_kernel": {"bound": "alu", "kernel": "k_pair_cand",
+        "cand_kernel": {"bound": "alu", "kernel": "k_pair_cand + k_pair_susp",
                         "achieved": cand_evals / (cand_ms * 1e-3) / 1e9 if cand_ms else None,
                         "peak": PEAK_EVALS / 1e9, "unit": "Geval/s",
                         "frac": cand_evals / (cand_ms * 1e-3) / PEAK_EVALS if cand_ms else None,
@@ -262,6 +274,7 @@ def main() -> int:
     achieved = pl["pair_evals"] / (pl["pair_ms"] * 1e-3)
     rec = {
         "metric": f"sample-pair evals/s (plain DirectLiNGAM ordering, d={d}, n={n})",
+        "reversed_edges": reversed_edges(pl["order"], sem.B),
         "value": value,
         "unit": "sample-pair evals/s",
         "n_gpus": 1,
@@ -299,22 +312,35 @@ def main() -> int:
                   "peak": 8000.0, "unit": "GB/s"},
         "learned": None,
     }
-    if not args.no_learned:
-        if os.path.exists(tp.WEIGHTS):
-            prop = tp.default_proposer()
-            _, meta = tp.load_weights()
-            lw = max(1, args.warmup)
-            rec["learned"] = run_learned(lg, X, n, d, args.steps, lw, prop, pl["order"],
-                                         ms_per_step)
-            rec["learned"]["proposer"] = {k: meta.get(k) for k in
-                                          ("sems", "d", "n", "lists", "holdout")}
-            # ablation: the same form with an untrained (random) network
+    if not args.no_learned and not os.path.exists(tp.WEIGHTS):
+        rec["learned"] = {"error": f"no trained proposer at {tp.WEIGHTS}"}
+    elif not args.no_learned:
+        prop = tp.default_proposer()
+        _, meta = tp.load_weights()
+        lw = max(1, args.warmup)
+        K = 64 if args.workload == "gene" else 256
+        B = sem.B
+        # exact form (the default): certified, suspects evaluated, or a full step
+        exact = lg.Learned(prop, topk=K)
+        progress("learned (exact)")
+        rec["learned"] = run_learned(lg, X, n, d, args.steps, lw, exact, pl["order"],
+                                     ms_per_step, B)
+        rec["learned"]["proposer"] = {k: meta.get(k) for k in
+                                      ("sems", "d", "n", "lists", "holdout")}
+        # fast form: no second pass, the best candidate is always taken
+        fast = lg.Learned(prop, topk=K, margin=-np.inf, max_suspects=0)
+        progress("learned (fast)")
+        rec["learned"]["fast"] = run_learned(lg, X, n, d, args.steps, lw, fast, pl["order"],
+                                             ms_per_step, B)
+        if args.workload == "gene":
+            # ablation: the exact form with an untrained (random) network (not on
+            # the large workload, where it runs about as long as the plain form)
             raw = prop.clone()
             raw[32:] = torch.as_tensor(tp.init_weights(1), device=raw.device)
-            rec["learned"]["untrained"] = run_learned(lg, X, n, d, 1, 0, raw, pl["order"],
-                                                      ms_per_step)
-        else:
-            rec["learned"] = {"error": f"no trained proposer at {tp.WEIGHTS}"}
+            progress("learned (untrained)")
+            rec["learned"]["untrained"] = run_learned(lg, X, n, d, 1, 0,
+                                                      lg.Learned(raw, topk=K), pl["order"],
+                                                      ms_per_step, B)
     if not args.no_batch and args.workload == "gene":
         rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed)
     if args.copy_calibration:

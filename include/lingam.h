@@ -33,7 +33,7 @@
  * other variable's k from below (sum over candidates c of max(0, R(c, l))^2);
  * the "suspects" are the variables whose bound does not exceed the best
  * candidate's k.  (a) No suspect: the best candidate is the plain search's
- * choice (certified).  (b) At most min(1024, m/2 - topk) suspects: their rows
+ * choice (certified).  (b) At most min(max_suspects, m/2 - topk) suspects: their rows
  * are evaluated exactly in a second pass and the best of candidates and
  * suspects is the plain choice.  (c) More: the best candidate is taken when
  * its score leads every non-candidate's by at least `margin`.  Otherwise, and
@@ -125,7 +125,9 @@ typedef struct lingam_opts {
   lingam_profile* profile;      /* HOST pointer or NULL: per-kernel timings (forces sync) */
   /* learned-proposal form (see the top of this file) */
   const float* proposer;        /* device FP32[LINGAM_PROPOSER_SIZE] or NULL: plain search */
-  int32_t topk;                 /* candidates per learned step: multiple of 8 in [8, 256];
+  int32_t topk;                 /* most candidates per learned step: multiple of 8 in
+                                   [8, 256]; a step with m variables takes about m/16 of
+                                   them (a multiple of 8), at least min(64, topk);
                                    default 64 */
   int32_t audit_every;          /* full-step audit when t % audit_every == 0; 0 = never;
                                    default 32 */
@@ -138,6 +140,13 @@ typedef struct lingam_opts {
   float* record_features;       /* device FP32[(d-1) * d * 16] or NULL: the 16 features of
                                    every active variable at every step, by step and original
                                    column id (training data); unwritten entries untouched */
+  int32_t max_suspects;         /* most suspects the second pass evaluates (0 = no second
+                                   pass); default 1024 */
+  int32_t reserved1;
+  int32_t* step_log;            /* device int32[d] or NULL (learned form): per step, the low
+                                   4 bits are 0 plain step, 1 learned choice, 2 full step
+                                   (fallback or forcing), 3 audit, 4 decided by the suspect
+                                   pass; the bits above hold the step's suspect count */
 } lingam_opts;
 
 /* Fill *opts with defaults (no forcing, no extra outputs, plain search, synchronous). */

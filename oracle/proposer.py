@@ -238,6 +238,13 @@ def topk(scores, slots, K: int) -> np.ndarray:
     return np.array(idx[:K], dtype=np.int64)
 
 
+def step_topk(m: int, K: int) -> int:
+    """Candidates of a learned step with m variables and at most K: about m/16
+    rounded up to a multiple of 8, at least min(64, K), at most K."""
+    k = -(-(m // 16) // 8) * 8
+    return min(max(k, min(64, K)), K)
+
+
 def suspect_cap(m: int, K: int, cap: int = 1024) -> int:
     """Most suspects the second pass evaluates at a step with m variables."""
     c = min(m // 2 - K, cap)
@@ -276,7 +283,8 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
     delta: score margin that accepts the best candidate when the suspects
     are too many for the second pass (+inf: never, so the order is the plain
     order).  audit_every: full step at t % audit_every == 0 (0: no audits).
-    Steps with m <= min_m (default 2K) are plain steps.
+    Steps with m <= min_m (default 2 min(K, 64)) are plain steps.  K is the
+    most candidates; a step with m variables takes step_topk(m, K).
     Returns (order, [StepInfo]).
     """
     X = np.asarray(np.asarray(X, dtype=np.float32), dtype=np.float64).copy()
@@ -284,7 +292,7 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
     prop = np.asarray(proposer, dtype=np.float64)
     norm, flat = prop[:N_NORM], prop[N_NORM:]
     if min_m is None:
-        min_m = 2 * K
+        min_m = 2 * min(K, 64)
     U = list(range(d))
     order, info = [], []
     t = 0
@@ -302,7 +310,8 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             s, _ = forward(flat, normalize(F, norm), emulate_bf16)
             if emulate_bf16:
                 s = s.astype(np.float32).astype(np.float64)
-            C = topk(s, U, K)
+            Kt = step_topk(m, K)
+            C = topk(s, U, Kt)
             inC = np.zeros(m, dtype=bool)
             inC[C] = True
             best = C[0]
@@ -318,7 +327,7 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             margin = s[best] - s_out
             audit = audit_every > 0 and t % audit_every == 0
             expand = (not audit) and (not certified) and \
-                sus.size <= suspect_cap(m, K, max_suspects)
+                sus.size <= suspect_cap(m, Kt, max_suspects)
             if audit:
                 p, kind = pc, "audit"
             elif certified:

@@ -153,12 +153,13 @@ struct HostJob {
   const int32_t* forced;
   int32_t forced_len;
   float* record = nullptr;  // optional feature record
+  int32_t* step_log = nullptr;  // optional per-step decision log (learned form)
 };
 
 // Learned-form configuration of a call (proposer == NULL: plain search).
 struct Learn {
   const float* proposer = nullptr;
-  int32_t K = 0, min_m = 0, audit_every = 0;
+  int32_t K = 0, min_m = 0, audit_every = 0, max_suspects = 0;
   float delta = 0.f;
 };
 
@@ -170,6 +171,7 @@ Learn learn_of(const lingam_opts* o) {
   l.min_m = o->learned_min_m;
   l.audit_every = o->audit_every;
   l.delta = o->margin;
+  l.max_suspects = o->max_suspects;
   return l;
 }
 
@@ -257,8 +259,8 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
       J.rc = reinterpret_cast<double*>(b + L.rc);
       J.kc = reinterpret_cast<double*>(b + L.kc);
       J.lb = reinterpret_cast<double*>(b + L.lb);
-      J.steplog = reinterpret_cast<int32_t*>(b + L.steplog);
-      J.cap_s = L.cap_s;
+      J.steplog = h.step_log ? h.step_log : reinterpret_cast<int32_t*>(b + L.steplog);
+      J.cap_s = std::min<int32_t>(L.cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars);
       J.cand2 = reinterpret_cast<int32_t*>(b + L.cand2);
       J.parts = reinterpret_cast<double*>(b + L.parts);
       J.rc2 = reinterpret_cast<double*>(b + L.rc2);
@@ -288,17 +290,19 @@ StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, l
     lg::job_split(js[k], (int32_t)P.L[k].n_pad, items, P.cu, tu);
     lg::job_split_cand(js[k], (int32_t)P.L[k].n_pad, items_c, P.cu, tu);
     for (int kind = 0; kind < lg::kNumKinds; ++kind)
-      T.g[kind] += lg::kind_count(js[k], kind, K);
+      T.g[kind] += lg::kind_count(js[k], kind);
     const int m = js[k].m;
     if (m >= 2 && !js[k].fp64) T.pair_evals += (double)m * (m - 1) * (double)jobs[k].n;
     if (js[k].learned) {
-      T.cand_evals += 2.0 * K * (double)(m - 1) * (double)jobs[k].n;
+      T.cand_evals += 2.0 * js[k].k * (double)(m - 1) * (double)jobs[k].n;
       // bounds of the suspect pass (its size is decided on the device)
       lg::JobStep b = js[k];
-      b.nsus = lg::suspect_cap(m, K, P.L[k].cap_s);
+      b.nsus = lg::suspect_cap(
+          m, b.k,
+          std::min<int32_t>(P.L[k].cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars));
       b.nct2 = lg::cdiv(b.nsus, lg::kTileVars) * b.nblk;
       for (int kind = lg::kKPairS; kind <= lg::kKLsel2; ++kind)
-        T.g[kind] += lg::kind_count(b, kind, K);
+        T.g[kind] += lg::kind_count(b, kind);
     }
     if (m > 2) T.resid_bytes += 28.0 * (double)jobs[k].n * (double)(m - 1);
   }
@@ -693,10 +697,13 @@ int check_learn(const lingam_opts* opts) {
                 lg::kMaxTopK);
   if (opts->audit_every < 0)
     return fail(LINGAM_E_INVALID, "audit_every %d < 0", opts->audit_every);
-  if (opts->learned_min_m < opts->topk || opts->learned_min_m < lg::kFp64MaxM)
-    return fail(LINGAM_E_INVALID, "learned_min_m %d must be >= topk and >= %d",
+  const int32_t k_lo = opts->topk < 64 ? opts->topk : 64;
+  if (opts->learned_min_m < 2 * k_lo || opts->learned_min_m < lg::kFp64MaxM)
+    return fail(LINGAM_E_INVALID, "learned_min_m %d must be >= 2 min(topk, 64) and >= %d",
                 opts->learned_min_m, lg::kFp64MaxM);
   if (opts->margin != opts->margin) return fail(LINGAM_E_INVALID, "margin is NaN");
+  if (opts->max_suspects < 0)
+    return fail(LINGAM_E_INVALID, "max_suspects %d < 0", opts->max_suspects);
   return LINGAM_OK;
 }
 
@@ -747,6 +754,7 @@ void lingam_opts_init(lingam_opts* o) {
   o->audit_every = 32;
   o->margin = INFINITY;
   o->learned_min_m = 128;
+  o->max_suspects = lg::kMaxSuspects;
 }
 
 const char* lingam_last_error(void) { return g_err; }
@@ -788,7 +796,7 @@ int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32
   rc = num_cu_of_current(&cu);
   if (rc != LINGAM_OK) return rc;
   const HostJob j{X,     nullptr, n, ldx, n, d, order, opts->step_measures, opts->step_gap,
-                  opts->forced_order, opts->forced_len, opts->record_features};
+                  opts->forced_order, opts->forced_len, opts->record_features, opts->step_log};
   const std::vector<HostJob> jobs{j};
   const Plan P = make_plan(jobs, cu, learn_of(opts));
   if (!ws || ws_bytes < P.total)
@@ -899,7 +907,7 @@ int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lag
   // the VAR residuals are the job's data rows: no X for the ingest kernel
   const HostJob j{nullptr,         nullptr,      T - lags, d, T - lags, d, order,
                   opts->step_measures, opts->step_gap, opts->forced_order, opts->forced_len,
-                  opts->record_features};
+                  opts->record_features, opts->step_log};
   const std::vector<HostJob> jobs{j};
   const Plan P = make_plan(jobs, cu, learn_of(opts));
   const lg::VarLayout V = lg::make_var_layout(T, d, lags, cu);

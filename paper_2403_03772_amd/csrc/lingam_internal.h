@@ -187,7 +187,17 @@ struct JobStep {
   int32_t split_len_c;
   int32_t nsus;       // suspects of the second pass (set after the learned decision)
   int32_t nct2;       // suspect tiles ceil(nsus / 8) * nblk
+  int32_t k;          // candidates of this step's learned pass
 };
+
+// Candidates of a learned step with m active variables and at most K: about
+// m / 16 (a multiple of 8), at least min(64, K) and at most K.
+__host__ __device__ inline int32_t step_topk(int32_t m, int32_t K) {
+  const int32_t lo = K < 64 ? K : 64;
+  int32_t k = (m / 16 + kTileVars - 1) / kTileVars * kTileVars;
+  k = k < lo ? lo : k;
+  return k > K ? K : k;
+}
 
 // Workgroup-count kinds with a prefix array each.
 enum Kind : int {
@@ -282,7 +292,10 @@ __host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t, int32_t K
   }
   s.learned = K > 0 && m > min_m && !s.fp64;
   s.feat = s.learned || rec;
-  if (s.learned) s.nct = (K / kTileVars) * s.nblk;
+  if (s.learned) {
+    s.k = step_topk(m, K);
+    s.nct = (s.k / kTileVars) * s.nblk;
+  }
   return s;
 }
 
@@ -321,7 +334,7 @@ __host__ __device__ inline void job_split_cand(JobStep& s, int32_t n_pad, int64_
   s.split_len_c = c.split_len;
 }
 
-__host__ __device__ inline int32_t kind_count(const JobStep& s, int kind, int32_t K = 0) {
+__host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
   if (s.m < 2) return 0;
   if (s.gate && gated_kind(kind)) return 0;
   switch (kind) {
@@ -336,7 +349,7 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind, int32_
     case kKTopk: return s.learned ? 1 : 0;
     case kKPairC: return s.learned ? s.nct * 2 * s.nsplit_c : 0;
     case kKCombC: return s.learned ? cdiv(s.nct, 4) : 0;
-    case kKRowkC: return s.learned ? cdiv(K, 4) : 0;
+    case kKRowkC: return s.learned ? cdiv(s.k, 4) : 0;
     case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
     case kKPairS: return s.nct2 * 2 * s.nsplit_c;

@@ -81,10 +81,8 @@ __device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, i
   const int lane = threadIdx.x & 63;
   JobStep s{};
   long long mine = 0, mine_c = 0;
-  int K = 0;
   if (lane < njobs) {
     const JobDev& J = jobs[lane];
-    K = J.K;
     s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
     if (s.m >= 2 && !s.fp64) mine = 2LL * s.ntiles;
     if (s.learned) mine_c = 2LL * s.nct;
@@ -101,7 +99,7 @@ __device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, i
     js[lane] = s;
   }
   for (int kind = 0; kind < kNumKinds; ++kind) {
-    const int32_t c = lane < njobs ? kind_count(s, kind, K) : 0;
+    const int32_t c = lane < njobs ? kind_count(s, kind) : 0;
     int32_t total;
     const int32_t ex = wave_excl_scan(c, total);
     int32_t* out = pre + (int64_t)kind * (njobs + 1);
@@ -147,7 +145,7 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
   __syncthreads();
   for (int kind = 0; kind < kNumKinds; ++kind)
     block_scan(
-        njobs, [&](int j) { return kind_count(js[j], kind, jobs[j].K); },
+        njobs, [&](int j) { return kind_count(js[j], kind); },
         pre + (int64_t)kind * (njobs + 1), sh);
 }
 
@@ -161,16 +159,14 @@ __global__ __launch_bounds__(1024) void k_gate_schedule(const JobDev* __restrict
     if (threadIdx.x >= 64) return;
     const int lane = threadIdx.x;
     JobStep s{};
-    int K = 0;
     if (lane < njobs) {
       s = js[lane];
       s.gate = s.learned && jobs[lane].ctrl->full == 0;
       js[lane] = s;
-      K = jobs[lane].K;
     }
     for (int kind = 0; kind < kNumKinds; ++kind) {
       if (!gated_kind(kind)) continue;
-      const int32_t c = lane < njobs ? kind_count(s, kind, K) : 0;
+      const int32_t c = lane < njobs ? kind_count(s, kind) : 0;
       int32_t total;
       const int32_t ex = wave_excl_scan(c, total);
       int32_t* out = pre + (int64_t)kind * (njobs + 1);
@@ -189,7 +185,7 @@ __global__ __launch_bounds__(1024) void k_gate_schedule(const JobDev* __restrict
   for (int kind = 0; kind < kNumKinds; ++kind)
     if (gated_kind(kind))
       block_scan(
-          njobs, [&](int j) { return kind_count(js[j], kind, jobs[j].K); },
+          njobs, [&](int j) { return kind_count(js[j], kind); },
           pre + (int64_t)kind * (njobs + 1), sh);
 }
 
@@ -1022,7 +1018,7 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
       JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
       if (!s.learned) continue;
       job_split_cand(s, (int32_t)L.n_pad, 2LL * s.nct, num_cu, worst);
-      const int32_t cs = suspect_cap(s.m, K, L.cap_s);
+      const int32_t cs = suspect_cap(s.m, s.k, L.cap_s);
       const size_t need = (size_t)cdiv(cs, kTileVars) * s.nblk * (size_t)s.nsplit_c * 256;
       if (need > ps) ps = need;
     }

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
   int jb, lb;
   if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
   const JobDev& J = jobs[jb];
-  const int m = js[jb].m, K = J.K;
+  const int m = js[jb].m, K = js[jb].k;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto key = [&](int p) -> unsigned long long {
     return ((unsigned long long)ord_f32(J.score[p]) << 32) |
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_cand_rowk(const JobDev* __restrict__ jo
   const int m = js[jb].m;
   const int lane = threadIdx.x & 63;
   const int c = lb * 4 + (threadIdx.x >> 6);
-  if (c >= J.K) return;
+  if (c >= js[jb].k) return;
   const double* row = J.rc + (int64_t)c * J.d;
   double k = 0.0;
   for (int q = lane; q < m; q += 64) {
@@ -508,9 +508,10 @@ __global__ __launch_bounds__(256) void k_cand_colk(const JobDev* __restrict__ jo
   const int m = js[jb].m;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l = lb * 64 + lane;
+  const int K = js[jb].k;
   double s = 0.0;
   if (l < m)
-    for (int c = wave; c < J.K; c += 4) {
+    for (int c = wave; c < K; c += 4) {
       const double x = J.rc[(int64_t)c * J.d + l];
       const double ps = x > 0.0 ? x : 0.0;
       s += ps * ps;
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
   int jb, lb;
   if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
   const JobDev& J = jobs[jb];
-  const int m = js[jb].m, K = J.K;
+  const int m = js[jb].m, K = js[jb].k;
   const int tid = threadIdx.x;
   const Best best =
       best_of_rows(J.kc, J.cand, K, J.act, Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
@@ -762,14 +763,14 @@ __global__ __launch_bounds__(256) void k_lselect2(const JobDev* __restrict__ job
     const JobDev& J = jobs[jb];
     const JobStep S = js[jb];
     const int tid = threadIdx.x;
-    Best b = best_of_rows(J.kc, J.cand, J.K, J.act,
+    Best b = best_of_rows(J.kc, J.cand, S.k, J.act,
                           Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
     b = best_of_rows(J.kc2, J.cand2, S.nsus, J.act, b, sh);
     if (J.measures) {
       double* row = J.measures + (int64_t)t * J.d;
       for (int v = tid; v < J.d; v += 256) row[v] = NAN;
       __syncthreads();
-      for (int c = tid; c < J.K; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
+      for (int c = tid; c < S.k; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
       for (int c = tid; c < S.nsus; c += 256) row[J.act[J.cand2[c]]] = -J.kc2[c];
     }
     __syncthreads();

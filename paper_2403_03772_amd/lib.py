@@ -84,6 +84,9 @@ class _Opts(ctypes.Structure):
         ("learned_min_m", ctypes.c_int32),
         ("learned_stats", ctypes.POINTER(_LearnedStats)),
         ("record_features", ctypes.c_void_p),
+        ("max_suspects", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
+        ("step_log", ctypes.c_void_p),
     ]
 
 
@@ -138,6 +141,7 @@ class Learned:
     audit_every: int = 32
     margin: float = math.inf
     min_m: int | None = None
+    max_suspects: int = 1024
 
 
 def load():
@@ -241,7 +245,8 @@ def _new_opts(lib, *, sync=True, graph=False, autotune=False, learned=None, prof
         opts.audit_every = int(learned.audit_every)
         opts.margin = float(learned.margin)
         opts.learned_min_m = int(learned.min_m if learned.min_m is not None
-                                 else max(2 * learned.topk, 64))
+                                 else max(2 * min(learned.topk, 64), 64))
+        opts.max_suspects = int(learned.max_suspects)
         stats = _LearnedStats()
         opts.learned_stats = ctypes.pointer(stats)
         if keep is not None:
@@ -275,7 +280,7 @@ def residualize_workspace_size(n: int, d: int) -> int:
 def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool = False,
                  workspace=None, sync: bool = True, graph: bool = False,
                  autotune: bool = False, learned: Learned | None = None,
-                 record_features: bool = False):
+                 record_features: bool = False, step_log: bool = False):
     """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
 
     Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
@@ -284,7 +289,8 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     FP32, NaN where not recorded) and ``learned_stats`` when any of those is
     asked for.  ``forced`` (sequence or tensor of column ids) fixes the first
     ``len(forced)`` choices (teacher forcing).  ``learned`` switches on the
-    learned-proposal form.
+    learned-proposal form; ``step_log`` returns its per-step decisions (see
+    ``lingam_opts.step_log``).
     """
     import torch
 
@@ -311,6 +317,10 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     if record_features and d > 1:
         feats = torch.full((d - 1, d, N_FEATURES), math.nan, dtype=torch.float32, device=dev)
         opts.record_features = feats.data_ptr()
+    slog = None
+    if step_log:
+        slog = torch.zeros(d, dtype=torch.int32, device=dev)
+        opts.step_log = slog.data_ptr()
     need = int(lib.lingam_workspace_size(n, d, ctypes.byref(opts)))
     if need == 0:
         raise LingamError(E_UNSUPPORTED, last_error() or f"unsupported size n={n} d={d}")
@@ -319,9 +329,11 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     code = lib.lingam_causal_order(_ptr(X), n, d, ldx, _ptr(order), ctypes.byref(opts),
                                    _ptr(workspace), workspace.numel(), _stream_ptr(torch, dev))
     _check(code)
-    if not (with_measures or profile or record_features or learned is not None):
+    if not (with_measures or profile or record_features or step_log or learned is not None):
         return order
     out = {"order": order, "measures": meas, "gaps": gaps, "workspace": workspace}
+    if slog is not None:
+        out["step_log"] = slog
     if feats is not None:
         out["features"] = feats
     if prof is not None:

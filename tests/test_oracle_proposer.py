@@ -169,6 +169,16 @@ def test_certificate_is_sound():
     assert checked > 0
 
 
+def test_step_topk():
+    assert P.step_topk(4096, 256) == 256
+    assert P.step_topk(2000, 256) == 128
+    assert P.step_topk(1024, 256) == 64
+    assert P.step_topk(300, 256) == 64
+    assert P.step_topk(4096, 64) == 64
+    assert P.step_topk(100, 8) == 8
+    assert P.step_topk(1000, 3) == 3
+
+
 def test_suspect_cap():
     assert P.suspect_cap(200, 64) == 32
     assert P.suspect_cap(130, 64) == 0
