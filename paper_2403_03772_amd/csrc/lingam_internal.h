@@ -208,12 +208,12 @@ enum Kind : int {
   kKSel,        // k_select: 1
   kKRes,        // k_resid: m - 1 when m > 2
   kKFeat,       // k_features: ceil(m / 4)
-  kKMlp,        // k_mlp: ceil(m / 64)
+  kKMlp,        // k_mlp: ceil(m / 16)
   kKTopk,       // k_topk: 1
   kKPairC,      // k_pair_cand: nct * 2 * nsplit_c
   kKCombC,      // k_combine_cand: ceil(nct / 4)
-  kKRowkC,      // k_cand_rowk: K / 4
-  kKColC,       // k_cand_colk: ceil(m / 64)
+  kKRowkC,      // k_cand_k rows: K / 4
+  kKColC,       // k_cand_k columns: ceil(m / 64)
   kKLsel,       // k_lselect: 1
   kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c (after the learned decision)
   kKCombS,      // k_combine_susp: ceil(nct2 / 4)
@@ -345,7 +345,7 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
     case kKSel: return 1;
     case kKRes: return s.m > 2 ? s.m - 1 : 0;
     case kKFeat: return s.feat ? cdiv(s.m, 4) : 0;
-    case kKMlp: return s.learned ? cdiv(s.m, 64) : 0;
+    case kKMlp: return s.learned ? cdiv(s.m, 16) : 0;
     case kKTopk: return s.learned ? 1 : 0;
     case kKPairC: return s.learned ? s.nct * 2 * s.nsplit_c : 0;
     case kKCombC: return s.learned ? cdiv(s.nct, 4) : 0;

@@ -11,14 +11,15 @@
 //                   of its marginal entropy, progress of the search)
 //   k_mlp           scores of a 16 -> 128 -> 128 -> 1 ReLU network, BF16
 //                   weights and activations on MFMA, FP32 accumulation
+//                   (the same code as the scores entry point's k_scores)
 //   k_topk          the K best scores (ties to the smaller original id) by an
 //                   8-bit radix select over 64-bit keys
 //   k_pair_cand     the pair moments of every (candidate, active) pair: the
 //                   all-pairs hot loop on (K / 8) x nblk tiles
 //   k_combine_cand  R(c, j) of every candidate row
-//   k_cand_rowk     exact k of every candidate
-//   k_cand_colk     for every other variable l, the lower bound
-//                   sum_c max(0, R(c, l))^2 <= k_l its candidate pairs give
+//   k_cand_k        exact k of every candidate, and for every other variable
+//                   l the lower bound sum_c max(0, R(c, l))^2 <= k_l its
+//                   candidate pairs give
 //   k_lselect       best candidate; it is certified when every lower bound
 //                   exceeds its k, and accepted when certified or when its
 //                   score beats every non-candidate's by the margin; audit
@@ -288,17 +289,86 @@ __device__ void mlp_tile(const PropDev& W, MlpShared& S, const float* __restrict
   }
 }
 
-// Scores of the active positions of every learned job, 64 per workgroup.
+// Inference of rows row0 .. row0 + 15 (rows >= nrows are zero inputs and
+// produce nothing): the four waves split the hidden units (wave w owns units
+// 32 w .. 32 w + 31 of both layers), share the first layer through LDS and add
+// their partial scores in a fixed order.  Same arithmetic as mlp_tile.
+struct Mlp16Shared {
+  uint16_t h1[16][kLdW];
+  float part[4][16];
+};
+
+__device__ void mlp16(const PropDev& W, Mlp16Shared& S, const float* __restrict__ feat,
+                      int64_t row0, int64_t nrows, float* __restrict__ score) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg4 = (lane >> 4) * 4;
+  bf16x4_t xa;
+  {
+    const int64_t row = row0 + li;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = lg4 + j;
+      float v = 0.f;
+      if (row < nrows) v = (feat[row * kFeat + f] - W.mu[f]) / W.sd[f];
+      xa[j] = (short)to_bf16(v);
+    }
+  }
+#pragma unroll
+  for (int t2 = 0; t2 < 2; ++t2) {
+    const int n = (wave * 2 + t2) * 16 + li;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma16(xa, load4(&W.w1[n * kFeat + lg4]), acc);
+    const float b = W.b1[n];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S.h1[lg4 + r][n] = to_bf16(fmaxf(acc[r] + b, 0.f));
+  }
+  __syncthreads();
+  float ps[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t2 = 0; t2 < 2; ++t2) {
+    const int n = (wave * 2 + t2) * 16 + li;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kHidden / 16; ++ks)
+      acc = mfma16(load4(&S.h1[li][ks * 16 + lg4]),
+                   load4(&W.w2[n * kHidden + ks * 16 + lg4]), acc);
+    const float b2 = W.b2[n], w3 = from_bf16(W.w3[n]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ps[r] = fmaf(fmaxf(acc[r] + b2, 0.f), w3, ps[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) ps[r] += __shfl_xor(ps[r], off);
+  if (li == 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S.part[wave][lg4 + r] = ps[r];
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int64_t row = row0 + threadIdx.x;
+    const float sc = ((S.part[0][threadIdx.x] + S.part[1][threadIdx.x]) +
+                      S.part[2][threadIdx.x]) + S.part[3][threadIdx.x];
+    if (row < nrows) score[row] = sc + W.b3;
+  }
+}
+
+// Scores of the active positions of every learned job, 16 per workgroup.
 __global__ __launch_bounds__(256) void k_mlp(const JobDev* __restrict__ jobs, int njobs,
                                              const JobStep* __restrict__ js,
                                              const int32_t* __restrict__ pre) {
-  __shared__ MlpShared S;
+  __shared__ Mlp16Shared S;
   int jb, lb;
   if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
   const JobDev& J = jobs[jb];
-  stage_w2(*J.prop, S);
-  __syncthreads();
-  mlp_tile(*J.prop, S, J.feat, (int64_t)lb * 64, js[jb].m, J.score, nullptr, nullptr);
+  mlp16(*J.prop, S, J.feat, (int64_t)lb * 16, js[jb].m, J.score);
+}
+
+// Scores of `rows` feature rows (the C entry point), 16 per workgroup.
+__global__ __launch_bounds__(256) void k_scores(const PropDev* __restrict__ W,
+                                                const float* __restrict__ feat, int64_t rows,
+                                                float* __restrict__ score) {
+  __shared__ Mlp16Shared S;
+  mlp16(*W, S, feat, (int64_t)blockIdx.x * 16, rows, score);
 }
 
 // ---------------------------------------------------------------------------
@@ -322,7 +392,7 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
                                                const int32_t* __restrict__ pre, int t) {
   __shared__ uint32_t hist[256];
   __shared__ unsigned long long s_prefix;
-  __shared__ int s_need;
+  __shared__ int s_need, s_done;
   __shared__ int32_t scan[1024];
   __shared__ float smax[16];
   int jb, lb;
@@ -337,6 +407,7 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
   if (tid == 0) {
     s_prefix = 0ull;
     s_need = K;
+    s_done = 0;
   }
   unsigned long long prefix = 0ull, mask = 0ull;
   for (int pass = 0; pass < 8; ++pass) {
@@ -378,11 +449,15 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
         }
         s_prefix = s_prefix | ((unsigned long long)dg << shift);
         s_need = need - (int)excl;
+        // every key in this digit's bucket is needed: the K-th largest key
+        // is at or above the prefix with the lower bits cleared
+        if (hist[dg] == (uint32_t)(need - (int)excl)) s_done = 1;
       }
     }
     __syncthreads();
     prefix = s_prefix;
     mask |= 0xFFull << shift;
+    if (s_done) break;
   }
   // prefix is the K-th largest key; compact positions p with key(p) >= prefix
   const int per = (m + 1023) / 1024;
@@ -471,44 +546,43 @@ __global__ __launch_bounds__(256) void k_combine_cand(const JobDev* __restrict__
   *out = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
 }
 
-// kc[c] = sum_j min(0, R(c, j))^2, one wave per candidate.
-__global__ __launch_bounds__(256) void k_cand_rowk(const JobDev* __restrict__ jobs, int njobs,
-                                                   const JobStep* __restrict__ js,
-                                                   const int32_t* __restrict__ pre) {
-  int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
-  const JobDev& J = jobs[jb];
-  const int m = js[jb].m;
-  const int lane = threadIdx.x & 63;
-  const int c = lb * 4 + (threadIdx.x >> 6);
-  if (c >= js[jb].k) return;
-  const double* row = J.rc + (int64_t)c * J.d;
-  double k = 0.0;
-  for (int q = lane; q < m; q += 64) {
-    const double x = row[q];
-    const double ng = x < 0.0 ? x : 0.0;
-    k += ng * ng;
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
-  if (lane == 0) J.kc[c] = k;
-}
-
-// lb[l] = sum_c max(0, R(c, l))^2 for non-candidate positions (a lower bound
-// of k_l, since R(l, c) = -R(c, l)); +inf at candidate positions.  A
-// workgroup covers 64 positions; wave w sums candidates c = w, w + 4, ...,
-// and the four partial sums are added in a fixed order.
-__global__ __launch_bounds__(256) void k_cand_colk(const JobDev* __restrict__ jobs, int njobs,
-                                                   const JobStep* __restrict__ js,
-                                                   const int32_t* __restrict__ pre, int t) {
+// Exact k of every candidate (kc[c] = sum_j min(0, R(c, j))^2, one wave per
+// candidate) and the lower bound of every other variable's k (lb[l] = sum_c
+// max(0, R(c, l))^2, since R(l, c) = -R(c, l); +inf at candidate positions).
+// One launch: the first workgroups (the row kind's schedule) do the rows, the
+// rest (the column kind's) the columns; a column workgroup covers 64
+// positions, wave w summing candidates c = w, w + 4, ... in a fixed order.
+__global__ __launch_bounds__(256) void k_cand_k(const JobDev* __restrict__ jobs, int njobs,
+                                                const JobStep* __restrict__ js,
+                                                const int32_t* __restrict__ pre_row,
+                                                const int32_t* __restrict__ pre_col, int t) {
   __shared__ double part[4][64];
+  const int nrow = pre_row[njobs];
   int jb, lb;
-  if (!locate(pre, njobs, blockIdx.x, jb, lb)) return;
+  if (blockIdx.x < nrow) {
+    if (!locate(pre_row, njobs, blockIdx.x, jb, lb)) return;
+    const JobDev& J = jobs[jb];
+    const int m = js[jb].m;
+    const int lane = threadIdx.x & 63;
+    const int c = lb * 4 + (threadIdx.x >> 6);
+    if (c >= js[jb].k) return;
+    const double* row = J.rc + (int64_t)c * J.d;
+    double k = 0.0;
+    for (int q = lane; q < m; q += 64) {
+      const double x = row[q];
+      const double ng = x < 0.0 ? x : 0.0;
+      k += ng * ng;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
+    if (lane == 0) J.kc[c] = k;
+    return;
+  }
+  if (!locate(pre_col, njobs, blockIdx.x - nrow, jb, lb)) return;
   const JobDev& J = jobs[jb];
-  const int m = js[jb].m;
+  const int m = js[jb].m, K = js[jb].k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l = lb * 64 + lane;
-  const int K = js[jb].k;
   double s = 0.0;
   if (l < m)
     for (int c = wave; c < K; c += 4) {
@@ -1072,10 +1146,9 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
   if (grid[kKLsel] <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine_cand, dim3((unsigned)grid[kKCombC]), dim3(256), 0, st, jobs,
                      njobs, js, pre_kind(sc, njobs, kKCombC));
-  hipLaunchKernelGGL(k_cand_rowk, dim3((unsigned)grid[kKRowkC]), dim3(256), 0, st, jobs, njobs,
-                     js, pre_kind(sc, njobs, kKRowkC));
-  hipLaunchKernelGGL(k_cand_colk, dim3((unsigned)grid[kKColC]), dim3(256), 0, st, jobs, njobs,
-                     js, pre_kind(sc, njobs, kKColC), t);
+  hipLaunchKernelGGL(k_cand_k, dim3((unsigned)(grid[kKRowkC] + grid[kKColC])), dim3(256), 0, st,
+                     jobs, njobs, js, pre_kind(sc, njobs, kKRowkC), pre_kind(sc, njobs, kKColC),
+                     t);
   hipLaunchKernelGGL(k_lselect, dim3((unsigned)grid[kKLsel]), dim3(256), 0, st, jobs, njobs, js,
                      pre_kind(sc, njobs, kKLsel), t);
   return hipGetLastError();
@@ -1138,9 +1211,8 @@ hipError_t launch_scores(const float* prop, const float* feat, int64_t rows, flo
   PropDev* W = reinterpret_cast<PropDev*>(ws);
   hipLaunchKernelGGL(k_prop_prep, dim3(1), dim3(256), 0, st, prop, W, (const JobDev*)nullptr, 0,
                      (int32_t*)nullptr);
-  const int64_t ntile = (rows + 63) / 64;
-  hipLaunchKernelGGL(k_train_fwd, dim3((unsigned)ntile), dim3(256), 0, st, (const PropDev*)W,
-                     feat, rows, score, (uint16_t*)nullptr, (float*)nullptr);
+  hipLaunchKernelGGL(k_scores, dim3((unsigned)((rows + 15) / 16)), dim3(256), 0, st,
+                     (const PropDev*)W, feat, rows, score);
   return hipGetLastError();
 }
 
