@@ -234,9 +234,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("gene", "large"), default="gene",
+    ap.add_argument("--workload", choices=("gene", "large", "batch"), default="gene",
                     help="gene: d=1024, n=8192 (default); large: d=4096, n=16384 "
-                         "(learned vs plain at scale; one plain ordering takes ~2 min)")
+                         "(learned vs plain at scale; one plain ordering takes ~2 min); "
+                         "batch: the bootstrap batch alone")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
@@ -257,6 +258,16 @@ def main() -> int:
     import paper_2403_03772_amd as lg
     from paper_2403_03772_amd import synth
     from paper_2403_03772_amd import train_proposer as tp
+
+    if args.workload == "batch":
+        b = bench_batch(max(1, args.steps), args.warmup, args.seed)
+        rec = {"metric": "sample-pair evals/s (batched bootstrap orderings)",
+               "value": b["value"], "unit": b["unit"], "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": b["ms"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": b["workload"], "jobs": b["jobs"]}, "batch": b}
+        print(json.dumps(rec), flush=True)
+        return 0
 
     d, n = (1024, 8192) if args.workload == "gene" else (4096, 16384)
     if args.workload == "large" and args.steps == 3 and args.warmup == 1:

@@ -80,16 +80,36 @@ __device__ double block_sum_256(double v, double* sh) {
   return r;
 }
 
-// Per-sample terms of the five moments kept for every variable:
-// log cosh z, z exp(-z^2/2), z^3, z^4, |z|.
-__device__ inline void add_moments(double z, double (&acc)[5]) {
-  const double z2 = z * z;
-  acc[0] += logcosh64(z);
-  acc[1] += gauss64(z);
-  acc[2] += z2 * z;
-  acc[3] += z2 * z2;
-  acc[4] += fabs(z);
-}
+// Per-thread sums of the five moments kept for every variable: log cosh z,
+// z exp(-z^2/2), z^3, z^4, |z|.  log cosh z = |z| + log(1 + e^{-2|z|}) - ln 2;
+// the logs are taken as the log of a running product (each factor in (1, 2],
+// flushed every 512 samples), one FP64 log per 512 samples.
+struct MomAcc {
+  double abs_sum = 0.0, log_sum = 0.0, g = 0.0, z3 = 0.0, z4 = 0.0, prod = 1.0;
+  int cnt = 0, tot = 0;
+  __device__ inline void add(double z) {
+    const double a = fabs(z), z2 = z * z;
+    abs_sum += a;
+    prod *= 1.0 + exp(-2.0 * a);
+    g += z * exp(-0.5 * z2);
+    z3 += z2 * z;
+    z4 += z2 * z2;
+    ++tot;
+    if (++cnt == 512) {
+      log_sum += log(prod);
+      prod = 1.0;
+      cnt = 0;
+    }
+  }
+  // the five sums in the order of store_moments
+  __device__ inline void sums(double (&acc)[5]) const {
+    acc[0] = abs_sum + (log_sum + log(prod)) - (double)tot * kLn2;
+    acc[1] = g;
+    acc[2] = z3;
+    acc[3] = z4;
+    acc[4] = abs_sum;
+  }
+};
 
 // Block-wide deterministic sum of five FP64 values (256 threads): wave
 // butterflies, then the four wave totals in order.  `sh` holds 20 doubles.

@@ -365,17 +365,19 @@ __global__ __launch_bounds__(256) void k_standardize(const JobDev* __restrict__ 
   float* zf = J.z + (int64_t)v * J.ldz;
   const double m = J.mu[v], is = 1.0 / J.sig[v];
   const int n = J.n;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  MomAcc ma;
   for (int k = threadIdx.x; k < J.n_pad; k += 256) {
     if (k < n) {
       const double z = (zd[k] - m) * is;
       zd[k] = z;
       zf[k] = (float)z;
-      add_moments(z, acc);
+      ma.add(z);
     } else {
       zf[k] = 0.f;
     }
   }
+  double acc[5];
+  ma.sums(acc);
   block_sum_5(acc, sh);
   if (threadIdx.x == 0) store_moments(J, v, acc, n);
 }
@@ -624,13 +626,15 @@ __global__ __launch_bounds__(256) void k_resid(const JobDev* __restrict__ jobs, 
   const double* ze = J.zd + (int64_t)se * ldz;
   float* zf = J.z + (int64_t)sp * ldz;
   const int n = J.n;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  MomAcc ma;
   for (int k = threadIdx.x; k < J.n_pad; k += 256) {
     const double z = al * (zp[k] - r * ze[k]);  // padded samples stay 0
     zp[k] = z;
     zf[k] = (float)z;
-    if (k < n) add_moments(z, acc);
+    if (k < n) ma.add(z);
   }
+  double acc[5];
+  ma.sums(acc);
   block_sum_5(acc, sh);
   if (threadIdx.x == 0) store_moments(J, sp, acc, n);
   double* rho_p = J.rho + (int64_t)sp * ldr;
