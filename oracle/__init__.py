@@ -26,6 +26,8 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
 * :func:`ols_adjacency` -- least-squares regression of every variable on its
   order predecessors (the instantaneous matrix B0 of VarLiNGAM).
 * :func:`varlingam` -- the three stages of VarLiNGAM together.
+* :func:`var_lagged_effects` -- the lagged effects of VarLiNGAM's structural
+  model, theta_tau = (I - B0) M_tau.
 
 The learned-proposal form of the search (features, the scoring network with
 its gradients and optimiser, the certified / margin / audit decisions) is in
@@ -249,6 +251,24 @@ def varlingam(X, lags: int = 1, forced=None, with_measures: bool = False):
     out["order"] = order
     out["B0"] = ols_adjacency(resid, order)
     return out
+
+
+def var_lagged_effects(M, B0) -> np.ndarray:
+    """Lagged effects theta_tau (tau = 1 .. lags) of VarLiNGAM's structural model.
+
+    Section 3.3 writes the model as x(t) = sum over tau = 0 .. k of
+    theta_tau x(t - tau) + eps(t), with theta_0 = B0 the instantaneous effects.
+    Moving theta_0 x(t) to the left gives (I - B0) x(t) = sum over tau >= 1 of
+    theta_tau x(t - tau) + eps(t), so the VAR (reduced-form) matrices are
+    M_tau = (I - B0)^-1 theta_tau and, inverted, theta_tau = (I - B0) M_tau.
+    ``M`` is lags x d x d (M[tau-1][i, j]: coefficient of x_j(t - tau) in the
+    equation of x_i); the result has the same layout.
+    """
+    M = np.asarray(M, dtype=np.float64)
+    B0 = np.asarray(B0, dtype=np.float64)
+    d = B0.shape[0]
+    A = np.eye(d) - B0
+    return np.stack([A @ M[t] for t in range(M.shape[0])])
 
 
 def _order_fp64(E, forced, with_measures):

@@ -352,6 +352,66 @@ def test_ols_adjacency_recovers_true_weights():
     assert np.max(np.abs(B - s.B)) < 0.02
 
 
+def _orthogonal_sem(n, d, seed):
+    """Data of an exact linear SEM whose noise columns are exactly orthogonal
+    and centred: x = B x + e, so X = E (I - B)^-T, plus column offsets."""
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(d)
+    B = np.zeros((d, d))
+    for k in range(1, d):
+        for q in range(k):
+            if rng.random() < 0.5:
+                B[order[k], order[q]] = rng.uniform(0.5, 2.0) * rng.choice([-1.0, 1.0])
+    E = rng.laplace(size=(n, d))
+    E -= E.mean(axis=0)
+    Q, _ = np.linalg.qr(E)
+    E = Q * rng.uniform(0.5, 3.0, size=d)  # orthogonal, centred, unequal scales
+    X = E @ np.linalg.inv(np.eye(d) - B).T + rng.normal(size=d) * 10.0
+    return X, B, order
+
+
+def test_ols_adjacency_exact_on_orthogonal_noise():
+    """With noise columns exactly orthogonal to each other and to the constant,
+    each variable's noise is orthogonal to its predecessors (which are
+    combinations of earlier noises), so least squares on the order
+    predecessors returns the generating weights exactly (up to rounding);
+    a transposed or mis-permuted matrix fails this."""
+    X, B, order = _orthogonal_sem(500, 9, seed=21)
+    Bh = oracle.ols_adjacency(X, order)
+    assert np.max(np.abs(Bh - B)) < 1e-9
+    assert np.all(Bh[order[0]] == 0.0) and np.all(np.diag(Bh) == 0.0)
+
+
+def test_ols_adjacency_simple_regression_slope():
+    """d = 2: the coefficient is the textbook simple-regression slope
+    cov(x0, x1) / var(x_parent), whichever variable comes first."""
+    rng = np.random.default_rng(5)
+    X = rng.exponential(size=(300, 2))
+    X[:, 1] += 0.7 * X[:, 0]
+    c = X - X.mean(axis=0)
+    for order, child, parent in (([0, 1], 1, 0), ([1, 0], 0, 1)):
+        Bh = oracle.ols_adjacency(X, np.array(order, dtype=np.int32))
+        slope = np.sum(c[:, 0] * c[:, 1]) / np.sum(c[:, parent] ** 2)
+        assert abs(Bh[child, parent] - slope) < 1e-12
+        assert Bh[parent, child] == 0.0
+
+
+def test_var_lagged_effects_inverts_the_reduced_form():
+    """theta_tau from M_tau = (I - B0)^-1 theta_tau (the reduced form of the
+    structural model) comes back exactly; B0 = 0 leaves M unchanged."""
+    rng = np.random.default_rng(2)
+    d, lags = 6, 2
+    perm = rng.permutation(d)
+    B0 = np.zeros((d, d))
+    for k in range(1, d):
+        for q in range(k):
+            B0[perm[k], perm[q]] = rng.normal() * (rng.random() < 0.6)
+    theta = rng.normal(size=(lags, d, d)) * 0.3
+    M = np.stack([np.linalg.solve(np.eye(d) - B0, theta[t]) for t in range(lags)])
+    assert np.max(np.abs(oracle.var_lagged_effects(M, B0) - theta)) < 1e-12
+    assert np.array_equal(oracle.var_lagged_effects(M, np.zeros((d, d))), M)
+
+
 def test_fp64_and_fp32_entries_agree():
     s = synth.er_sem(9, 800, indeg=2.0, seed=6)
     X32 = s.X.astype(np.float32)
