@@ -174,16 +174,24 @@ def _oracle_step(X32, prefix, prop, K):
     return np.array(U), s.astype(np.float32).astype(np.float64), k
 
 
-def test_pure_learned_order_matches_oracle(lib):
+@pytest.mark.parametrize("max_suspects", [1024, 0])
+def test_pure_learned_order_matches_oracle(lib, max_suspects):
+    """margin = -inf: the learned choice is never handed to a full step; with
+    the second pass (max_suspects 1024) or without it (0, the fast form)."""
     d, n, K = 110, 1500, 8
     s = _sem(d, n, 12)
     X32 = s.X.astype(np.float32)
     prop = _proposer(7)
     out = lib.causal_order(_t(X32), learned=lib.Learned(_t(prop), topk=K, audit_every=0,
-                                                        margin=-np.inf, min_m=64))
+                                                        margin=-np.inf, min_m=64,
+                                                        max_suspects=max_suspects))
     go = out["order"].cpu().numpy()
-    assert out["learned_stats"].fallbacks == 0 and out["learned_stats"].audits == 0
-    ro, info = OP.learned_order(X32, prop, K=K, delta=-np.inf, audit_every=0, min_m=64)
+    st = out["learned_stats"]
+    assert st.fallbacks == 0 and st.audits == 0
+    if max_suspects == 0:
+        assert st.expanded == 0
+    ro, info = OP.learned_order(X32, prop, K=K, delta=-np.inf, audit_every=0, min_m=64,
+                                max_suspects=max_suspects)
     diff = np.flatnonzero(go != ro)
     if diff.size == 0:
         return
@@ -254,3 +262,24 @@ def test_training_lowers_loss(lib):
         lib.proposer_adam(P, g, m1, m2, step, lr=3e-3)
     print("loss", losses[0], "->", losses[-1], flush=True)
     assert losses[-1] < 0.8 * losses[0]
+
+
+def test_step_log_matches_stats(lib):
+    """The per-step decision log agrees with the counters and the schedule."""
+    s = _sem(200, 2000, 21)
+    P = _t(_proposer(10))
+    out = lib.causal_order(_t(s.X), learned=lib.Learned(P, topk=16, audit_every=8, min_m=64),
+                           step_log=True)
+    log = out["step_log"].cpu().numpy()
+    st = out["learned_stats"]
+    kind, nsus = log & 15, log >> 4
+    m = 200 - np.arange(200)
+    learned = (m > 64) & (np.arange(200) < 199)
+    assert np.all(kind[~learned] == 0)
+    assert np.all(kind[learned] > 0)
+    assert int(np.sum(kind == 3)) == st.audits == int(np.sum(learned & (np.arange(200) % 8 == 0)))
+    assert int(np.sum(kind == 4)) == st.expanded
+    assert int(np.sum(kind == 2)) == st.fallbacks
+    assert int(np.sum(kind == 1)) + st.expanded + st.fallbacks + st.audits == st.learned_steps
+    assert np.all(nsus[kind == 4] > 0) and np.all(nsus[kind != 4] == 0)
+    assert np.all(nsus[kind == 4] <= np.maximum((m[kind == 4] // 2 - 16) // 8 * 8, 0))
