@@ -236,6 +236,28 @@ size_t lingam_residualize_workspace_size(int64_t n, int64_t d);
 int lingam_residualize(float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* active,
                        int32_t n_active, int32_t exo, void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes for lingam_adjacency on an n x d matrix (0 if unsupported). */
+size_t lingam_adjacency_workspace_size(int64_t n, int64_t d);
+
+/*
+ * Weighted adjacency matrix from a causal order: every variable is regressed
+ * by least squares, with an intercept, on the variables that precede it in
+ * `order` (DirectLiNGAM's second phase, described in Section 1; the model is
+ * the linear structural equation of Section 2.1).
+ *   X      device FP32 [n x ldx] row-major, read only.
+ *   order  device int32[d], a permutation of 0 .. d-1, exogenous first.
+ *   B      device double[d * d] row-major: B[i d + j] is the coefficient of
+ *          x_j in the regression of x_i when x_j precedes x_i; 0 elsewhere
+ *          (the diagonal, the first variable's row, all later variables).
+ * FP64 throughout (the data are widened on load): centred covariance on FP64
+ * MFMA, blocked Cholesky of it in the causal order, B = I - diag(L) L^-1.
+ * Synchronizes.  Returns LINGAM_E_INVALID if `order` is not a permutation,
+ * LINGAM_E_DEGENERATE for non-finite data or a covariance that is not
+ * positive definite (collinear variables, or n <= d).
+ */
+int lingam_adjacency(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* order,
+                     double* B, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * Workspace bytes for varlingam_fit on a T x d series with `lags` lags
  * (0 if unsupported: d < 1, lags < 1, or T - lags <= 1 + lags * d).
@@ -262,6 +284,19 @@ size_t varlingam_workspace_size(int64_t T, int64_t d, int32_t lags, const lingam
 int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lags, double* M,
                   float* resid, int32_t* order, double* B0, const lingam_opts* opts, void* ws,
                   size_t ws_bytes, void* stream);
+
+/*
+ * Lagged effects of VarLiNGAM's structural model (Section 3.3): with the VAR
+ * matrices M_tau and the instantaneous matrix B0 that varlingam_fit returns,
+ * theta_tau = (I - B0) M_tau for tau = 1 .. lags (the model equation solved
+ * for x(t) gives M_tau = (I - B0)^-1 theta_tau).
+ *   M      device double[lags * d * d], layout of varlingam_fit's M.
+ *   B0     device double[d * d].
+ *   theta  device double[lags * d * d], same layout as M; must not alias M.
+ * Enqueued on `stream`; no workspace, no sync.
+ */
+int varlingam_lagged_effects(const double* M, const double* B0, int64_t d, int32_t lags,
+                             double* theta, void* stream);
 
 /*
  * Proposer network (the learned-proposal form; its kernels are the ones the

@@ -14,6 +14,10 @@ Functions mirror the C entry points:
   variable's effect, Section 2.2).
 * :func:`varlingam_fit` -- ``varlingam_fit`` (VAR least squares, ordering of
   the residuals, instantaneous matrix B0; Section 3.3).
+* :func:`adjacency` -- ``lingam_adjacency`` (least squares of every
+  variable on its order predecessors: the weighted adjacency matrix).
+* :func:`varlingam_lagged_effects` -- ``varlingam_lagged_effects``
+  (theta_tau = (I - B0) M_tau).
 * :func:`batch_causal_order` -- ``lingam_batch_causal_order`` (many
   independent orderings, e.g. bootstrap resamples, in one batched run).
 * :func:`workspace_size`, :func:`residualize_workspace_size`.
@@ -30,6 +34,7 @@ from .lib import (  # noqa: F401
     LearnedStats,
     LingamError,
     Profile,
+    adjacency,
     batch_causal_order,
     causal_order,
     last_error,
@@ -40,6 +45,7 @@ from .lib import (  # noqa: F401
     residualize,
     residualize_workspace_size,
     varlingam_fit,
+    varlingam_lagged_effects,
     version,
     workspace_size,
 )

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblingam_mi355x.so")
-SOURCES = ["lingam_kernels.hip", "lingam_learned.hip", "lingam_abi.cpp"]
+SOURCES = ["lingam_kernels.hip", "lingam_learned.hip", "lingam_linalg.hip", "lingam_abi.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

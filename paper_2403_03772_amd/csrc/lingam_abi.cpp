@@ -932,6 +932,57 @@ int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lag
       });
 }
 
+size_t lingam_adjacency_workspace_size(int64_t n, int64_t d) {
+  if (n < 2 || d < 1 || n > kMaxN || d > kMaxD) return 0;
+  return lg::make_adj_layout(n, d).total;
+}
+
+int lingam_adjacency(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* order,
+                     double* B, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!X || !order || !B) return fail(LINGAM_E_INVALID, "X, order and B must be non-NULL");
+  if (n < 2 || d < 1 || ldx < d)
+    return fail(LINGAM_E_INVALID, "bad sizes n=%lld d=%lld ldx=%lld", (long long)n,
+                (long long)d, (long long)ldx);
+  if (n > kMaxN || d > kMaxD) return fail(LINGAM_E_UNSUPPORTED, "size beyond supported range");
+  const lg::AdjLayout A = lg::make_adj_layout(n, d);
+  if (!ws || ws_bytes < A.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", A.total,
+                ws ? ws_bytes : (size_t)0);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  int32_t s = 0;
+  // the order indexes device arrays: check it before anything reads through it
+  LG_TRY(lg::launch_adj_check(A, w, order, st), "adjacency check");
+  LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s != 0) return fail(LINGAM_E_INVALID, "order is not a permutation of 0 .. d-1");
+  LG_TRY(lg::launch_adjacency(A, w, X, ldx, order, B, st), "adjacency launch");
+  LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s != 0)
+    return fail(LINGAM_E_DEGENERATE,
+                "non-finite data or a covariance that is not positive definite");
+  return LINGAM_OK;
+}
+
+int varlingam_lagged_effects(const double* M, const double* B0, int64_t d, int32_t lags,
+                             double* theta, void* stream) {
+  g_err[0] = 0;
+  if (!M || !B0 || !theta) return fail(LINGAM_E_INVALID, "M, B0 and theta must be non-NULL");
+  if (d < 1 || lags < 1)
+    return fail(LINGAM_E_INVALID, "need d >= 1 and lags >= 1 (got d=%lld lags=%d)",
+                (long long)d, lags);
+  if (d > kMaxD || lags > 65535)
+    return fail(LINGAM_E_UNSUPPORTED, "d <= %lld and lags <= 65535 supported", (long long)kMaxD);
+  if (theta == M) return fail(LINGAM_E_INVALID, "theta must not alias M");
+  LG_TRY(lg::launch_lagged_effects(M, B0, (int)d, lags, theta, (hipStream_t)stream),
+         "lagged effects");
+  return LINGAM_OK;
+}
+
 size_t lingam_residualize_workspace_size(int64_t n, int64_t d) {
   if (n < 2 || d < 1 || n > kMaxN || d > kMaxD) return 0;
   return lg::resid_ws_size(n, d);

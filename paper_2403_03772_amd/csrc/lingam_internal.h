@@ -462,7 +462,9 @@ struct VarLayout {
   size_t ones;   // double [N]
   size_t w;      // double [q * q] Gram of [1, lags, response]; Cholesky + solution in place
   size_t rho0;   // double [d * d] residual correlations before the ordering
-  size_t scr;    // double [d * d] scratch of the B0 factorisation
+  size_t scr;    // double [d * d] permuted residual covariance, then its Cholesky factor
+  size_t y;      // double [d * d] columns of the inverse factor (B0 recurrence)
+  size_t tol;    // double         pivot tolerance of the current factorisation
   size_t total;
 };
 
@@ -473,6 +475,54 @@ hipError_t launch_var_fit(const VarLayout& V, char* ws, char* job, const float* 
 hipError_t launch_save_rho(const VarLayout& V, char* ws, char* job, hipStream_t st);
 hipError_t launch_b0(const VarLayout& V, char* ws, char* job, const int32_t* order, double* B0,
                      hipStream_t st);
+
+// Least-squares adjacency from a causal order: one region set per call.
+struct AdjLayout {
+  int64_t n, d, ldx;  // ldx = n rounded up to 64
+  size_t ctrl;   // Ctrl (status only)
+  size_t mark;   // int32  [d]   permutation check
+  size_t tol;    // double       pivot tolerance
+  size_t mu;     // double [d]   column means
+  size_t xd;     // double [(d + 1) * ldx] the data, variable-major
+  size_t s;      // double [d * d] permuted covariance, then its Cholesky factor
+  size_t y;      // double [d * d] columns of the inverse factor
+  size_t total;
+};
+
+AdjLayout make_adj_layout(int64_t n, int64_t d);
+// Zero the status, check that `order` is a permutation (status kInvalid if not).
+hipError_t launch_adj_check(const AdjLayout& A, char* ws, const int32_t* order, hipStream_t st);
+// B (d x d, row-major) after a passed check; status kDegenerate on non-finite
+// data or a covariance that is not positive definite.
+hipError_t launch_adjacency(const AdjLayout& A, char* ws, const float* X, int64_t ldx,
+                            const int32_t* order, double* B, hipStream_t st);
+
+// Dense FP64 pieces shared by the adjacency and VarLiNGAM.
+// In-place Cholesky of the leading p x p block of A (lower triangle holds L;
+// the upper triangle and columns >= p are left alone).  Status kDegenerate
+// for a pivot <= 1e-13 max |A_jj| or a non-finite one.
+hipError_t launch_cholesky(double* A, int64_t lda, int p, double* tol, Ctrl* ctrl,
+                           hipStream_t st);
+// B (p x p, ld p) = least-squares coefficients of every variable on its order
+// predecessors from the Cholesky factor L of the order-permuted covariance;
+// B[order[i]][order[k]] for k < i, zero elsewhere.  Y: p x p scratch.
+hipError_t launch_tri_adjacency(const double* L, int64_t ldl, int p, const int32_t* order,
+                                double* B, double* Y, hipStream_t st);
+// S[a][b] = sig[o_a] sig[o_b] rho[o_a][o_b].
+hipError_t launch_perm_scale(const double* rho, int64_t ldr, const double* sig,
+                             const int32_t* order, int d, double* S, hipStream_t st);
+// mu = row means of Xd[0..d-1][0..n-1]; S = centred Gram permuted into `order`.
+hipError_t launch_cov_perm(const double* Xd, int64_t ldx, int n, int d, const int32_t* order,
+                           double* mu, double* S, hipStream_t st);
+// theta[t] = (I - B0) M[t], t < lags (d x d each, row-major).
+hipError_t launch_lagged_effects(const double* M, const double* B0, int d, int lags,
+                                 double* theta, hipStream_t st);
+
+#define LG_HIP(call)                    \
+  do {                                  \
+    const hipError_t lg_e_ = (call);    \
+    if (lg_e_ != hipSuccess) return lg_e_; \
+  } while (0)
 
 // Standalone residualisation on a row-major matrix.
 size_t resid_ws_size(int64_t n, int64_t d);

@@ -749,46 +749,6 @@ __global__ __launch_bounds__(256) void k_gram_design(const double* __restrict__ 
   }
 }
 
-// In-place Cholesky A = L L^T of the leading p x p block (lower triangle holds
-// L; the upper triangle is left as it was).  One workgroup, right-looking.
-__device__ void chol_block(double* A, int64_t lda, int p, Ctrl* ctrl) {
-  __shared__ double piv, tol;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) {
-    double mx = 0.0;
-    for (int j = 0; j < p; ++j) mx = fmax(mx, fabs(A[(int64_t)j * lda + j]));
-    tol = mx * 1e-13;  // pivots below this are rounding noise: the matrix is singular
-  }
-  __syncthreads();
-  for (int j = 0; j < p; ++j) {
-    if (tid == 0) {
-      double a = A[(int64_t)j * lda + j];
-      if (!(a > tol) || !isfinite(a)) {
-        set_status(ctrl, kStDegenerate);
-        a = 1.0;
-      }
-      piv = sqrt(a);
-      A[(int64_t)j * lda + j] = piv;
-    }
-    __syncthreads();
-    const double l = piv;
-    for (int i = j + 1 + tid; i < p; i += nt) A[(int64_t)i * lda + j] /= l;
-    __syncthreads();
-    const int w = p - j - 1;  // trailing block rows/cols j+1 .. p-1, lower part
-    for (int e = tid; e < w * w; e += nt) {
-      const int ii = e / w, kk = e - ii * w;
-      if (kk > ii) continue;
-      const int i = j + 1 + ii, k = j + 1 + kk;
-      A[(int64_t)i * lda + k] -= A[(int64_t)i * lda + j] * A[(int64_t)k * lda + j];
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_chol(double* A, int64_t lda, int p, Ctrl* ctrl) {
-  chol_block(A, lda, p, ctrl);
-}
-
 // Solve (L L^T) x = c in place for columns c = A[0:p, p + j], j < nrhs.
 // One thread per right-hand side; L is read row-wise (broadcast).
 __global__ __launch_bounds__(64) void k_chol_solve(double* A, int64_t lda, int p, int nrhs) {
@@ -850,37 +810,6 @@ __global__ void k_zero_pad(double* Zd, float* Z, int64_t ldz, int d, int n, int 
     Z[(int64_t)d * ldz + i] = 0.f;
   }
 }
-
-// B0 by least squares of every variable on its order predecessors, from the
-// covariance of the residuals S = diag(sig) rho0 diag(sig): with the order-
-// permuted S = L L^T, the coefficients b of variable o_i on o_0 .. o_{i-1}
-// solve L[0:i, 0:i]^T b = L[i, 0:i]^T.  One workgroup; `scr` holds d x d.
-__global__ __launch_bounds__(1024) void k_b0(const double* __restrict__ rho0, int64_t ldr,
-                                             const double* __restrict__ sig,
-                                             const int32_t* __restrict__ order, int d,
-                                             double* __restrict__ scr, double* __restrict__ B0,
-                                             Ctrl* ctrl) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < d * d; e += 1024) {
-    const int a = e / d, b = e - a * d;
-    const int oa = order[a], ob = order[b];
-    scr[e] = sig[oa] * sig[ob] * rho0[(int64_t)oa * ldr + ob];
-    B0[e] = 0.0;
-  }
-  __syncthreads();
-  chol_block(scr, d, d, ctrl);
-  // row i: back substitution with the leading i x i block of L; the solution is
-  // written straight into row order[i] of B0 (entries needed later are final)
-  for (int i = 1 + tid; i < d; i += 1024) {
-    const double* Li = scr + (int64_t)i * d;
-    for (int k = i - 1; k >= 0; --k) {
-      double s = Li[k];
-      for (int q = k + 1; q < i; ++q) s -= scr[(int64_t)q * d + k] * B0[(int64_t)order[i] * d + order[q]];
-      B0[(int64_t)order[i] * d + order[k]] = s / scr[(int64_t)k * d + k];
-    }
-  }
-}
-
 
 // ---------------------------------------------------------------------------
 // standalone residualisation on a row-major matrix
@@ -950,6 +879,21 @@ __global__ __launch_bounds__(256) void k_rr_apply(float* __restrict__ X, int64_t
 }
 
 __global__ void k_zero_i32(int32_t* p) { p[0] = 0; }
+
+// Status kInvalid unless order is a permutation of 0 .. d-1 (mark starts at 0).
+__global__ __launch_bounds__(1024) void k_check_perm(const int32_t* __restrict__ order, int d,
+                                                     int32_t* __restrict__ mark, Ctrl* ctrl) {
+  for (int i = threadIdx.x; i < d; i += 1024) {
+    const int v = order[i];
+    if (v < 0 || v >= d || atomicAdd(&mark[v], 1) != 0) set_status(ctrl, kStInvalid);
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
 
 }  // namespace
 
@@ -1226,6 +1170,8 @@ VarLayout make_var_layout(int64_t T, int64_t d, int lags, int num_cu) {
   V.w = take(sizeof(double) * (size_t)V.q * (size_t)V.q);
   V.rho0 = take(sizeof(double) * (size_t)d * (size_t)d);
   V.scr = take(sizeof(double) * (size_t)d * (size_t)d);
+  V.y = take(sizeof(double) * (size_t)d * (size_t)d);
+  V.tol = take(sizeof(double));
   V.total = off;
   return V;
 }
@@ -1246,7 +1192,7 @@ hipError_t launch_var_fit(const VarLayout& V, char* ws, char* job, const float* 
   const int nb = (int)((V.q + 31) / 32);
   hipLaunchKernelGGL(k_gram_design, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, st, Xd,
                      V.ldx, ones, (int)V.d, V.lags, (int)V.N, (int)V.q, nb, W, V.q);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, W, V.q, (int)V.p, ctrl);
+  LG_HIP(launch_cholesky(W, V.q, (int)V.p, at<double>(ws, V.tol), ctrl, st));
   hipLaunchKernelGGL(k_chol_solve, dim3((unsigned)((V.d + 63) / 64)), dim3(64), 0, st, W, V.q,
                      (int)V.p, (int)V.d);
   dim3 g2((unsigned)V.N, (unsigned)((V.d + 63) / 64));
@@ -1264,12 +1210,65 @@ hipError_t launch_save_rho(const VarLayout& V, char* ws, char* job, hipStream_t 
                         hipMemcpyDeviceToDevice, st);
 }
 
+// B0: least squares of every residual on its order predecessors, from the
+// residual covariance diag(sig) rho0 diag(sig) permuted into the order.
 hipError_t launch_b0(const VarLayout& V, char* ws, char* job, const int32_t* order, double* B0,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_b0, dim3(1), dim3(1024), 0, st, at<double>(ws, V.rho0), V.d,
-                     at<double>(job, V.ord.sig), order, (int)V.d, at<double>(ws, V.scr), B0,
-                     at<Ctrl>(job, V.ord.ctrl));
+  double* S = at<double>(ws, V.scr);
+  LG_HIP(launch_perm_scale(at<double>(ws, V.rho0), V.d, at<double>(job, V.ord.sig), order,
+                           (int)V.d, S, st));
+  LG_HIP(launch_cholesky(S, V.d, (int)V.d, at<double>(ws, V.tol), at<Ctrl>(job, V.ord.ctrl), st));
+  return launch_tri_adjacency(S, V.d, (int)V.d, order, B0, at<double>(ws, V.y), st);
+}
+
+// ---------------------------------------------------------------------------
+// least-squares adjacency from a causal order
+// ---------------------------------------------------------------------------
+
+AdjLayout make_adj_layout(int64_t n, int64_t d) {
+  AdjLayout A{};
+  A.n = n;
+  A.d = d;
+  A.ldx = (n + 63) / 64 * 64;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  A.ctrl = take(sizeof(Ctrl));
+  A.mark = take(sizeof(int32_t) * (size_t)d);
+  A.tol = take(sizeof(double));
+  A.mu = take(sizeof(double) * (size_t)d);
+  A.xd = take(sizeof(double) * (size_t)(d + 1) * (size_t)A.ldx);
+  A.s = take(sizeof(double) * (size_t)d * (size_t)d);
+  A.y = take(sizeof(double) * (size_t)d * (size_t)d);
+  A.total = off;
+  return A;
+}
+
+hipError_t launch_adj_check(const AdjLayout& A, char* ws, const int32_t* order, hipStream_t st) {
+  Ctrl* ctrl = at<Ctrl>(ws, A.ctrl);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, &ctrl->status);
+  const int64_t g = (A.d + 255) / 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(g < 1024 ? g : 1024)), dim3(256), 0, st,
+                     at<int32_t>(ws, A.mark), A.d, 0);
+  hipLaunchKernelGGL(k_check_perm, dim3(1), dim3(1024), 0, st, order, (int)A.d,
+                     at<int32_t>(ws, A.mark), ctrl);
   return hipGetLastError();
+}
+
+hipError_t launch_adjacency(const AdjLayout& A, char* ws, const float* X, int64_t ldx,
+                            const int32_t* order, double* B, hipStream_t st) {
+  Ctrl* ctrl = at<Ctrl>(ws, A.ctrl);
+  double* Xd = at<double>(ws, A.xd);
+  double* S = at<double>(ws, A.s);
+  dim3 g1((unsigned)(A.ldx / 64), (unsigned)((A.d + 1 + 63) / 64));
+  hipLaunchKernelGGL(k_transpose_f64, g1, dim3(256), 0, st, X, ldx, (int)A.n, (int)A.d,
+                     (int)A.ldx, Xd, A.ldx, ctrl);
+  LG_HIP(launch_cov_perm(Xd, A.ldx, (int)A.n, (int)A.d, order, at<double>(ws, A.mu), S, st));
+  LG_HIP(launch_cholesky(S, A.d, (int)A.d, at<double>(ws, A.tol), ctrl, st));
+  return launch_tri_adjacency(S, A.d, (int)A.d, order, B, at<double>(ws, A.y), st);
 }
 
 }  // namespace lg

@@ -185,6 +185,12 @@ def load():
         lib.lingam_proposer_grad.restype = ctypes.c_int
         lib.lingam_proposer_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
         lib.lingam_proposer_adam.restype = ctypes.c_int
+        lib.lingam_adjacency_workspace_size.argtypes = [i64, i64]
+        lib.lingam_adjacency_workspace_size.restype = sz
+        lib.lingam_adjacency.argtypes = [P, i64, i64, i64, P, P, P, sz, P]
+        lib.lingam_adjacency.restype = ctypes.c_int
+        lib.varlingam_lagged_effects.argtypes = [P, P, i64, i32, P, P]
+        lib.varlingam_lagged_effects.restype = ctypes.c_int
         lib.lingam_last_error.argtypes = []
         lib.lingam_last_error.restype = ctypes.c_char_p
         lib.lingam_version.argtypes = []
@@ -359,13 +365,59 @@ def residualize(X, active, exo: int):
     return X
 
 
+def adjacency(X, order, *, workspace=None):
+    """Least-squares adjacency of a CUDA float32 ``X`` (n x d) given a causal
+    ``order``: B[i, j] = coefficient of x_j when x_i is regressed (with
+    intercept) on its order predecessors.  Returns a d x d float64 tensor."""
+    import torch
+
+    lib = load()
+    _cuda_f32_matrix(torch, X)
+    n, d = X.shape
+    o = torch.as_tensor(order, dtype=torch.int32).to(X.device).contiguous()
+    if o.numel() != d:
+        raise ValueError(f"order has {o.numel()} entries, X has {d} columns")
+    need = int(lib.lingam_adjacency_workspace_size(n, d))
+    if need == 0:
+        raise LingamError(E_INVALID, f"unsupported size n={n} d={d}")
+    ws = workspace
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    B = torch.empty((d, d), dtype=torch.float64, device=X.device)
+    code = lib.lingam_adjacency(_ptr(X), n, d, X.stride(0), _ptr(o), _ptr(B), _ptr(ws),
+                                ws.numel(), _stream_ptr(torch, X.device))
+    _check(code)
+    return B
+
+
+def varlingam_lagged_effects(M, B0):
+    """theta_tau = (I - B0) M_tau for CUDA float64 ``M`` (lags x d x d) and ``B0``."""
+    import torch
+
+    lib = load()
+    if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float64
+            and M.dim() == 3 and M.shape[1] == M.shape[2] and M.is_contiguous()):
+        raise TypeError("M must be a contiguous CUDA float64 tensor of shape (lags, d, d)")
+    lags, d, _ = M.shape
+    if not (isinstance(B0, torch.Tensor) and B0.is_cuda and B0.dtype == torch.float64
+            and tuple(B0.shape) == (d, d) and B0.is_contiguous()):
+        raise TypeError("B0 must be a contiguous CUDA float64 tensor of shape (d, d)")
+    theta = torch.empty_like(M)
+    _check(lib.varlingam_lagged_effects(_ptr(M), _ptr(B0), d, int(lags), _ptr(theta),
+                                        _stream_ptr(torch, M.device)))
+    return theta
+
+
 def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
-                  profile: bool = False, learned: Learned | None = None):
+                  profile: bool = False, learned: Learned | None = None,
+                  lagged_effects: bool = True):
     """VarLiNGAM on a CUDA float32 series ``X`` (T x d, time in rows).
 
     Returns a dict: ``M`` (lags x d x d float64), ``resid`` ((T-lags) x d
-    float32), ``order`` (int32), ``B0`` (d x d float64), plus ``measures`` /
-    ``gaps`` / ``profile`` / ``learned_stats`` when asked.
+    float32), ``order`` (int32), ``B0`` (d x d float64), ``theta``
+    (lags x d x d float64, the lagged effects (I - B0) M_tau, unless
+    ``lagged_effects`` is False), plus ``measures`` / ``gaps`` / ``profile``
+    / ``learned_stats`` when asked.
     """
     import torch
 
@@ -399,6 +451,8 @@ def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
                              _ptr(out["resid"]), _ptr(out["order"]), _ptr(out["B0"]),
                              ctypes.byref(opts), _ptr(ws), ws.numel(), _stream_ptr(torch, dev))
     _check(code)
+    if lagged_effects:
+        out["theta"] = varlingam_lagged_effects(out["M"], out["B0"])
     if prof is not None:
         out["profile"] = _profile_of(prof)
     if stats is not None:

@@ -120,6 +120,37 @@ def test_residualize_argument_errors():
     assert c(exo=-1) == L.E_INVALID
 
 
+def test_adjacency_argument_errors():
+    """Host-side checks of lingam_adjacency / varlingam_lagged_effects (no GPU call)."""
+    lib = pkg.load()
+    v = ctypes.c_void_p(1)
+    c = lambda **k: lib.lingam_adjacency(
+        v if k.get("X", 1) else None, k.get("n", 10), k.get("d", 3), k.get("ldx", 3),
+        v if k.get("order", 1) else None, v if k.get("B", 1) else None, v,
+        k.get("ws", 1 << 30), None)
+    assert c(X=0) == L.E_INVALID
+    assert c(order=0) == L.E_INVALID
+    assert c(B=0) == L.E_INVALID
+    assert c(n=1) == L.E_INVALID
+    assert c(d=0) == L.E_INVALID
+    assert c(ldx=2) == L.E_INVALID
+    assert c(d=1 << 20, ldx=1 << 20) == L.E_UNSUPPORTED
+    assert c(ws=16) == L.E_WORKSPACE
+    assert lib.lingam_adjacency_workspace_size(1, 3) == 0
+    assert lib.lingam_adjacency_workspace_size(10, 0) == 0
+    # n = 100, d = 8: covariance, factor and inverse columns dominate
+    assert lib.lingam_adjacency_workspace_size(100, 8) >= 8 * (9 * 128 + 2 * 64)
+    e = lambda **k: lib.varlingam_lagged_effects(
+        v if k.get("M", 1) else None, v if k.get("B0", 1) else None, k.get("d", 3),
+        k.get("lags", 1), ctypes.c_void_p(k.get("theta", 2)), None)
+    assert e(M=0) == L.E_INVALID
+    assert e(B0=0) == L.E_INVALID
+    assert e(d=0) == L.E_INVALID
+    assert e(lags=0) == L.E_INVALID
+    assert e(theta=1) == L.E_INVALID  # aliases M
+    assert e(d=1 << 20) == L.E_UNSUPPORTED
+
+
 def test_product_path_has_no_oracle_dependency():
     """The binding and the library never load the oracle."""
     src = open(os.path.join(ROOT, "paper_2403_03772_amd", "lib.py")).read()

@@ -44,6 +44,9 @@ def test_varlingam_matches_oracle(lib, d, T, lags, seed):
     # B0 on the GPU order
     b_ref = oracle.ols_adjacency(ref["resid"], order)
     assert np.max(np.abs(g["B0"] - b_ref)) <= 1e-8 * max(1.0, np.max(np.abs(b_ref)))
+    # lagged effects (I - B0) M_tau from the GPU's own M and B0
+    th_ref = oracle.var_lagged_effects(g["M"], g["B0"])
+    assert np.max(np.abs(g["theta"] - th_ref)) <= 1e-12 * max(1.0, np.max(np.abs(th_ref)))
 
 
 def test_varlingam_stock_shape(lib):
@@ -55,6 +58,9 @@ def test_varlingam_stock_shape(lib):
     assert np.max(np.abs(g["M"][0] - coef[1:].T)) <= 1e-8 * max(1.0, np.max(np.abs(coef)))
     order = g["order"]
     assert sorted(order.tolist()) == list(range(487))
+    # B0 over 16 Cholesky panels against the oracle's per-variable normal equations
+    b_ref = oracle.ols_adjacency(resid, order)
+    assert np.max(np.abs(g["B0"] - b_ref)) <= 1e-8 * max(1.0, np.max(np.abs(b_ref)))
     # sampled rows of the residual ordering, teacher-forced
     for t in (0, 200):
         rows = np.flatnonzero(~np.isin(np.arange(487), order[:t]))[:4].astype(np.int32)
