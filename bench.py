@@ -66,8 +66,9 @@ def measured_traffic(d: int, n: int):
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_2403_03772_amd", "csrc")
-    h = hashlib.sha256(open(os.path.join(src, "lingam_kernels.hip"), "rb").read()
-                       + open(os.path.join(src, "lingam_internal.h"), "rb").read()).hexdigest()
+    h = hashlib.sha256(b"".join(open(os.path.join(src, f), "rb").read() for f in
+                                ("lingam_kernels.hip", "lingam_internal.h",
+                                 "lingam_device.h"))).hexdigest()
     if fields.get("kernel_sources_sha256") != h or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
@@ -198,6 +199,46 @@ def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None):
 
 def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_adjacency(lg, X, n, d, order, reps=5):
+    """lingam_adjacency on the ordering's input along its order: mean ms per call
+    (the call synchronizes) and FP64 rate against the algorithmic flops:
+    covariance n d (d + 1) (upper triangle, one multiply-add per sample), the
+    Cholesky d^3 / 3 and the inverse-factor recurrence d^3 / 3."""
+    import torch
+
+    ws = torch.empty(int(lg.load().lingam_adjacency_workspace_size(n, d)), dtype=torch.uint8,
+                     device=X.device)
+    lg.adjacency(X, order, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lg.adjacency(X, order, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flops = float(n) * d * (d + 1) + 2.0 * d ** 3 / 3.0
+    return {"ms": ms, "bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": 78.6,
+            "unit": "TFLOP/s (fp64)", "frac": flops / (ms * 1e-3) / 78.6e12,
+            "flops": flops, "reps": reps}
+
+
+def run_varlingam(lg, reps=3):
+    """varlingam_fit on the stock-shaped series (d = 487, T = 1258, VAR(1)):
+    mean ms per fit, lagged effects included."""
+    import torch
+    from paper_2403_03772_amd import synth
+
+    v = synth.var_series(d=487, T=1258, seed=0)
+    X = torch.as_tensor(np.ascontiguousarray(v.X, dtype=np.float32), device="cuda:0")
+    lg.varlingam_fit(X, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lg.varlingam_fit(X, 1)
+    torch.cuda.synchronize()
+    return {"ms": (time.perf_counter() - t0) * 1e3 / reps, "d": 487, "T": 1258, "lags": 1,
+            "reps": reps}
 
 
 def run_plain(lg, X, n, d, steps, warmup):
@@ -351,6 +392,11 @@ def main() -> int:
             rec["learned"]["untrained"] = run_learned(lg, X, n, d, 1, 0,
                                                       lg.Learned(raw, topk=K), pl["order"],
                                                       ms_per_step, B)
+    if args.workload == "gene":
+        progress("adjacency along the plain order")
+        rec["adjacency"] = run_adjacency(lg, X, n, d, torch.as_tensor(pl["order"]).cuda())
+        progress("varlingam (stock shape)")
+        rec["varlingam"] = run_varlingam(lg)
     if not args.no_batch and args.workload == "gene":
         rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed)
     if args.copy_calibration:

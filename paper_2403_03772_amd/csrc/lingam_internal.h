@@ -461,6 +461,8 @@ struct VarLayout {
   size_t xd;     // double [(d + 1) * ldx] the series, variable-major
   size_t ones;   // double [N]
   size_t w;      // double [q * q] Gram of [1, lags, response]; Cholesky + solution in place
+  size_t linv;   // double [p * p] inverse of the Cholesky factor
+  size_t tmp;    // double [p * d] half-solved right-hand sides
   size_t rho0;   // double [d * d] residual correlations before the ordering
   size_t scr;    // double [d * d] permuted residual covariance, then its Cholesky factor
   size_t y;      // double [d * d] columns of the inverse factor (B0 recurrence)
@@ -503,9 +505,17 @@ hipError_t launch_adjacency(const AdjLayout& A, char* ws, const float* X, int64_
 // for a pivot <= 1e-13 max |A_jj| or a non-finite one.
 hipError_t launch_cholesky(double* A, int64_t lda, int p, double* tol, Ctrl* ctrl,
                            hipStream_t st);
+// X (ld ldx) = L^-1 for the lower-triangular p x p L (the upper triangle of
+// X's diagonal blocks is written as zero; blocks above them are not touched).
+hipError_t launch_tri_inverse(const double* L, int64_t ldl, int p, double* X, int64_t ldx,
+                              hipStream_t st);
+// C = op(A) B, A lower-triangular M x M (op: A, or A^T when trans), B M x N;
+// C must not alias B.
+hipError_t launch_trmm(int M, int N, const double* A, int64_t lda, bool trans, const double* B,
+                       int64_t ldb, double* C, int64_t ldc, hipStream_t st);
 // B (p x p, ld p) = least-squares coefficients of every variable on its order
 // predecessors from the Cholesky factor L of the order-permuted covariance;
-// B[order[i]][order[k]] for k < i, zero elsewhere.  Y: p x p scratch.
+// B[order[i]][order[k]] for k < i, zero elsewhere.  Y: p x p scratch (L^-1).
 hipError_t launch_tri_adjacency(const double* L, int64_t ldl, int p, const int32_t* order,
                                 double* B, double* Y, hipStream_t st);
 // S[a][b] = sig[o_a] sig[o_b] rho[o_a][o_b].

@@ -749,25 +749,6 @@ __global__ __launch_bounds__(256) void k_gram_design(const double* __restrict__ 
   }
 }
 
-// Solve (L L^T) x = c in place for columns c = A[0:p, p + j], j < nrhs.
-// One thread per right-hand side; L is read row-wise (broadcast).
-__global__ __launch_bounds__(64) void k_chol_solve(double* A, int64_t lda, int p, int nrhs) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= nrhs) return;
-  double* c = A + p + j;
-  for (int i = 0; i < p; ++i) {
-    double s = c[(int64_t)i * lda];
-    const double* Li = A + (int64_t)i * lda;
-    for (int k = 0; k < i; ++k) s -= Li[k] * c[(int64_t)k * lda];
-    c[(int64_t)i * lda] = s / Li[i];
-  }
-  for (int i = p - 1; i >= 0; --i) {
-    double s = c[(int64_t)i * lda];
-    for (int k = i + 1; k < p; ++k) s -= A[(int64_t)k * lda + i] * c[(int64_t)k * lda];
-    c[(int64_t)i * lda] = s / A[(int64_t)i * lda + i];
-  }
-}
-
 // Residuals e_v(r) = x_v(r + lags) - sum_q D[r][q] A[q][v] into the ordering's
 // FP64 data rows Zd[v][r]; optional FP32 row-major copy; VAR matrices M.
 __global__ __launch_bounds__(64) void k_var_resid(const double* __restrict__ Xd, int64_t ldx,
@@ -1172,6 +1153,8 @@ VarLayout make_var_layout(int64_t T, int64_t d, int lags, int num_cu) {
   V.scr = take(sizeof(double) * (size_t)d * (size_t)d);
   V.y = take(sizeof(double) * (size_t)d * (size_t)d);
   V.tol = take(sizeof(double));
+  V.linv = take(sizeof(double) * (size_t)V.p * (size_t)V.p);
+  V.tmp = take(sizeof(double) * (size_t)V.p * (size_t)d);
   V.total = off;
   return V;
 }
@@ -1193,8 +1176,12 @@ hipError_t launch_var_fit(const VarLayout& V, char* ws, char* job, const float* 
   hipLaunchKernelGGL(k_gram_design, dim3((unsigned)(nb * (nb + 1) / 2)), dim3(256), 0, st, Xd,
                      V.ldx, ones, (int)V.d, V.lags, (int)V.N, (int)V.q, nb, W, V.q);
   LG_HIP(launch_cholesky(W, V.q, (int)V.p, at<double>(ws, V.tol), ctrl, st));
-  hipLaunchKernelGGL(k_chol_solve, dim3((unsigned)((V.d + 63) / 64)), dim3(64), 0, st, W, V.q,
-                     (int)V.p, (int)V.d);
+  // coefficients (L L^T)^-1 C = X^T (X C), X = L^-1, C = W[0:p, p:q]
+  double* Xi = at<double>(ws, V.linv);
+  double* T = at<double>(ws, V.tmp);
+  LG_HIP(launch_tri_inverse(W, V.q, (int)V.p, Xi, V.p, st));
+  LG_HIP(launch_trmm((int)V.p, (int)V.d, Xi, V.p, false, W + V.p, V.q, T, V.d, st));
+  LG_HIP(launch_trmm((int)V.p, (int)V.d, Xi, V.p, true, T, V.d, W + V.p, V.q, st));
   dim3 g2((unsigned)V.N, (unsigned)((V.d + 63) / 64));
   hipLaunchKernelGGL(k_var_resid, g2, dim3(64), 0, st, Xd, V.ldx, (int)V.d, V.lags, (int)V.N,
                      W, V.q, at<double>(job, L.zd), L.ldz, resid_out, M_out);

@@ -14,12 +14,14 @@
 //                        o_0 .. o_{i-1} solve S_i b = s_i with S_i = L_i L_i^T
 //                        (leading i x i blocks) and s_i = L_i l_i (l_i = row i
 //                        of L left of the diagonal), so b = L_i^-T l_i.
-//                        Stacked over i this is B = I - diag(L) L^-1: with
-//                        y = column k of L^-1 (y_k = 1 / L_kk), entry i > k
-//                        is s = sum_{k <= t < i} L_it y_t, B(i, k) = s and
-//                        y_i = -s / L_ii.  One workgroup runs that recurrence
-//                        for 8 adjacent columns, so each row of L is read
-//                        once per 8 columns.
+//                        Stacked over i this is B = I - diag(L) L^-1.
+//   triangular inverse   X = L^-1 by 32 x 32 blocks: the diagonal blocks are
+//                        inverted in LDS (all at once), then block row I is
+//                        X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ for all J < I
+//                        in one launch (both products on FP64 MFMA), so the
+//                        dependency chain is p / 32 launches long.
+//   triangular products  op(X) B for the normal equations of the VAR fit:
+//                        (L L^T)^-1 C = X^T (X C).
 //   covariance           centred Gram matrix of variable rows, permuted into
 //                        a given order, on FP64 MFMA.
 //   lagged effects       theta_tau = (I - B0) M_tau of VarLiNGAM (Section
@@ -154,62 +156,148 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ A, int
   }
 }
 
-constexpr int kTriCols = 8;  // columns of L^-1 per workgroup
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-// Adjacency from the Cholesky factor L (lower triangle of a p x p matrix):
-// for the columns k = k0 .. k0 + 7, B[order[i]][order[k]] = s_i(k) for i > k
-// (recurrence in the header).  Y (p x p scratch) holds y = L^-1 e_k in row k;
-// only the waves of this workgroup touch those rows.  B's other entries are
-// left alone (the launcher zeroes B first).
-__global__ __launch_bounds__(256) void k_tri_adj(const double* __restrict__ L, int64_t ldl, int p,
-                                                 const int32_t* __restrict__ order,
-                                                 double* __restrict__ B, int64_t ldb,
-                                                 double* __restrict__ Y) {
-  __shared__ double red[4][kTriCols];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k0 = blockIdx.x * kTriCols;
-  const int ncol = min(kTriCols, p - k0);
-  double* y0 = Y + (int64_t)k0 * p;  // row k0 + c of Y is y0 + c p
-  if (tid < ncol) y0[(int64_t)tid * p + k0 + tid] = 1.0 / L[(int64_t)(k0 + tid) * ldl + k0 + tid];
+// Diagonal 32 x 32 blocks of X = L^-1: X_II = L_II^-1, written in full (zeros
+// above the diagonal; past p the block is cut).  One workgroup per block;
+// thread j < 32 runs the forward substitution of column j in LDS.
+__global__ __launch_bounds__(64) void k_trinv_diag(const double* __restrict__ L, int64_t ldl,
+                                                   int p, double* __restrict__ X, int64_t ldx) {
+  __shared__ double Ls[kNb][kNb + 1];
+  __shared__ double Ds[kNb][kNb + 1];
+  const int I0 = blockIdx.x * kNb, kb = min(kNb, p - I0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kNb * kNb; e += 64) {
+    const int i = e / kNb, j = e - i * kNb;
+    Ls[i][j] = (i < kb && j <= i) ? L[(int64_t)(I0 + i) * ldl + I0 + j] : 0.0;
+  }
   __syncthreads();
-  for (int i = k0 + 1; i < p; ++i) {
-    const double* Li = L + (int64_t)i * ldl;
-    double acc[kTriCols];
-#pragma unroll
-    for (int c = 0; c < kTriCols; ++c) acc[c] = 0.0;
-    for (int t = k0 + tid; t < i; t += 256) {
-      const double l = Li[t];
-#pragma unroll
-      for (int c = 0; c < kTriCols; ++c)
-        if (c < ncol && t >= k0 + c) acc[c] += l * y0[(int64_t)c * p + t];
+  if (tid < kb) {
+    const int j = tid;
+    for (int i = 0; i < kNb; ++i) Ds[i][j] = 0.0;
+    Ds[j][j] = 1.0 / Ls[j][j];
+    for (int i = j + 1; i < kb; ++i) {
+      double s = 0.0;
+      for (int t = j; t < i; ++t) s += Ls[i][t] * Ds[t][j];
+      Ds[i][j] = -s / Ls[i][i];
     }
-#pragma unroll
-    for (int c = 0; c < kTriCols; ++c) acc[c] = wave_sum(acc[c]);
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < kTriCols; ++c) red[wave][c] = acc[c];
-    }
-    __syncthreads();
-    if (tid < ncol && i > k0 + tid) {
-      const int c = tid;
-      const double s = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-      B[(int64_t)order[i] * ldb + order[k0 + c]] = s;
-      y0[(int64_t)c * p + i] = -s / Li[i];
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = tid; e < kb * kb; e += 64) {
+    const int i = e / kb, j = e - i * kb;
+    X[(int64_t)(I0 + i) * ldx + I0 + j] = Ds[i][j];
   }
 }
 
-__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
+// Block row I of X = L^-1 left of the diagonal: X_IJ = -X_II sum_{J <= K < I}
+// L_IK X_KJ for every J < I (one workgroup each), both products on FP64 MFMA.
+// Blocks K < I and J < I are full (only the last block row can be cut by p).
+__global__ __launch_bounds__(256) void k_trinv_row(const double* __restrict__ L, int64_t ldl,
+                                                   int p, int I, double* __restrict__ X,
+                                                   int64_t ldx) {
+  __shared__ double As[kNb][kNb + 1];
+  __shared__ double Bs[kNb][kNb + 1];
+  const int J = blockIdx.x;
+  const int I0 = I * kNb, J0 = J * kNb;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lv = tid >> 3, ls = (tid & 7) * 4;
+  const bool row_ok = I0 + lv < p;
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int K = J; K < I; ++K) {
+    const int K0 = K * kNb;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[ls + u][lv] = row_ok ? L[(int64_t)(I0 + lv) * ldl + K0 + ls + u] : 0.0;  // L_IK[lv][k]
+      Bs[lv][ls + u] = X[(int64_t)(K0 + lv) * ldx + J0 + ls + u];                // X_KJ[k][j]
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kNb / 4; ++kk) {
+      const double a = As[kk * 4 + (lane >> 4)][wi * 16 + (lane & 15)];
+      const double b = Bs[kk * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  // T = acc becomes the right operand; X_II the left one
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Bs[wi * 16 + 4 * r + (lane >> 4)][wj * 16 + (lane & 15)] = acc[r];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    As[ls + u][lv] = (row_ok && I0 + ls + u < p) ? X[(int64_t)(I0 + lv) * ldx + I0 + ls + u] : 0.0;
+  __syncthreads();
+  double4_t out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < kNb / 4; ++kk) {
+    const double a = As[kk * 4 + (lane >> 4)][wi * 16 + (lane & 15)];
+    const double b = Bs[kk * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+    out = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, out, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = I0 + wi * 16 + 4 * r + (lane >> 4);
+    const int j = J0 + wj * 16 + (lane & 15);
+    if (i < p) X[(int64_t)i * ldx + j] = -out[r];
+  }
+}
+
+// B[order[i]][order[k]] = -L_ii X_ik for k < i, 0 otherwise (every entry of B
+// written once: order is a permutation).
+__global__ void k_adj_scatter(const double* __restrict__ L, int64_t ldl,
+                              const double* __restrict__ X, int64_t ldx, int p,
+                              const int32_t* __restrict__ order, double* __restrict__ B) {
+  const int64_t total = (int64_t)p * p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p), k = (int)(e - (int64_t)i * p);
+    const double v = k < i ? -L[(int64_t)i * ldl + i] * X[(int64_t)i * ldx + k] : 0.0;
+    B[(int64_t)order[i] * p + order[k]] = v;
+  }
+}
+
+// C = op(A) B for a lower-triangular M x M A (op = A or A^T), B: M x N,
+// 32 x 32 output tiles on FP64 MFMA, visiting only the K blocks where op(A)'s
+// row block is nonzero.  C must not alias B.
+__global__ __launch_bounds__(256) void k_trmm(int M, int N, const double* __restrict__ A,
+                                              int64_t lda, int trans, const double* __restrict__ B,
+                                              int64_t ldb, double* __restrict__ C, int64_t ldc) {
+  __shared__ double As[kNb][kNb + 1];
+  __shared__ double Bs[kNb][kNb + 1];
+  const int I0 = blockIdx.y * kNb, J0 = blockIdx.x * kNb;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lv = tid >> 3, ls = (tid & 7) * 4;
+  const int kbeg = trans ? I0 : 0;
+  const int kend = trans ? M : min(M, I0 + kNb);
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kbeg; k0 < kend; k0 += kNb) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!trans) {  // op(A)[i][k] = A[i][k]: lv = i, ls + u = k
+        const int i = I0 + lv, k = k0 + ls + u;
+        As[ls + u][lv] = (i < M && k < M) ? A[(int64_t)i * lda + k] : 0.0;
+      } else {       // op(A)[i][k] = A[k][i]: lv = k, ls + u = i
+        const int k = k0 + lv, i = I0 + ls + u;
+        As[lv][ls + u] = (i < M && k < M) ? A[(int64_t)k * lda + i] : 0.0;
+      }
+      const int k = k0 + lv, j = J0 + ls + u;
+      Bs[lv][ls + u] = (k < M && j < N) ? B[(int64_t)k * ldb + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kNb / 4; ++kk) {
+      const double a = As[kk * 4 + (lane >> 4)][wi * 16 + (lane & 15)];
+      const double b = Bs[kk * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = I0 + wi * 16 + 4 * r + (lane >> 4);
+    const int j = J0 + wj * 16 + (lane & 15);
+    if (i < M && j < N) C[(int64_t)i * ldc + j] = acc[r];
+  }
 }
 
 // S[a][b] = sig[o_a] sig[o_b] rho[o_a][o_b]: a correlation matrix scaled to a
@@ -331,13 +419,27 @@ hipError_t launch_cholesky(double* A, int64_t lda, int p, double* tol, Ctrl* ctr
   return hipGetLastError();
 }
 
+hipError_t launch_tri_inverse(const double* L, int64_t ldl, int p, double* X, int64_t ldx,
+                              hipStream_t st) {
+  const int nb = (p + kNb - 1) / kNb;
+  hipLaunchKernelGGL(k_trinv_diag, dim3((unsigned)nb), dim3(64), 0, st, L, ldl, p, X, ldx);
+  for (int I = 1; I < nb; ++I)
+    hipLaunchKernelGGL(k_trinv_row, dim3((unsigned)I), dim3(256), 0, st, L, ldl, p, I, X, ldx);
+  return hipGetLastError();
+}
+
 hipError_t launch_tri_adjacency(const double* L, int64_t ldl, int p, const int32_t* order,
                                 double* B, double* Y, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((int64_t)p * p)), dim3(256), 0, st, B,
-                     (int64_t)p * p, 0.0);
-  if (p < 2) return hipGetLastError();
-  hipLaunchKernelGGL(k_tri_adj, dim3((unsigned)((p - 1 + kTriCols - 1) / kTriCols)), dim3(256), 0,
-                     st, L, ldl, p, order, B, (int64_t)p, Y);
+  LG_HIP(launch_tri_inverse(L, ldl, p, Y, p, st));
+  hipLaunchKernelGGL(k_adj_scatter, dim3(grid_for((int64_t)p * p)), dim3(256), 0, st, L, ldl, Y,
+                     (int64_t)p, p, order, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm(int M, int N, const double* A, int64_t lda, bool trans, const double* B,
+                       int64_t ldb, double* C, int64_t ldc, hipStream_t st) {
+  dim3 g((unsigned)((N + kNb - 1) / kNb), (unsigned)((M + kNb - 1) / kNb));
+  hipLaunchKernelGGL(k_trmm, g, dim3(256), 0, st, M, N, A, lda, trans ? 1 : 0, B, ldb, C, ldc);
   return hipGetLastError();
 }
 
