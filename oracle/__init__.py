@@ -28,6 +28,8 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
 * :func:`varlingam` -- the three stages of VarLiNGAM together.
 * :func:`var_lagged_effects` -- the lagged effects of VarLiNGAM's structural
   model, theta_tau = (I - B0) M_tau.
+* :func:`bootstrap_counts` -- order / edge counts over row resamples, each
+  regressed along a given order.
 
 The learned-proposal form of the search (features, the scoring network with
 its gradients and optimiser, the certified / margin / audit decisions) is in
@@ -269,6 +271,28 @@ def var_lagged_effects(M, B0) -> np.ndarray:
     d = B0.shape[0]
     A = np.eye(d) - B0
     return np.stack([A @ M[t] for t in range(M.shape[0])])
+
+
+def bootstrap_counts(X, resamples, orders, threshold: float = 0.0):
+    """Bootstrap statistics by definition: for every resample (row indices into
+    X, with replacement) and its causal order, B = least squares of each
+    variable on its order predecessors (:func:`ols_adjacency` on X[rows]);
+    order_count[i, j] counts resamples in which x_j precedes x_i,
+    edge_count[i, j] those with |B[i, j]| > threshold; coef_sum adds B."""
+    X = np.asarray(X, dtype=np.float64)
+    d = X.shape[1]
+    order_count = np.zeros((d, d), dtype=np.int64)
+    edge_count = np.zeros((d, d), dtype=np.int64)
+    coef_sum = np.zeros((d, d))
+    for rows, order in zip(resamples, orders):
+        order = np.asarray(order)
+        B = ols_adjacency(X[np.asarray(rows)], order)
+        pos = np.empty(d, dtype=np.int64)
+        pos[order] = np.arange(d)
+        order_count += pos[None, :] < pos[:, None]
+        edge_count += np.abs(B) > threshold
+        coef_sum += B
+    return order_count, edge_count, coef_sum
 
 
 def _order_fp64(E, forced, with_measures):

@@ -412,6 +412,28 @@ def test_var_lagged_effects_inverts_the_reduced_form():
     assert np.array_equal(oracle.var_lagged_effects(M, np.zeros((d, d))), M)
 
 
+def test_bootstrap_counts_invariants():
+    """Every unordered pair is ordered one way in each resample; an edge needs
+    its parent to precede; duplicating every row leaves least squares (and so
+    the counts) unchanged; one identity resample gives the plain adjacency."""
+    s = synth.er_sem(6, 400, indeg=2.0, noise_family="laplace", seed=3)
+    rng = np.random.default_rng(0)
+    res = [rng.integers(0, 400, size=400) for _ in range(5)]
+    ords = [rng.permutation(6) for _ in range(5)]
+    oc, ec, cs = oracle.bootstrap_counts(s.X, res, ords, threshold=0.05)
+    assert np.array_equal(oc + oc.T, 5 * (1 - np.eye(6, dtype=np.int64)))
+    assert np.all(ec <= oc)
+    twice = [np.repeat(r, 2) for r in res]
+    oc2, ec2, cs2 = oracle.bootstrap_counts(s.X, twice, ords, threshold=0.05)
+    assert np.array_equal(oc2, oc) and np.array_equal(ec2, ec)
+    assert np.max(np.abs(cs2 - cs)) < 1e-9
+    ident = np.arange(400)
+    _, ec1, cs1 = oracle.bootstrap_counts(s.X, [ident], [s.order], threshold=0.0)
+    B = oracle.ols_adjacency(s.X, s.order)
+    assert np.array_equal(ec1, (B != 0).astype(np.int64))
+    assert np.array_equal(cs1, B)
+
+
 def test_fp64_and_fp32_entries_agree():
     s = synth.er_sem(9, 800, indeg=2.0, seed=6)
     X32 = s.X.astype(np.float32)
