@@ -128,6 +128,32 @@ def bench_batch(steps: int, warmup: int, seed: int) -> dict:
             "unit": "sample-pair evals/s", "workspace_bytes": int(ws.numel())}
 
 
+def bench_bootstrap(seed: int) -> dict:
+    """Bootstrap statistics of the d = 200 base sample over its 256 resamples:
+    batched orderings (graph-captured) plus one adjacency and one count update
+    per resample; one untimed call first."""
+    import torch
+
+    import paper_2403_03772_amd as lg
+    from paper_2403_03772_amd import synth
+
+    wl = synth.workload_bootstrap_batch(seed=seed)
+    base = torch.as_tensor(np.ascontiguousarray(wl.base.X, dtype=np.float32), device="cuda:0")
+    res = [torch.as_tensor(r, device="cuda:0") for r in wl.rows]
+    lg.bootstrap(base, res, threshold=0.01, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = lg.bootstrap(base, res, threshold=0.01, graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    true_edges = wl.base.B != 0
+    ep = out["edge_prob"].cpu().numpy()
+    return {"workload": "256 bootstrap resamples of one d=200 sample (n~U[500,5000])",
+            "ms": dt * 1e3, "resamples": len(res), "threshold": 0.01,
+            "mean_edge_prob_true_edges": float(ep[true_edges].mean()),
+            "mean_edge_prob_other": float(ep[~true_edges].mean())}
+
+
 def kendall_tau(a, b) -> float:
     """Kendall rank correlation of two orders of the same items."""
     from scipy import stats
@@ -399,6 +425,8 @@ def main() -> int:
         rec["varlingam"] = run_varlingam(lg)
     if not args.no_batch and args.workload == "gene":
         rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed)
+        progress("bootstrap statistics")
+        rec["bootstrap"] = bench_bootstrap(args.seed)
     if args.copy_calibration:
         src = torch.ones(256 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)

@@ -236,7 +236,7 @@ size_t lingam_residualize_workspace_size(int64_t n, int64_t d);
 int lingam_residualize(float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* active,
                        int32_t n_active, int32_t exo, void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes for lingam_adjacency on an n x d matrix (0 if unsupported). */
+/* Workspace bytes for lingam_adjacency on n samples of d variables (0 if unsupported). */
 size_t lingam_adjacency_workspace_size(int64_t n, int64_t d);
 
 /*
@@ -244,19 +244,40 @@ size_t lingam_adjacency_workspace_size(int64_t n, int64_t d);
  * by least squares, with an intercept, on the variables that precede it in
  * `order` (DirectLiNGAM's second phase, described in Section 1; the model is
  * the linear structural equation of Section 2.1).
- *   X      device FP32 [n x ldx] row-major, read only.
- *   order  device int32[d], a permutation of 0 .. d-1, exogenous first.
- *   B      device double[d * d] row-major: B[i d + j] is the coefficient of
- *          x_j in the regression of x_i when x_j precedes x_i; 0 elsewhere
- *          (the diagonal, the first variable's row, all later variables).
+ *   X       device FP32 [n_rows x ldx] row-major, read only.
+ *   rows    device int32[n] or NULL: sample s is row rows[s] of X (a
+ *           bootstrap resample); NULL = rows 0 .. n-1 (then n <= n_rows).
+ *   n, d    samples and variables.
+ *   order   device int32[d], a permutation of 0 .. d-1, exogenous first.
+ *   B       device double[d * d] row-major: B[i d + j] is the coefficient of
+ *           x_j in the regression of x_i when x_j precedes x_i; 0 elsewhere
+ *           (the diagonal, the first variable's row, all later variables).
  * FP64 throughout (the data are widened on load): centred covariance on FP64
  * MFMA, blocked Cholesky of it in the causal order, B = I - diag(L) L^-1.
- * Synchronizes.  Returns LINGAM_E_INVALID if `order` is not a permutation,
- * LINGAM_E_DEGENERATE for non-finite data or a covariance that is not
- * positive definite (collinear variables, or n <= d).
+ * Synchronizes.  Returns LINGAM_E_INVALID if `order` is not a permutation or
+ * a row index is outside [0, n_rows), LINGAM_E_DEGENERATE for non-finite
+ * data or a covariance that is not positive definite (collinear variables,
+ * or n <= d).
  */
-int lingam_adjacency(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* order,
-                     double* B, void* ws, size_t ws_bytes, void* stream);
+int lingam_adjacency(const float* X, int64_t n_rows, int64_t ldx, const int32_t* rows, int64_t n,
+                     int64_t d, const int32_t* order, double* B, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * Bootstrap statistics (resampling the rows, ordering and regressing each
+ * resample): add one resample's result to running counts.
+ *   order        device int32[d]: the resample's causal order (a permutation;
+ *                entries outside [0, d) are skipped, never written through).
+ *   B            device double[d * d]: its adjacency (lingam_adjacency).
+ *   order_count  device int32[d * d]: [i d + j] += 1 when x_j precedes x_i.
+ *   edge_count   device int32[d * d]: [i d + j] += 1 when |B[i d + j]| > threshold.
+ *   coef_sum     device double[d * d] or NULL: += B.
+ * Enqueued on `stream`; no sync.  Divided by the number of resamples, the
+ * counts are the order and edge probabilities.
+ */
+int lingam_bootstrap_accumulate(const int32_t* order, const double* B, int64_t d,
+                                double threshold, int32_t* order_count, int32_t* edge_count,
+                                double* coef_sum, void* stream);
 
 /*
  * Workspace bytes for varlingam_fit on a T x d series with `lags` lags

@@ -16,6 +16,9 @@ Functions mirror the C entry points:
   the residuals, instantaneous matrix B0; Section 3.3).
 * :func:`adjacency` -- ``lingam_adjacency`` (least squares of every
   variable on its order predecessors: the weighted adjacency matrix).
+* :func:`bootstrap`, :func:`bootstrap_accumulate` -- bootstrap order and
+  edge probabilities (batched orderings of resamples, their adjacencies,
+  ``lingam_bootstrap_accumulate``).
 * :func:`varlingam_lagged_effects` -- ``varlingam_lagged_effects``
   (theta_tau = (I - B0) M_tau).
 * :func:`batch_causal_order` -- ``lingam_batch_causal_order`` (many
@@ -36,6 +39,8 @@ from .lib import (  # noqa: F401
     Profile,
     adjacency,
     batch_causal_order,
+    bootstrap,
+    bootstrap_accumulate,
     causal_order,
     last_error,
     load,

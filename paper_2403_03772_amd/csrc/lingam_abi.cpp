@@ -937,14 +937,16 @@ size_t lingam_adjacency_workspace_size(int64_t n, int64_t d) {
   return lg::make_adj_layout(n, d).total;
 }
 
-int lingam_adjacency(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* order,
-                     double* B, void* ws, size_t ws_bytes, void* stream) {
+int lingam_adjacency(const float* X, int64_t n_rows, int64_t ldx, const int32_t* rows, int64_t n,
+                     int64_t d, const int32_t* order, double* B, void* ws, size_t ws_bytes,
+                     void* stream) {
   g_err[0] = 0;
   if (!X || !order || !B) return fail(LINGAM_E_INVALID, "X, order and B must be non-NULL");
-  if (n < 2 || d < 1 || ldx < d)
-    return fail(LINGAM_E_INVALID, "bad sizes n=%lld d=%lld ldx=%lld", (long long)n,
-                (long long)d, (long long)ldx);
-  if (n > kMaxN || d > kMaxD) return fail(LINGAM_E_UNSUPPORTED, "size beyond supported range");
+  if (n < 2 || d < 1 || ldx < d || n_rows < 1 || (!rows && n > n_rows))
+    return fail(LINGAM_E_INVALID, "bad sizes n=%lld d=%lld ldx=%lld n_rows=%lld", (long long)n,
+                (long long)d, (long long)ldx, (long long)n_rows);
+  if (n > kMaxN || d > kMaxD || n_rows > kMaxN)
+    return fail(LINGAM_E_UNSUPPORTED, "size beyond supported range");
   const lg::AdjLayout A = lg::make_adj_layout(n, d);
   if (!ws || ws_bytes < A.total)
     return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", A.total,
@@ -952,19 +954,37 @@ int lingam_adjacency(const float* X, int64_t n, int64_t d, int64_t ldx, const in
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
   int32_t s = 0;
-  // the order indexes device arrays: check it before anything reads through it
-  LG_TRY(lg::launch_adj_check(A, w, order, st), "adjacency check");
+  // the order and the row map index device arrays: check them before
+  // anything reads through them
+  LG_TRY(lg::launch_adj_check(A, w, order, rows, n_rows, st), "adjacency check");
   LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
          "hipMemcpyAsync(status)");
   LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-  if (s != 0) return fail(LINGAM_E_INVALID, "order is not a permutation of 0 .. d-1");
-  LG_TRY(lg::launch_adjacency(A, w, X, ldx, order, B, st), "adjacency launch");
+  if (s != 0)
+    return fail(LINGAM_E_INVALID,
+                "order is not a permutation of 0 .. d-1, or a row index is outside [0, n_rows)");
+  LG_TRY(lg::launch_adjacency(A, w, X, ldx, rows, order, B, st), "adjacency launch");
   LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
          "hipMemcpyAsync(status)");
   LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
   if (s != 0)
     return fail(LINGAM_E_DEGENERATE,
                 "non-finite data or a covariance that is not positive definite");
+  return LINGAM_OK;
+}
+
+int lingam_bootstrap_accumulate(const int32_t* order, const double* B, int64_t d,
+                                double threshold, int32_t* order_count, int32_t* edge_count,
+                                double* coef_sum, void* stream) {
+  g_err[0] = 0;
+  if (!order || !B || !order_count || !edge_count)
+    return fail(LINGAM_E_INVALID, "order, B, order_count and edge_count must be non-NULL");
+  if (d < 1) return fail(LINGAM_E_INVALID, "need d >= 1 (got %lld)", (long long)d);
+  if (d > kMaxD) return fail(LINGAM_E_UNSUPPORTED, "d <= %lld supported", (long long)kMaxD);
+  if (!(threshold >= 0.0)) return fail(LINGAM_E_INVALID, "threshold must be >= 0");
+  LG_TRY(lg::launch_boot_accumulate(order, B, (int)d, threshold, order_count, edge_count,
+                                    coef_sum, (hipStream_t)stream),
+         "bootstrap accumulate");
   return LINGAM_OK;
 }
 

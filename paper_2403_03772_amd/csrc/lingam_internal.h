@@ -492,12 +492,20 @@ struct AdjLayout {
 };
 
 AdjLayout make_adj_layout(int64_t n, int64_t d);
-// Zero the status, check that `order` is a permutation (status kInvalid if not).
-hipError_t launch_adj_check(const AdjLayout& A, char* ws, const int32_t* order, hipStream_t st);
-// B (d x d, row-major) after a passed check; status kDegenerate on non-finite
-// data or a covariance that is not positive definite.
+// Zero the status; status kInvalid unless `order` is a permutation and every
+// rows[s] (s < n, if rows is given) lies in [0, n_rows).
+hipError_t launch_adj_check(const AdjLayout& A, char* ws, const int32_t* order,
+                            const int32_t* rows, int64_t n_rows, hipStream_t st);
+// B (d x d, row-major) after a passed check; sample s is row s of X, or row
+// rows[s]; status kDegenerate on non-finite data or a covariance that is not
+// positive definite.
 hipError_t launch_adjacency(const AdjLayout& A, char* ws, const float* X, int64_t ldx,
-                            const int32_t* order, double* B, hipStream_t st);
+                            const int32_t* rows, const int32_t* order, double* B,
+                            hipStream_t st);
+// One resample's bootstrap counts (see lingam_bootstrap_accumulate).
+hipError_t launch_boot_accumulate(const int32_t* order, const double* B, int d, double thr,
+                                  int32_t* order_count, int32_t* edge_count, double* coef_sum,
+                                  hipStream_t st);
 
 // Dense FP64 pieces shared by the adjacency and VarLiNGAM.
 // In-place Cholesky of the leading p x p block of A (lower triangle holds L;

@@ -655,7 +655,10 @@ __global__ void k_gather_status(const JobDev* __restrict__ jobs, int njobs, int3
 
 // X row-major [n x ldx] -> Zd[v][s] (FP64) for the VAR series: zero padding
 // for s >= n and row d.
+// Sample s of the output is row s of X, or row rows[s] when a row map is given
+// (indices are checked before the launch).
 __global__ __launch_bounds__(256) void k_transpose_f64(const float* __restrict__ X, int64_t ldx,
+                                                       const int32_t* __restrict__ rows,
                                                        int n, int d, int n_pad,
                                                        double* __restrict__ Zd, int64_t ldz,
                                                        Ctrl* ctrl) {
@@ -667,7 +670,7 @@ __global__ __launch_bounds__(256) void k_transpose_f64(const float* __restrict__
     const int sl = ty * 16 + i, s = s0 + sl, v = v0 + tx;
     float val = 0.f;
     if (s < n && v < d) {
-      val = X[(int64_t)s * ldx + v];
+      val = X[(int64_t)(rows ? rows[s] : s) * ldx + v];
       bad |= !isfinite(val);
     }
     tile[sl][tx] = val;
@@ -861,12 +864,40 @@ __global__ __launch_bounds__(256) void k_rr_apply(float* __restrict__ X, int64_t
 
 __global__ void k_zero_i32(int32_t* p) { p[0] = 0; }
 
-// Status kInvalid unless order is a permutation of 0 .. d-1 (mark starts at 0).
+// Status kInvalid unless order is a permutation of 0 .. d-1 (mark starts at 0)
+// and every row index rows[0 .. n-1] (if given) lies in [0, n_rows).
 __global__ __launch_bounds__(1024) void k_check_perm(const int32_t* __restrict__ order, int d,
-                                                     int32_t* __restrict__ mark, Ctrl* ctrl) {
+                                                     const int32_t* __restrict__ rows, int64_t n,
+                                                     int64_t n_rows, int32_t* __restrict__ mark,
+                                                     Ctrl* ctrl) {
   for (int i = threadIdx.x; i < d; i += 1024) {
     const int v = order[i];
     if (v < 0 || v >= d || atomicAdd(&mark[v], 1) != 0) set_status(ctrl, kStInvalid);
+  }
+  if (rows)
+    for (int64_t s = threadIdx.x; s < n; s += 1024)
+      if (rows[s] < 0 || rows[s] >= n_rows) set_status(ctrl, kStInvalid);
+}
+
+// Bootstrap counts of one resample: order_count[i][j] += 1 when x_j precedes
+// x_i; edge_count[i][j] += 1 when |B[i][j]| > thr; coef_sum += B (if given).
+__global__ void k_boot_accumulate(const int32_t* __restrict__ order,
+                                  const double* __restrict__ B, int d, double thr,
+                                  int32_t* __restrict__ order_count,
+                                  int32_t* __restrict__ edge_count,
+                                  double* __restrict__ coef_sum) {
+  const int64_t total = (int64_t)d * d;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / d), b = (int)(e - (int64_t)a * d);  // positions a > b
+    if (a > b) {
+      const int oa = order[a], ob = order[b];
+      if ((unsigned)oa < (unsigned)d && (unsigned)ob < (unsigned)d)  // never write outside
+        order_count[(int64_t)oa * d + ob] += 1;
+    }
+    const double w = B[e];
+    if (fabs(w) > thr) edge_count[e] += 1;
+    if (coef_sum) coef_sum[e] += w;
   }
 }
 
@@ -1168,7 +1199,8 @@ hipError_t launch_var_fit(const VarLayout& V, char* ws, char* job, const float* 
   double* W = at<double>(ws, V.w);
   // series -> variable-major FP64 (padding beyond T is zero)
   dim3 g1((unsigned)(V.ldx / 64), (unsigned)((V.d + 1 + 63) / 64));
-  hipLaunchKernelGGL(k_transpose_f64, g1, dim3(256), 0, st, X, ldx_in, (int)V.T, (int)V.d,
+  hipLaunchKernelGGL(k_transpose_f64, g1, dim3(256), 0, st, X, ldx_in, (const int32_t*)nullptr,
+                     (int)V.T, (int)V.d,
                      (int)V.ldx, Xd, V.ldx, ctrl);
   hipLaunchKernelGGL(k_fill, dim3((unsigned)((V.N + 255) / 256)), dim3(256), 0, st, ones,
                      (int)V.N, 1.0);
@@ -1234,28 +1266,39 @@ AdjLayout make_adj_layout(int64_t n, int64_t d) {
   return A;
 }
 
-hipError_t launch_adj_check(const AdjLayout& A, char* ws, const int32_t* order, hipStream_t st) {
+hipError_t launch_adj_check(const AdjLayout& A, char* ws, const int32_t* order,
+                            const int32_t* rows, int64_t n_rows, hipStream_t st) {
   Ctrl* ctrl = at<Ctrl>(ws, A.ctrl);
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, &ctrl->status);
   const int64_t g = (A.d + 255) / 256;
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(g < 1024 ? g : 1024)), dim3(256), 0, st,
                      at<int32_t>(ws, A.mark), A.d, 0);
-  hipLaunchKernelGGL(k_check_perm, dim3(1), dim3(1024), 0, st, order, (int)A.d,
-                     at<int32_t>(ws, A.mark), ctrl);
+  hipLaunchKernelGGL(k_check_perm, dim3(1), dim3(1024), 0, st, order, (int)A.d, rows, A.n,
+                     n_rows, at<int32_t>(ws, A.mark), ctrl);
   return hipGetLastError();
 }
 
 hipError_t launch_adjacency(const AdjLayout& A, char* ws, const float* X, int64_t ldx,
-                            const int32_t* order, double* B, hipStream_t st) {
+                            const int32_t* rows, const int32_t* order, double* B,
+                            hipStream_t st) {
   Ctrl* ctrl = at<Ctrl>(ws, A.ctrl);
   double* Xd = at<double>(ws, A.xd);
   double* S = at<double>(ws, A.s);
   dim3 g1((unsigned)(A.ldx / 64), (unsigned)((A.d + 1 + 63) / 64));
-  hipLaunchKernelGGL(k_transpose_f64, g1, dim3(256), 0, st, X, ldx, (int)A.n, (int)A.d,
+  hipLaunchKernelGGL(k_transpose_f64, g1, dim3(256), 0, st, X, ldx, rows, (int)A.n, (int)A.d,
                      (int)A.ldx, Xd, A.ldx, ctrl);
   LG_HIP(launch_cov_perm(Xd, A.ldx, (int)A.n, (int)A.d, order, at<double>(ws, A.mu), S, st));
   LG_HIP(launch_cholesky(S, A.d, (int)A.d, at<double>(ws, A.tol), ctrl, st));
   return launch_tri_adjacency(S, A.d, (int)A.d, order, B, at<double>(ws, A.y), st);
+}
+
+hipError_t launch_boot_accumulate(const int32_t* order, const double* B, int d, double thr,
+                                  int32_t* order_count, int32_t* edge_count, double* coef_sum,
+                                  hipStream_t st) {
+  const int64_t g = ((int64_t)d * d + 255) / 256;
+  hipLaunchKernelGGL(k_boot_accumulate, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st,
+                     order, B, d, thr, order_count, edge_count, coef_sum);
+  return hipGetLastError();
 }
 
 }  // namespace lg

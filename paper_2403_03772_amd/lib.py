@@ -187,7 +187,9 @@ def load():
         lib.lingam_proposer_adam.restype = ctypes.c_int
         lib.lingam_adjacency_workspace_size.argtypes = [i64, i64]
         lib.lingam_adjacency_workspace_size.restype = sz
-        lib.lingam_adjacency.argtypes = [P, i64, i64, i64, P, P, P, sz, P]
+        lib.lingam_adjacency.argtypes = [P, i64, i64, P, i64, i64, P, P, P, sz, P]
+        lib.lingam_bootstrap_accumulate.argtypes = [P, P, i64, ctypes.c_double, P, P, P, P]
+        lib.lingam_bootstrap_accumulate.restype = ctypes.c_int
         lib.lingam_adjacency.restype = ctypes.c_int
         lib.varlingam_lagged_effects.argtypes = [P, P, i64, i32, P, P]
         lib.varlingam_lagged_effects.restype = ctypes.c_int
@@ -365,18 +367,25 @@ def residualize(X, active, exo: int):
     return X
 
 
-def adjacency(X, order, *, workspace=None):
-    """Least-squares adjacency of a CUDA float32 ``X`` (n x d) given a causal
-    ``order``: B[i, j] = coefficient of x_j when x_i is regressed (with
-    intercept) on its order predecessors.  Returns a d x d float64 tensor."""
+def adjacency(X, order, *, rows=None, workspace=None):
+    """Least-squares adjacency of a CUDA float32 ``X`` (n_rows x d) given a
+    causal ``order``: B[i, j] = coefficient of x_j when x_i is regressed (with
+    intercept) on its order predecessors.  ``rows`` (int32 row indices, e.g. a
+    bootstrap resample) selects the samples; default all rows.  Returns a
+    d x d float64 tensor."""
     import torch
 
     lib = load()
     _cuda_f32_matrix(torch, X)
-    n, d = X.shape
+    n_rows, d = X.shape
     o = torch.as_tensor(order, dtype=torch.int32).to(X.device).contiguous()
     if o.numel() != d:
         raise ValueError(f"order has {o.numel()} entries, X has {d} columns")
+    r = None
+    n = n_rows
+    if rows is not None:
+        r = torch.as_tensor(rows, dtype=torch.int32).to(X.device).contiguous()
+        n = r.numel()
     need = int(lib.lingam_adjacency_workspace_size(n, d))
     if need == 0:
         raise LingamError(E_INVALID, f"unsupported size n={n} d={d}")
@@ -384,10 +393,57 @@ def adjacency(X, order, *, workspace=None):
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=X.device)
     B = torch.empty((d, d), dtype=torch.float64, device=X.device)
-    code = lib.lingam_adjacency(_ptr(X), n, d, X.stride(0), _ptr(o), _ptr(B), _ptr(ws),
-                                ws.numel(), _stream_ptr(torch, X.device))
+    code = lib.lingam_adjacency(_ptr(X), n_rows, X.stride(0), _ptr(r), n, d, _ptr(o), _ptr(B),
+                                _ptr(ws), ws.numel(), _stream_ptr(torch, X.device))
     _check(code)
     return B
+
+
+def bootstrap_accumulate(order, B, threshold, order_count, edge_count, coef_sum=None):
+    """Add one resample's order and adjacency to the running counts (in place)."""
+    import torch
+
+    lib = load()
+    d = B.shape[0]
+    _check(lib.lingam_bootstrap_accumulate(_ptr(order), _ptr(B), d, float(threshold),
+                                           _ptr(order_count), _ptr(edge_count), _ptr(coef_sum),
+                                           _stream_ptr(torch, B.device)))
+
+
+def bootstrap(X, resamples, *, threshold: float = 0.0, graph: bool = False,
+              autotune: bool = False, learned: Learned | None = None):
+    """Bootstrap statistics of DirectLiNGAM on a CUDA float32 ``X`` (n x d).
+
+    ``resamples``: sequence of int32 row-index arrays (drawn by the caller,
+    with replacement).  All resamples are ordered in one batched run, then
+    regressed along their orders; returns a dict with ``orders`` (list),
+    ``order_prob`` (d x d: P(x_j precedes x_i) at [i, j]), ``edge_prob``
+    (P(|B[i, j]| > threshold)), ``coef_mean`` (mean of B) and ``n`` (the
+    number of resamples).
+    """
+    import torch
+
+    lib = load()
+    _cuda_f32_matrix(torch, X)
+    d = X.shape[1]
+    dev = X.device
+    rows = [torch.as_tensor(r, dtype=torch.int32).to(dev).contiguous() for r in resamples]
+    if not rows:
+        raise ValueError("no resamples")
+    out = batch_causal_order([{"X": X, "rows": r} for r in rows], graph=graph,
+                             autotune=autotune, learned=learned)
+    order_count = torch.zeros((d, d), dtype=torch.int32, device=dev)
+    edge_count = torch.zeros((d, d), dtype=torch.int32, device=dev)
+    coef_sum = torch.zeros((d, d), dtype=torch.float64, device=dev)
+    need = max(int(lib.lingam_adjacency_workspace_size(r.numel(), d)) for r in rows)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    for r, o in zip(rows, out["orders"]):
+        B = adjacency(X, o, rows=r, workspace=ws)
+        bootstrap_accumulate(o, B, threshold, order_count, edge_count, coef_sum)
+    R = float(len(rows))
+    return {"orders": out["orders"], "order_prob": order_count.double() / R,
+            "edge_prob": edge_count.double() / R, "coef_mean": coef_sum / R, "n": len(rows),
+            "order_count": order_count, "edge_count": edge_count}
 
 
 def varlingam_lagged_effects(M, B0):

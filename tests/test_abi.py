@@ -125,7 +125,8 @@ def test_adjacency_argument_errors():
     lib = pkg.load()
     v = ctypes.c_void_p(1)
     c = lambda **k: lib.lingam_adjacency(
-        v if k.get("X", 1) else None, k.get("n", 10), k.get("d", 3), k.get("ldx", 3),
+        v if k.get("X", 1) else None, k.get("n_rows", 10), k.get("ldx", 3),
+        v if k.get("rows", 0) else None, k.get("n", 10), k.get("d", 3),
         v if k.get("order", 1) else None, v if k.get("B", 1) else None, v,
         k.get("ws", 1 << 30), None)
     assert c(X=0) == L.E_INVALID
@@ -134,8 +135,22 @@ def test_adjacency_argument_errors():
     assert c(n=1) == L.E_INVALID
     assert c(d=0) == L.E_INVALID
     assert c(ldx=2) == L.E_INVALID
+    assert c(n=11) == L.E_INVALID          # more samples than rows, no row map
+    assert c(n_rows=0, rows=1) == L.E_INVALID
     assert c(d=1 << 20, ldx=1 << 20) == L.E_UNSUPPORTED
     assert c(ws=16) == L.E_WORKSPACE
+    a = lambda **k: lib.lingam_bootstrap_accumulate(
+        v if k.get("order", 1) else None, v if k.get("B", 1) else None, k.get("d", 3),
+        k.get("thr", 0.0), v if k.get("oc", 1) else None, v if k.get("ec", 1) else None,
+        None, None)
+    assert a(order=0) == L.E_INVALID
+    assert a(B=0) == L.E_INVALID
+    assert a(oc=0) == L.E_INVALID
+    assert a(ec=0) == L.E_INVALID
+    assert a(d=0) == L.E_INVALID
+    assert a(thr=-1.0) == L.E_INVALID
+    assert a(thr=float("nan")) == L.E_INVALID
+    assert a(d=1 << 20) == L.E_UNSUPPORTED
     assert lib.lingam_adjacency_workspace_size(1, 3) == 0
     assert lib.lingam_adjacency_workspace_size(10, 0) == 0
     # n = 100, d = 8: covariance, factor and inverse columns dominate

@@ -109,3 +109,54 @@ def test_lagged_effects_matches_oracle(lib):
                                           torch.as_tensor(B0).cuda()).cpu().numpy()
         ref = oracle.var_lagged_effects(M, B0)
         assert np.max(np.abs(th - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_adjacency_row_map(lib):
+    """A row map regresses the gathered rows: same result as the gathered matrix."""
+    import torch
+    s = synth.er_sem(20, 800, indeg=2.0, noise_family=("uniform", "laplace"), seed=11)
+    X32 = s.X.astype(np.float32)
+    rows = np.random.default_rng(1).integers(0, 800, size=1500).astype(np.int32)
+    X = torch.as_tensor(X32).cuda()
+    B = lib.adjacency(X, s.order, rows=rows).cpu().numpy()
+    G = lib.adjacency(torch.as_tensor(np.ascontiguousarray(X32[rows])).cuda(),
+                      s.order).cpu().numpy()
+    assert np.max(np.abs(B - G)) <= 1e-12 * max(1.0, np.max(np.abs(G)))
+    ref = oracle.ols_adjacency(X32[rows].astype(np.float64), s.order)
+    assert np.max(np.abs(B - ref)) <= _tol(ref)
+    with pytest.raises(lib.LingamError) as e:
+        lib.adjacency(X, s.order, rows=np.array([0, 5, 800], dtype=np.int32))
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("threshold", [0.0, 0.1])
+def test_bootstrap_matches_oracle(lib, threshold):
+    """Bootstrap statistics: the GPU's batched orders of the resamples are
+    handed to the oracle, which regresses and counts by definition.  Counts
+    must agree exactly except where an oracle coefficient lies within 1e-7 of
+    the threshold (either side of it is then correct)."""
+    import torch
+    s = synth.er_sem(12, 600, indeg=2.0, noise_family=("uniform", "laplace", "exp"), seed=5)
+    X32 = s.X.astype(np.float32)
+    rng = np.random.default_rng(2)
+    res = [rng.integers(0, 600, size=int(rng.integers(300, 900))).astype(np.int32)
+           for _ in range(16)]
+    out = lib.bootstrap(torch.as_tensor(X32).cuda(), res, threshold=threshold)
+    orders = [o.cpu().numpy() for o in out["orders"]]
+    for o in orders:
+        assert sorted(o.tolist()) == list(range(12))
+    oc, ec, cs = oracle.bootstrap_counts(X32.astype(np.float64), res, orders, threshold)
+    assert np.array_equal(out["order_count"].cpu().numpy(), oc)
+    near = np.zeros((12, 12), dtype=bool)
+    for r, o in zip(res, orders):
+        B = oracle.ols_adjacency(X32[r].astype(np.float64), o)
+        near |= np.abs(np.abs(B) - threshold) <= 1e-7
+    if threshold == 0.0:
+        near[:] = False  # exact zeros outside the predecessors, nonzero inside
+    ok = ~near
+    assert np.array_equal(out["edge_count"].cpu().numpy()[ok], ec[ok])
+    assert np.max(np.abs(out["coef_mean"].cpu().numpy() * 16 - cs)) <= 1e-8 * max(
+        1.0, np.max(np.abs(cs)))
+    # orders: each resample's order is the batch engine's ordering of the gathered rows
+    o0 = lib.causal_order(torch.as_tensor(np.ascontiguousarray(X32[res[0]])).cuda())
+    assert np.array_equal(o0.cpu().numpy(), orders[0])
