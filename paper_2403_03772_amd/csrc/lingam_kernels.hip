@@ -627,11 +627,28 @@ __global__ __launch_bounds__(256) void k_resid(const JobDev* __restrict__ jobs, 
   float* zf = J.z + (int64_t)sp * ldz;
   const int n = J.n;
   MomAcc ma;
-  for (int k = threadIdx.x; k < J.n_pad; k += 256) {
-    const double z = al * (zp[k] - r * ze[k]);  // padded samples stay 0
-    zp[k] = z;
-    zf[k] = (float)z;
-    if (k < n) ma.add(z);
+  // four samples per thread in flight: all loads are issued before the stores
+  // (the rows of p and e are distinct), the samples are added in index order
+  constexpr int kU = 4;
+  const int n_pad = J.n_pad;
+  for (int k0 = threadIdx.x; k0 < n_pad; k0 += 256 * kU) {
+    double a[kU], b[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * 256;
+      a[u] = k < n_pad ? zp[k] : 0.0;
+      b[u] = k < n_pad ? ze[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * 256;
+      if (k < n_pad) {
+        const double z = al * (a[u] - r * b[u]);  // padded samples stay 0
+        zp[k] = z;
+        zf[k] = (float)z;
+        if (k < n) ma.add(z);
+      }
+    }
   }
   double acc[5];
   ma.sums(acc);
