@@ -205,6 +205,28 @@ def listwise_ce(s, offsets, targets):
     return loss / nl, ds / nl
 
 
+def listwise_ce_soft(s, offsets, weights):
+    """Mean over lists of the cross-entropy between the target distribution
+    q = weights / sum(weights) (per list, weights >= 0, positive sum) and
+    softmax(s_list): sum_r -q_r log softmax(s)_r.  With one-hot weights this
+    is :func:`listwise_ce`.  Returns (loss, ds)."""
+    s = np.asarray(s, dtype=np.float64)
+    w = np.asarray(weights, dtype=np.float64)
+    ds = np.zeros_like(s)
+    nl = len(offsets) - 1
+    loss = 0.0
+    for L in range(nl):
+        a, b = offsets[L], offsets[L + 1]
+        z = s[a:b]
+        q = w[a:b] / w[a:b].sum()
+        mx = z.max()
+        e = np.exp(z - mx)
+        lse = mx + np.log(e.sum())
+        loss += np.sum(q * (lse - z))
+        ds[a:b] = e / e.sum() - q
+    return loss / nl, ds / nl
+
+
 @dataclass
 class Adam:
     """Adam (Kingma & Ba, 2015) with bias correction."""

@@ -117,6 +117,37 @@ def test_listwise_ce_closed_forms():
     assert P.listwise_ce(s, offs, tg)[0] < 1e-20
 
 
+def test_listwise_ce_soft_pins():
+    """Soft targets: one-hot weights give the hard loss and gradient; uniform
+    weights on zero scores give loss log m (cross-entropy of a uniform target
+    against a uniform prediction) and zero gradient; scaling a list's weights
+    changes nothing; the gradient matches central differences of the loss."""
+    rng = np.random.default_rng(4)
+    sizes = [6, 11, 4]
+    offs, tg = _lists(rng, sizes)
+    s = rng.normal(size=offs[-1])
+    w = np.zeros(offs[-1])
+    w[tg] = 1.0
+    l_h, d_h = P.listwise_ce(s, offs, tg)
+    l_s, d_s = P.listwise_ce_soft(s, offs, w)
+    assert abs(l_h - l_s) < 1e-14 and np.max(np.abs(d_h - d_s)) < 1e-15
+    l_u, d_u = P.listwise_ce_soft(np.zeros(offs[-1]), offs, np.ones(offs[-1]))
+    assert abs(l_u - np.mean(np.log(sizes))) < 1e-15 and np.max(np.abs(d_u)) < 1e-16
+    w2 = rng.uniform(0.0, 2.0, size=offs[-1])
+    sc = w2.copy()
+    for L in range(len(sizes)):
+        sc[offs[L]:offs[L + 1]] *= 10.0 ** L
+    a = P.listwise_ce_soft(s, offs, w2)
+    b = P.listwise_ce_soft(s, offs, sc)
+    assert abs(a[0] - b[0]) < 1e-13 and np.max(np.abs(a[1] - b[1])) < 1e-15
+    h = 1e-6
+    for i in range(offs[-1]):
+        e = np.zeros(offs[-1])
+        e[i] = h
+        fd = (P.listwise_ce_soft(s + e, offs, w2)[0] - P.listwise_ce_soft(s - e, offs, w2)[0]) / (2 * h)
+        assert abs(fd - a[1][i]) < 1e-8
+
+
 def test_adam_first_step_and_convergence():
     rng = np.random.default_rng(3)
     x = rng.normal(size=50)
