@@ -295,9 +295,50 @@ def _plain_choice(k, U):
     return best
 
 
+def witnesses(Xc, active, W: int = 4) -> np.ndarray:
+    """For every active column (position p into ``active``), the positions of
+    the W other active columns with the largest |correlation| with it (ties to
+    the smaller position; -1 past the last when fewer exist).  Their pair
+    measures are the extra columns of the learned form's lower bound on k: a
+    variable with parents is strongly correlated with them, and R against a
+    parent is strongly negative."""
+    U = np.asarray(active)
+    m = U.size
+    n = Xc.shape[0]
+    Z = np.stack([standardize(Xc[:, v]) for v in U])
+    a = np.abs((Z @ Z.T) / n)
+    out = np.full((m, W), -1, dtype=np.int64)
+    for p in range(m):
+        others = sorted((q for q in range(m) if q != p), key=lambda q: (-a[p, q], q))
+        out[p, :min(W, len(others))] = others[:W]
+    return out
+
+
+def lower_bounds(D, C, wit=None) -> np.ndarray:
+    """Lower bound on k_l = sum_j min(0, R(l, j))^2 for every position l from
+    the columns measured in a learned step: the candidate rows give R(c, l) =
+    -R(l, c) for every c in C, and each non-candidate's witnesses w (not in C)
+    give R(l, w).  Every column is counted once, so the bound never exceeds
+    k_l.  D[a, b] = R(U[a], U[b])."""
+    D = np.asarray(D, dtype=np.float64)
+    m = D.shape[0]
+    inC = np.zeros(m, dtype=bool)
+    inC[np.asarray(C, dtype=np.int64)] = True
+    pos = np.maximum(D[np.asarray(C, dtype=np.int64)], 0.0)
+    lb = np.sum(pos * pos, axis=0)
+    if wit is not None:
+        for l in range(m):
+            if inC[l]:
+                continue
+            for w in wit[l]:
+                if w >= 0 and not inC[w]:
+                    lb[l] += min(0.0, D[l, w]) ** 2
+    return lb
+
+
 def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: int = 32,
                   min_m: int | None = None, emulate_bf16: bool = True,
-                  max_suspects: int = 1024):
+                  max_suspects: int = 1024, n_witness: int = 4):
     """Causal order by the learned-proposal form.
 
     X: n x d samples (cast to FP32 first, like the library's input).
@@ -306,7 +347,9 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
     are too many for the second pass (+inf: never, so the order is the plain
     order).  audit_every: full step at t % audit_every == 0 (0: no audits).
     Steps with m <= min_m (default 2 min(K, 64)) are plain steps.  K is the
-    most candidates; a step with m variables takes step_topk(m, K).
+    most candidates; a step with m variables takes step_topk(m, K).  The
+    lower bound on the non-candidates' k adds ``n_witness`` witness columns
+    per variable (:func:`witnesses`, :func:`lower_bounds`).
     Returns (order, [StepInfo]).
     """
     X = np.asarray(np.asarray(X, dtype=np.float32), dtype=np.float64).copy()
@@ -340,8 +383,8 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             for c in C[1:]:
                 if k[c] < k[best] or (k[c] == k[best] and U[c] < U[best]):
                     best = c
-            pos = np.maximum(D[C], 0.0)            # R(c, l) > 0 -> k_l contribution
-            lb = np.sum(pos * pos, axis=0)
+            wit = witnesses(X, U, n_witness) if n_witness > 0 else None
+            lb = lower_bounds(D, C, wit)
             excl = ~inC
             sus = np.flatnonzero(excl & ~(lb > k[best]))
             certified = sus.size == 0

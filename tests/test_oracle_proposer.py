@@ -148,6 +148,33 @@ def test_listwise_ce_soft_pins():
         assert abs(fd - a[1][i]) < 1e-8
 
 
+def test_lower_bounds_are_bounds():
+    """The learned step's bound never exceeds k, adding witness columns never
+    lowers it, and when the candidates and witnesses cover every column it is
+    k itself (for every non-candidate)."""
+    s = synth.er_sem(14, 1500, indeg=2.5, noise_family=("uniform", "laplace"), seed=9)
+    U = list(range(14))
+    X = s.X.astype(np.float32).astype(np.float64)
+    D = oracle.pair_matrix(X, U)
+    neg = np.minimum(D, 0.0)
+    k = np.sum(neg * neg, axis=1)
+    C = np.array([2, 7, 11])
+    lb0 = P.lower_bounds(D, C)
+    lb4 = P.lower_bounds(D, C, P.witnesses(X, U, 4))
+    full = P.lower_bounds(D, C, P.witnesses(X, U, 13))
+    notc = np.setdiff1d(np.arange(14), C)
+    assert np.all(lb0[notc] <= lb4[notc] + 1e-18)
+    assert np.all(lb4[notc] <= k[notc] * (1 + 1e-12))
+    assert np.max(np.abs(full[notc] - k[notc])) <= 1e-12 * np.max(k)
+    wit = P.witnesses(X, U, 3)
+    Z = (X - X.mean(0)) / X.std(0)
+    a = np.abs(Z.T @ Z / X.shape[0])
+    for p in range(14):
+        others = [q for q in range(14) if q != p]
+        top = sorted(others, key=lambda q: -a[p, q])[:3]
+        assert list(wit[p]) == top
+
+
 def test_adam_first_step_and_convergence():
     rng = np.random.default_rng(3)
     x = rng.normal(size=50)
