@@ -403,9 +403,10 @@ def main() -> int:
         rec["learned"] = run_learned(lg, X, n, d, args.steps, lw, exact, pl["order"],
                                      ms_per_step, B)
         rec["learned"]["proposer"] = {k: meta.get(k) for k in
-                                      ("sems", "d", "n", "lists", "holdout")}
+                                      ("sems", "d", "n", "big_sems", "big_d", "target",
+                                       "lists", "holdout", "holdout_big")}
         # fast form: no second pass, the best candidate is always taken
-        fast = lg.Learned(prop, topk=K, margin=-np.inf, max_suspects=0)
+        fast = lg.Learned(prop, topk=K, margin=-np.inf, max_suspects=0, audit_every=32)
         progress("learned (fast)")
         rec["learned"]["fast"] = run_learned(lg, X, n, d, args.steps, lw, fast, pl["order"],
                                              ms_per_step, B)

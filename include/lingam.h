@@ -30,15 +30,17 @@
  * 128 -> 128 -> 1, ReLU, BF16 weights, FP32 accumulation) scores the active
  * variables, the exact measure k_i is computed only for the `topk` best
  * scored, and the choice is made as follows.  The candidates' rows bound every
- * other variable's k from below (sum over candidates c of max(0, R(c, l))^2);
- * the "suspects" are the variables whose bound does not exceed the best
+ * other variable's k from below (sum over candidates c of max(0, R(c, l))^2),
+ * and so do its pair measures against its four most correlated non-candidate
+ * variables ("witnesses": sum of min(0, R(l, w))^2), each column counted
+ * once; the "suspects" are the variables whose bound does not exceed the best
  * candidate's k.  (a) No suspect: the best candidate is the plain search's
  * choice (certified).  (b) At most min(max_suspects, m/2 - topk) suspects: their rows
  * are evaluated exactly in a second pass and the best of candidates and
  * suspects is the plain choice.  (c) More: the best candidate is taken when
  * its score leads every non-candidate's by at least `margin`.  Otherwise, and
- * at every audit step (t % audit_every == 0), the full step of the exact
- * search decides.  With margin = +inf the order is the plain order.  This proposal layer is not part of the paper's method; it
+ * at every audit step (t % audit_every == 0, a check of the margin rule), the
+ * full step of the exact search decides.  With margin = +inf the order is the plain order.  This proposal layer is not part of the paper's method; it
  * is an addition on top of the exact search it accelerates.
  */
 #ifndef LINGAM_MI355X_H
@@ -130,7 +132,8 @@ typedef struct lingam_opts {
                                    them (a multiple of 8), at least min(64, topk);
                                    default 64 */
   int32_t audit_every;          /* full-step audit when t % audit_every == 0; 0 = never;
-                                   default 32 */
+                                   default 0 (with margin = +inf every decision is
+                                   already the exact one, so an audit only repeats it) */
   float margin;                 /* score lead that accepts the best candidate when the
                                    suspects are too many for the second pass; +inf never
                                    does (exact); default +inf */
@@ -351,6 +354,20 @@ int lingam_proposer_grad(const float* proposer, const float* features, int64_t r
                          const int64_t* offsets, const int64_t* targets, int32_t n_lists,
                          float* grad, float* loss, float* scores, void* ws, size_t ws_bytes,
                          void* stream);
+
+/*
+ * As lingam_proposer_grad with a soft target per list: weights device
+ * FP32[rows] >= 0; the target distribution of list L is its rows' weights
+ * divided by their sum, and loss = mean over lists of
+ * sum_r q_r (logsumexp(s_L) - s_r) (one-hot weights give the hard loss).
+ * Uses the workspace of lingam_proposer_grad_workspace_size.  Synchronizes;
+ * malformed offsets, a negative or non-finite weight, or a list whose weights
+ * sum to 0 return LINGAM_E_INVALID.
+ */
+int lingam_proposer_grad_soft(const float* proposer, const float* features, int64_t rows,
+                              const int64_t* offsets, const float* weights, int32_t n_lists,
+                              float* grad, float* loss, float* scores, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /*
  * One Adam step (bias-corrected; Kingma and Ba) on the trainable values of

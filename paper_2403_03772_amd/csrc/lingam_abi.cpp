@@ -259,6 +259,8 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
       J.rc = reinterpret_cast<double*>(b + L.rc);
       J.kc = reinterpret_cast<double*>(b + L.kc);
       J.lb = reinterpret_cast<double*>(b + L.lb);
+      J.wit = reinterpret_cast<int32_t*>(b + L.wit);
+      J.wr = reinterpret_cast<double*>(b + L.wr);
       J.steplog = h.step_log ? h.step_log : reinterpret_cast<int32_t*>(b + L.steplog);
       J.cap_s = std::min<int32_t>(L.cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars);
       J.cand2 = reinterpret_cast<int32_t*>(b + L.cand2);
@@ -365,6 +367,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
       if (pf) pf->cand_evals += T.cand_evals;
     }
+    if (T.g[lg::kKWit] > 0)
+      LG_TRY(lg::launch_pair_wit(table, P.njobs, t, sc, T.g[lg::kKWit], st), "witness pairs");
     // learned steps: the full-step kernels are gated on the device, so their
     // host grids are only bounds; bounded grids walk the items instead
     const bool gated = T.g[lg::kKLsel] > 0;
@@ -751,7 +755,7 @@ void lingam_opts_init(lingam_opts* o) {
   memset(o, 0, sizeof(*o));
   o->struct_size = sizeof(lingam_opts);
   o->topk = 64;
-  o->audit_every = 32;
+  o->audit_every = 0;
   o->margin = INFINITY;
   o->learned_min_m = 128;
   o->max_suspects = lg::kMaxSuspects;
@@ -1061,14 +1065,16 @@ size_t lingam_proposer_grad_workspace_size(int64_t rows, int32_t n_lists) {
   return lg::make_train_layout(rows, n_lists).total;
 }
 
-int lingam_proposer_grad(const float* proposer, const float* features, int64_t rows,
-                         const int64_t* offsets, const int64_t* targets, int32_t n_lists,
-                         float* grad, float* loss, float* scores, void* ws, size_t ws_bytes,
-                         void* stream) {
+namespace {
+
+int proposer_grad(const float* proposer, const float* features, int64_t rows,
+                  const int64_t* offsets, const int64_t* targets, const float* weights,
+                  int32_t n_lists, float* grad, float* loss, float* scores, void* ws,
+                  size_t ws_bytes, void* stream) {
   g_err[0] = 0;
-  if (!proposer || !features || !offsets || !targets || !grad)
+  if (!proposer || !features || !offsets || !(targets || weights) || !grad)
     return fail(LINGAM_E_INVALID,
-                "proposer, features, offsets, targets and grad must be non-NULL");
+                "proposer, features, offsets, targets (or weights) and grad must be non-NULL");
   if (rows < 1 || rows > kMaxN || n_lists < 1)
     return fail(LINGAM_E_INVALID, "need 1 <= rows <= %lld and n_lists >= 1", (long long)kMaxN);
   const lg::TrainLayout T = lg::make_train_layout(rows, n_lists);
@@ -1076,8 +1082,8 @@ int lingam_proposer_grad(const float* proposer, const float* features, int64_t r
     return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", T.total,
                 ws ? ws_bytes : (size_t)0);
   hipStream_t st = (hipStream_t)stream;
-  LG_TRY(lg::launch_grad(T, proposer, features, offsets, targets, grad, loss, scores, (char*)ws,
-                         st),
+  LG_TRY(lg::launch_grad(T, proposer, features, offsets, weights ? nullptr : targets, weights,
+                         grad, loss, scores, (char*)ws, st),
          "proposer grad");
   int32_t status = 0;
   LG_TRY(hipMemcpyAsync(&status, (char*)ws + T.status, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -1085,10 +1091,38 @@ int lingam_proposer_grad(const float* proposer, const float* features, int64_t r
          "hipMemcpyAsync(status)");
   LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
   if (status == 1)
-    return fail(LINGAM_E_INVALID, "a list lies outside [0, rows) or a target outside its list");
+    return fail(LINGAM_E_INVALID,
+                weights ? "a list lies outside [0, rows) or has invalid or all-zero weights"
+                        : "a list lies outside [0, rows) or a target outside its list");
   if (status == 2)
     return fail(LINGAM_E_INVALID, "non-finite proposer value or feature scale <= 0");
   return LINGAM_OK;
+}
+
+}  // namespace
+
+int lingam_proposer_grad(const float* proposer, const float* features, int64_t rows,
+                         const int64_t* offsets, const int64_t* targets, int32_t n_lists,
+                         float* grad, float* loss, float* scores, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!targets) {
+    g_err[0] = 0;
+    return fail(LINGAM_E_INVALID, "targets must be non-NULL");
+  }
+  return proposer_grad(proposer, features, rows, offsets, targets, nullptr, n_lists, grad, loss,
+                       scores, ws, ws_bytes, stream);
+}
+
+int lingam_proposer_grad_soft(const float* proposer, const float* features, int64_t rows,
+                              const int64_t* offsets, const float* weights, int32_t n_lists,
+                              float* grad, float* loss, float* scores, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!weights) {
+    g_err[0] = 0;
+    return fail(LINGAM_E_INVALID, "weights must be non-NULL");
+  }
+  return proposer_grad(proposer, features, rows, offsets, nullptr, weights, n_lists, grad, loss,
+                       scores, ws, ws_bytes, stream);
 }
 
 int lingam_proposer_adam(float* proposer, const float* grad, float* m1, float* m2, int32_t step,

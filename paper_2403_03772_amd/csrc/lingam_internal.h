@@ -40,6 +40,9 @@ constexpr int kMaxTopK = 256;
 // Most suspects (non-candidates whose lower bound does not exceed the best
 // candidate's k) a second candidate pass evaluates in one step.
 constexpr int kMaxSuspects = 1024;
+// Witnesses per variable: the most correlated other active variables, whose
+// pair measures join the candidates' in a learned step's lower bound on k.
+constexpr int kWit = 4;
 // offsets of the trainable parameters inside the flat FP32 block
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kHidden * kFeat;
@@ -107,6 +110,8 @@ struct Layout {
   size_t rc;     // double [K * d]  R(candidate, position)
   size_t kc;     // double [K]      exact k of every candidate
   size_t lb;     // double [d]      lower bound of k at excluded positions
+  size_t wit;    // int32  [d * kWit] witness positions of every position (-1: none)
+  size_t wr;     // double [d * kWit] min(0, R(l, w))^2 of each counted witness, else 0
   size_t steplog;  // int32 [d]     per step: 0 plain, 1 learned, 2 fallback, 3 audit
   // second candidate pass over the suspects
   int32_t cap_s;   // most suspects listed (kMaxSuspects or less, multiple of 8)
@@ -156,6 +161,8 @@ struct JobDev {
   double* rc;
   double* kc;
   double* lb;
+  int32_t* wit;
+  double* wr;
   int32_t* steplog;
   int32_t cap_s;
   int32_t* cand2;
@@ -215,6 +222,7 @@ enum Kind : int {
   kKRowkC,      // k_cand_k rows: K / 4
   kKColC,       // k_cand_k columns: ceil(m / 64)
   kKLsel,       // k_lselect: 1
+  kKWit,        // k_pair_wit: m
   kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c (after the learned decision)
   kKCombS,      // k_combine_susp: ceil(nct2 / 4)
   kKRowkS,      // k_susp_rowk: ceil(nsus / 4)
@@ -352,6 +360,7 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
     case kKRowkC: return s.learned ? cdiv(s.k, 4) : 0;
     case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
+    case kKWit: return s.learned ? s.m : 0;
     case kKPairS: return s.nct2 * 2 * s.nsplit_c;
     case kKCombS: return cdiv(s.nct2, 4);
     case kKRowkS: return cdiv(s.nsus, 4);
@@ -423,6 +432,9 @@ hipError_t launch_learned_front(const JobDev* jobs, int njobs, int t, SchedDev s
                                 const int32_t* grid, hipStream_t st);
 hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid,
                             hipStream_t st);
+// Witness pairs of every non-candidate (after the top-K, before the decision).
+hipError_t launch_pair_wit(const JobDev* jobs, int njobs, int t, SchedDev sc, int grid,
+                           hipStream_t st);
 hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                const int32_t* grid, hipStream_t st);
 // The second (suspect) pass: its schedule, its pair kernel (a bounded grid that
@@ -445,9 +457,10 @@ TrainLayout make_train_layout(int64_t rows, int32_t n_lists);
 // Scores of `rows` feature rows; ws holds a PropDev.
 hipError_t launch_scores(const float* prop, const float* feat, int64_t rows, float* score,
                          char* ws, hipStream_t st);
+// targets (hard) or weights (soft target distributions; targets then unused).
 hipError_t launch_grad(const TrainLayout& T, const float* prop, const float* feat,
-                       const int64_t* offsets, const int64_t* targets, float* grad,
-                       float* loss, float* score_out, char* ws, hipStream_t st);
+                       const int64_t* offsets, const int64_t* targets, const float* weights,
+                       float* grad, float* loss, float* score_out, char* ws, hipStream_t st);
 hipError_t launch_adam(float* prop, const float* grad, float* m1, float* m2, float lr,
                        float beta1, float beta2, float eps, float c1, float c2, hipStream_t st);
 

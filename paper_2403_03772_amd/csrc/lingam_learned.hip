@@ -137,6 +137,14 @@ __global__ __launch_bounds__(256) void k_features(const JobDev* __restrict__ job
   const double* rr = J.rho + (int64_t)si * J.d;
   double mx = 0.0, s1 = 0.0, s2 = 0.0, sw = 0.0;
   int c5 = 0, rk = 0;
+  // this lane's kWit largest |rho| (ties to the smaller position), descending
+  double ta[kWit];
+  int tq[kWit];
+#pragma unroll
+  for (int w = 0; w < kWit; ++w) {
+    ta[w] = -1.0;
+    tq[w] = -1;
+  }
   for (int q = lane; q < m; q += 64) {
     const int sq = J.act[q];
     const double Hq = J.hm[sq];
@@ -148,6 +156,47 @@ __global__ __launch_bounds__(256) void k_features(const JobDev* __restrict__ job
     s2 += r2;
     sw += r2 * Hq;
     c5 += a > 0.5 ? 1 : 0;
+    // q grows along the lane, so an equal |rho| never displaces an earlier q
+    double ca = a;
+    int cq = q;
+#pragma unroll
+    for (int w = 0; w < kWit; ++w) {
+      if (ca > ta[w]) {
+        const double xa = ta[w];
+        const int xq = tq[w];
+        ta[w] = ca;
+        tq[w] = cq;
+        ca = xa;
+        cq = xq;
+      }
+    }
+  }
+  if (J.wit) {
+    // kWit rounds of a wave-wide arg-max over the lanes' list heads
+    int head = 0;
+    for (int w = 0; w < kWit; ++w) {
+      double ba = -1.0;
+      int bq = -1;
+#pragma unroll
+      for (int h = 0; h < kWit; ++h)
+        if (h == head) {
+          ba = ta[h];
+          bq = tq[h];
+        }
+      double va = ba;
+      int vq = bq;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double oa = __shfl_xor(va, off);
+        const int oq = __shfl_xor(vq, off);
+        if (oa > va || (oa == va && oq >= 0 && (vq < 0 || oq < vq))) {
+          va = oa;
+          vq = oq;
+        }
+      }
+      if (vq >= 0 && vq == bq && head < kWit) ++head;  // the owner pops its head
+      if (lane == 0) J.wit[(int64_t)p * kWit + w] = vq;
+    }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -504,6 +553,146 @@ __global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jo
   pair_tiles<kModeCand, false>(jobs, njobs, js, pre, G);
 }
 
+// Witness pairs: one workgroup per non-candidate position l and its kWit
+// witnesses w (the most correlated other active variables, from
+// k_features).  For each w that is not a candidate the workgroup evaluates
+// both residual directions of (l, w) over all samples with the hot loop's
+// arithmetic (the four waves take interleaved 64-sample blocks, the next
+// block prefetched), reduces in FP64 and stores wr[l][q] =
+// min(0, R(l, w))^2, the share of k_l in that column; skipped slots (and
+// candidate rows l) store 0.
+__global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ jobs, int njobs,
+                                                  const JobStep* __restrict__ js,
+                                                  const int32_t* __restrict__ pre, int t) {
+  __shared__ double red[4][4 * kWit];
+  int jb, l;
+  if (!locate(pre, njobs, blockIdx.x, jb, l)) return;
+  const JobDev& J = jobs[jb];
+  const int m = js[jb].m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (l >= m) return;  // workgroup-uniform
+  double* out = J.wr + (int64_t)l * kWit;
+  const bool l_cand = J.cmark[l] == t + 1;
+  int wq[kWit];
+  bool on[kWit];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < kWit; ++q) {
+    const int w = J.wit[(int64_t)l * kWit + q];
+    on[q] = !l_cand && w >= 0 && w < m && w != l && J.cmark[w] != t + 1;
+    wq[q] = on[q] ? w : l;
+    any |= on[q];
+  }
+  if (!any) {
+    if (threadIdx.x < kWit) out[threadIdx.x] = 0.0;
+    return;
+  }
+  const int64_t ldz = J.ldz;
+  const int sl = J.act[l];
+  const float* zl = J.z + (int64_t)sl * ldz;
+  const float* zw[kWit];
+  float kr[kWit], kh[kWit], kl[kWit];
+#pragma unroll
+  for (int q = 0; q < kWit; ++q) {
+    const int sw = J.act[wq[q]];
+    zw[q] = J.z + (int64_t)sw * ldz;
+    double r = on[q] ? J.rho[(int64_t)sl * J.d + sw] : 0.0;
+    const double lim = 1.0 - kCollinear;
+    r = r > lim ? lim : (r < -lim ? -lim : r);
+    const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
+    kr[q] = (float)r;
+    kh[q] = (float)c1;
+    kl[q] = (float)(c1 - (double)kh[q]);
+  }
+  // dir 0: residual of l on w; dir 1: residual of w on l
+  float P0[kWit], A0[kWit], B0[kWit], P1[kWit], A1[kWit], B1[kWit];
+#pragma unroll
+  for (int q = 0; q < kWit; ++q) {
+    P0[q] = P1[q] = 1.f;
+    A0[q] = A1[q] = -kS1Start;
+    B0[q] = B1[q] = 0.f;
+  }
+  const int nk = J.n_pad / 64;  // 64-sample blocks; this wave takes k = wave, wave + 4, ...
+  int k = wave;
+  float x = 0.f, y[kWit];
+#pragma unroll
+  for (int q = 0; q < kWit; ++q) y[q] = 0.f;
+  if (k < nk) {
+    x = zl[k * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < kWit; ++q) y[q] = zw[q][k * 64 + lane];
+  }
+  int kb = 0;
+  for (; k < nk; k += 4) {
+    const bool more = k + 4 < nk;
+    const int s1 = (more ? k + 4 : k) * 64 + lane;  // the last block re-reads itself
+    const float nx = zl[s1];
+    float ny[kWit];
+#pragma unroll
+    for (int q = 0; q < kWit; ++q) ny[q] = zw[q][s1];
+#pragma unroll
+    for (int q = 0; q < kWit; ++q) {
+      eval_dir(x, y[q], kr[q], kh[q], kl[q], P0[q], A0[q], B0[q]);
+      eval_dir(y[q], x, kr[q], kh[q], kl[q], P1[q], A1[q], B1[q]);
+    }
+    if (++kb == kLogBlock || !more) {
+      const float off = 1.5f * (float)kb;  // exact
+#pragma unroll
+      for (int q = 0; q < kWit; ++q) {
+        A0[q] += __builtin_amdgcn_logf(P0[q]) - off;
+        A1[q] += __builtin_amdgcn_logf(P1[q]) - off;
+        P0[q] = P1[q] = 1.f;
+      }
+      kb = 0;
+    }
+    x = nx;
+#pragma unroll
+    for (int q = 0; q < kWit; ++q) y[q] = ny[q];
+  }
+  double v[4 * kWit];
+#pragma unroll
+  for (int q = 0; q < kWit; ++q) {
+    v[4 * q] = (double)A0[q];
+    v[4 * q + 1] = (double)B0[q];
+    v[4 * q + 2] = (double)A1[q];
+    v[4 * q + 3] = (double)B1[q];
+  }
+#pragma unroll
+  for (int i = 0; i < 4 * kWit; ++i) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4 * kWit; ++i) red[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x >= kWit) return;
+  const int q = threadIdx.x;
+  double res = 0.0;
+#pragma unroll
+  for (int h = 0; h < kWit; ++h) {
+    if (h != q || !on[h]) continue;
+    double sm[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      sm[c] = ((red[0][4 * h + c] + red[1][4 * h + c]) + red[2][4 * h + c]) + red[3][4 * h + c];
+    const int sw = J.act[wq[h]];
+    double r = J.rho[(int64_t)sl * J.d + sw];
+    const double lim = 1.0 - kCollinear;
+    r = r > lim ? lim : (r < -lim ? -lim : r);
+    const double al = 1.0 / sqrt(1.0 - r * r);
+    // every lane of the four waves started its log cosh sum at -kS1Start
+    const double bias = 256.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+    const double inv_n = 1.0 / (double)J.n;
+    const double h_lw = entropy_from_moments(kLn2 * (sm[0] + bias) * inv_n, al * sm[1] * inv_n);
+    const double h_wl = entropy_from_moments(kLn2 * (sm[2] + bias) * inv_n, al * sm[3] * inv_n);
+    const double R = (J.hm[sw] + h_lw) - (J.hm[sl] + h_wl);
+    res = R < 0.0 ? R * R : 0.0;
+  }
+  out[q] = res;
+}
+
 // R(c, j) for candidate c against every active position j (0 for j = c),
 // stored rc[c * d + j].  Same arithmetic as the all-pairs combine.
 __global__ __launch_bounds__(256) void k_combine_cand(const JobDev* __restrict__ jobs, int njobs,
@@ -592,9 +781,14 @@ __global__ __launch_bounds__(256) void k_cand_k(const JobDev* __restrict__ jobs,
     }
   part[wave][lane] = s;
   __syncthreads();
-  if (wave == 0 && l < m)
-    J.lb[l] = J.cmark[l] == t + 1 ? INFINITY
-                                  : ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (wave == 0 && l < m) {
+    double w = 0.0;  // the witness columns (0 where skipped)
+#pragma unroll
+    for (int q = 0; q < kWit; ++q) w += J.wr[(int64_t)l * kWit + q];
+    J.lb[l] = J.cmark[l] == t + 1
+                  ? INFINITY
+                  : (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) + w;
+  }
 }
 
 // Best of a list of measured rows (-k, ties to the smaller original id),
@@ -876,18 +1070,39 @@ __global__ __launch_bounds__(256) void k_train_fwd(const PropDev* __restrict__ W
 // loss_L = logsumexp(s_L) - s_target, ds = (softmax - onehot) / n_lists.
 // A list outside [0, rows] or a target outside its list sets *status = 1 and
 // contributes nothing.
+// With `weights` (soft targets) the target distribution of list L is
+// q = weights / sum(weights) over its rows and `targets` is not read; the
+// loss is sum_r q_r (logsumexp(s) - s_r) and ds = (softmax(s) - q) / n_lists.
+// Negative or non-finite weights, or a list whose weights sum to 0, set the
+// status like a malformed list.
 __global__ __launch_bounds__(256) void k_list_ce(const float* __restrict__ score, int64_t rows,
                                                  const int64_t* __restrict__ offsets,
                                                  const int64_t* __restrict__ targets,
+                                                 const float* __restrict__ weights,
                                                  int n_lists, float* __restrict__ ds,
                                                  double* __restrict__ loss_part,
                                                  int32_t* __restrict__ status) {
   __shared__ double sh[256];
+  __shared__ int s_bad;
   const int L = blockIdx.x;
   const int64_t a = offsets[L], b = offsets[L + 1];
-  const int64_t tg = targets[L];
   const int tid = threadIdx.x;
-  if (!(0 <= a && a <= b && b <= rows && a <= tg && tg < b)) {
+  const int64_t tg = weights ? a : targets[L];
+  bool bad = !(0 <= a && a <= b && b <= rows && a <= tg && tg < b);
+  double wsum = 0.0;
+  if (weights && !bad) {
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    double loc = 0.0;
+    for (int64_t r = a + tid; r < b; r += 256) {
+      const float w = weights[r];
+      if (!(w >= 0.f) || !isfinite(w)) s_bad = 1;
+      loc += (double)w;
+    }
+    wsum = block_sum_256(loc, sh);  // synchronizes: s_bad is final
+    bad = s_bad != 0 || !(wsum > 0.0);
+  }
+  if (bad) {
     if (tid == 0) {
       *status = 1;
       loss_part[L] = 0.0;
@@ -908,11 +1123,24 @@ __global__ __launch_bounds__(256) void k_list_ce(const float* __restrict__ score
   for (int64_t r = a + tid; r < b; r += 256) se += exp((double)score[r] - mx);
   const double tot = block_sum_256(se, sh);
   const double inv = 1.0 / (double)n_lists;
+  const double lse = mx + log(tot);
+  if (weights) {
+    double qs = 0.0;  // sum_r q_r s_r
+    for (int64_t r = a + tid; r < b; r += 256) {
+      const double q = (double)weights[r] / wsum;
+      const double p = exp((double)score[r] - mx) / tot;
+      ds[r] = (float)((p - q) * inv);
+      qs += q * (double)score[r];
+    }
+    qs = block_sum_256(qs, sh);
+    if (tid == 0) loss_part[L] = lse - qs;
+    return;
+  }
   for (int64_t r = a + tid; r < b; r += 256) {
     const double p = exp((double)score[r] - mx) / tot;
     ds[r] = (float)((p - (r == tg ? 1.0 : 0.0)) * inv);
   }
-  if (tid == 0) loss_part[L] = (mx + log(tot)) - (double)score[tg];
+  if (tid == 0) loss_part[L] = lse - (double)score[tg];
 }
 
 __global__ void k_zero_f32(float* __restrict__ p, int64_t n, int32_t* __restrict__ status) {
@@ -1140,6 +1368,14 @@ hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid
   return hipGetLastError();
 }
 
+hipError_t launch_pair_wit(const JobDev* jobs, int njobs, int t, SchedDev sc, int grid,
+                           hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_wit, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKWit), t);
+  return hipGetLastError();
+}
+
 hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                const int32_t* grid, hipStream_t st) {
   const JobStep* js = sc.js;
@@ -1217,8 +1453,8 @@ hipError_t launch_scores(const float* prop, const float* feat, int64_t rows, flo
 }
 
 hipError_t launch_grad(const TrainLayout& T, const float* prop, const float* feat,
-                       const int64_t* offsets, const int64_t* targets, float* grad,
-                       float* loss, float* score_out, char* ws, hipStream_t st) {
+                       const int64_t* offsets, const int64_t* targets, const float* weights,
+                       float* grad, float* loss, float* score_out, char* ws, hipStream_t st) {
   PropDev* W = reinterpret_cast<PropDev*>(ws + T.prop);
   float* score = reinterpret_cast<float*>(ws + T.score);
   float* ds = reinterpret_cast<float*>(ws + T.ds);
@@ -1235,7 +1471,8 @@ hipError_t launch_grad(const TrainLayout& T, const float* prop, const float* fea
   hipLaunchKernelGGL(k_train_fwd, dim3((unsigned)ntile), dim3(256), 0, st, (const PropDev*)W,
                      feat, T.rows, score, H1, H2);
   hipLaunchKernelGGL(k_list_ce, dim3((unsigned)T.n_lists), dim3(256), 0, st,
-                     (const float*)score, T.rows, offsets, targets, T.n_lists, ds, lp, status);
+                     (const float*)score, T.rows, offsets, targets, weights, T.n_lists, ds, lp,
+                     status);
   hipLaunchKernelGGL(k_train_bwd, dim3((unsigned)T.nparts), dim3(256), 0, st, (const PropDev*)W,
                      feat, T.rows, (const float*)ds, (const uint16_t*)H1, (const float*)H2,
                      part);

@@ -138,7 +138,7 @@ class Learned:
     of PROPOSER_SIZE values (feature mean, feature scale, network weights)."""
     proposer: object
     topk: int = 64
-    audit_every: int = 32
+    audit_every: int = 0
     margin: float = math.inf
     min_m: int | None = None
     max_suspects: int = 1024
@@ -183,6 +183,8 @@ def load():
         lib.lingam_proposer_grad_workspace_size.restype = sz
         lib.lingam_proposer_grad.argtypes = [P, P, i64, P, P, i32, P, P, P, P, sz, P]
         lib.lingam_proposer_grad.restype = ctypes.c_int
+        lib.lingam_proposer_grad_soft.argtypes = [P, P, i64, P, P, i32, P, P, P, P, sz, P]
+        lib.lingam_proposer_grad_soft.restype = ctypes.c_int
         lib.lingam_proposer_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
         lib.lingam_proposer_adam.restype = ctypes.c_int
         lib.lingam_adjacency_workspace_size.argtypes = [i64, i64]
@@ -622,11 +624,13 @@ def proposer_scores(proposer, features):
     return scores
 
 
-def proposer_grad(proposer, features, offsets, targets, *, workspace=None):
+def proposer_grad(proposer, features, offsets, targets=None, *, weights=None, workspace=None):
     """Listwise softmax cross-entropy and its gradient.
 
-    ``offsets`` (int64, n_lists + 1) delimit the lists of feature rows,
-    ``targets`` (int64, n_lists) name each list's target row.  Returns
+    ``offsets`` (int64, n_lists + 1) delimit the lists of feature rows;
+    ``targets`` (int64, n_lists) name each list's target row, or ``weights``
+    (float32 per row, >= 0) give each list a soft target distribution (its
+    rows' weights over their sum; ``lingam_proposer_grad_soft``).  Returns
     ``(loss, grad, scores, workspace)`` with ``grad`` of N_PARAMS values.
     """
     import torch
@@ -634,13 +638,22 @@ def proposer_grad(proposer, features, offsets, targets, *, workspace=None):
     lib = load()
     _check_proposer(torch, proposer)
     _check_features(torch, features)
+    if (targets is None) == (weights is None):
+        raise ValueError("give exactly one of targets and weights")
     dev = features.device
     rows = features.shape[0]
     off = torch.as_tensor(offsets, dtype=torch.int64).to(dev).contiguous()
-    tg = torch.as_tensor(targets, dtype=torch.int64).to(dev).contiguous()
-    nl = tg.numel()
-    if off.numel() != nl + 1:
-        raise ValueError("offsets must have n_lists + 1 entries")
+    nl = off.numel() - 1
+    if targets is not None:
+        tg = torch.as_tensor(targets, dtype=torch.int64).to(dev).contiguous()
+        if tg.numel() != nl:
+            raise ValueError("offsets must have n_lists + 1 entries")
+    else:
+        wt = torch.as_tensor(weights, dtype=torch.float32).to(dev).contiguous()
+        if wt.numel() != rows:
+            raise ValueError("weights must have one value per feature row")
+    if nl < 1:
+        raise LingamError(E_INVALID, "empty training batch")
     need = int(lib.lingam_proposer_grad_workspace_size(rows, nl))
     if need == 0:
         raise LingamError(E_INVALID, "empty training batch")
@@ -649,9 +662,17 @@ def proposer_grad(proposer, features, offsets, targets, *, workspace=None):
     grad = torch.empty(N_PARAMS, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     scores = torch.empty(rows, dtype=torch.float32, device=dev)
-    _check(lib.lingam_proposer_grad(_ptr(proposer), _ptr(features), rows, _ptr(off), _ptr(tg),
-                                    nl, _ptr(grad), _ptr(loss), _ptr(scores), _ptr(workspace),
-                                    workspace.numel(), _stream_ptr(torch, dev)))
+    if targets is not None:
+        code = lib.lingam_proposer_grad(_ptr(proposer), _ptr(features), rows, _ptr(off),
+                                        _ptr(tg), nl, _ptr(grad), _ptr(loss), _ptr(scores),
+                                        _ptr(workspace), workspace.numel(),
+                                        _stream_ptr(torch, dev))
+    else:
+        code = lib.lingam_proposer_grad_soft(_ptr(proposer), _ptr(features), rows, _ptr(off),
+                                             _ptr(wt), nl, _ptr(grad), _ptr(loss), _ptr(scores),
+                                             _ptr(workspace), workspace.numel(),
+                                             _stream_ptr(torch, dev))
+    _check(code)
     return loss, grad, scores, workspace
 
 

@@ -196,7 +196,7 @@ def test_batch_argument_errors():
 def test_learned_options_are_validated():
     lib = pkg.load()
     o = _opts()
-    assert o.topk == 64 and o.audit_every == 32 and o.learned_min_m == 128
+    assert o.topk == 64 and o.audit_every == 0 and o.learned_min_m == 128
     o.proposer = 1
     assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) > \
         lib.lingam_workspace_size(1000, 300, None)
@@ -229,6 +229,12 @@ def test_proposer_argument_errors():
                                     None) == L.E_INVALID
     assert lib.lingam_proposer_grad(P, P, 100, P, P, 3, P, None, None, P, 8,
                                     None) == L.E_WORKSPACE
+    assert lib.lingam_proposer_grad_soft(P, P, 100, P, None, 3, P, None, None, P, 1 << 30,
+                                         None) == L.E_INVALID
+    assert lib.lingam_proposer_grad(P, P, 100, P, None, 3, P, None, None, P, 1 << 30,
+                                    None) == L.E_INVALID
+    assert lib.lingam_proposer_grad_soft(P, P, 100, P, P, 3, P, None, None, P, 8,
+                                         None) == L.E_WORKSPACE
     assert lib.lingam_proposer_adam(P, P, P, P, 0, 1e-3, 0.9, 0.999, 1e-8, None) == L.E_INVALID
     assert lib.lingam_proposer_adam(P, P, P, P, 1, 1e-3, 1.0, 0.999, 1e-8, None) == L.E_INVALID
     assert lib.lingam_proposer_adam(P, P, None, P, 1, 1e-3, 0.9, 0.999, 1e-8,

@@ -89,6 +89,57 @@ def test_grad_matches_oracle(lib):
         assert err <= 1e-2, name
 
 
+def test_grad_soft_matches_oracle(lib):
+    """Soft target distributions: loss and gradient against the oracle's
+    soft cross-entropy at the BF16-rounded weights; one-hot weights give the
+    hard-target call's loss and gradient."""
+    rng = np.random.default_rng(7)
+    prop = _proposer(4)
+    sizes = [int(x) for x in rng.integers(2, 200, 30)]
+    offs, tg = _lists(rng, sizes)
+    rows = int(offs[-1])
+    F = rng.normal(size=(rows, 16)).astype(np.float32)
+    w = (rng.uniform(size=rows) ** 4).astype(np.float32)
+    print(f"grad soft rows={rows} lists={len(sizes)}", flush=True)
+    loss, grad, _, _ = lib.proposer_grad(_t(prop), _t(F), _t(offs, np.int64), weights=_t(w))
+    g = grad.cpu().numpy().astype(np.float64)
+    flat = prop[32:].copy()
+    p = OP.unpack(flat)
+    for k in ("W1", "W2", "w3"):
+        p[k] = OP.bf16(p[k])
+    flat_b = OP.pack(p)
+    s, cache = OP.forward(flat_b, OP.bf16(OP.normalize(F, prop[:32])), emulate_bf16=True)
+    ref_loss, ds = OP.listwise_ce_soft(s.astype(np.float32).astype(np.float64), offs,
+                                       w.astype(np.float64))
+    ref = OP.backward(flat_b, cache, ds)
+    assert abs(float(loss.item()) - ref_loss) <= 1e-4 * max(1.0, abs(ref_loss))
+    o = 0
+    for name, shp in OP.SHAPES:
+        k = int(np.prod(shp))
+        a, b = g[o:o + k], ref[o:o + k]
+        o += k
+        if name == "b3":
+            assert abs(a[0]) <= 1e-6  # softmax minus a distribution sums to 0
+            continue
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        print(f"  {name}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-2, name
+    onehot = np.zeros(rows, dtype=np.float32)
+    onehot[tg] = 3.0
+    l1, g1, _, _ = lib.proposer_grad(_t(prop), _t(F), _t(offs, np.int64), weights=_t(onehot))
+    l0, g0, _, _ = lib.proposer_grad(_t(prop), _t(F), _t(offs, np.int64), _t(tg, np.int64))
+    assert abs(float(l1.item()) - float(l0.item())) <= 1e-6 * max(1.0, abs(float(l0.item())))
+    assert float((g1 - g0).abs().max()) <= 1e-6 * max(1e-3, float(g0.abs().max()))
+    bad = w.copy()
+    bad[offs[1]:offs[2]] = 0.0  # a list with no mass
+    with pytest.raises(lib.LingamError):
+        lib.proposer_grad(_t(prop), _t(F), _t(offs, np.int64), weights=_t(bad))
+    bad = w.copy()
+    bad[3] = -1.0
+    with pytest.raises(lib.LingamError):
+        lib.proposer_grad(_t(prop), _t(F), _t(offs, np.int64), weights=_t(bad))
+
+
 def test_adam_matches_oracle(lib):
     import torch
     rng = np.random.default_rng(4)
