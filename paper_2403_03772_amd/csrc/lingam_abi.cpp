@@ -260,7 +260,6 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
       J.kc = reinterpret_cast<double*>(b + L.kc);
       J.lb = reinterpret_cast<double*>(b + L.lb);
       J.wit = reinterpret_cast<int32_t*>(b + L.wit);
-      J.wr = reinterpret_cast<double*>(b + L.wr);
       J.steplog = h.step_log ? h.step_log : reinterpret_cast<int32_t*>(b + L.steplog);
       J.cap_s = std::min<int32_t>(L.cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars);
       J.cand2 = reinterpret_cast<int32_t*>(b + L.cand2);
@@ -367,8 +366,6 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
       if (pf) pf->cand_evals += T.cand_evals;
     }
-    if (T.g[lg::kKWit] > 0)
-      LG_TRY(lg::launch_pair_wit(table, P.njobs, t, sc, T.g[lg::kKWit], st), "witness pairs");
     // learned steps: the full-step kernels are gated on the device, so their
     // host grids are only bounds; bounded grids walk the items instead
     const bool gated = T.g[lg::kKLsel] > 0;

@@ -111,7 +111,6 @@ struct Layout {
   size_t kc;     // double [K]      exact k of every candidate
   size_t lb;     // double [d]      lower bound of k at excluded positions
   size_t wit;    // int32  [d * kWit] witness positions of every position (-1: none)
-  size_t wr;     // double [d * kWit] min(0, R(l, w))^2 of each counted witness, else 0
   size_t steplog;  // int32 [d]     per step: 0 plain, 1 learned, 2 fallback, 3 audit
   // second candidate pass over the suspects
   int32_t cap_s;   // most suspects listed (kMaxSuspects or less, multiple of 8)
@@ -162,7 +161,6 @@ struct JobDev {
   double* kc;
   double* lb;
   int32_t* wit;
-  double* wr;
   int32_t* steplog;
   int32_t cap_s;
   int32_t* cand2;
@@ -432,9 +430,6 @@ hipError_t launch_learned_front(const JobDev* jobs, int njobs, int t, SchedDev s
                                 const int32_t* grid, hipStream_t st);
 hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid,
                             hipStream_t st);
-// Witness pairs of every non-candidate (after the top-K, before the decision).
-hipError_t launch_pair_wit(const JobDev* jobs, int njobs, int t, SchedDev sc, int grid,
-                           hipStream_t st);
 hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                const int32_t* grid, hipStream_t st);
 // The second (suspect) pass: its schedule, its pair kernel (a bounded grid that

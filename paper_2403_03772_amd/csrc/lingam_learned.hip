@@ -20,11 +20,17 @@
 //   k_cand_k        exact k of every candidate, and for every other variable
 //                   l the lower bound sum_c max(0, R(c, l))^2 <= k_l its
 //                   candidate pairs give
+//   k_pair_wit      for the variables that bound leaves at or below the best
+//                   candidate's k: their pair measures against their most
+//                   correlated non-candidate variables (witnesses), added to
+//                   the bound
 //   k_lselect       best candidate; it is certified when every lower bound
-//                   exceeds its k, and accepted when certified or when its
-//                   score beats every non-candidate's by the margin; audit
-//                   steps and small margins hand the step to the full kernels
-//                   (gated by k_gate_schedule)
+//                   exceeds its k; otherwise the suspects (bound <= its k)
+//                   are listed for a second pass over their rows, or, when
+//                   too many, the best candidate is accepted if its score
+//                   beats every non-candidate's by the margin; audit steps
+//                   and the rest hand the step to the full kernels (gated by
+//                   k_gate_schedule)
 //
 // and the training kernels of the network (forward with saved activations,
 // listwise softmax cross-entropy, backward on MFMA, gradient reduction, Adam).
@@ -553,40 +559,45 @@ __global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jo
   pair_tiles<kModeCand, false>(jobs, njobs, js, pre, G);
 }
 
-// Witness pairs: one workgroup per non-candidate position l and its kWit
-// witnesses w (the most correlated other active variables, from
-// k_features).  For each w that is not a candidate the workgroup evaluates
-// both residual directions of (l, w) over all samples with the hot loop's
-// arithmetic (the four waves take interleaved 64-sample blocks, the next
-// block prefetched), reduces in FP64 and stores wr[l][q] =
-// min(0, R(l, w))^2, the share of k_l in that column; skipped slots (and
-// candidate rows l) store 0.
+// Witness pairs: one workgroup per non-candidate position l whose candidate
+// bound lb[l] (from k_cand_k) does not exceed the best candidate's k (the
+// others are bounded already).  For each of its kWit witnesses w (the most
+// correlated other active variables, from k_features) that is not a
+// candidate, the workgroup evaluates both residual directions of (l, w) over
+// all samples with the hot loop's arithmetic (the four waves take
+// interleaved 64-sample blocks, the next block prefetched), reduces in FP64,
+// and adds min(0, R(l, w))^2 (the share of k_l in that column) to lb[l].
 __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ jobs, int njobs,
                                                   const JobStep* __restrict__ js,
                                                   const int32_t* __restrict__ pre, int t) {
   __shared__ double red[4][4 * kWit];
+  __shared__ double s_kb[4];
   int jb, l;
   if (!locate(pre, njobs, blockIdx.x, jb, l)) return;
   const JobDev& J = jobs[jb];
-  const int m = js[jb].m;
+  const int m = js[jb].m, K = js[jb].k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (l >= m) return;  // workgroup-uniform
-  double* out = J.wr + (int64_t)l * kWit;
-  const bool l_cand = J.cmark[l] == t + 1;
+  if (l >= m || J.cmark[l] == t + 1) return;  // workgroup-uniform
+  // the best candidate's k
+  double kb0 = INFINITY;
+  for (int c = threadIdx.x; c < K; c += 256) kb0 = fmin(kb0, J.kc[c]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) kb0 = fmin(kb0, __shfl_xor(kb0, off));
+  if (lane == 0) s_kb[wave] = kb0;
+  __syncthreads();
+  const double kbest = fmin(fmin(s_kb[0], s_kb[1]), fmin(s_kb[2], s_kb[3]));
+  if (J.lb[l] > kbest) return;  // bounded by the candidates alone
   int wq[kWit];
   bool on[kWit];
   bool any = false;
 #pragma unroll
   for (int q = 0; q < kWit; ++q) {
     const int w = J.wit[(int64_t)l * kWit + q];
-    on[q] = !l_cand && w >= 0 && w < m && w != l && J.cmark[w] != t + 1;
+    on[q] = w >= 0 && w < m && w != l && J.cmark[w] != t + 1;
     wq[q] = on[q] ? w : l;
     any |= on[q];
   }
-  if (!any) {
-    if (threadIdx.x < kWit) out[threadIdx.x] = 0.0;
-    return;
-  }
+  if (!any) return;
   const int64_t ldz = J.ldz;
   const int sl = J.act[l];
   const float* zl = J.z + (int64_t)sl * ldz;
@@ -668,7 +679,7 @@ __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ job
   }
   __syncthreads();
   if (threadIdx.x >= kWit) return;
-  const int q = threadIdx.x;
+  const int q = threadIdx.x;  // lanes 0 .. kWit-1 of wave 0, one witness each
   double res = 0.0;
 #pragma unroll
   for (int h = 0; h < kWit; ++h) {
@@ -690,7 +701,11 @@ __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ job
     const double R = (J.hm[sw] + h_lw) - (J.hm[sl] + h_wl);
     res = R < 0.0 ? R * R : 0.0;
   }
-  out[q] = res;
+  // lanes 0 .. kWit-1 of wave 0 hold the terms: lane 0 adds them in order
+  double tot = res;
+#pragma unroll
+  for (int h = 1; h < kWit; ++h) tot += __shfl(res, h, 64);
+  if (q == 0) J.lb[l] += tot;
 }
 
 // R(c, j) for candidate c against every active position j (0 for j = c),
@@ -781,14 +796,9 @@ __global__ __launch_bounds__(256) void k_cand_k(const JobDev* __restrict__ jobs,
     }
   part[wave][lane] = s;
   __syncthreads();
-  if (wave == 0 && l < m) {
-    double w = 0.0;  // the witness columns (0 where skipped)
-#pragma unroll
-    for (int q = 0; q < kWit; ++q) w += J.wr[(int64_t)l * kWit + q];
-    J.lb[l] = J.cmark[l] == t + 1
-                  ? INFINITY
-                  : (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) + w;
-  }
+  if (wave == 0 && l < m)
+    J.lb[l] = J.cmark[l] == t + 1 ? INFINITY
+                                  : ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // Best of a list of measured rows (-k, ties to the smaller original id),
@@ -1368,14 +1378,6 @@ hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid
   return hipGetLastError();
 }
 
-hipError_t launch_pair_wit(const JobDev* jobs, int njobs, int t, SchedDev sc, int grid,
-                           hipStream_t st) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair_wit, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
-                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKWit), t);
-  return hipGetLastError();
-}
-
 hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                const int32_t* grid, hipStream_t st) {
   const JobStep* js = sc.js;
@@ -1385,6 +1387,9 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
   hipLaunchKernelGGL(k_cand_k, dim3((unsigned)(grid[kKRowkC] + grid[kKColC])), dim3(256), 0, st,
                      jobs, njobs, js, pre_kind(sc, njobs, kKRowkC), pre_kind(sc, njobs, kKColC),
                      t);
+  if (grid[kKWit] > 0)
+    hipLaunchKernelGGL(k_pair_wit, dim3((unsigned)grid[kKWit]), dim3(256), 0, st, jobs, njobs,
+                       js, pre_kind(sc, njobs, kKWit), t);
   hipLaunchKernelGGL(k_lselect, dim3((unsigned)grid[kKLsel]), dim3(256), 0, st, jobs, njobs, js,
                      pre_kind(sc, njobs, kKLsel), t);
   return hipGetLastError();
