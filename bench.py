@@ -395,7 +395,7 @@ def main() -> int:
         prop = tp.default_proposer()
         _, meta = tp.load_weights()
         lw = max(1, args.warmup)
-        K = 64 if args.workload == "gene" else 256
+        K = 64 if args.workload == "gene" else 128
         B = sem.B
         # exact form (the default): certified, suspects evaluated, or a full step
         exact = lg.Learned(prop, topk=K)

@@ -31,7 +31,7 @@
  * variables, the exact measure k_i is computed only for the `topk` best
  * scored, and the choice is made as follows.  The candidates' rows bound every
  * other variable's k from below (sum over candidates c of max(0, R(c, l))^2),
- * and so do its pair measures against its four most correlated non-candidate
+ * and so do its pair measures against its eight most correlated non-candidate
  * variables ("witnesses": sum of min(0, R(l, w))^2), each column counted
  * once; the "suspects" are the variables whose bound does not exceed the best
  * candidate's k.  (a) No suspect: the best candidate is the plain search's

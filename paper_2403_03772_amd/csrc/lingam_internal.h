@@ -42,7 +42,7 @@ constexpr int kMaxTopK = 256;
 constexpr int kMaxSuspects = 1024;
 // Witnesses per variable: the most correlated other active variables, whose
 // pair measures join the candidates' in a learned step's lower bound on k.
-constexpr int kWit = 4;
+constexpr int kWit = 8;
 // offsets of the trainable parameters inside the flat FP32 block
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kHidden * kFeat;
