@@ -564,14 +564,16 @@ __global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jo
 // others are bounded already).  For each of its kWit witnesses w (the most
 // correlated other active variables, from k_features) that is not a
 // candidate, the workgroup evaluates both residual directions of (l, w) over
-// all samples with the hot loop's arithmetic (the four waves take
+// all samples with the hot loop's arithmetic (the eight waves take
 // interleaved 64-sample blocks, the next block prefetched), reduces in FP64,
 // and adds min(0, R(l, w))^2 (the share of k_l in that column) to lb[l].
-__global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ jobs, int njobs,
+constexpr int kWitWaves = 8;  // waves per witness workgroup
+
+__global__ __launch_bounds__(64 * kWitWaves) void k_pair_wit(const JobDev* __restrict__ jobs, int njobs,
                                                   const JobStep* __restrict__ js,
                                                   const int32_t* __restrict__ pre, int t) {
-  __shared__ double red[4][4 * kWit];
-  __shared__ double s_kb[4];
+  __shared__ double red[kWitWaves][4 * kWit];
+  __shared__ double s_kb[kWitWaves];
   int jb, l;
   if (!locate(pre, njobs, blockIdx.x, jb, l)) return;
   const JobDev& J = jobs[jb];
@@ -580,12 +582,14 @@ __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ job
   if (l >= m || J.cmark[l] == t + 1) return;  // workgroup-uniform
   // the best candidate's k
   double kb0 = INFINITY;
-  for (int c = threadIdx.x; c < K; c += 256) kb0 = fmin(kb0, J.kc[c]);
+  for (int c = threadIdx.x; c < K; c += 64 * kWitWaves) kb0 = fmin(kb0, J.kc[c]);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) kb0 = fmin(kb0, __shfl_xor(kb0, off));
   if (lane == 0) s_kb[wave] = kb0;
   __syncthreads();
-  const double kbest = fmin(fmin(s_kb[0], s_kb[1]), fmin(s_kb[2], s_kb[3]));
+  double kbest = s_kb[0];
+#pragma unroll
+  for (int w = 1; w < kWitWaves; ++w) kbest = fmin(kbest, s_kb[w]);
   if (J.lb[l] > kbest) return;  // bounded by the candidates alone
   int wq[kWit];
   bool on[kWit];
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ job
     A0[q] = A1[q] = -kS1Start;
     B0[q] = B1[q] = 0.f;
   }
-  const int nk = J.n_pad / 64;  // 64-sample blocks; this wave takes k = wave, wave + 4, ...
+  const int nk = J.n_pad / 64;  // 64-sample blocks; this wave takes k = wave, wave + kWitWaves, ...
   int k = wave;
   float x = 0.f, y[kWit];
 #pragma unroll
@@ -634,9 +638,9 @@ __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ job
     for (int q = 0; q < kWit; ++q) y[q] = zw[q][k * 64 + lane];
   }
   int kb = 0;
-  for (; k < nk; k += 4) {
-    const bool more = k + 4 < nk;
-    const int s1 = (more ? k + 4 : k) * 64 + lane;  // the last block re-reads itself
+  for (; k < nk; k += kWitWaves) {
+    const bool more = k + kWitWaves < nk;
+    const int s1 = (more ? k + kWitWaves : k) * 64 + lane;  // the last block re-reads itself
     const float nx = zl[s1];
     float ny[kWit];
 #pragma unroll
@@ -686,15 +690,18 @@ __global__ __launch_bounds__(256) void k_pair_wit(const JobDev* __restrict__ job
     if (h != q || !on[h]) continue;
     double sm[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      sm[c] = ((red[0][4 * h + c] + red[1][4 * h + c]) + red[2][4 * h + c]) + red[3][4 * h + c];
+    for (int c = 0; c < 4; ++c) {
+      sm[c] = red[0][4 * h + c];
+#pragma unroll
+      for (int w = 1; w < kWitWaves; ++w) sm[c] += red[w][4 * h + c];
+    }
     const int sw = J.act[wq[h]];
     double r = J.rho[(int64_t)sl * J.d + sw];
     const double lim = 1.0 - kCollinear;
     r = r > lim ? lim : (r < -lim ? -lim : r);
     const double al = 1.0 / sqrt(1.0 - r * r);
-    // every lane of the four waves started its log cosh sum at -kS1Start
-    const double bias = 256.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+    // every lane of the workgroup started its log cosh sum at -kS1Start
+    const double bias = 64.0 * kWitWaves * (double)kS1Start + 0.5 * (double)J.n_pad;
     const double inv_n = 1.0 / (double)J.n;
     const double h_lw = entropy_from_moments(kLn2 * (sm[0] + bias) * inv_n, al * sm[1] * inv_n);
     const double h_wl = entropy_from_moments(kLn2 * (sm[2] + bias) * inv_n, al * sm[3] * inv_n);
@@ -1388,7 +1395,8 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
                      jobs, njobs, js, pre_kind(sc, njobs, kKRowkC), pre_kind(sc, njobs, kKColC),
                      t);
   if (grid[kKWit] > 0)
-    hipLaunchKernelGGL(k_pair_wit, dim3((unsigned)grid[kKWit]), dim3(256), 0, st, jobs, njobs,
+    hipLaunchKernelGGL(k_pair_wit, dim3((unsigned)grid[kKWit]), dim3(64 * kWitWaves), 0, st,
+                       jobs, njobs,
                        js, pre_kind(sc, njobs, kKWit), t);
   hipLaunchKernelGGL(k_lselect, dim3((unsigned)grid[kKLsel]), dim3(256), 0, st, jobs, njobs, js,
                      pre_kind(sc, njobs, kKLsel), t);
