@@ -311,6 +311,9 @@ def main() -> int:
                     help="skip the batched bootstrap workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal form")
+    ap.add_argument("--no-aux", action="store_true",
+                    help="skip the adjacency, VarLiNGAM and bootstrap records (their "
+                         "orderings would mix into a profile of the plain one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device-to-device with a plain copy "
                          "kernel (reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -419,15 +422,16 @@ def main() -> int:
             rec["learned"]["untrained"] = run_learned(lg, X, n, d, 1, 0,
                                                       lg.Learned(raw, topk=K), pl["order"],
                                                       ms_per_step, B)
-    if args.workload == "gene":
+    if args.workload == "gene" and not args.no_aux:
         progress("adjacency along the plain order")
         rec["adjacency"] = run_adjacency(lg, X, n, d, torch.as_tensor(pl["order"]).cuda())
         progress("varlingam (stock shape)")
         rec["varlingam"] = run_varlingam(lg)
     if not args.no_batch and args.workload == "gene":
         rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed)
-        progress("bootstrap statistics")
-        rec["bootstrap"] = bench_bootstrap(args.seed)
+        if not args.no_aux:
+            progress("bootstrap statistics")
+            rec["bootstrap"] = bench_bootstrap(args.seed)
     if args.copy_calibration:
         src = torch.ones(256 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
