@@ -311,6 +311,8 @@ def main() -> int:
                     help="skip the batched bootstrap workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal form")
+    ap.add_argument("--exact-only", action="store_true",
+                    help="of the learned forms, run only the exact one (for its profile)")
     ap.add_argument("--no-aux", action="store_true",
                     help="skip the adjacency, VarLiNGAM and bootstrap records (their "
                          "orderings would mix into a profile of the plain one)")
@@ -410,10 +412,11 @@ def main() -> int:
                                        "lists", "holdout", "holdout_big")}
         # fast form: no second pass, the best candidate is always taken
         fast = lg.Learned(prop, topk=K, margin=-np.inf, max_suspects=0, audit_every=32)
-        progress("learned (fast)")
-        rec["learned"]["fast"] = run_learned(lg, X, n, d, args.steps, lw, fast, pl["order"],
-                                             ms_per_step, B)
-        if args.workload == "gene":
+        if not args.exact_only:
+            progress("learned (fast)")
+            rec["learned"]["fast"] = run_learned(lg, X, n, d, args.steps, lw, fast,
+                                                 pl["order"], ms_per_step, B)
+        if args.workload == "gene" and not args.exact_only:
             # ablation: the exact form with an untrained (random) network (not on
             # the large workload, where it runs about as long as the plain form)
             raw = prop.clone()

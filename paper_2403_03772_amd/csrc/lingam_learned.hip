@@ -151,29 +151,48 @@ __global__ __launch_bounds__(256) void k_features(const JobDev* __restrict__ job
     ta[w] = -1.0;
     tq[w] = -1;
   }
-  for (int q = lane; q < m; q += 64) {
-    const int sq = J.act[q];
-    const double Hq = J.hm[sq];
-    rk += (Hq < Hi || (Hq == Hi && sq < si)) ? 1 : 0;  // never true for q == p
-    if (q == p) continue;
-    const double r = rr[sq], a = fabs(r), r2 = r * r;
-    mx = fmax(mx, a);
-    s1 += a;
-    s2 += r2;
-    sw += r2 * Hq;
-    c5 += a > 0.5 ? 1 : 0;
-    // q grows along the lane, so an equal |rho| never displaces an earlier q
-    double ca = a;
-    int cq = q;
+  // four positions per lane per pass: their gathers are issued together
+  constexpr int kU = 4;
+  for (int q0 = lane; q0 < m; q0 += 64 * kU) {
+    int sqv[kU];
+    double Hv[kU], rv[kU];
 #pragma unroll
-    for (int w = 0; w < kWit; ++w) {
-      if (ca > ta[w]) {
-        const double xa = ta[w];
-        const int xq = tq[w];
-        ta[w] = ca;
-        tq[w] = cq;
-        ca = xa;
-        cq = xq;
+    for (int u = 0; u < kU; ++u) {
+      const int q = q0 + 64 * u;
+      sqv[u] = q < m ? J.act[q] : si;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      Hv[u] = J.hm[sqv[u]];
+      rv[u] = rr[sqv[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = q0 + 64 * u;
+      if (q >= m) break;
+      const int sq = sqv[u];
+      const double Hq = Hv[u];
+      rk += (Hq < Hi || (Hq == Hi && sq < si)) ? 1 : 0;  // never true for q == p
+      if (q == p) continue;
+      const double r = rv[u], a = fabs(r), r2 = r * r;
+      mx = fmax(mx, a);
+      s1 += a;
+      s2 += r2;
+      sw += r2 * Hq;
+      c5 += a > 0.5 ? 1 : 0;
+      // q grows along the lane, so an equal |rho| never displaces an earlier q
+      double ca = a;
+      int cq = q;
+#pragma unroll
+      for (int w = 0; w < kWit; ++w) {
+        if (ca > ta[w]) {
+          const double xa = ta[w];
+          const int xq = tq[w];
+          ta[w] = ca;
+          tq[w] = cq;
+          ca = xa;
+          cq = xq;
+        }
       }
     }
   }
