@@ -588,9 +588,11 @@ __global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jo
 // and adds min(0, R(l, w))^2 (the share of k_l in that column) to lb[l].
 constexpr int kWitWaves = 8;  // waves per witness workgroup
 
-__global__ __launch_bounds__(64 * kWitWaves) void k_pair_wit(const JobDev* __restrict__ jobs, int njobs,
-                                                  const JobStep* __restrict__ js,
-                                                  const int32_t* __restrict__ pre, int t) {
+__global__ __launch_bounds__(64 * kWitWaves) void k_pair_wit(const JobDev* __restrict__ jobs,
+                                                              int njobs,
+                                                              const JobStep* __restrict__ js,
+                                                              const int32_t* __restrict__ pre,
+                                                              int t) {
   __shared__ double red[kWitWaves][4 * kWit];
   __shared__ double s_kb[kWitWaves];
   int jb, l;
