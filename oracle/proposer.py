@@ -14,12 +14,13 @@ matrix of the C oracle:
   moments, higher moments, correlation statistics, rank and progress;
 * a 16 -> 128 -> 128 -> 1 ReLU perceptron scoring every active variable
   (forward, backward, listwise softmax cross-entropy against the plain
-  search's choice, Adam);
+  search's choice or against a soft target distribution, Adam);
 * one learned step: the K best-scored variables are the candidates, their
   exact k_i = sum_j min(0, R(i, j))^2 is taken from the measure.  For an
   excluded variable l the candidates' rows already give R(l, c) = -R(c, l),
-  so k_l >= LB_l = sum_{c in C} max(0, R(c, l))^2.  The suspects are the
-  excluded variables with LB_l <= k_best.  No suspect: the best candidate is
+  so k_l >= LB_l = sum_{c in C} max(0, R(c, l))^2, and its witnesses (its
+  most correlated excluded variables w) add min(0, R(l, w))^2 each.  The
+  suspects are the excluded variables with LB_l <= k_best.  No suspect: the best candidate is
   the plain choice (certified).  At most cap(m) = min(1024, m/2 - K) (rounded
   down to a multiple of 8) suspects: their exact k is evaluated and the best
   of candidates and suspects is the plain choice.  More: the best candidate
