@@ -334,3 +334,50 @@ def test_step_log_matches_stats(lib):
     assert int(np.sum(kind == 1)) + st.expanded + st.fallbacks + st.audits == st.learned_steps
     assert np.all(nsus[kind == 4] > 0) and np.all(nsus[kind != 4] == 0)
     assert np.all(nsus[kind == 4] <= np.maximum((m[kind == 4] // 2 - 16) // 8 * 8, 0))
+
+
+def test_exact_decisions_match_oracle(lib):
+    """Exact mode step by step against the oracle's learned form (same
+    network, K, witnesses): the plain order, and at every learned step the
+    same decision (certified by the bound, or a second pass over the same
+    number of suspects).  The bound compares FP32-path measures on the GPU
+    with FP64 ones in the oracle, so a step whose suspect count differs is
+    accepted only where some non-candidate's oracle bound lies within 1e-3
+    of the best candidate's k."""
+    d, n, K = 130, 2500, 16
+    s = _sem(d, n, 31)
+    X32 = s.X.astype(np.float32)
+    prop = _proposer(11)
+    out = lib.causal_order(_t(X32), learned=lib.Learned(_t(prop), topk=K, min_m=64),
+                           step_log=True)
+    go = out["order"].cpu().numpy()
+    log = out["step_log"].cpu().numpy()
+    ro, info = OP.learned_order(X32, prop, K=K, delta=np.inf, audit_every=0, min_m=64)
+    assert np.array_equal(go, ro)
+    mism = 0
+    for st in info:
+        if st.kind == "plain":
+            assert log[st.t] & 15 == 0
+            continue
+        g_kind, g_sus = int(log[st.t] & 15), int(log[st.t] >> 4)
+        o_sus = 0 if st.certified else st.suspects
+        if (g_kind == 1) == st.certified and g_sus == o_sus:
+            continue
+        mism += 1
+        # the oracle's bounds at this step: some must sit at the best
+        # candidate's k within the FP32 path's error
+        Xc = X32.astype(np.float64)
+        U = list(range(d))
+        for e in ro[:st.t]:
+            Xc = oracle.residualize(Xc, U, int(e))
+            U.remove(int(e))
+        D = oracle.pair_matrix(Xc, U)
+        k = np.sum(np.minimum(D, 0) ** 2, axis=1)
+        C = np.asarray(st.candidates)
+        lb = OP.lower_bounds(D, C, OP.witnesses(Xc, U, 8))
+        kb = np.min(k[C])
+        notc = np.setdiff1d(np.arange(len(U)), C)
+        near = np.abs(lb[notc] - kb) <= 1e-3 * kb
+        assert near.any(), (st.t, g_kind, g_sus, st.certified, o_sus)
+    print(f"exact decisions: {len(info)} steps, {mism} with a different suspect count",
+          flush=True)
