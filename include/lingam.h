@@ -266,6 +266,30 @@ int lingam_adjacency(const float* X, int64_t n_rows, int64_t ldx, const int32_t*
                      int64_t d, const int32_t* order, double* B, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* Workspace bytes for lingam_adjacency_pruned (0 if unsupported). */
+size_t lingam_adjacency_pruned_workspace_size(int64_t n, int64_t d);
+
+/*
+ * Adjacency matrix pruned by the adaptive lasso (a reading of ours: the paper
+ * stops at the regressions of lingam_adjacency).  For every variable y and
+ * its order predecessors P, on standardized data (population moments): the
+ * least-squares coefficients b give weights w = |b|; the lasso path of y on
+ * the weighted predictors is followed by least angle regression with the
+ * lasso modification (Efron et al. 2004) up to max_active active
+ * predictors; the breakpoint of least BIC, n log(2 pi s2) + RSS/s2 +
+ * log(n) df with s2 = RSS_ols / (n - |P| - 1) and df its nonzero count, is
+ * kept; its predictors are refitted by least squares with an intercept.
+ *   Arguments as for lingam_adjacency; max_active in [1, 64].
+ *   B      device double[d * d]: the refitted coefficients of the kept
+ *          predictors, 0 elsewhere.
+ * FP64 throughout.  Synchronizes.  LINGAM_E_INVALID as for lingam_adjacency;
+ * LINGAM_E_DEGENERATE for n <= d + 1, non-finite data or a correlation
+ * matrix that is not positive definite.
+ */
+int lingam_adjacency_pruned(const float* X, int64_t n_rows, int64_t ldx, const int32_t* rows,
+                            int64_t n, int64_t d, const int32_t* order, int32_t max_active,
+                            double* B, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * Bootstrap statistics (resampling the rows, ordering and regressing each
  * resample): add one resample's result to running counts.

@@ -16,6 +16,8 @@ Functions mirror the C entry points:
   the residuals, instantaneous matrix B0; Section 3.3).
 * :func:`adjacency` -- ``lingam_adjacency`` (least squares of every
   variable on its order predecessors: the weighted adjacency matrix).
+* :func:`adjacency_pruned` -- ``lingam_adjacency_pruned`` (the adjacency
+  pruned by the adaptive lasso).
 * :func:`bootstrap`, :func:`bootstrap_accumulate` -- bootstrap order and
   edge probabilities (batched orderings of resamples, their adjacencies,
   ``lingam_bootstrap_accumulate``).
@@ -38,6 +40,7 @@ from .lib import (  # noqa: F401
     LingamError,
     Profile,
     adjacency,
+    adjacency_pruned,
     batch_causal_order,
     bootstrap,
     bootstrap_accumulate,

@@ -23,6 +23,7 @@
 
 #include "../../include/lingam.h"
 #include "lingam_internal.h"
+#include "lingam_linalg.h"
 
 namespace {
 
@@ -971,6 +972,57 @@ int lingam_adjacency(const float* X, int64_t n_rows, int64_t ldx, const int32_t*
   if (s != 0)
     return fail(LINGAM_E_DEGENERATE,
                 "non-finite data or a covariance that is not positive definite");
+  return LINGAM_OK;
+}
+
+size_t lingam_adjacency_pruned_workspace_size(int64_t n, int64_t d) {
+  if (n < 2 || d < 1 || n > kMaxN || d > kMaxD) return 0;
+  return lg::make_prune_layout(n, d).total;
+}
+
+int lingam_adjacency_pruned(const float* X, int64_t n_rows, int64_t ldx, const int32_t* rows,
+                            int64_t n, int64_t d, const int32_t* order, int32_t max_active,
+                            double* B, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!X || !order || !B) return fail(LINGAM_E_INVALID, "X, order and B must be non-NULL");
+  if (n < 2 || d < 1 || ldx < d || n_rows < 1 || (!rows && n > n_rows))
+    return fail(LINGAM_E_INVALID, "bad sizes n=%lld d=%lld ldx=%lld n_rows=%lld", (long long)n,
+                (long long)d, (long long)ldx, (long long)n_rows);
+  if (max_active < 1 || max_active > lg::kLassoMaxActive)
+    return fail(LINGAM_E_INVALID, "max_active %d outside [1, %d]", max_active,
+                lg::kLassoMaxActive);
+  if (n > kMaxN || d > kMaxD || n_rows > kMaxN)
+    return fail(LINGAM_E_UNSUPPORTED, "size beyond supported range");
+  if (n <= d + 1)
+    return fail(LINGAM_E_DEGENERATE, "n (%lld) must exceed d + 1 (%lld)", (long long)n,
+                (long long)(d + 1));
+  const lg::PruneLayout A = lg::make_prune_layout(n, d);
+  if (!ws || ws_bytes < A.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", A.total,
+                ws ? ws_bytes : (size_t)0);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  lg::AdjLayout V{};  // the check's view of the same status and mark regions
+  V.n = n;
+  V.d = d;
+  V.ctrl = A.ctrl;
+  V.mark = A.mark;
+  int32_t s = 0;
+  LG_TRY(lg::launch_adj_check(V, w, order, rows, n_rows, st), "pruned adjacency check");
+  LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s != 0)
+    return fail(LINGAM_E_INVALID,
+                "order is not a permutation of 0 .. d-1, or a row index is outside [0, n_rows)");
+  LG_TRY(lg::launch_adjacency_pruned(A, w, X, ldx, rows, order, max_active, B, st),
+         "pruned adjacency launch");
+  LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s != 0)
+    return fail(LINGAM_E_DEGENERATE,
+                "non-finite data or a correlation matrix that is not positive definite");
   return LINGAM_OK;
 }
 

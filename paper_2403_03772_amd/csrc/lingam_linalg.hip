@@ -27,6 +27,7 @@
 //   lagged effects       theta_tau = (I - B0) M_tau of VarLiNGAM (Section
 //                        3.3: the model's lagged matrices from the VAR ones).
 #include "lingam_device.h"
+#include "lingam_linalg.h"
 
 namespace lg {
 namespace {
@@ -395,6 +396,392 @@ __global__ __launch_bounds__(256) void k_lagged(const double* __restrict__ M,
   if (i < d && j < d) theta[(int64_t)blockIdx.z * d * d + (int64_t)i * d + j] = Mk[(int64_t)i * d + j] - s;
 }
 
+// ---------------------------------------------------------------------------
+// adaptive-lasso pruning of the adjacency
+// ---------------------------------------------------------------------------
+
+// Xd[v][s] = X[row(s)][v] in FP64 (row(s) = rows[s] or s); padding 0.
+__global__ __launch_bounds__(256) void k_gather_f64(const float* __restrict__ X, int64_t ldx,
+                                                    const int32_t* __restrict__ rows, int n,
+                                                    int d, int n_pad, double* __restrict__ Xd,
+                                                    int64_t ldz, Ctrl* ctrl) {
+  __shared__ float tile[64][65];
+  const int s0 = blockIdx.x * 64, v0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  bool bad = false;
+  for (int i = 0; i < 16; ++i) {
+    const int sl = ty * 16 + i, s = s0 + sl, v = v0 + tx;
+    float val = 0.f;
+    if (s < n && v < d) {
+      val = X[(int64_t)(rows ? rows[s] : s) * ldx + v];
+      bad |= !isfinite(val);
+    }
+    tile[sl][tx] = val;
+  }
+  __syncthreads();
+  for (int i = 0; i < 16; ++i) {
+    const int vl = ty * 16 + i, v = v0 + vl, s = s0 + tx;
+    if (v < d && s < n_pad) Xd[(int64_t)v * ldz + s] = (double)tile[tx][vl];
+  }
+  if (bad) set_status(ctrl, kStDegenerate);
+}
+
+// sd[a] = sqrt(S[a][a] / n); R = S scaled to unit diagonal; L = R (to be
+// factored).  A zero variance sets the status.
+__global__ void k_corr(const double* __restrict__ S, int d, int n, double* __restrict__ sd,
+                       double* __restrict__ R, double* __restrict__ L, Ctrl* ctrl) {
+  const int64_t total = (int64_t)d * d;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / d), b = (int)(e - (int64_t)a * d);
+    const double saa = S[(int64_t)a * d + a], sbb = S[(int64_t)b * d + b];
+    if (!(saa > 0.0) || !(sbb > 0.0)) {
+      set_status(ctrl, kStDegenerate);
+      R[e] = L[e] = (a == b) ? 1.0 : 0.0;
+    } else {
+      const double r = S[e] / sqrt(saa * sbb);
+      R[e] = L[e] = r;
+    }
+    if (a == b) sd[a] = sqrt(fmax(saa, 0.0) / (double)n);
+  }
+}
+
+__global__ void k_zero_f64(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+struct LarsShared {
+  double M[kLassoMaxActive][kLassoMaxActive + 1];  // inverse of G on the active set
+  double g[kLassoMaxActive], v[kLassoMaxActive], wv[kLassoMaxActive];
+  double sgn[kLassoMaxActive];
+  int idx[kLassoMaxActive];
+  int best_idx[kLassoMaxActive];
+  double rv[256];
+  int ri[256];
+  double sv;
+  int si;
+};
+
+// Block arg-min of (value, index), ties to the smaller index; index -1 = none.
+__device__ inline void block_argmin(double v, int i, LarsShared& S, double& ov, int& oi) {
+  const int tid = threadIdx.x;
+  S.rv[tid] = v;
+  S.ri[tid] = i;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      const double a = S.rv[tid], b = S.rv[tid + off];
+      const int ia = S.ri[tid], ib = S.ri[tid + off];
+      if (ib >= 0 && (ia < 0 || b < a || (b == a && ib < ia))) {
+        S.rv[tid] = b;
+        S.ri[tid] = ib;
+      }
+    }
+    __syncthreads();
+  }
+  ov = S.rv[0];
+  oi = S.ri[0];
+  __syncthreads();
+}
+
+__device__ inline double block_sum(double v, LarsShared& S) {
+  const int tid = threadIdx.x;
+  S.rv[tid] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) S.rv[tid] += S.rv[tid + off];
+    __syncthreads();
+  }
+  const double r = S.rv[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per target position t >= 1 (predictors: positions 0 .. t-1).
+// Adaptive weights w_k = |b_k| from the least-squares row of B = I -
+// diag(L) L^-1 on the correlation matrix; the lasso path of the weighted
+// standardized predictors by least angle regression with the lasso
+// modification (covariance form, G_jk = n w_j w_k R_jk, c_k = n w_k R_kt),
+// at most max_active active; the breakpoint of least BIC
+// n log(2 pi s2) + RSS / s2 + log(n) df, s2 = n L_tt^2 / (n - t - 1); the
+// kept predictors refitted by least squares (standardized, then rescaled).
+// The path state (correlations, coefficients, directions, flags) lives in
+// st[t][4][d]; the inverse of G on the active set in LDS, updated by the
+// Schur complement on a join and the rank-1 downdate on a leave.
+__global__ __launch_bounds__(256) void k_lars(const double* __restrict__ R,
+                                              const double* __restrict__ L,
+                                              const double* __restrict__ Y,
+                                              const double* __restrict__ sd,
+                                              const int32_t* __restrict__ order, int d, int n,
+                                              int cap, double* __restrict__ st,
+                                              double* __restrict__ B, Ctrl* ctrl) {
+  __shared__ LarsShared S;
+  const int t = blockIdx.x + 1;
+  const int p = t;
+  const int tid = threadIdx.x;
+  const double nn = (double)n;
+  double* corr = st + (int64_t)t * 4 * d;
+  double* beta = corr + d;
+  double* av = beta + d;
+  double* flag = av + d;
+  const double Ltt = L[(int64_t)t * d + t];
+  const double* Yt = Y + (int64_t)t * d;
+  const double* Rt = R + (int64_t)t * d;  // row t = column t (symmetric)
+  auto wgt = [&](int k) { return fabs(Ltt * Yt[k]); };
+  auto cval = [&](int k) { return nn * wgt(k) * Rt[k]; };
+  double cmax = 0.0;
+  for (int k = tid; k < p; k += 256) {
+    const double c = cval(k);
+    corr[k] = c;
+    beta[k] = 0.0;
+    flag[k] = 0.0;
+    cmax = fmax(cmax, fabs(c));
+  }
+  // max |c| through the arg-min of its negation
+  double mv;
+  int mi;
+  block_argmin(-cmax, tid, S, mv, mi);
+  const double tiny = 1e-14 * fmax(1.0, -mv);
+  const double s2 = nn * Ltt * Ltt / (double)(n - p - 1);
+  const double logterm = nn * log(2.0 * 3.14159265358979323846 * s2);
+  const double lnn = log(nn);
+  double best = logterm + nn / s2;  // beta = 0: RSS = n, df = 0
+  int best_na = 0;
+  int na = 0;
+  bool joined = true;
+  const int cap_a = cap < p ? cap : p;
+  const int max_iter = 8 * kLassoMaxActive + 16;  // bound on the loop (never reached in practice)
+  for (int iter = 0; iter < max_iter; ++iter) {
+    if (joined) {
+      if (na == p) break;
+      // inactive predictor of largest |corr| (ties to the smaller position)
+      double bv = INFINITY;
+      int bi = -1;
+      for (int k = tid; k < p; k += 256)
+        if (flag[k] == 0.0) {
+          const double v = -fabs(corr[k]);
+          if (v < bv) {
+            bv = v;
+            bi = k;
+          }
+        }
+      double jv;
+      int j;
+      block_argmin(bv, bi, S, jv, j);
+      if (j < 0 || -jv <= tiny) break;
+      // Schur complement: append j to the inverse of G on the active set
+      const double wj = wgt(j);
+      const double* Rj = R + (int64_t)j * d;
+      if (tid < na) S.g[tid] = nn * wgt(S.idx[tid]) * wj * Rj[S.idx[tid]];
+      __syncthreads();
+      if (tid < na) {
+        double acc = 0.0;
+        for (int q = 0; q < na; ++q) acc += S.M[tid][q] * S.g[q];
+        S.v[tid] = acc;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double gv = 0.0;
+        for (int q = 0; q < na; ++q) gv += S.g[q] * S.v[q];
+        S.sv = nn * wj * wj * Rj[j] - gv;
+      }
+      __syncthreads();
+      const double sch = S.sv;
+      if (!(sch > 1e-12 * nn * wj * wj)) break;  // the new predictor is (nearly) collinear
+      for (int e = tid; e < na * na; e += 256) {
+        const int r = e / na, q = e - r * na;
+        S.M[r][q] += S.v[r] * S.v[q] / sch;
+      }
+      if (tid < na) {
+        S.M[tid][na] = -S.v[tid] / sch;
+        S.M[na][tid] = -S.v[tid] / sch;
+      }
+      if (tid == 0) {
+        S.M[na][na] = 1.0 / sch;
+        S.idx[na] = j;
+        flag[j] = 1.0;
+      }
+      __syncthreads();
+      ++na;
+    }
+    // equiangular direction on the active set
+    if (tid < na) S.sgn[tid] = corr[S.idx[tid]] >= 0.0 ? 1.0 : -1.0;
+    __syncthreads();
+    if (tid < na) {
+      double acc = 0.0;
+      for (int q = 0; q < na; ++q) acc += S.M[tid][q] * S.sgn[q];
+      S.v[tid] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sx = 0.0, cm = 0.0;
+      for (int q = 0; q < na; ++q) {
+        sx += S.sgn[q] * S.v[q];
+        cm = fmax(cm, fabs(corr[S.idx[q]]));
+      }
+      S.sv = sx;
+      S.rv[0] = cm;
+    }
+    __syncthreads();
+    const double AA = 1.0 / sqrt(S.sv);
+    const double C = S.rv[0];
+    __syncthreads();
+    if (tid < na) S.wv[tid] = AA * S.v[tid];
+    __syncthreads();
+    // a_k = sum_r G(k, idx_r) wv_r, and the first join along the direction
+    double gj = INFINITY;
+    int kj = -1;
+    for (int k = tid; k < p; k += 256) {
+      double acc = 0.0;
+      for (int r = 0; r < na; ++r) {
+        const int ir = S.idx[r];
+        acc += nn * wgt(ir) * R[(int64_t)ir * d + k] * S.wv[r];
+      }
+      acc *= wgt(k);
+      av[k] = acc;
+      if (flag[k] == 0.0) {
+        const double ck = corr[k];
+        const double d1 = AA - acc, d2 = AA + acc;
+        if (d1 > 0.0) {
+          const double g = (C - ck) / d1;
+          if (g > 0.0 && g < gj) {
+            gj = g;
+            kj = k;
+          }
+        }
+        if (d2 > 0.0) {
+          const double g = (C + ck) / d2;
+          if (g > 0.0 && g < gj) {
+            gj = g;
+            kj = k;
+          }
+        }
+      }
+    }
+    double gjoin;
+    int jn;
+    block_argmin(gj, kj, S, gjoin, jn);
+    double gam = C / AA;
+    int event = 0;  // 0 end, 1 join, 2 leave
+    if (jn >= 0 && gjoin < gam) {
+      gam = gjoin;
+      event = 1;
+    }
+    // first active coefficient to reach zero
+    double gl = INFINITY;
+    int rl = -1;
+    if (tid < na && S.wv[tid] != 0.0) {
+      const double g = -beta[S.idx[tid]] / S.wv[tid];
+      if (g > 0.0) {
+        gl = g;
+        rl = tid;
+      }
+    }
+    double gleave;
+    int lr;
+    block_argmin(gl, rl, S, gleave, lr);
+    if (lr >= 0 && gleave < gam) {
+      gam = gleave;
+      event = 2;
+    }
+    // step
+    if (tid < na) beta[S.idx[tid]] += gam * S.wv[tid];
+    for (int k = tid; k < p; k += 256) corr[k] -= gam * av[k];
+    __syncthreads();
+    if (event == 2) {
+      const int who = S.idx[lr];
+      // rank-1 downdate of the inverse without row / column lr, then compaction
+      const double piv = S.M[lr][lr];
+      double keep[16];
+      const int nb = na - 1;
+      int cnt = 0;
+      for (int e = tid; e < nb * nb; e += 256, ++cnt) {
+        const int r2 = e / nb, q2 = e - r2 * nb;
+        const int r = r2 + (r2 >= lr ? 1 : 0), q = q2 + (q2 >= lr ? 1 : 0);
+        keep[cnt] = S.M[r][q] - S.M[r][lr] * S.M[lr][q] / piv;
+      }
+      int idx_keep = tid < nb ? S.idx[tid + (tid >= lr ? 1 : 0)] : 0;
+      __syncthreads();
+      cnt = 0;
+      for (int e = tid; e < nb * nb; e += 256, ++cnt) {
+        const int r2 = e / nb, q2 = e - r2 * nb;
+        S.M[r2][q2] = keep[cnt];
+      }
+      if (tid < nb) S.idx[tid] = idx_keep;
+      if (tid == 0) {
+        beta[who] = 0.0;
+        flag[who] = 0.0;
+      }
+      __syncthreads();
+      na = nb;
+    }
+    // criterion at the new breakpoint: RSS = n - beta'c - beta'corr
+    double part = 0.0;
+    if (tid < na) {
+      const int k = S.idx[tid];
+      part = beta[k] * (cval(k) + corr[k]);
+    }
+    const double bsum = block_sum(part, S);
+    const double crit = logterm + (nn - bsum) / s2 + lnn * (double)na;
+    if (crit < best) {
+      best = crit;
+      best_na = na;
+      if (tid < na) S.best_idx[tid] = S.idx[tid];
+    }
+    __syncthreads();
+    if (event == 0) break;
+    if (event == 1 && na >= cap_a) break;
+    joined = event == 1;
+  }
+  // refit the kept predictors by least squares on the standardized data
+  const int ns = best_na;
+  if (ns == 0) return;
+  for (int e = tid; e < ns * ns; e += 256) {
+    const int r = e / ns, q = e - r * ns;
+    S.M[r][q] = R[(int64_t)S.best_idx[r] * d + S.best_idx[q]];
+  }
+  if (tid < ns) S.g[tid] = Rt[S.best_idx[tid]];
+  __syncthreads();
+  for (int j = 0; j < ns; ++j) {  // Cholesky in LDS, lower triangle
+    if (tid == 0) {
+      double a = S.M[j][j];
+      if (!(a > 1e-13)) {
+        set_status(ctrl, kStDegenerate);
+        a = 1.0;
+      }
+      S.M[j][j] = sqrt(a);
+    }
+    __syncthreads();
+    if (tid > j && tid < ns) S.M[tid][j] /= S.M[j][j];
+    __syncthreads();
+    const int w = ns - j - 1;
+    for (int e = tid; e < w * w; e += 256) {
+      const int ii = e / w, kk = e - ii * w;
+      if (kk <= ii) S.M[j + 1 + ii][j + 1 + kk] -= S.M[j + 1 + ii][j] * S.M[j + 1 + kk][j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int i = 0; i < ns; ++i) {  // forward, then backward substitution
+      double acc = S.g[i];
+      for (int q = 0; q < i; ++q) acc -= S.M[i][q] * S.g[q];
+      S.g[i] = acc / S.M[i][i];
+    }
+    for (int i = ns - 1; i >= 0; --i) {
+      double acc = S.g[i];
+      for (int q = i + 1; q < ns; ++q) acc -= S.M[q][i] * S.g[q];
+      S.g[i] = acc / S.M[i][i];
+    }
+  }
+  __syncthreads();
+  if (tid < ns) {
+    const int k = S.best_idx[tid];
+    B[(int64_t)order[t] * d + order[k]] = S.g[tid] * sd[t] / sd[k];
+  }
+}
+
 unsigned grid_for(int64_t n) {
   const int64_t g = (n + 255) / 256;
   return (unsigned)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
@@ -463,6 +850,63 @@ hipError_t launch_lagged_effects(const double* M, const double* B0, int d, int l
                                  double* theta, hipStream_t st) {
   const unsigned g = (unsigned)((d + 15) / 16);
   hipLaunchKernelGGL(k_lagged, dim3(g, g, (unsigned)lags), dim3(256), 0, st, M, B0, d, theta);
+  return hipGetLastError();
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+PruneLayout make_prune_layout(int64_t n, int64_t d) {
+  PruneLayout A{};
+  A.n = n;
+  A.d = d;
+  A.ldx = (n + 63) / 64 * 64;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t dd = sizeof(double) * (size_t)d * (size_t)d;
+  A.ctrl = take(sizeof(Ctrl));
+  A.mark = take(sizeof(int32_t) * (size_t)d);
+  A.tol = take(sizeof(double));
+  A.mu = take(sizeof(double) * (size_t)d);
+  A.sd = take(sizeof(double) * (size_t)d);
+  A.xd = take(sizeof(double) * (size_t)d * (size_t)A.ldx);
+  A.s = take(dd);
+  A.r = take(dd);
+  A.l = take(dd);
+  A.y = take(dd);
+  A.st = take(4 * dd);
+  A.total = off;
+  return A;
+}
+
+hipError_t launch_adjacency_pruned(const PruneLayout& A, char* ws, const float* X, int64_t ldx,
+                                   const int32_t* rows, const int32_t* order, int max_active,
+                                   double* B, hipStream_t st) {
+  Ctrl* ctrl = at<Ctrl>(ws, A.ctrl);
+  double* Xd = at<double>(ws, A.xd);
+  double* Sm = at<double>(ws, A.s);
+  double* Rm = at<double>(ws, A.r);
+  double* Lm = at<double>(ws, A.l);
+  double* Ym = at<double>(ws, A.y);
+  const int d = (int)A.d, n = (int)A.n;
+  dim3 g1((unsigned)(A.ldx / 64), (unsigned)((A.d + 63) / 64));
+  hipLaunchKernelGGL(k_gather_f64, g1, dim3(256), 0, st, X, ldx, rows, n, d, (int)A.ldx, Xd,
+                     A.ldx, ctrl);
+  LG_HIP(launch_cov_perm(Xd, A.ldx, n, d, order, at<double>(ws, A.mu), Sm, st));
+  const int64_t dd = (int64_t)d * d;
+  hipLaunchKernelGGL(k_corr, dim3(grid_for(dd)), dim3(256), 0, st, (const double*)Sm, d, n,
+                     at<double>(ws, A.sd), Rm, Lm, ctrl);
+  LG_HIP(launch_cholesky(Lm, d, d, at<double>(ws, A.tol), ctrl, st));
+  LG_HIP(launch_tri_inverse(Lm, d, d, Ym, d, st));
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(dd)), dim3(256), 0, st, B, dd);
+  if (d < 2) return hipGetLastError();
+  const int cap = max_active < kLassoMaxActive ? max_active : kLassoMaxActive;
+  hipLaunchKernelGGL(k_lars, dim3((unsigned)(d - 1)), dim3(256), 0, st, (const double*)Rm,
+                     (const double*)Lm, (const double*)Ym, (const double*)at<double>(ws, A.sd),
+                     order, d, n, cap, at<double>(ws, A.st), B, ctrl);
   return hipGetLastError();
 }
 

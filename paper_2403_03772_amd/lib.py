@@ -190,6 +190,10 @@ def load():
         lib.lingam_adjacency_workspace_size.argtypes = [i64, i64]
         lib.lingam_adjacency_workspace_size.restype = sz
         lib.lingam_adjacency.argtypes = [P, i64, i64, P, i64, i64, P, P, P, sz, P]
+        lib.lingam_adjacency_pruned_workspace_size.argtypes = [i64, i64]
+        lib.lingam_adjacency_pruned_workspace_size.restype = sz
+        lib.lingam_adjacency_pruned.argtypes = [P, i64, i64, P, i64, i64, P, i32, P, P, sz, P]
+        lib.lingam_adjacency_pruned.restype = ctypes.c_int
         lib.lingam_bootstrap_accumulate.argtypes = [P, P, i64, ctypes.c_double, P, P, P, P]
         lib.lingam_bootstrap_accumulate.restype = ctypes.c_int
         lib.lingam_adjacency.restype = ctypes.c_int
@@ -401,6 +405,37 @@ def adjacency(X, order, *, rows=None, workspace=None):
     return B
 
 
+def adjacency_pruned(X, order, *, rows=None, max_active: int = 64, workspace=None):
+    """Adjacency of a CUDA float32 ``X`` along ``order`` pruned by the adaptive
+    lasso (BIC over the least-angle lasso path, least-squares refit of the
+    kept predictors; ``lingam_adjacency_pruned``).  Returns d x d float64."""
+    import torch
+
+    lib = load()
+    _cuda_f32_matrix(torch, X)
+    n_rows, d = X.shape
+    o = torch.as_tensor(order, dtype=torch.int32).to(X.device).contiguous()
+    if o.numel() != d:
+        raise ValueError(f"order has {o.numel()} entries, X has {d} columns")
+    r = None
+    n = n_rows
+    if rows is not None:
+        r = torch.as_tensor(rows, dtype=torch.int32).to(X.device).contiguous()
+        n = r.numel()
+    need = int(lib.lingam_adjacency_pruned_workspace_size(n, d))
+    if need == 0:
+        raise LingamError(E_INVALID, f"unsupported size n={n} d={d}")
+    ws = workspace
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    B = torch.empty((d, d), dtype=torch.float64, device=X.device)
+    code = lib.lingam_adjacency_pruned(_ptr(X), n_rows, X.stride(0), _ptr(r), n, d, _ptr(o),
+                                       int(max_active), _ptr(B), _ptr(ws), ws.numel(),
+                                       _stream_ptr(torch, X.device))
+    _check(code)
+    return B
+
+
 def bootstrap_accumulate(order, B, threshold, order_count, edge_count, coef_sum=None):
     """Add one resample's order and adjacency to the running counts (in place)."""
     import torch
@@ -413,7 +448,7 @@ def bootstrap_accumulate(order, B, threshold, order_count, edge_count, coef_sum=
 
 
 def bootstrap(X, resamples, *, threshold: float = 0.0, graph: bool = False,
-              autotune: bool = False, learned: Learned | None = None):
+              autotune: bool = False, learned: Learned | None = None, prune: bool = False):
     """Bootstrap statistics of DirectLiNGAM on a CUDA float32 ``X`` (n x d).
 
     ``resamples``: sequence of int32 row-index arrays (drawn by the caller,
@@ -421,7 +456,7 @@ def bootstrap(X, resamples, *, threshold: float = 0.0, graph: bool = False,
     regressed along their orders; returns a dict with ``orders`` (list),
     ``order_prob`` (d x d: P(x_j precedes x_i) at [i, j]), ``edge_prob``
     (P(|B[i, j]| > threshold)), ``coef_mean`` (mean of B) and ``n`` (the
-    number of resamples).
+    number of resamples).  ``prune``: B from :func:`adjacency_pruned`.
     """
     import torch
 
@@ -437,10 +472,13 @@ def bootstrap(X, resamples, *, threshold: float = 0.0, graph: bool = False,
     order_count = torch.zeros((d, d), dtype=torch.int32, device=dev)
     edge_count = torch.zeros((d, d), dtype=torch.int32, device=dev)
     coef_sum = torch.zeros((d, d), dtype=torch.float64, device=dev)
-    need = max(int(lib.lingam_adjacency_workspace_size(r.numel(), d)) for r in rows)
+    size_of = (lib.lingam_adjacency_pruned_workspace_size if prune
+               else lib.lingam_adjacency_workspace_size)
+    need = max(int(size_of(r.numel(), d)) for r in rows)
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    fit = adjacency_pruned if prune else adjacency
     for r, o in zip(rows, out["orders"]):
-        B = adjacency(X, o, rows=r, workspace=ws)
+        B = fit(X, o, rows=r, workspace=ws)
         bootstrap_accumulate(o, B, threshold, order_count, edge_count, coef_sum)
     R = float(len(rows))
     return {"orders": out["orders"], "order_prob": order_count.double() / R,

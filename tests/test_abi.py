@@ -139,6 +139,14 @@ def test_adjacency_argument_errors():
     assert c(n_rows=0, rows=1) == L.E_INVALID
     assert c(d=1 << 20, ldx=1 << 20) == L.E_UNSUPPORTED
     assert c(ws=16) == L.E_WORKSPACE
+    pr = lambda **k: lib.lingam_adjacency_pruned(
+        v, k.get("n_rows", 100), 3, None, k.get("n", 100), k.get("d", 3), v, k.get("ma", 64), v,
+        v, k.get("ws", 1 << 30), None)
+    assert pr(ma=0) == L.E_INVALID
+    assert pr(ma=65) == L.E_INVALID
+    assert pr(n=4, n_rows=4) == L.E_DEGENERATE     # n <= d + 1
+    assert pr(ws=16) == L.E_WORKSPACE
+    assert lib.lingam_adjacency_pruned_workspace_size(1, 3) == 0
     a = lambda **k: lib.lingam_bootstrap_accumulate(
         v if k.get("order", 1) else None, v if k.get("B", 1) else None, k.get("d", 3),
         k.get("thr", 0.0), v if k.get("oc", 1) else None, v if k.get("ec", 1) else None,

@@ -160,3 +160,58 @@ def test_bootstrap_matches_oracle(lib, threshold):
     # orders: each resample's order is the batch engine's ordering of the gathered rows
     o0 = lib.causal_order(torch.as_tensor(np.ascontiguousarray(X32[res[0]])).cuda())
     assert np.array_equal(o0.cpu().numpy(), orders[0])
+
+
+@pytest.mark.parametrize("d,n,seed,cap", [(2, 200, 0, 64), (9, 800, 5, 64), (40, 3000, 1, 64),
+                                          (100, 4000, 2, 64), (30, 2000, 3, 2)])
+def test_adjacency_pruned_matches_oracle(lib, d, n, seed, cap):
+    """Adaptive-lasso pruning against the oracle (same definition, FP64 on
+    both sides): the kept predictors exactly, their coefficients to 1e-8."""
+    import torch
+    from oracle import lasso as LA
+    s = synth.er_sem(d, n, indeg=2.0, noise_family=("uniform", "laplace", "exp"), seed=seed)
+    X32 = s.X.astype(np.float32)
+    print(f"pruned d={d} n={n} seed={seed} cap={cap}", flush=True)
+    X = torch.as_tensor(X32).cuda()
+    for order in (s.order, np.random.default_rng(seed).permutation(d)):
+        B = lib.adjacency_pruned(X, order, max_active=cap).cpu().numpy()
+        ref = LA.adaptive_lasso_adjacency(X32.astype(np.float64), order, max_active=cap)
+        assert np.array_equal(B != 0, ref != 0), np.argwhere((B != 0) != (ref != 0))[:5]
+        assert np.max(np.abs(B - ref)) <= _tol(ref)
+        assert np.all(np.count_nonzero(B, axis=1) <= cap)
+
+
+def test_adjacency_pruned_keeps_true_edges(lib):
+    """Along the true order at large n the pruned matrix has the generating
+    support (the plain least-squares matrix is dense)."""
+    import torch
+    s = synth.er_sem(16, 100_000, indeg=2.0, noise_family="uniform", seed=4, rescale=False)
+    X = torch.as_tensor(s.X.astype(np.float32)).cuda()
+    B = lib.adjacency_pruned(X, s.order).cpu().numpy()
+    assert np.array_equal(B != 0, s.B != 0)
+    assert np.max(np.abs(B - s.B)) < 0.05
+    dense = lib.adjacency(X, s.order).cpu().numpy()
+    assert np.count_nonzero(dense) > np.count_nonzero(B)
+
+
+def test_adjacency_pruned_errors_and_bootstrap(lib):
+    import torch
+    X = torch.randn((6, 5), device="cuda")
+    with pytest.raises(lib.LingamError) as e:
+        lib.adjacency_pruned(X, [0, 1, 2, 3, 4])  # n <= d + 1
+    assert e.value.code == -2
+    Y = torch.randn((300, 5), device="cuda")
+    with pytest.raises(lib.LingamError) as e:
+        lib.adjacency_pruned(Y, [0, 1, 2, 2, 4])
+    assert e.value.code == -1
+    s = synth.er_sem(10, 600, indeg=2.0, noise_family=("uniform", "laplace"), seed=8)
+    X32 = s.X.astype(np.float32)
+    rng = np.random.default_rng(3)
+    res = [rng.integers(0, 600, size=600).astype(np.int32) for _ in range(6)]
+    out = lib.bootstrap(torch.as_tensor(X32).cuda(), res, prune=True)
+    from oracle import lasso as LA
+    orders = [o.cpu().numpy() for o in out["orders"]]
+    ec = np.zeros((10, 10), dtype=np.int64)
+    for r, o in zip(res, orders):
+        ec += LA.adaptive_lasso_adjacency(X32[r].astype(np.float64), o) != 0
+    assert np.array_equal(out["edge_count"].cpu().numpy(), ec)
