@@ -249,6 +249,25 @@ def run_adjacency(lg, X, n, d, order, reps=5):
             "flops": flops, "reps": reps}
 
 
+def run_adjacency_pruned(lg, X, order, B_true, reps=3):
+    """lingam_adjacency_pruned along the plain order: mean ms per call and the
+    edges it keeps against the generating DAG (precision, recall)."""
+    import torch
+
+    lg.adjacency_pruned(X, order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B = lg.adjacency_pruned(X, order)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    kept = B.cpu().numpy() != 0
+    true = np.asarray(B_true) != 0
+    tp = int(np.sum(kept & true))
+    return {"ms": ms, "reps": reps, "edges_kept": int(kept.sum()), "edges_true": int(true.sum()),
+            "precision": tp / max(int(kept.sum()), 1), "recall": tp / max(int(true.sum()), 1)}
+
+
 def run_varlingam(lg, reps=3):
     """varlingam_fit on the stock-shaped series (d = 487, T = 1258, VAR(1)):
     mean ms per fit, lagged effects included."""
@@ -435,6 +454,9 @@ def main() -> int:
     if args.workload == "gene" and not args.no_aux:
         progress("adjacency along the plain order")
         rec["adjacency"] = run_adjacency(lg, X, n, d, torch.as_tensor(pl["order"]).cuda())
+        progress("adaptive-lasso pruning along the plain order")
+        rec["adjacency_pruned"] = run_adjacency_pruned(lg, X, torch.as_tensor(pl["order"]).cuda(),
+                                                       sem.B)
         progress("varlingam (stock shape)")
         rec["varlingam"] = run_varlingam(lg)
     if not args.no_batch and args.workload == "gene":

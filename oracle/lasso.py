@@ -104,10 +104,12 @@ def bic_select(G, c, n: int, rss_ols: float, path) -> int:
     return arg
 
 
-def adaptive_lasso_adjacency(X, order, max_active: int = 64) -> np.ndarray:
+def adaptive_lasso_adjacency(X, order, max_active: int = 64, positions=None) -> np.ndarray:
     """Pruned weighted adjacency matrix: B[y, j] is the refitted coefficient
     of x_j for every predictor j the adaptive lasso keeps in the regression
-    of x_y on its order predecessors; 0 elsewhere (see the module header)."""
+    of x_y on its order predecessors; 0 elsewhere (see the module header).
+    ``positions``: only the rows of the variables at these order positions
+    (the others stay 0)."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
     order = np.asarray(order, dtype=np.int64)
@@ -116,7 +118,9 @@ def adaptive_lasso_adjacency(X, order, max_active: int = 64) -> np.ndarray:
     Z = Xc / sd
     R = (Z.T @ Z) / n                      # correlation matrix
     B = np.zeros((d, d))
-    for pos in range(1, d):
+    for pos in (range(1, d) if positions is None else positions):
+        if pos < 1:
+            continue
         y, P = order[pos], order[:pos]
         p = P.size
         Rpp, rpy = R[np.ix_(P, P)], R[P, y]

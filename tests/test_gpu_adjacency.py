@@ -215,3 +215,19 @@ def test_adjacency_pruned_errors_and_bootstrap(lib):
     for r, o in zip(res, orders):
         ec += LA.adaptive_lasso_adjacency(X32[r].astype(np.float64), o) != 0
     assert np.array_equal(out["edge_count"].cpu().numpy(), ec)
+
+
+def test_adjacency_pruned_workload_sampled_rows(lib):
+    """d = 1024, n = 8192 (the ordering workload) along its generating order:
+    sampled rows against the oracle."""
+    import torch
+    from oracle import lasso as LA
+    s = synth.workload_gene_scale(seed=0)
+    X32 = np.ascontiguousarray(s.X, dtype=np.float32)
+    B = lib.adjacency_pruned(torch.as_tensor(X32).cuda(), s.order).cpu().numpy()
+    pos = [1, 2, 40, 511, 1023]
+    ref = LA.adaptive_lasso_adjacency(X32.astype(np.float64), s.order, positions=pos)
+    for p_ in pos:
+        y = s.order[p_]
+        assert np.array_equal(B[y] != 0, ref[y] != 0), p_
+        assert np.max(np.abs(B[y] - ref[y])) <= _tol(ref[y]), p_
