@@ -450,3 +450,22 @@ def test_varlingam_recovers_structure():
     assert np.max(np.abs(out["M"][0] - v.A1)) < 0.05
     assert synth.is_topological(out["order"], v.B0)
     assert np.max(np.abs(out["B0"] - v.B0)) < 0.08
+
+
+def test_golden_small_sem_reproduced():
+    """The stored oracle values (tests/golden/make_golden.py) are reproduced:
+    a drift of the oracle's arithmetic shows here."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "small_sem_d10_n1000.json")))
+    s = synth.workload_small(seed=0)
+    X32 = s.X.astype(np.float32)
+    order, meas, gaps = oracle.causal_order(X32, mode="literal", with_measures=True)
+    assert [int(v) for v in order] == g["order"]
+    ref = np.array([[np.nan if x is None else x for x in row] for row in g["measures"]])
+    assert np.array_equal(np.isfinite(ref), np.isfinite(meas))
+    fin = np.isfinite(ref)
+    assert np.max(np.abs(meas[fin] - ref[fin])) <= 1e-13 * np.max(np.abs(ref[fin]))
+    B = oracle.ols_adjacency(X32.astype(np.float64), order)
+    assert np.max(np.abs(B - np.array(g["adjacency"]))) <= 1e-12
