@@ -129,7 +129,7 @@ typedef struct lingam_opts {
   const float* proposer;        /* device FP32[LINGAM_PROPOSER_SIZE] or NULL: plain search */
   int32_t topk;                 /* most candidates per learned step: multiple of 8 in
                                    [8, 256]; a step with m variables takes about m/16 of
-                                   them (a multiple of 8), at least min(64, topk);
+                                   them (a multiple of 8), at least min(32, topk);
                                    default 64 */
   int32_t audit_every;          /* full-step audit when t % audit_every == 0; 0 = never;
                                    default 0 (with margin = +inf every decision is

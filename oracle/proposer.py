@@ -263,9 +263,9 @@ def topk(scores, slots, K: int) -> np.ndarray:
 
 def step_topk(m: int, K: int) -> int:
     """Candidates of a learned step with m variables and at most K: about m/16
-    rounded up to a multiple of 8, at least min(64, K), at most K."""
+    rounded up to a multiple of 8, at least min(32, K), at most K."""
     k = -(-(m // 16) // 8) * 8
-    return min(max(k, min(64, K)), K)
+    return min(max(k, min(32, K)), K)
 
 
 def suspect_cap(m: int, K: int, cap: int = 1024) -> int:

@@ -196,9 +196,9 @@ struct JobStep {
 };
 
 // Candidates of a learned step with m active variables and at most K: about
-// m / 16 (a multiple of 8), at least min(64, K) and at most K.
+// m / 16 (a multiple of 8), at least min(32, K) and at most K.
 __host__ __device__ inline int32_t step_topk(int32_t m, int32_t K) {
-  const int32_t lo = K < 64 ? K : 64;
+  const int32_t lo = K < 32 ? K : 32;
   int32_t k = (m / 16 + kTileVars - 1) / kTileVars * kTileVars;
   k = k < lo ? lo : k;
   return k > K ? K : k;

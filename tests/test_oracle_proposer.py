@@ -231,7 +231,8 @@ def test_step_topk():
     assert P.step_topk(4096, 256) == 256
     assert P.step_topk(2000, 256) == 128
     assert P.step_topk(1024, 256) == 64
-    assert P.step_topk(300, 256) == 64
+    assert P.step_topk(300, 256) == 32
+    assert P.step_topk(600, 64) == 40
     assert P.step_topk(4096, 64) == 64
     assert P.step_topk(100, 8) == 8
     assert P.step_topk(1000, 3) == 3
