@@ -80,3 +80,20 @@ def test_sampled_rows_match_oracle(run, t):
     if best_ref != order[t]:
         kb, kc = -ref[rows == best_ref][0], -ref[rows == order[t]][0]
         assert abs(kb - kc) <= 2 * REL * max(kb, kc, s_t)
+
+
+def test_learned_exact_form_gives_the_plain_order(run, lib):
+    """The learned form with the shipped network at its defaults (exact mode)
+    on the same workload: the plain order, with every learned step decided
+    by the certificate or the suspect pass."""
+    import os
+    import torch
+    from paper_2403_03772_amd import train_proposer as tp
+    if not os.path.exists(tp.WEIGHTS):
+        pytest.skip("no trained network shipped")
+    s, X32, order, _, _ = run
+    out = lib.causal_order(torch.as_tensor(X32).cuda(), learned=lib.Learned(tp.default_proposer()))
+    assert np.array_equal(out["order"].cpu().numpy(), order)
+    st = out["learned_stats"]
+    assert st.learned_steps == D - 128 and st.audits == 0
+    assert st.certified + st.expanded + st.fallbacks == st.learned_steps
