@@ -623,22 +623,27 @@ __global__ __launch_bounds__(64 * kWitWaves) void k_pair_wit(const JobDev* __res
     any |= on[q];
   }
   if (!any) return;
+  // everything below up to the sample loop is workgroup-uniform: keep the
+  // row bases and pair constants in SGPRs
+  auto uni = [](float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+  };
   const int64_t ldz = J.ldz;
-  const int sl = J.act[l];
+  const int sl = __builtin_amdgcn_readfirstlane(J.act[l]);
   const float* zl = J.z + (int64_t)sl * ldz;
   const float* zw[kWit];
   float kr[kWit], kh[kWit], kl[kWit];
 #pragma unroll
   for (int q = 0; q < kWit; ++q) {
-    const int sw = J.act[wq[q]];
+    const int sw = __builtin_amdgcn_readfirstlane(J.act[wq[q]]);
     zw[q] = J.z + (int64_t)sw * ldz;
     double r = on[q] ? J.rho[(int64_t)sl * J.d + sw] : 0.0;
     const double lim = 1.0 - kCollinear;
     r = r > lim ? lim : (r < -lim ? -lim : r);
     const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
-    kr[q] = (float)r;
-    kh[q] = (float)c1;
-    kl[q] = (float)(c1 - (double)kh[q]);
+    kr[q] = uni((float)r);
+    kh[q] = uni((float)c1);
+    kl[q] = uni((float)(c1 - (double)(float)c1));
   }
   // dir 0: residual of l on w; dir 1: residual of w on l
   float P0[kWit], A0[kWit], B0[kWit], P1[kWit], A1[kWit], B1[kWit];
@@ -685,22 +690,19 @@ __global__ __launch_bounds__(64 * kWitWaves) void k_pair_wit(const JobDev* __res
 #pragma unroll
     for (int q = 0; q < kWit; ++q) y[q] = ny[q];
   }
-  double v[4 * kWit];
+  // FP64 wave sums, one witness at a time (few registers live at once)
 #pragma unroll
   for (int q = 0; q < kWit; ++q) {
-    v[4 * q] = (double)A0[q];
-    v[4 * q + 1] = (double)B0[q];
-    v[4 * q + 2] = (double)A1[q];
-    v[4 * q + 3] = (double)B1[q];
-  }
+    double v[4] = {(double)A0[q], (double)B0[q], (double)A1[q], (double)B1[q]};
 #pragma unroll
-  for (int i = 0; i < 4 * kWit; ++i) {
+    for (int i = 0; i < 4; ++i) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
-  }
-  if (lane == 0) {
+      for (int off = 32; off >= 1; off >>= 1) v[i] += __shfl_xor(v[i], off);
+    }
+    if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < 4 * kWit; ++i) red[wave][i] = v[i];
+      for (int i = 0; i < 4; ++i) red[wave][4 * q + i] = v[i];
+    }
   }
   __syncthreads();
   if (threadIdx.x >= kWit) return;
