@@ -30,6 +30,8 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
   model, theta_tau = (I - B0) M_tau.
 * :func:`bootstrap_counts` -- order / edge counts over row resamples, each
   regressed along a given order.
+* :func:`total_effects` -- total causal effects (I - B)^-1 of a weighted
+  adjacency matrix (Section 4.2 ranks variables by them).
 
 The learned-proposal form of the search (features, the scoring network with
 its gradients and optimiser, the certified / margin / audit decisions) is in
@@ -271,6 +273,16 @@ def var_lagged_effects(M, B0) -> np.ndarray:
     d = B0.shape[0]
     A = np.eye(d) - B0
     return np.stack([A @ M[t] for t in range(M.shape[0])])
+
+
+def total_effects(B) -> np.ndarray:
+    """Total causal effects of the linear acyclic model x = B x + e (Section
+    2.1): x = (I - B)^-1 e, so T = (I - B)^-1 and T[i, j] is the effect on
+    x_i of a unit change of x_j along all directed paths (T[i, i] = 1).
+    Section 4.2 ranks the variables that exert and receive the largest total
+    effects."""
+    B = np.asarray(B, dtype=np.float64)
+    return np.linalg.inv(np.eye(B.shape[0]) - B)
 
 
 def bootstrap_counts(X, resamples, orders, threshold: float = 0.0):

@@ -434,6 +434,31 @@ def test_bootstrap_counts_invariants():
     assert np.array_equal(cs1, B)
 
 
+def test_total_effects_paths():
+    """T = (I - B)^-1 equals the sum over directed paths (the Neumann series
+    of the nilpotent B of a DAG), a chain multiplies its weights, and the
+    diagonal is 1."""
+    rng = np.random.default_rng(4)
+    d = 8
+    perm = rng.permutation(d)
+    B = np.zeros((d, d))
+    for k in range(1, d):
+        for q in range(k):
+            if rng.random() < 0.4:
+                B[perm[k], perm[q]] = rng.uniform(-1.5, 1.5)
+    T = oracle.total_effects(B)
+    S, P = np.eye(d), np.eye(d)
+    for _ in range(d):
+        P = P @ B
+        S += P
+    assert np.max(np.abs(T - S)) < 1e-12
+    assert np.allclose(np.diag(T), 1.0)
+    C = np.zeros((3, 3))
+    C[1, 0], C[2, 1] = 0.7, -2.0
+    Tc = oracle.total_effects(C)
+    assert abs(Tc[2, 0] - (-1.4)) < 1e-15 and Tc[0, 2] == 0.0
+
+
 def test_fp64_and_fp32_entries_agree():
     s = synth.er_sem(9, 800, indeg=2.0, seed=6)
     X32 = s.X.astype(np.float32)
