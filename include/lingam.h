@@ -290,6 +290,26 @@ int lingam_adjacency_pruned(const float* X, int64_t n_rows, int64_t ldx, const i
                             int64_t n, int64_t d, const int32_t* order, int32_t max_active,
                             double* B, void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes for lingam_total_effects (0 if unsupported). */
+size_t lingam_total_effects_workspace_size(int64_t d);
+
+/*
+ * Total causal effects of the linear acyclic model x = B x + e (Section 2.1;
+ * Section 4.2 ranks the variables by them): T = (I - B)^-1, T[i d + j] the
+ * effect on x_i of a unit change of x_j along all directed paths, T[i d + i] =
+ * 1.
+ *   B      device double[d * d]: an adjacency along `order` (as from
+ *          lingam_adjacency); entries not below the order's diagonal (x_j
+ *          after x_i) are ignored.
+ *   order  device int32[d], a permutation of 0 .. d-1.
+ *   T      device double[d * d], must not alias B.
+ * I - B is unit lower triangular in the order; its inverse is the blocked
+ * FP64 MFMA triangular inverse.  Synchronizes once (the order check); a
+ * non-permutation returns LINGAM_E_INVALID.
+ */
+int lingam_total_effects(const double* B, int64_t d, const int32_t* order, double* T, void* ws,
+                         size_t ws_bytes, void* stream);
+
 /*
  * Bootstrap statistics (resampling the rows, ordering and regressing each
  * resample): add one resample's result to running counts.

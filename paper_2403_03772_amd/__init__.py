@@ -21,6 +21,8 @@ Functions mirror the C entry points:
 * :func:`bootstrap`, :func:`bootstrap_accumulate` -- bootstrap order and
   edge probabilities (batched orderings of resamples, their adjacencies,
   ``lingam_bootstrap_accumulate``).
+* :func:`total_effects` -- ``lingam_total_effects`` ((I - B)^-1, the
+  total causal effects along all directed paths).
 * :func:`varlingam_lagged_effects` -- ``varlingam_lagged_effects``
   (theta_tau = (I - B0) M_tau).
 * :func:`batch_causal_order` -- ``lingam_batch_causal_order`` (many
@@ -52,6 +54,7 @@ from .lib import (  # noqa: F401
     proposer_scores,
     residualize,
     residualize_workspace_size,
+    total_effects,
     varlingam_fit,
     varlingam_lagged_effects,
     version,

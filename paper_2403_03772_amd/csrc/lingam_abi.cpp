@@ -1026,6 +1026,39 @@ int lingam_adjacency_pruned(const float* X, int64_t n_rows, int64_t ldx, const i
   return LINGAM_OK;
 }
 
+size_t lingam_total_effects_workspace_size(int64_t d) {
+  if (d < 1 || d > kMaxD) return 0;
+  return lg::make_effects_layout(d).total;
+}
+
+int lingam_total_effects(const double* B, int64_t d, const int32_t* order, double* T, void* ws,
+                         size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!B || !order || !T) return fail(LINGAM_E_INVALID, "B, order and T must be non-NULL");
+  if (d < 1) return fail(LINGAM_E_INVALID, "need d >= 1 (got %lld)", (long long)d);
+  if (d > kMaxD) return fail(LINGAM_E_UNSUPPORTED, "d <= %lld supported", (long long)kMaxD);
+  if (T == B) return fail(LINGAM_E_INVALID, "T must not alias B");
+  const lg::EffectsLayout A = lg::make_effects_layout(d);
+  if (!ws || ws_bytes < A.total)
+    return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", A.total,
+                ws ? ws_bytes : (size_t)0);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  lg::AdjLayout V{};  // the check's view of the status and mark regions
+  V.n = 2;
+  V.d = d;
+  V.ctrl = A.ctrl;
+  V.mark = A.mark;
+  int32_t s = 0;
+  LG_TRY(lg::launch_adj_check(V, w, order, nullptr, 0, st), "total effects check");
+  LG_TRY(hipMemcpyAsync(&s, w + A.ctrl, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+         "hipMemcpyAsync(status)");
+  LG_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s != 0) return fail(LINGAM_E_INVALID, "order is not a permutation of 0 .. d-1");
+  LG_TRY(lg::launch_total_effects(A, w, B, order, T, st), "total effects");
+  return LINGAM_OK;
+}
+
 int lingam_bootstrap_accumulate(const int32_t* order, const double* B, int64_t d,
                                 double threshold, int32_t* order_count, int32_t* edge_count,
                                 double* coef_sum, void* stream) {

@@ -27,6 +27,20 @@ struct PruneLayout {
 };
 
 PruneLayout make_prune_layout(int64_t n, int64_t d);
+
+// Workspace of lingam_total_effects.
+struct EffectsLayout {
+  int64_t d;
+  size_t ctrl;   // Ctrl (status only)
+  size_t mark;   // int32  [d]   permutation check
+  size_t a;      // double [d * d] I - B permuted into the order (unit lower)
+  size_t x;      // double [d * d] its inverse
+  size_t total;
+};
+EffectsLayout make_effects_layout(int64_t d);
+// T = (I - B)^-1 through the order (after the permutation check).
+hipError_t launch_total_effects(const EffectsLayout& A, char* ws, const double* B,
+                                const int32_t* order, double* T, hipStream_t st);
 // After the permutation / row check of launch_adj_check (run on an AdjLayout
 // view of the same ctrl and mark regions): B (d x d, row-major) = the pruned
 // adjacency.  Status kDegenerate on non-finite data or a correlation matrix

@@ -782,6 +782,29 @@ __global__ __launch_bounds__(256) void k_lars(const double* __restrict__ R,
   }
 }
 
+// A[a][b] = 1 (a == b), -B[o_a][o_b] (a > b), 0 (a < b): I - B in the causal
+// order, unit lower triangular (entries of B above that triangle ignored).
+__global__ void k_unit_lower(const double* __restrict__ B, const int32_t* __restrict__ order,
+                             int d, double* __restrict__ A) {
+  const int64_t total = (int64_t)d * d;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / d), b = (int)(e - (int64_t)a * d);
+    A[e] = a == b ? 1.0 : (a > b ? -B[(int64_t)order[a] * d + order[b]] : 0.0);
+  }
+}
+
+// T[o_a][o_b] = X[a][b] for a >= b, 0 otherwise (every entry written once).
+__global__ void k_scatter_lower(const double* __restrict__ X, const int32_t* __restrict__ order,
+                                int d, double* __restrict__ T) {
+  const int64_t total = (int64_t)d * d;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / d), b = (int)(e - (int64_t)a * d);
+    T[(int64_t)order[a] * d + order[b]] = a >= b ? X[e] : 0.0;
+  }
+}
+
 unsigned grid_for(int64_t n) {
   const int64_t g = (n + 255) / 256;
   return (unsigned)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
@@ -907,6 +930,36 @@ hipError_t launch_adjacency_pruned(const PruneLayout& A, char* ws, const float* 
   hipLaunchKernelGGL(k_lars, dim3((unsigned)(d - 1)), dim3(256), 0, st, (const double*)Rm,
                      (const double*)Lm, (const double*)Ym, (const double*)at<double>(ws, A.sd),
                      order, d, n, cap, at<double>(ws, A.st), B, ctrl);
+  return hipGetLastError();
+}
+
+EffectsLayout make_effects_layout(int64_t d) {
+  EffectsLayout A{};
+  A.d = d;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  A.ctrl = take(sizeof(Ctrl));
+  A.mark = take(sizeof(int32_t) * (size_t)d);
+  A.a = take(sizeof(double) * (size_t)d * (size_t)d);
+  A.x = take(sizeof(double) * (size_t)d * (size_t)d);
+  A.total = off;
+  return A;
+}
+
+hipError_t launch_total_effects(const EffectsLayout& A, char* ws, const double* B,
+                                const int32_t* order, double* T, hipStream_t st) {
+  const int d = (int)A.d;
+  const int64_t dd = (int64_t)d * d;
+  double* Am = at<double>(ws, A.a);
+  double* Xm = at<double>(ws, A.x);
+  hipLaunchKernelGGL(k_unit_lower, dim3(grid_for(dd)), dim3(256), 0, st, B, order, d, Am);
+  LG_HIP(launch_tri_inverse(Am, d, d, Xm, d, st));
+  hipLaunchKernelGGL(k_scatter_lower, dim3(grid_for(dd)), dim3(256), 0, st, (const double*)Xm,
+                     order, d, T);
   return hipGetLastError();
 }
 

@@ -197,6 +197,10 @@ def load():
         lib.lingam_bootstrap_accumulate.argtypes = [P, P, i64, ctypes.c_double, P, P, P, P]
         lib.lingam_bootstrap_accumulate.restype = ctypes.c_int
         lib.lingam_adjacency.restype = ctypes.c_int
+        lib.lingam_total_effects_workspace_size.argtypes = [i64]
+        lib.lingam_total_effects_workspace_size.restype = sz
+        lib.lingam_total_effects.argtypes = [P, i64, P, P, P, sz, P]
+        lib.lingam_total_effects.restype = ctypes.c_int
         lib.varlingam_lagged_effects.argtypes = [P, P, i64, i32, P, P]
         lib.varlingam_lagged_effects.restype = ctypes.c_int
         lib.lingam_last_error.argtypes = []
@@ -434,6 +438,34 @@ def adjacency_pruned(X, order, *, rows=None, max_active: int = 64, workspace=Non
                                        _stream_ptr(torch, X.device))
     _check(code)
     return B
+
+
+def total_effects(B, order, *, workspace=None):
+    """Total causal effects T = (I - B)^-1 of a CUDA float64 adjacency ``B``
+    (d x d) along ``order`` (``lingam_total_effects``): T[i, j] is the effect
+    on x_i of a unit change of x_j over all directed paths.  Entries of ``B``
+    not below the order's diagonal are ignored.  Returns d x d float64."""
+    import torch
+
+    lib = load()
+    if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64
+            and B.dim() == 2 and B.shape[0] == B.shape[1]):
+        raise ValueError("B must be a square CUDA float64 tensor")
+    B = B.contiguous()
+    d = B.shape[0]
+    o = torch.as_tensor(order, dtype=torch.int32).to(B.device).contiguous()
+    if o.numel() != d:
+        raise ValueError(f"order has {o.numel()} entries, B is {d} x {d}")
+    need = int(lib.lingam_total_effects_workspace_size(d))
+    if need == 0:
+        raise LingamError(E_UNSUPPORTED, f"unsupported size d={d}")
+    ws = workspace
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=B.device)
+    T = torch.empty((d, d), dtype=torch.float64, device=B.device)
+    _check(lib.lingam_total_effects(_ptr(B), d, _ptr(o), _ptr(T), _ptr(ws), ws.numel(),
+                                    _stream_ptr(torch, B.device)))
+    return T
 
 
 def bootstrap_accumulate(order, B, threshold, order_count, edge_count, coef_sum=None):

@@ -163,6 +163,18 @@ def test_adjacency_argument_errors():
     assert lib.lingam_adjacency_workspace_size(10, 0) == 0
     # n = 100, d = 8: covariance, factor and inverse columns dominate
     assert lib.lingam_adjacency_workspace_size(100, 8) >= 8 * (9 * 128 + 2 * 64)
+    t = lambda **k: lib.lingam_total_effects(
+        v if k.get("B", 1) else None, k.get("d", 3), v if k.get("order", 1) else None,
+        ctypes.c_void_p(k.get("T", 2)), v, k.get("ws", 1 << 30), None)
+    assert t(B=0) == L.E_INVALID
+    assert t(order=0) == L.E_INVALID
+    assert t(T=0) == L.E_INVALID
+    assert t(T=1) == L.E_INVALID       # aliases B
+    assert t(d=0) == L.E_INVALID
+    assert t(d=1 << 20) == L.E_UNSUPPORTED
+    assert t(ws=16) == L.E_WORKSPACE
+    assert lib.lingam_total_effects_workspace_size(0) == 0
+    assert lib.lingam_total_effects_workspace_size(100) >= 2 * 100 * 100 * 8
     e = lambda **k: lib.varlingam_lagged_effects(
         v if k.get("M", 1) else None, v if k.get("B0", 1) else None, k.get("d", 3),
         k.get("lags", 1), ctypes.c_void_p(k.get("theta", 2)), None)

@@ -231,3 +231,64 @@ def test_adjacency_pruned_workload_sampled_rows(lib):
         y = s.order[p_]
         assert np.array_equal(B[y] != 0, ref[y] != 0), p_
         assert np.max(np.abs(B[y] - ref[y])) <= _tol(ref[y]), p_
+
+
+def _total_gpu(lib, B, order):
+    import torch
+    return lib.total_effects(torch.as_tensor(B).cuda(),
+                             np.asarray(order, dtype=np.int32)).cpu().numpy()
+
+
+@pytest.mark.parametrize("d,seed", [(1, 0), (2, 1), (31, 2), (33, 3), (100, 4), (257, 5)])
+def test_total_effects_matches_oracle(lib, d, seed):
+    """(I - B)^-1 along a random order: a dense B with N(0, 1/d) weights below
+    the order's diagonal (several 32-wide blocks and a ragged tail), and the
+    same B with unrelated values above that diagonal, which must be ignored
+    bit for bit.  Condition numbers stay below 10, so the blocked inverse and
+    numpy's differ by rounding only (bound 1e-10)."""
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(d)
+    pos = np.empty(d, dtype=np.int64)
+    pos[order] = np.arange(d)
+    below = pos[:, None] > pos[None, :]
+    B = np.where(below, rng.standard_normal((d, d)) / np.sqrt(d), 0.0)
+    print(f"case total effects d={d} seed={seed}", flush=True)
+    T = _total_gpu(lib, B, order)
+    ref = oracle.total_effects(B)
+    assert np.max(np.abs(T - ref)) <= 1e-10 * max(1.0, float(np.max(np.abs(ref))))
+    assert np.all(np.diag(T) == 1.0)
+    assert np.all(T[~below & ~np.eye(d, dtype=bool)] == 0.0)
+    noisy = np.where(below, B, rng.standard_normal((d, d)))
+    assert np.array_equal(_total_gpu(lib, noisy, order), T)
+
+
+def test_total_effects_of_sem_adjacency(lib):
+    """On the adjacency estimated along a SEM's true order (d = 1024, n = 8192,
+    the ordering workload): T against the oracle, and T - B T = I."""
+    import torch
+    s = synth.workload_gene_scale(seed=0)
+    X = torch.as_tensor(np.ascontiguousarray(s.X, dtype=np.float32)).cuda()
+    d = X.shape[1]
+    print(f"case total effects of adjacency d={d}", flush=True)
+    Bt = lib.adjacency(X, np.asarray(s.order, dtype=np.int32))
+    T = lib.total_effects(Bt, s.order).cpu().numpy()
+    B = Bt.cpu().numpy()
+    ref = oracle.total_effects(B)
+    scale = max(1.0, float(np.max(np.abs(ref))))
+    assert np.max(np.abs(T - ref)) <= 1e-10 * scale
+    assert np.max(np.abs(T - B @ T - np.eye(d))) <= 1e-10 * scale
+
+
+def test_total_effects_errors(lib):
+    import torch
+    B = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.LingamError):
+        lib.total_effects(B, np.array([0, 1, 1, 3], dtype=np.int32))
+    with pytest.raises(lib.LingamError):
+        lib.total_effects(B, np.array([0, 1, 2, 4], dtype=np.int32))
+    with pytest.raises(ValueError):
+        lib.total_effects(B[:, :3], np.arange(4))
+    with pytest.raises(ValueError):
+        lib.total_effects(B.float(), np.arange(4))
+    T = lib.total_effects(B, np.arange(4))           # the call after an error still works
+    assert torch.equal(T.cpu(), torch.eye(4, dtype=torch.float64))
