@@ -285,6 +285,7 @@ class StepInfo:
     margin: float = float("nan")
     candidates: np.ndarray = None
     suspects: int = 0
+    rows: int = 0        # suspects whose full rows were measured (after the extension)
 
 
 def _plain_choice(k, U):
@@ -337,9 +338,26 @@ def lower_bounds(D, C, wit=None) -> np.ndarray:
     return lb
 
 
+def extension_bounds(D, lb, S, E, wit=None) -> np.ndarray:
+    """The suspects' bounds after the extension columns: for every suspect l
+    in S, add min(0, R(l, j))^2 for each extension column j in E (variables
+    ranked right after the candidates) that is not l itself and not one of
+    l's witnesses (already counted).  E holds no candidate, so every column
+    still enters a bound at most once and the bound stays <= k_l.  Returns a
+    new array; D[a, b] = R(U[a], U[b])."""
+    D = np.asarray(D, dtype=np.float64)
+    out = np.array(lb, dtype=np.float64, copy=True)
+    for l in np.asarray(S, dtype=np.int64):
+        seen = set() if wit is None else {int(w) for w in wit[l] if w >= 0}
+        for j in np.asarray(E, dtype=np.int64):
+            if j != l and int(j) not in seen:
+                out[l] += min(0.0, D[l, j]) ** 2
+    return out
+
+
 def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: int = 32,
                   min_m: int | None = None, emulate_bf16: bool = True,
-                  max_suspects: int = 1024, n_witness: int = 8):
+                  max_suspects: int = 1024, n_witness: int = 8, n_ext: int = 128):
     """Causal order by the learned-proposal form.
 
     X: n x d samples (cast to FP32 first, like the library's input).
@@ -350,8 +368,11 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
     Steps with m <= min_m (default 2 min(K, 64)) are plain steps.  K is the
     most candidates; a step with m variables takes step_topk(m, K).  The
     lower bound on the non-candidates' k adds ``n_witness`` witness columns
-    per variable (:func:`witnesses`, :func:`lower_bounds`).
-    Returns (order, [StepInfo]).
+    per variable (:func:`witnesses`, :func:`lower_bounds`).  Before the
+    second pass the suspects' bounds also take the ``n_ext`` variables ranked
+    right after the candidates (:func:`extension_bounds`); only suspects whose
+    bound still does not exceed the best candidate's k have their rows
+    measured.  Returns (order, [StepInfo]).
     """
     X = np.asarray(np.asarray(X, dtype=np.float32), dtype=np.float64).copy()
     n, d = X.shape
@@ -377,7 +398,8 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             if emulate_bf16:
                 s = s.astype(np.float32).astype(np.float64)
             Kt = step_topk(m, K)
-            C = topk(s, U, Kt)
+            ranked = topk(s, U, min(m, Kt + n_ext))
+            C, E = ranked[:Kt], ranked[Kt:]
             inC = np.zeros(m, dtype=bool)
             inC[C] = True
             best = C[0]
@@ -394,14 +416,21 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             audit = audit_every > 0 and t % audit_every == 0
             expand = (not audit) and (not certified) and \
                 sus.size <= suspect_cap(m, Kt, max_suspects)
+            rows = 0
+            if expand:
+                # extension columns first; the rest of the suspects' rows
+                # only where the bound still allows them to win
+                lb2 = extension_bounds(D, lb, sus, E, wit)
+                rest = sus[~(lb2[sus] > k[best])]
+                rows = int(rest.size)
             if audit:
                 p, kind = pc, "audit"
             elif certified:
                 p, kind = best, "learned"
             elif expand:
-                # exact k of the suspects; the best of candidates and suspects
+                # exact k of the remaining suspects; the best of candidates and them
                 p = best
-                for c in sus:
+                for c in rest:
                     if k[c] < k[p] or (k[c] == k[p] and U[c] < U[p]):
                         p = c
                 kind = "expanded"
@@ -410,7 +439,7 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             else:
                 p, kind = pc, "fallback"
             info.append(StepInfo(t, kind, U[p], U[pc], U[best], certified, float(margin), C,
-                                 int(sus.size)))
+                                 int(sus.size), rows))
         e = U[p]
         order.append(e)
         xe = X[:, e]

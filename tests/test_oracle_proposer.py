@@ -175,6 +175,41 @@ def test_lower_bounds_are_bounds():
         assert list(wit[p]) == top
 
 
+def test_extension_bounds_pins():
+    """The extension columns keep the bound a bound: it never exceeds k; with
+    candidates, witnesses and extension covering every column it is k itself
+    (a witness inside the extension is counted once, not twice); only the
+    listed suspects change; and a hand-made 4 x 4 case gives the sum of the
+    negative squares of the added, non-witness columns."""
+    s = synth.er_sem(16, 1500, indeg=2.5, noise_family=("uniform", "laplace"), seed=12)
+    U = list(range(16))
+    X = s.X.astype(np.float32).astype(np.float64)
+    D = oracle.pair_matrix(X, U)
+    k = np.sum(np.minimum(D, 0.0) ** 2, axis=1)
+    C = np.array([1, 5, 9])
+    notc = np.setdiff1d(np.arange(16), C)
+    wit = P.witnesses(X, U, 3)
+    lb = P.lower_bounds(D, C, wit)
+    S = notc[::2]
+    E = notc[:6]
+    lb2 = P.extension_bounds(D, lb, S, E, wit)
+    assert np.all(lb2[notc] <= k[notc] * (1 + 1e-12))
+    assert np.all(lb2[S] >= lb[S]) and np.array_equal(np.delete(lb2, S), np.delete(lb, S))
+    full = P.extension_bounds(D, lb, notc, notc, wit)     # every column covered
+    assert np.max(np.abs(full[notc] - k[notc])) <= 1e-12 * np.max(k)
+    # hand case: R antisymmetric, candidate {0}, suspect 2 with witness 3
+    R = np.array([[0.0, 0.5, 0.2, 0.1],
+                  [-0.5, 0.0, 0.3, -0.4],
+                  [-0.2, -0.3, 0.0, -0.7],
+                  [-0.1, 0.4, 0.7, 0.0]])
+    w = np.array([[-1], [-1], [3], [-1]])
+    lb_h = P.lower_bounds(R, np.array([0]), w)
+    assert abs(lb_h[2] - (0.2 ** 2 + 0.7 ** 2)) < 1e-15   # max(0, R(0,2))^2 + min(0, R(2,3))^2
+    got = P.extension_bounds(R, lb_h, [2], [1, 2, 3], w)
+    assert abs(got[2] - (lb_h[2] + 0.3 ** 2)) < 1e-15      # only column 1 is new
+    assert got[1] == lb_h[1] and got[3] == lb_h[3]
+
+
 def test_adam_first_step_and_convergence():
     rng = np.random.default_rng(3)
     x = rng.normal(size=50)
@@ -270,6 +305,15 @@ def test_learned_order_reduces_to_plain(seed):
                                 max_suspects=0)
     assert np.array_equal(o4, plain)
     assert not any(i.kind == "expanded" for i in info4)
+    # the extension columns only shrink the rows measured, never the order
+    o5, info5 = P.learned_order(s.X, prop, K=3, delta=np.inf, audit_every=0, min_m=3,
+                                n_ext=0)
+    assert np.array_equal(o5, plain)
+    ex1 = [i for i in info1 if i.kind == "expanded"]
+    ex5 = [i for i in info5 if i.kind == "expanded"]
+    assert [i.suspects for i in ex1] == [i.suspects for i in ex5]
+    assert all(i.rows == i.suspects for i in ex5)
+    assert all(i.rows <= i.suspects for i in ex1)
 
 
 def test_kendall_tau_matches_scipy():
