@@ -208,13 +208,16 @@ def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None):
         "topk": cfg.topk, "audit_every": cfg.audit_every,
         "margin": cfg.margin if np.isfinite(cfg.margin) else str(cfg.margin),
         "max_suspects": cfg.max_suspects,
+        "extension": cfg.extension,
         "stats": {"learned_steps": st.learned_steps, "certified": st.certified,
                   "expanded": st.expanded, "fallbacks": st.fallbacks, "audits": st.audits,
                   "audit_agree": st.audit_agree,
-                  "suspects_mean": st.suspects_sum / max(st.learned_steps, 1)},
+                  "suspects_mean": st.suspects_sum / max(st.learned_steps, 1),
+                  "cleared": st.cleared,
+                  "rows_mean": st.rows_sum / max(st.learned_steps, 1)},
         "evals_done": done,
         "evals_done_per_s": done / dt,
-        "cand_kernel": {"bound": "alu", "kernel": "k_pair_cand + k_pair_susp",
+        "cand_kernel": {"bound": "alu", "kernel": "k_pair_cand + k_pair_ext + k_pair_susp",
                         "achieved": cand_evals / (cand_ms * 1e-3) / 1e9 if cand_ms else None,
                         "peak": PEAK_EVALS / 1e9, "unit": "Geval/s",
                         "frac": cand_evals / (cand_ms * 1e-3) / PEAK_EVALS if cand_ms else None,

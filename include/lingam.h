@@ -35,9 +35,12 @@
  * variables ("witnesses": sum of min(0, R(l, w))^2), each column counted
  * once; the "suspects" are the variables whose bound does not exceed the best
  * candidate's k.  (a) No suspect: the best candidate is the plain search's
- * choice (certified).  (b) At most min(max_suspects, m/2 - topk) suspects: their rows
- * are evaluated exactly in a second pass and the best of candidates and
- * suspects is the plain choice.  (c) More: the best candidate is taken when
+ * choice (certified).  (b) At most min(max_suspects, m/2 - topk) suspects:
+ * the second pass first measures them against the `extension` variables
+ * ranked right after the candidates (columns not yet counted), which raises
+ * their bounds; the rows of those still at or below the best candidate's k
+ * are then evaluated exactly, and the best of candidates and these suspects
+ * is the plain choice.  (c) More: the best candidate is taken when
  * its score leads every non-candidate's by at least `margin`.  Otherwise, and
  * at every audit step (t % audit_every == 0, a check of the margin rule), the
  * full step of the exact search decides.  With margin = +inf the order is the plain order.  This proposal layer is not part of the paper's method; it
@@ -83,9 +86,12 @@ typedef struct lingam_profile {
   double gram_flops;      /* algorithmic flops of that Gram: 2 * n * d * d */
   double resid_ms;        /* summed duration of the residualize kernels */
   double resid_bytes;     /* algorithmic HBM bytes of those: 28 * n * (m - 1) per step */
-  double cand_ms;         /* learned form: summed duration of the candidate-row kernel */
+  double cand_ms;         /* learned form: summed duration of the candidate, extension
+                             and suspect-row pair kernels */
   int64_t cand_launches;  /* ... its launches */
-  double cand_evals;      /* ... its sample-pair evaluations: 2 K (m - 1) n per step */
+  double cand_evals;      /* ... its sample-pair evaluations (with the extension and
+                             suspect-row passes): 2 K (m - 1) n per step, plus
+                             2 n (suspects * extension + measured rows * (m - 1)) */
 } lingam_profile;
 
 /* Decisions of the learned form, summed over the jobs of a call (host). */
@@ -98,8 +104,9 @@ typedef struct lingam_learned_stats {
   int32_t suspects_max;   /* most non-candidates in one step whose lower bound did not
                              exceed the best candidate's k (0 = certified) */
   int64_t suspects_sum;   /* ... summed over learned steps */
-  int32_t expanded;       /* steps decided exactly by evaluating the suspects' rows */
-  int32_t reserved;
+  int32_t expanded;       /* steps decided exactly by the second pass */
+  int32_t cleared;        /* ... of which the extension columns cleared every suspect */
+  int64_t rows_sum;       /* suspects whose full rows the second pass measured */
 } lingam_learned_stats;
 
 /* The proposer network.  A proposer block is LINGAM_PROPOSER_SIZE FP32 values
@@ -145,11 +152,17 @@ typedef struct lingam_opts {
                                    column id (training data); unwritten entries untouched */
   int32_t max_suspects;         /* most suspects the second pass evaluates (0 = no second
                                    pass); default 1024 */
-  int32_t reserved1;
+  int32_t extension;            /* extension columns: the suspects are first measured
+                                   against the variables ranked right after the
+                                   candidates (this many; a multiple of 8 in [0, 256]),
+                                   and only those whose bound still allows them to win
+                                   have their full rows measured; 0 = none; default 128 */
   int32_t* step_log;            /* device int32[d] or NULL (learned form): per step, the low
                                    4 bits are 0 plain step, 1 learned choice, 2 full step
                                    (fallback or forcing), 3 audit, 4 decided by the suspect
-                                   pass; the bits above hold the step's suspect count */
+                                   pass; bits 4..15 hold the step's suspect count and the
+                                   bits from 16 up the suspects whose rows the second
+                                   pass measured */
 } lingam_opts;
 
 /* Fill *opts with defaults (no forcing, no extra outputs, plain search, synchronous). */

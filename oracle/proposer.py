@@ -286,6 +286,7 @@ class StepInfo:
     candidates: np.ndarray = None
     suspects: int = 0
     rows: int = 0        # suspects whose full rows were measured (after the extension)
+    extension: np.ndarray = None  # extension positions (ranked after the candidates)
 
 
 def _plain_choice(k, U):
@@ -439,7 +440,7 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             else:
                 p, kind = pc, "fallback"
             info.append(StepInfo(t, kind, U[p], U[pc], U[best], certified, float(margin), C,
-                                 int(sus.size), rows))
+                                 int(sus.size), rows, E))
         e = U[p]
         order.append(e)
         xe = X[:, e]

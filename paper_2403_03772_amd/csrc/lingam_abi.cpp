@@ -160,7 +160,7 @@ struct HostJob {
 // Learned-form configuration of a call (proposer == NULL: plain search).
 struct Learn {
   const float* proposer = nullptr;
-  int32_t K = 0, min_m = 0, audit_every = 0, max_suspects = 0;
+  int32_t K = 0, min_m = 0, audit_every = 0, max_suspects = 0, extension = 0;
   float delta = 0.f;
 };
 
@@ -173,6 +173,7 @@ Learn learn_of(const lingam_opts* o) {
   l.audit_every = o->audit_every;
   l.delta = o->margin;
   l.max_suspects = o->max_suspects;
+  l.extension = o->extension;
   return l;
 }
 
@@ -261,6 +262,8 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
       J.kc = reinterpret_cast<double*>(b + L.kc);
       J.lb = reinterpret_cast<double*>(b + L.lb);
       J.wit = reinterpret_cast<int32_t*>(b + L.wit);
+      J.ext = reinterpret_cast<int32_t*>(b + L.ext);
+      J.ne_max = P.lc.extension;
       J.steplog = h.step_log ? h.step_log : reinterpret_cast<int32_t*>(b + L.steplog);
       J.cap_s = std::min<int32_t>(L.cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars);
       J.cand2 = reinterpret_cast<int32_t*>(b + L.cand2);
@@ -303,7 +306,9 @@ StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, l
           m, b.k,
           std::min<int32_t>(P.L[k].cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars));
       b.nct2 = lg::cdiv(b.nsus, lg::kTileVars) * b.nblk;
-      for (int kind = lg::kKPairS; kind <= lg::kKLsel2; ++kind)
+      b.ne = lg::ext_count(m, b.k, P.lc.extension);
+      b.nct3 = b.ne > 0 ? lg::cdiv(b.nsus, lg::kTileVars) * lg::cdiv(b.ne, lg::kTileVars) : 0;
+      for (int kind = lg::kKPairE; kind <= lg::kKLsel2; ++kind)
         T.g[kind] += lg::kind_count(b, kind);
     }
     if (m > 2) T.resid_bytes += 28.0 * (double)jobs[k].n * (double)(m - 1);
@@ -375,7 +380,19 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     };
     if (gated) {
       LG_TRY(lg::launch_learned_back(table, P.njobs, t, sc, T.g, st), "learned decision");
-      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, st), "suspect schedule");
+      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 0, st), "extension schedule");
+      if (T.g[lg::kKPairE] > 0) {
+        if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
+        LG_TRY(lg::launch_pair_ext(table, P.njobs, sc,
+                                   std::min<int32_t>(T.g[lg::kKPairE], P.cu * 8), st),
+               "pair ext");
+        if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
+        LG_TRY(lg::launch_ext_back(table, P.njobs, t, sc,
+                                   std::min<int32_t>(T.g[lg::kKBoundE], P.cu * 4),
+                                   std::min<int32_t>(T.g[lg::kKCompE], P.njobs), st),
+               "extension bounds");
+      }
+      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 1, st), "suspect schedule");
       if (T.g[lg::kKPairS] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_susp(table, P.njobs, sc,
@@ -562,6 +579,8 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
       ls->suspects_max = std::max(ls->suspects_max, c.n_suspects_max);
       ls->suspects_sum += c.n_suspects_sum;
       ls->expanded += c.n_expanded;
+      ls->cleared += c.n_cleared;
+      ls->rows_sum += c.n_rows_sum;
     }
   }
   if (pf.tm.on && opts->profile) {
@@ -582,15 +601,22 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
     pr->cand_launches = (int64_t)(pf.cand_ev.size() / 2);
     pr->cand_evals = pf.cand_evals;
     // steps a learned decision took did not run the all-pairs kernel; steps
-    // decided by the second pass evaluated their suspects' rows
+    // decided by the second pass measured their suspects against the
+    // extension columns, then the remaining suspects' rows
     for (int k = 0; k < (int)logs.size(); ++k) {
       const int64_t d = P.L[k].d, n = P.L[k].n;
       for (int64_t t = 0; t + 1 < d; ++t) {
         const int64_t m = d - t;
-        const int32_t kind = logs[k][(size_t)t] & 15, nsus = logs[k][(size_t)t] >> 4;
+        const int32_t e = logs[k][(size_t)t];
+        const int32_t kind = e & 15, nsus = (e >> 4) & 0xFFF, rows = e >> 16;
         if ((kind == 1 || kind == 4) && m > lg::kFp64MaxM)
           pr->pair_evals -= (double)m * (double)(m - 1) * (double)n;
-        if (kind == 4) pr->cand_evals += 2.0 * nsus * (double)(m - 1) * (double)n;
+        if (kind == 4) {
+          const int32_t ne =
+              lg::ext_count((int32_t)m, lg::step_topk((int32_t)m, P.lc.K), P.lc.extension);
+          pr->cand_evals += 2.0 * nsus * (double)ne * (double)n;
+          pr->cand_evals += 2.0 * rows * (double)(m - 1) * (double)n;
+        }
       }
     }
   }
@@ -706,6 +732,9 @@ int check_learn(const lingam_opts* opts) {
   if (opts->margin != opts->margin) return fail(LINGAM_E_INVALID, "margin is NaN");
   if (opts->max_suspects < 0)
     return fail(LINGAM_E_INVALID, "max_suspects %d < 0", opts->max_suspects);
+  if (opts->extension < 0 || opts->extension > lg::kMaxExt || opts->extension % 8 != 0)
+    return fail(LINGAM_E_INVALID, "extension %d must be a multiple of 8 in [0, %d]",
+                opts->extension, lg::kMaxExt);
   return LINGAM_OK;
 }
 
@@ -757,6 +786,7 @@ void lingam_opts_init(lingam_opts* o) {
   o->margin = INFINITY;
   o->learned_min_m = 128;
   o->max_suspects = lg::kMaxSuspects;
+  o->extension = 128;
 }
 
 const char* lingam_last_error(void) { return g_err; }

@@ -256,7 +256,9 @@ __device__ __forceinline__ void for_blocks(const int32_t* __restrict__ pre, int 
 // workgroup p takes items p * chunk .. p * chunk + chunk - 1, chunk =
 // ceil(total / G), so a gated-off step costs a few thousand empty workgroups
 // instead of the bound.
-enum PairMode : int { kModeAll = 0, kModeCand = 1, kModeSusp = 2 };
+// Extension mode: the suspect rows against the extension columns only
+// (ceil(nsus / 8) x ceil(ne / 8) tiles whose j side lists positions too).
+enum PairMode : int { kModeAll = 0, kModeCand = 1, kModeSusp = 2, kModeExt = 3 };
 
 template <int kMode>
 __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int local,
@@ -294,15 +296,19 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   constexpr bool kCand = kMode != kModeAll;
   const int m = S.m;
   const int nsplit = kCand ? S.nsplit_c : S.nsplit;
-  const int ntiles = kMode == kModeAll ? S.ntiles : (kMode == kModeCand ? S.nct : S.nct2);
+  const int ntiles = kMode == kModeAll    ? S.ntiles
+                     : kMode == kModeCand ? S.nct
+                     : kMode == kModeSusp ? S.nct2
+                                          : S.nct3;
   const int split_len = kCand ? S.split_len_c : S.split_len;
   const int per_tile = 2 * nsplit;
   const int tile = local / per_tile, rem = local - tile * per_tile;
   const int dir = rem / nsplit, split = rem - dir * nsplit;
   int bi, bj;
   if (kCand) {
-    bi = tile / S.nblk;
-    bj = tile - bi * S.nblk;
+    const int ncol = kMode == kModeExt ? cdiv(S.ne, kTileVars) : S.nblk;
+    bi = tile / ncol;
+    bj = tile - bi * ncol;
   } else {
     decode_tile_st(tile, S.nblk, bi, bj);
   }
@@ -315,6 +321,7 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   const int32_t* list = kMode == kModeCand ? J.cand : J.cand2;
   const int64_t ldz = J.ldz, ldr = J.d;
   auto ipos = [&](int a) { return kCand ? list[i0 + a] : i0 + a; };
+  auto jpos = [&](int a) { return kMode == kModeExt ? J.ext[pj0 + a] : pj0 + a; };
 
   // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
   // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
@@ -322,7 +329,7 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   float my_r = 0.f, my_c1h = 0.f, my_c1l = 0.f;
   {
     const int q = lane & 15, a = q >> 2, c = q & 3;
-    const int pi = ipos(dir == 0 ? a : c), pj = pj0 + (dir == 0 ? c : a);
+    const int pi = ipos(dir == 0 ? a : c), pj = jpos(dir == 0 ? c : a);
     const bool valid = kCand ? (pi < m && pj < m && pi != pj) : (pi < m && pj < m && pi < pj);
     if (valid) {
       double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
@@ -348,7 +355,7 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   gchar_t* zx[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int pi = ipos(a), pj = pj0 + a;
+    const int pi = ipos(a), pj = jpos(a);
     const int pr = dir == 0 ? pi : pj, px = dir == 0 ? pj : pi;
     // the row ids are wave-uniform: keep them (and the row bases) in SGPRs
     const int sr = __builtin_amdgcn_readfirstlane(pr < m ? act[pr] : J.d);

@@ -43,6 +43,9 @@ constexpr int kMaxSuspects = 1024;
 // Witnesses per variable: the most correlated other active variables, whose
 // pair measures join the candidates' in a learned step's lower bound on k.
 constexpr int kWit = 8;
+// Most extension columns: the variables ranked right after the candidates,
+// measured against the suspects before their full rows are.
+constexpr int kMaxExt = 256;
 // offsets of the trainable parameters inside the flat FP32 block
 constexpr int kOffW1 = 0;
 constexpr int kOffB1 = kOffW1 + kHidden * kFeat;
@@ -81,7 +84,9 @@ struct Ctrl {
   long long n_suspects_sum;
   int32_t nsus;            // this step: suspects listed for the second pass (0: none)
   int32_t n_expanded;      // learned steps decided exactly by the second pass
-  int32_t pad[48];
+  int32_t n_cleared;       // ... of which every suspect was cleared by the extension columns
+  long long n_rows_sum;    // suspects whose full rows the second pass measured
+  int32_t pad[44];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 
@@ -111,6 +116,7 @@ struct Layout {
   size_t kc;     // double [K]      exact k of every candidate
   size_t lb;     // double [d]      lower bound of k at excluded positions
   size_t wit;    // int32  [d * kWit] witness positions of every position (-1: none)
+  size_t ext;    // int32  [kMaxExt] extension positions (ascending; padding = m)
   size_t steplog;  // int32 [d]     per step: 0 plain, 1 learned, 2 fallback, 3 audit
   // second candidate pass over the suspects
   int32_t cap_s;   // most suspects listed (kMaxSuspects or less, multiple of 8)
@@ -161,6 +167,8 @@ struct JobDev {
   double* kc;
   double* lb;
   int32_t* wit;
+  int32_t* ext;
+  int32_t ne_max;        // extension columns per learned step (0: none)
   int32_t* steplog;
   int32_t cap_s;
   int32_t* cand2;
@@ -193,6 +201,8 @@ struct JobStep {
   int32_t nsus;       // suspects of the second pass (set after the learned decision)
   int32_t nct2;       // suspect tiles ceil(nsus / 8) * nblk
   int32_t k;          // candidates of this step's learned pass
+  int32_t ne;         // extension columns (set with the suspect plan)
+  int32_t nct3;       // extension tiles ceil(nsus / 8) * ceil(ne / 8)
 };
 
 // Candidates of a learned step with m active variables and at most K: about
@@ -221,6 +231,9 @@ enum Kind : int {
   kKColC,       // k_cand_k columns: ceil(m / 64)
   kKLsel,       // k_lselect: 1
   kKWit,        // k_pair_wit: m
+  kKPairE,      // k_pair_ext: nct3 * 2 * nsplit_c (after the learned decision)
+  kKBoundE,     // k_ext_bound: ceil(nsus / 4) when nct3 > 0
+  kKCompE,      // k_ext_compact: 1 when nct3 > 0
   kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c (after the learned decision)
   kKCombS,      // k_combine_susp: ceil(nct2 / 4)
   kKRowkS,      // k_susp_rowk: ceil(nsus / 4)
@@ -320,6 +333,13 @@ __host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t ite
   s.nsplit = (int32_t)((iters + per - 1) / per);
 }
 
+// Extension columns of a learned step: the next ne_max ranks after the K
+// candidates, as many as there are.
+__host__ __device__ inline int32_t ext_count(int32_t m, int32_t K, int32_t ne_max) {
+  const int32_t r = m - K;
+  return r < ne_max ? (r > 0 ? r : 0) : ne_max;
+}
+
 // Most suspects a job with m active variables and K candidates lists: the
 // second pass must cost less than the full step (2 (K + S) < m rows), and at
 // most cap_s (the layout's room); a multiple of 8.
@@ -359,6 +379,9 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
     case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
     case kKWit: return s.learned ? s.m : 0;
+    case kKPairE: return s.nct3 * 2 * s.nsplit_c;
+    case kKBoundE: return s.nct3 > 0 ? cdiv(s.nsus, 4) : 0;
+    case kKCompE: return s.nct3 > 0 ? 1 : 0;
     case kKPairS: return s.nct2 * 2 * s.nsplit_c;
     case kKCombS: return cdiv(s.nct2, 4);
     case kKRowkS: return cdiv(s.nsus, 4);
@@ -434,7 +457,11 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
                                const int32_t* grid, hipStream_t st);
 // The second (suspect) pass: its schedule, its pair kernel (a bounded grid that
 // walks the items), and combine / row k / exact decision (grid-stride).
-hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st);
+hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, int stage,
+                                hipStream_t st);
+hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
+hipError_t launch_ext_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_bound,
+                           int g_comp, hipStream_t st);
 hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid,
                             hipStream_t st);
 hipError_t launch_susp_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_comb,

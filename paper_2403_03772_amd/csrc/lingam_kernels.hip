@@ -987,6 +987,7 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
     L.kc = take(sizeof(double) * (size_t)K);
     L.lb = take(sizeof(double) * (size_t)d);
     L.wit = take(sizeof(int32_t) * (size_t)d * kWit);
+    L.ext = take(sizeof(int32_t) * kMaxExt);
     L.steplog = take(sizeof(int32_t) * (size_t)d);
     int64_t cap = d / 2 - K;
     cap = cap < kMaxSuspects ? cap : kMaxSuspects;

@@ -478,13 +478,16 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
     return ((unsigned long long)ord_f32(J.score[p]) << 32) |
            (unsigned long long)(0xFFFFFFFFu - (uint32_t)J.act[p]);
   };
-  if (tid == 0) {
-    s_prefix = 0ull;
-    s_need = K;
-    s_done = 0;
-  }
-  unsigned long long prefix = 0ull, mask = 0ull;
-  for (int pass = 0; pass < 8; ++pass) {
+  // the need-th largest key: 8-bit radix passes from the top byte down
+  auto select = [&](int need0) -> unsigned long long {
+    __syncthreads();  // a previous select's readers are done with the shared state
+    if (tid == 0) {
+      s_prefix = 0ull;
+      s_need = need0;
+      s_done = 0;
+    }
+    unsigned long long prefix = 0ull, mask = 0ull;
+    for (int pass = 0; pass < 8; ++pass) {
     const int shift = 56 - 8 * pass;
     if (tid < 256) hist[tid] = 0u;
     __syncthreads();
@@ -532,7 +535,10 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
     prefix = s_prefix;
     mask |= 0xFFull << shift;
     if (s_done) break;
-  }
+    }
+    return prefix;
+  };
+  const unsigned long long prefix = select(K);
   // prefix is the K-th largest key; compact positions p with key(p) >= prefix
   const int per = (m + 1023) / 1024;
   const int p0 = tid * per, p1 = min(p0 + per, m);
@@ -566,6 +572,35 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
     for (int i = 1; i < 16; ++i) b = fmaxf(b, smax[i]);
     J.ctrl->s_out = b;
   }
+  // extension list: the ne keys below the candidates' (keys are distinct, so
+  // exactly ne positions lie in [pe, prefix)), ascending, padded with m
+  const int ne = ext_count(m, K, J.ne_max);
+  if (ne <= 0) return;  // workgroup-uniform
+  const unsigned long long pe = select(K + ne);
+  int ce = 0;
+  for (int p = p0; p < p1; ++p) {
+    const unsigned long long k = key(p);
+    ce += (k >= pe && k < prefix) ? 1 : 0;
+  }
+  __syncthreads();
+  scan[tid] = ce;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = tid >= off ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  int we = scan[tid] - ce;
+  for (int p = p0; p < p1; ++p) {
+    const unsigned long long k = key(p);
+    if (k >= pe && k < prefix) {
+      if (we < ne) J.ext[we] = p;
+      ++we;
+    }
+  }
+  const int padded = cdiv(ne, kTileVars) * kTileVars;
+  for (int c = ne + tid; c < padded; c += 1024) J.ext[c] = m;
 }
 
 // ---------------------------------------------------------------------------
@@ -948,23 +983,32 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
 }
 
 // Plan of the second pass: per job, the suspects listed at this step (0 for
-// jobs without a listing) and the prefix sums of the suspect kinds.
+// jobs without a listing) and the prefix sums of its kinds.  Stage 0 plans
+// the extension columns (kinds kKPairE .. kKCompE) for the suspects k_lselect
+// listed; stage 1 the suspects' full rows (kKPairS .. kKLsel2) for those
+// the extension left (or all listed, without extension columns).
 __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict__ jobs,
                                                         int njobs, JobStep* __restrict__ js,
-                                                        int32_t* __restrict__ pre) {
+                                                        int32_t* __restrict__ pre, int stage) {
   auto plan = [&](int j) {
     JobStep s = js[j];
     s.nsus = s.learned ? jobs[j].ctrl->nsus : 0;
-    s.nct2 = cdiv(s.nsus, kTileVars) * s.nblk;
+    if (stage == 0) {
+      s.ne = s.learned ? ext_count(s.m, s.k, jobs[j].ne_max) : 0;
+      s.nct3 = s.ne > 0 ? cdiv(s.nsus, kTileVars) * cdiv(s.ne, kTileVars) : 0;
+    } else {
+      s.nct2 = cdiv(s.nsus, kTileVars) * s.nblk;
+    }
     js[j] = s;
     return s;
   };
+  const int k0 = stage == 0 ? kKPairE : kKPairS, k1 = stage == 0 ? kKCompE : kKLsel2;
   if (njobs <= 64) {  // one wave, no barriers
     if (threadIdx.x >= 64) return;
     const int lane = threadIdx.x;
     JobStep s{};
     if (lane < njobs) s = plan(lane);
-    for (int kind = kKPairS; kind <= kKLsel2; ++kind) {
+    for (int kind = k0; kind <= k1; ++kind) {
       const int32_t c = lane < njobs ? kind_count(s, kind) : 0;
       int32_t incl = c;
 #pragma unroll
@@ -981,7 +1025,7 @@ __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict
   __shared__ int32_t sh[1024];
   for (int j = threadIdx.x; j < njobs; j += 1024) plan(j);
   __syncthreads();
-  for (int kind = kKPairS; kind <= kKLsel2; ++kind)
+  for (int kind = k0; kind <= k1; ++kind)
     block_scan(
         njobs, [&](int j) { return kind_count(js[j], kind); },
         pre + (int64_t)kind * (njobs + 1), sh);
@@ -991,6 +1035,135 @@ __global__ __launch_bounds__(256) void k_pair_susp(const JobDev* __restrict__ jo
                                                    const JobStep* __restrict__ js,
                                                    const int32_t* __restrict__ pre, int G) {
   pair_tiles<kModeSusp, true>(jobs, njobs, js, pre, G);
+}
+
+__global__ __launch_bounds__(256) void k_pair_ext(const JobDev* __restrict__ jobs, int njobs,
+                                                  const JobStep* __restrict__ js,
+                                                  const int32_t* __restrict__ pre, int G) {
+  pair_tiles<kModeExt, true>(jobs, njobs, js, pre, G);
+}
+
+// The extension columns' share of every listed suspect's k: one wave per
+// suspect l sums min(0, R(l, j))^2 over the extension columns j that are
+// neither l nor one of l's witnesses (those entered the bound already), in
+// a fixed order, and adds it to lb[l].  R as in the other combines.
+__global__ __launch_bounds__(256) void k_ext_bound(const JobDev* __restrict__ jobs, int njobs,
+                                                   const JobStep* __restrict__ js,
+                                                   const int32_t* __restrict__ pre) {
+  for_blocks(pre, njobs, [&](int jb, int lb) {
+    const JobDev& J = jobs[jb];
+    const JobStep S = js[jb];
+    const int lane = threadIdx.x & 63;
+    const int ci = lb * 4 + (threadIdx.x >> 6);
+    if (ci >= S.nsus) return;  // wave-uniform; no barriers below
+    const int l = J.cand2[ci];
+    const int sl = J.act[l];
+    const int nbe = cdiv(S.ne, kTileVars);
+    int wl[kWit];
+#pragma unroll
+    for (int q = 0; q < kWit; ++q) wl[q] = J.wit[(int64_t)l * kWit + q];
+    const double s1_bias =
+        (double)S.nsplit_c * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+    const double inv_n = 1.0 / (double)J.n;
+    const double lim = 1.0 - kCollinear;
+    double acc = 0.0;
+    for (int e = lane; e < S.ne; e += 64) {
+      const int j = J.ext[e];
+      bool skip = j == l;
+#pragma unroll
+      for (int q = 0; q < kWit; ++q) skip |= j == wl[q];
+      if (skip) continue;
+      // the pair's slot in the extension pass's partial sums
+      const int tile = (ci / kTileVars) * nbe + e / kTileVars;
+      const int wave = ((ci % kTileVars) / kWaveVars) * 2 + (e % kTileVars) / kWaveVars;
+      const int q = (ci % kWaveVars) * 4 + (e % kWaveVars);
+      double sm[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int sp = 0; sp < S.nsplit_c; ++sp) {
+        const double* src = J.parts + (((int64_t)sp * S.nct3 + tile) * 4 + wave) * 64 + q * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sm[c] += src[c];
+      }
+      const int sj = J.act[j];
+      double r = J.rho[(int64_t)sl * J.d + sj];
+      r = r > lim ? lim : (r < -lim ? -lim : r);
+      const double al = 1.0 / sqrt(1.0 - r * r);
+      const double h_lj =
+          entropy_from_moments(kLn2 * (sm[0] + s1_bias) * inv_n, al * sm[1] * inv_n);
+      const double h_jl =
+          entropy_from_moments(kLn2 * (sm[2] + s1_bias) * inv_n, al * sm[3] * inv_n);
+      const double R = (J.hm[sj] + h_lj) - (J.hm[sl] + h_jl);
+      if (R < 0.0) acc += R * R;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) J.lb[l] += acc;
+  });
+}
+
+// Keep the listed suspects whose bound still does not exceed the best
+// candidate's k (in place, ascending, padded with m); the count goes to
+// ctrl->nsus for the rows pass.  None left: the best candidate is the exact
+// choice and is committed here.
+__global__ __launch_bounds__(256) void k_ext_compact(const JobDev* __restrict__ jobs, int njobs,
+                                                     const JobStep* __restrict__ js,
+                                                     const int32_t* __restrict__ pre, int t) {
+  static_assert(kMaxSuspects <= 4 * 256, "four listed suspects per thread");
+  __shared__ Best sh[256];
+  __shared__ int shs[256];
+  for_blocks(pre, njobs, [&](int jb, int) {
+    const JobDev& J = jobs[jb];
+    const JobStep S = js[jb];
+    const int tid = threadIdx.x;
+    const int m = S.m, n1 = S.nsus;
+    const Best best =
+        best_of_rows(J.kc, J.cand, S.k, J.act, Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
+    const double kbest = -best.v;
+    const int per = (n1 + 255) / 256;
+    const int c0 = min(tid * per, n1), c1 = min(c0 + per, n1);
+    int v[4];
+    bool keep[4];
+    int mine = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = c0 + i;
+      v[i] = c < c1 ? J.cand2[c] : 0;
+      const double b = c < c1 ? J.lb[v[i]] : INFINITY;
+      keep[i] = c < c1 && !(b == b && b > kbest);  // NaN bounds stay suspects
+      mine += keep[i] ? 1 : 0;
+    }
+    shs[tid] = mine;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int x = tid >= off ? shs[tid - off] : 0;
+      __syncthreads();
+      shs[tid] += x;
+      __syncthreads();
+    }
+    const int n2 = shs[255];
+    int w = shs[tid] - mine;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (keep[i]) J.cand2[w++] = v[i];
+    const int padded = cdiv(n2, kTileVars) * kTileVars;
+    for (int c = n2 + tid; c < padded; c += 256) J.cand2[c] = m;
+    if (n2 == 0 && J.measures) {
+      double* row = J.measures + (int64_t)t * J.d;
+      for (int x = tid; x < J.d; x += 256) row[x] = NAN;
+      __syncthreads();
+      for (int c = tid; c < S.k; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Ctrl* C = J.ctrl;
+      C->nsus = n2;
+      if (n2 == 0) {
+        C->n_expanded += 1;
+        C->n_cleared += 1;
+        commit_choice(J, t, m, best);
+      }
+    }
+    __syncthreads();
+  });
 }
 
 // R(s, j) of every listed suspect against every active position (0 for j = s).
@@ -1084,6 +1257,8 @@ __global__ __launch_bounds__(256) void k_lselect2(const JobDev* __restrict__ job
     __syncthreads();
     if (tid == 0) {
       J.ctrl->n_expanded += 1;
+      J.ctrl->n_rows_sum += S.nsus;
+      if (J.steplog) J.steplog[t] |= S.nsus << 16;
       commit_choice(J, t, S.m, b);
     }
     __syncthreads();
@@ -1426,8 +1601,28 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
   return hipGetLastError();
 }
 
-hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_susp_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, sc.js, sc.pre);
+hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, int stage,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_susp_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, sc.js, sc.pre,
+                     stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_ext, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKPairE), grid);
+  return hipGetLastError();
+}
+
+hipError_t launch_ext_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_bound,
+                           int g_comp, hipStream_t st) {
+  if (g_comp <= 0) return hipSuccess;
+  const JobStep* js = sc.js;
+  hipLaunchKernelGGL(k_ext_bound, dim3((unsigned)g_bound), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKBoundE));
+  hipLaunchKernelGGL(k_ext_compact, dim3((unsigned)g_comp), dim3(256), 0, st, jobs, njobs, js,
+                     pre_kind(sc, njobs, kKCompE), t);
   return hipGetLastError();
 }
 

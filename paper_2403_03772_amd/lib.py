@@ -62,7 +62,8 @@ class _LearnedStats(ctypes.Structure):
         ("suspects_max", ctypes.c_int32),
         ("suspects_sum", ctypes.c_int64),
         ("expanded", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("cleared", ctypes.c_int32),
+        ("rows_sum", ctypes.c_int64),
     ]
 
 
@@ -85,7 +86,7 @@ class _Opts(ctypes.Structure):
         ("learned_stats", ctypes.POINTER(_LearnedStats)),
         ("record_features", ctypes.c_void_p),
         ("max_suspects", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("extension", ctypes.c_int32),
         ("step_log", ctypes.c_void_p),
     ]
 
@@ -130,6 +131,8 @@ class LearnedStats:
     suspects_max: int
     suspects_sum: int
     expanded: int
+    cleared: int        # expanded steps whose suspects the extension columns all cleared
+    rows_sum: int       # suspects whose full rows were measured
 
 
 @dataclass
@@ -142,6 +145,7 @@ class Learned:
     margin: float = math.inf
     min_m: int | None = None
     max_suspects: int = 1024
+    extension: int = 128
 
 
 def load():
@@ -265,6 +269,7 @@ def _new_opts(lib, *, sync=True, graph=False, autotune=False, learned=None, prof
         opts.learned_min_m = int(learned.min_m if learned.min_m is not None
                                  else max(2 * min(learned.topk, 64), 64))
         opts.max_suspects = int(learned.max_suspects)
+        opts.extension = int(learned.extension)
         stats = _LearnedStats()
         opts.learned_stats = ctypes.pointer(stats)
         if keep is not None:
@@ -280,8 +285,7 @@ def _profile_of(prof):
 
 
 def _stats_of(stats):
-    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_
-                           if k != "reserved"})
+    return LearnedStats(**{k: getattr(stats, k) for k, _ in _LearnedStats._fields_})
 
 
 def workspace_size(n: int, d: int, learned: Learned | None = None) -> int:

@@ -217,11 +217,13 @@ def test_learned_options_are_validated():
     lib = pkg.load()
     o = _opts()
     assert o.topk == 64 and o.audit_every == 0 and o.learned_min_m == 128
+    assert o.max_suspects == 1024 and o.extension == 128
     o.proposer = 1
     assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) > \
         lib.lingam_workspace_size(1000, 300, None)
     for field, bad in (("topk", 12), ("topk", 0), ("topk", 264), ("audit_every", -1),
-                       ("learned_min_m", 32)):
+                       ("learned_min_m", 32), ("extension", -8), ("extension", 12),
+                       ("extension", 264)):
         o = _opts()
         o.proposer = 1
         setattr(o, field, bad)
@@ -266,5 +268,5 @@ def test_struct_layouts_match_header():
     o = _opts()
     assert o.struct_size == ctypes.sizeof(L._Opts)
     assert ctypes.sizeof(L._Profile) == 11 * 8
-    assert ctypes.sizeof(L._LearnedStats) == 40
+    assert ctypes.sizeof(L._LearnedStats) == 48
     assert ctypes.sizeof(L._Job) == 10 * 8

@@ -323,7 +323,7 @@ def test_step_log_matches_stats(lib):
                            step_log=True)
     log = out["step_log"].cpu().numpy()
     st = out["learned_stats"]
-    kind, nsus = log & 15, log >> 4
+    kind, nsus, rows = log & 15, (log >> 4) & 0xFFF, log >> 16
     m = 200 - np.arange(200)
     learned = (m > 64) & (np.arange(200) < 199)
     assert np.all(kind[~learned] == 0)
@@ -334,16 +334,21 @@ def test_step_log_matches_stats(lib):
     assert int(np.sum(kind == 1)) + st.expanded + st.fallbacks + st.audits == st.learned_steps
     assert np.all(nsus[kind == 4] > 0) and np.all(nsus[kind != 4] == 0)
     assert np.all(nsus[kind == 4] <= np.maximum((m[kind == 4] // 2 - 16) // 8 * 8, 0))
+    # the extension columns leave some of the suspects for the rows pass
+    assert np.all(rows <= nsus) and np.all(rows[kind != 4] == 0)
+    assert int(np.sum(rows)) == st.rows_sum
+    assert int(np.sum((kind == 4) & (rows == 0))) == st.cleared
 
 
 def test_exact_decisions_match_oracle(lib):
     """Exact mode step by step against the oracle's learned form (same
-    network, K, witnesses): the plain order, and at every learned step the
-    same decision (certified by the bound, or a second pass over the same
-    number of suspects).  The bound compares FP32-path measures on the GPU
-    with FP64 ones in the oracle, so a step whose suspect count differs is
-    accepted only where some non-candidate's oracle bound lies within 1e-3
-    of the best candidate's k."""
+    network, K, witnesses, extension columns): the plain order, and at every
+    learned step the same decision (certified by the bound, or a second pass
+    over the same number of suspects, of which the same number have their
+    rows measured after the extension columns).  The bound compares
+    FP32-path measures on the GPU with FP64 ones in the oracle, so a step
+    whose counts differ is accepted only where some oracle bound lies within
+    1e-3 of the best candidate's k."""
     d, n, K = 130, 2500, 16
     s = _sem(d, n, 31)
     X32 = s.X.astype(np.float32)
@@ -355,13 +360,17 @@ def test_exact_decisions_match_oracle(lib):
     ro, info = OP.learned_order(X32, prop, K=K, delta=np.inf, audit_every=0, min_m=64)
     assert np.array_equal(go, ro)
     mism = 0
+    rows_checked = 0
     for st in info:
         if st.kind == "plain":
             assert log[st.t] & 15 == 0
             continue
-        g_kind, g_sus = int(log[st.t] & 15), int(log[st.t] >> 4)
+        g_kind, g_sus = int(log[st.t] & 15), int((log[st.t] >> 4) & 0xFFF)
+        g_rows = int(log[st.t] >> 16)
         o_sus = 0 if st.certified else st.suspects
-        if (g_kind == 1) == st.certified and g_sus == o_sus:
+        same = (g_kind == 1) == st.certified and g_sus == o_sus
+        if same and (g_kind != 4 or g_rows == st.rows):
+            rows_checked += g_kind == 4
             continue
         mism += 1
         # the oracle's bounds at this step: some must sit at the best
@@ -374,10 +383,45 @@ def test_exact_decisions_match_oracle(lib):
         D = oracle.pair_matrix(Xc, U)
         k = np.sum(np.minimum(D, 0) ** 2, axis=1)
         C = np.asarray(st.candidates)
-        lb = OP.lower_bounds(D, C, OP.witnesses(Xc, U, 8))
+        wit = OP.witnesses(Xc, U, 8)
+        lb = OP.lower_bounds(D, C, wit)
         kb = np.min(k[C])
         notc = np.setdiff1d(np.arange(len(U)), C)
+        if same:   # same suspects, a different count of measured rows
+            sus = notc[~(lb[notc] > kb)]
+            lb = OP.extension_bounds(D, lb, sus, st.extension, wit)
+            notc = sus
         near = np.abs(lb[notc] - kb) <= 1e-3 * kb
-        assert near.any(), (st.t, g_kind, g_sus, st.certified, o_sus)
-    print(f"exact decisions: {len(info)} steps, {mism} with a different suspect count",
-          flush=True)
+        assert near.any(), (st.t, g_kind, g_sus, g_rows, st.certified, o_sus, st.rows)
+    print(f"exact decisions: {len(info)} steps, {mism} with different counts, "
+          f"{rows_checked} second passes with equal measured rows", flush=True)
+    assert rows_checked > 0
+
+
+def test_extension_columns_only_shrink_the_rows(lib):
+    """The extension columns change only how many suspects' rows are
+    measured: with and without them the order is the plain order and the
+    decisions and suspects of every step are the same; without them every
+    suspect's row is measured, with them fewer (shipped network, d = 400)."""
+    from paper_2403_03772_amd import train_proposer as TP
+    s = _sem(400, 4000, 41)
+    X = _t(s.X)
+    P = TP.default_proposer()
+    plain = lib.causal_order(X).cpu().numpy()
+    runs = {}
+    for ext in (0, 128, 8):
+        print(f"extension {ext}", flush=True)
+        out = lib.causal_order(X, learned=lib.Learned(P, topk=32, extension=ext),
+                               step_log=True)
+        assert np.array_equal(out["order"].cpu().numpy(), plain), ext
+        runs[ext] = (out["learned_stats"], out["step_log"].cpu().numpy())
+    (a, la), (b, lb), (c, lc) = runs[0], runs[128], runs[8]
+    for st, lg_ in ((b, lb), (c, lc)):
+        assert np.array_equal(lg_ & 0xFFFF, la & 0xFFFF)
+        assert (st.certified, st.expanded, st.suspects_sum) == \
+            (a.certified, a.expanded, a.suspects_sum)
+    assert a.rows_sum == a.suspects_sum and a.cleared == 0
+    assert b.rows_sum <= c.rows_sum <= a.rows_sum
+    assert a.expanded > 0 and b.rows_sum < a.rows_sum
+    print(f"rows measured: none {a.rows_sum}, 8 columns {c.rows_sum}, 128 columns "
+          f"{b.rows_sum} (cleared {b.cleared} of {b.expanded})", flush=True)
