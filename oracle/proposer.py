@@ -358,7 +358,7 @@ def extension_bounds(D, lb, S, E, wit=None) -> np.ndarray:
 
 def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: int = 32,
                   min_m: int | None = None, emulate_bf16: bool = True,
-                  max_suspects: int = 1024, n_witness: int = 8, n_ext: int = 128):
+                  max_suspects: int = 1024, n_witness: int = 8, n_ext: int = 0):
     """Causal order by the learned-proposal form.
 
     X: n x d samples (cast to FP32 first, like the library's input).

@@ -380,7 +380,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     };
     if (gated) {
       LG_TRY(lg::launch_learned_back(table, P.njobs, t, sc, T.g, st), "learned decision");
-      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 0, st), "extension schedule");
+      if (P.lc.extension > 0)
+        LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 0, st), "extension schedule");
       if (T.g[lg::kKPairE] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_ext(table, P.njobs, sc,
@@ -786,7 +787,7 @@ void lingam_opts_init(lingam_opts* o) {
   o->margin = INFINITY;
   o->learned_min_m = 128;
   o->max_suspects = lg::kMaxSuspects;
-  o->extension = 128;
+  o->extension = 0;
 }
 
 const char* lingam_last_error(void) { return g_err; }

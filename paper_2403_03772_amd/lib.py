@@ -145,7 +145,7 @@ class Learned:
     margin: float = math.inf
     min_m: int | None = None
     max_suspects: int = 1024
-    extension: int = 128
+    extension: int = 0
 
 
 def load():

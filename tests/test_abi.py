@@ -217,7 +217,7 @@ def test_learned_options_are_validated():
     lib = pkg.load()
     o = _opts()
     assert o.topk == 64 and o.audit_every == 0 and o.learned_min_m == 128
-    assert o.max_suspects == 1024 and o.extension == 128
+    assert o.max_suspects == 1024 and o.extension == 0
     o.proposer = 1
     assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) > \
         lib.lingam_workspace_size(1000, 300, None)

@@ -319,7 +319,8 @@ def test_step_log_matches_stats(lib):
     """The per-step decision log agrees with the counters and the schedule."""
     s = _sem(200, 2000, 21)
     P = _t(_proposer(10))
-    out = lib.causal_order(_t(s.X), learned=lib.Learned(P, topk=16, audit_every=8, min_m=64),
+    out = lib.causal_order(_t(s.X), learned=lib.Learned(P, topk=16, audit_every=8, min_m=64,
+                                                        extension=64),
                            step_log=True)
     log = out["step_log"].cpu().numpy()
     st = out["learned_stats"]
@@ -353,11 +354,13 @@ def test_exact_decisions_match_oracle(lib):
     s = _sem(d, n, 31)
     X32 = s.X.astype(np.float32)
     prop = _proposer(11)
-    out = lib.causal_order(_t(X32), learned=lib.Learned(_t(prop), topk=K, min_m=64),
+    out = lib.causal_order(_t(X32), learned=lib.Learned(_t(prop), topk=K, min_m=64,
+                                                        extension=32),
                            step_log=True)
     go = out["order"].cpu().numpy()
     log = out["step_log"].cpu().numpy()
-    ro, info = OP.learned_order(X32, prop, K=K, delta=np.inf, audit_every=0, min_m=64)
+    ro, info = OP.learned_order(X32, prop, K=K, delta=np.inf, audit_every=0, min_m=64,
+                                n_ext=32)
     assert np.array_equal(go, ro)
     mism = 0
     rows_checked = 0
