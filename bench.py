@@ -252,6 +252,29 @@ def run_adjacency(lg, X, n, d, order, reps=5):
             "flops": flops, "reps": reps}
 
 
+def run_total_effects(lg, X, order, reps=10):
+    """lingam_total_effects on the adjacency along the plain order: mean ms per
+    call (the call synchronizes once, for its order check) and the FP64 rate
+    of the blocked triangular inverse against its algorithmic d^3 / 3 flops."""
+    import torch
+
+    B = lg.adjacency(X, order)
+    d = B.shape[0]
+    ws = torch.empty(int(lg.load().lingam_total_effects_workspace_size(d)), dtype=torch.uint8,
+                     device=X.device)
+    lg.total_effects(B, order, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lg.total_effects(B, order, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flops = d ** 3 / 3.0
+    return {"ms": ms, "bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12, "peak": 78.6,
+            "unit": "TFLOP/s (fp64)", "frac": flops / (ms * 1e-3) / 78.6e12, "flops": flops,
+            "reps": reps}
+
+
 def run_adjacency_pruned(lg, X, order, B_true, reps=3):
     """lingam_adjacency_pruned along the plain order: mean ms per call and the
     edges it keeps against the generating DAG (precision, recall)."""
@@ -457,6 +480,8 @@ def main() -> int:
     if args.workload == "gene" and not args.no_aux:
         progress("adjacency along the plain order")
         rec["adjacency"] = run_adjacency(lg, X, n, d, torch.as_tensor(pl["order"]).cuda())
+        progress("total effects along the plain order")
+        rec["total_effects"] = run_total_effects(lg, X, torch.as_tensor(pl["order"]).cuda())
         progress("adaptive-lasso pruning along the plain order")
         rec["adjacency_pruned"] = run_adjacency_pruned(lg, X, torch.as_tensor(pl["order"]).cuda(),
                                                        sem.B)
