@@ -13,7 +13,8 @@
 //                   weights and activations on MFMA, FP32 accumulation
 //                   (the same code as the scores entry point's k_scores)
 //   k_topk          the K best scores (ties to the smaller original id) by an
-//                   8-bit radix select over 64-bit keys
+//                   8-bit radix select over 64-bit keys (and the extension
+//                   columns ranked next, when asked for)
 //   k_pair_cand     the pair moments of every (candidate, active) pair: the
 //                   all-pairs hot loop on (K / 8) x nblk tiles
 //   k_combine_cand  R(c, j) of every candidate row
@@ -31,6 +32,14 @@
 //                   beats every non-candidate's by the margin; audit steps
 //                   and the rest hand the step to the full kernels (gated by
 //                   k_gate_schedule)
+//   k_pair_ext, k_ext_bound, k_ext_compact  (optional) the listed suspects
+//                   against the extension columns (the variables ranked right
+//                   after the candidates), their share added to the bounds,
+//                   and the list cut to the suspects still at or below the
+//                   best candidate's k (none left: the best candidate is
+//                   committed)
+//   k_pair_susp, k_combine_susp, k_susp_rowk, k_lselect2  the remaining
+//                   suspects' full rows and the exact choice
 //
 // and the training kernels of the network (forward with saved activations,
 // listwise softmax cross-entropy, backward on MFMA, gradient reduction, Adam).
