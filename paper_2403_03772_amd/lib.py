@@ -138,7 +138,16 @@ class LearnedStats:
 @dataclass
 class Learned:
     """Learned-proposal configuration: ``proposer`` is a CUDA float32 tensor
-    of PROPOSER_SIZE values (feature mean, feature scale, network weights)."""
+    of PROPOSER_SIZE values (feature mean, feature scale, network weights).
+
+    ``topk``: most candidates per step (a step with m variables takes about
+    m/16, at least min(32, topk)); ``audit_every``: full-step audit period
+    (0 = none); ``margin``: score lead that accepts the best candidate when
+    the suspects are too many (+inf = never, the exact mode); ``min_m``:
+    steps with at most this many variables are plain (default 2 min(topk,
+    64)); ``max_suspects``: most suspects whose rows the second pass
+    measures; ``extension``: extension columns measured against the suspects
+    first (0 = none).  Mirrors the learned fields of ``lingam_opts``."""
     proposer: object
     topk: int = 64
     audit_every: int = 0
