@@ -97,7 +97,8 @@ typedef struct lingam_profile {
 /* Decisions of the learned form, summed over the jobs of a call (host). */
 typedef struct lingam_learned_stats {
   int32_t learned_steps;  /* steps with a learned pass */
-  int32_t certified;      /* ... whose best candidate was certified */
+  int32_t certified;      /* ... whose best candidate was certified (audit and forced
+                             steps included: the full step still decides those) */
   int32_t fallbacks;      /* ... decided by the full step because the margin was small */
   int32_t audits;         /* ... decided by the full step as audits */
   int32_t audit_agree;    /* audits whose full choice equalled the learned choice */
