@@ -270,3 +270,16 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L._Profile) == 11 * 8
     assert ctypes.sizeof(L._LearnedStats) == 48
     assert ctypes.sizeof(L._Job) == 10 * 8
+
+
+def test_binding_rejects_host_tensors():
+    """The Python functions refuse host tensors before any device call."""
+    import torch
+    X = torch.zeros((100, 4), dtype=torch.float32)
+    B = torch.zeros((4, 4), dtype=torch.float64)
+    for call in (lambda: pkg.causal_order(X), lambda: pkg.adjacency(X, [0, 1, 2, 3]),
+                 lambda: pkg.adjacency_pruned(X, [0, 1, 2, 3])):
+        with pytest.raises(TypeError):
+            call()
+    with pytest.raises(ValueError):
+        pkg.total_effects(B, [0, 1, 2, 3])
