@@ -283,3 +283,27 @@ def test_binding_rejects_host_tensors():
             call()
     with pytest.raises(ValueError):
         pkg.total_effects(B, [0, 1, 2, 3])
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/lingam.h compiles as C99 (pedantic) and a C program links the
+    library and calls it (no device call: the options initializer)."""
+    import shutil
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "lingam.h"\n'
+                   "int main(void) {\n"
+                   "  lingam_opts o;\n"
+                   "  lingam_opts_init(&o);\n"
+                   "  return (o.struct_size == sizeof(lingam_opts) && o.topk == 64) ? 0 : 1;\n"
+                   "}\n")
+    exe = tmp_path / "use"
+    libdir = os.path.dirname(pkg.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), str(src), "-L", libdir,
+                        "-llingam_mi355x", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert subprocess.run([str(exe)]).returncode == 0
