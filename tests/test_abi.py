@@ -307,3 +307,33 @@ def test_header_is_plain_c(tmp_path):
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert subprocess.run([str(exe)]).returncode == 0
+
+
+def test_ctypes_mirrors_match_c_offsets(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler
+    gives the same field of the header's struct, and the sizes agree."""
+    import shutil
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"lingam_opts": L._Opts, "lingam_profile": L._Profile,
+               "lingam_learned_stats": L._LearnedStats, "lingam_job": L._Job}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lingam.h"',
+             "int main(void) {"]
+    for cname, mirror in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in mirror._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "offsets.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "offsets"
+    r = subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, mirror in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(mirror), cname
+        for f, _ in mirror._fields_:
+            assert got[(cname, f)] == getattr(mirror, f).offset, (cname, f)
