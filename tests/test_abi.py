@@ -337,3 +337,22 @@ def test_ctypes_mirrors_match_c_offsets(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(mirror), cname
         for f, _ in mirror._fields_:
             assert got[(cname, f)] == getattr(mirror, f).offset, (cname, f)
+
+
+def test_binding_declares_every_signature():
+    """The binding gives every declared entry point its argument types and the
+    header's result type (64-bit sizes and pointers must not pass through
+    ctypes' int default)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    ret = dict((n, t.replace(" ", "")) for t, n in re.findall(
+        r"^(size_t|int|const char\s*\*|void)\s*\b((?:lingam|varlingam)_\w+)\s*\(", text,
+        flags=re.M))
+    want = {"size_t": ctypes.c_size_t, "int": ctypes.c_int, "constchar*": ctypes.c_char_p,
+            "void": None}
+    lib = pkg.load()
+    names = _declared_functions()
+    assert set(ret) == set(names)
+    for name in names:
+        fn = getattr(lib, name)
+        assert fn.argtypes is not None, name
+        assert fn.restype is want[ret[name]], (name, ret[name], fn.restype)
