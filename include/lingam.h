@@ -157,7 +157,9 @@ typedef struct lingam_opts {
                                    against the variables ranked right after the
                                    candidates (this many; a multiple of 8 in [0, 256]),
                                    and only those whose bound still allows them to win
-                                   have their full rows measured; 0 = none (default:
+                                   have their full rows measured (single orderings
+                                   only: a batched call with extension > 0 returns
+                                   LINGAM_E_UNSUPPORTED); 0 = none (default:
                                    on the d = 1024 and 4096 workloads the suspects that
                                    survive the candidates and witnesses mostly survive
                                    the extension too, and its pass costs what it saves) */

@@ -858,6 +858,7 @@ size_t lingam_batch_workspace_size(const lingam_job* jobs, int32_t n_jobs,
                                    const lingam_opts* opts) {
   if (opts && (opts->struct_size != sizeof(lingam_opts) || check_learn(opts) != LINGAM_OK))
     return 0;
+  if (opts && opts->proposer && opts->extension > 0) return 0;
   std::vector<HostJob> hj;
   if (batch_jobs(jobs, n_jobs, &hj) != LINGAM_OK) return 0;
   int cu = 0;
@@ -881,6 +882,8 @@ int lingam_batch_causal_order(const lingam_job* jobs, int32_t n_jobs, int32_t* j
                 "no forcing");
   int rc = check_learn(opts);
   if (rc != LINGAM_OK) return rc;
+  if (opts->proposer && opts->extension > 0)
+    return fail(LINGAM_E_UNSUPPORTED, "extension columns are available to single orderings only");
   std::vector<HostJob> hj;
   rc = batch_jobs(jobs, n_jobs, &hj);
   if (rc != LINGAM_OK) return rc;

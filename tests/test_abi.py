@@ -233,6 +233,18 @@ def test_learned_options_are_validated():
     o.proposer = 1
     o.margin = float("nan")
     assert _call(opts=o) == L.E_INVALID
+    # extension columns: single orderings only
+    J = (L._Job * 1)()
+    J[0].X, J[0].n_rows, J[0].ldx, J[0].n, J[0].d, J[0].order = 1, 1000, 300, 1000, 300, 1
+    o = _opts()
+    o.proposer = 1
+    o.extension = 64
+    assert lib.lingam_batch_workspace_size(J, 1, ctypes.byref(o)) == 0
+    assert lib.lingam_batch_causal_order(J, 1, None, ctypes.byref(o), ctypes.c_void_p(1),
+                                         1 << 30, None) == L.E_UNSUPPORTED
+    assert "single orderings" in pkg.last_error()
+    o.extension = 0
+    assert lib.lingam_batch_workspace_size(J, 1, ctypes.byref(o)) > 0
 
 
 def test_proposer_argument_errors():
