@@ -265,7 +265,7 @@ size_t lingam_adjacency_workspace_size(int64_t n, int64_t d);
  * Weighted adjacency matrix from a causal order: every variable is regressed
  * by least squares, with an intercept, on the variables that precede it in
  * `order` (DirectLiNGAM's second phase, described in Section 1; the model is
- * the linear structural equation of Section 2.1).
+ * the linear structural equation of Section 2.2).
  *   X       device FP32 [n_rows x ldx] row-major, read only.
  *   rows    device int32[n] or NULL: sample s is row rows[s] of X (a
  *           bootstrap resample); NULL = rows 0 .. n-1 (then n <= n_rows).
@@ -313,7 +313,7 @@ int lingam_adjacency_pruned(const float* X, int64_t n_rows, int64_t ldx, const i
 size_t lingam_total_effects_workspace_size(int64_t d);
 
 /*
- * Total causal effects of the linear acyclic model x = B x + e (Section 2.1;
+ * Total causal effects of the linear acyclic model x = B x + e (Section 2.2;
  * Section 4.2 ranks the variables by them): T = (I - B)^-1, T[i d + j] the
  * effect on x_i of a unit change of x_j along all directed paths, T[i d + i] =
  * 1.
@@ -352,7 +352,7 @@ int lingam_bootstrap_accumulate(const int32_t* order, const double* B, int64_t d
 size_t varlingam_workspace_size(int64_t T, int64_t d, int32_t lags, const lingam_opts* opts);
 
 /*
- * VarLiNGAM (Section 3.3): least-squares VAR(lags) with intercept, the
+ * VarLiNGAM (Section 3.2): least-squares VAR(lags) with intercept, the
  * DirectLiNGAM causal order of its residuals, and the instantaneous matrix B0.
  *   X      device FP32 [T x ldx] row-major series (time in rows), read only.
  *   M      device double[lags * d * d] or NULL: M[(tau-1) d d + i d + j] is the
@@ -373,7 +373,7 @@ int varlingam_fit(const float* X, int64_t T, int64_t d, int64_t ldx, int32_t lag
                   size_t ws_bytes, void* stream);
 
 /*
- * Lagged effects of VarLiNGAM's structural model (Section 3.3): with the VAR
+ * Lagged effects of VarLiNGAM's structural model (Section 3.2): with the VAR
  * matrices M_tau and the instantaneous matrix B0 that varlingam_fit returns,
  * theta_tau = (I - B0) M_tau for tau = 1 .. lags (the model equation solved
  * for x(t) gives M_tau = (I - B0)^-1 theta_tau).

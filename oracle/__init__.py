@@ -18,10 +18,11 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
 * :func:`causal_order` -- the DirectLiNGAM outer loop (Section 2.2) around
   Algorithm 1, in literal or memoised ("table") mode, with optional teacher
   forcing.
+* :class:`OrderRun` -- the same search advanced in resumable pieces.
 * :func:`step_measures_rows` -- k_list entries of chosen rows at one step.
 * :func:`pair_matrix` -- the whole measure matrix between active columns.
 * :func:`residualize` -- least-squares removal of one variable's effect.
-* :func:`var_fit` -- least-squares VAR fit with intercept (Section 3.3, the
+* :func:`var_fit` -- least-squares VAR fit with intercept (Section 3.2, the
   first stage of VarLiNGAM).
 * :func:`ols_adjacency` -- least-squares regression of every variable on its
   order predecessors (the instantaneous matrix B0 of VarLiNGAM).
@@ -104,6 +105,8 @@ def _load():
         lib.lo_var_fit.restype = ctypes.c_int
         lib.lo_ols_adjacency.argtypes = [P, i64, i64, i64, P, P]
         lib.lo_ols_adjacency.restype = ctypes.c_int
+        lib.lo_causal_order_resume.argtypes = [P, i64, i64, P, P, i32, i32, P, P, P]
+        lib.lo_causal_order_resume.restype = ctypes.c_int
         lib.lo_num_threads.argtypes = []
         lib.lo_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -189,6 +192,65 @@ def causal_order(X, forced=None, mode: str = "literal", with_measures: bool = Fa
     return order
 
 
+class OrderRun:
+    """The free-running search (DirectLiNGAM outer loop, Section 2.2, around
+    Algorithm 1) advanced in pieces, so that a long ordering can be
+    checkpointed between pieces and resumed.  Same arithmetic as
+    :func:`causal_order`: X is cast to FP32 (what the GPU receives), then to
+    FP64.  State: ``Xc`` (the residual columns, FP64, variable-major), ``U``
+    (active original ids, ascending), ``m`` (their count); results so far:
+    ``order``, ``measures`` (row t = k_list of step t by original id, NaN for
+    ordered columns) and ``gaps``."""
+
+    FIELDS = ("Xc", "U", "m", "order", "measures", "gaps", "mode")
+
+    def __init__(self, X=None, mode: str = "table"):
+        if X is None:
+            return
+        X = np.asarray(X, dtype=np.float32)
+        n, d = X.shape
+        self.Xc = np.ascontiguousarray(X.T, dtype=np.float64)
+        self.U = np.arange(d, dtype=np.int32)
+        self.m = np.array([d], dtype=np.int32)
+        self.order = np.full(d, -1, dtype=np.int32)
+        self.measures = np.full((max(d - 1, 1), d), np.nan)
+        self.gaps = np.full(max(d - 1, 1), np.nan)
+        self.mode = np.array([{"literal": 0, "table": 1}[mode]], dtype=np.int32)
+
+    @property
+    def d(self) -> int:
+        return self.Xc.shape[0]
+
+    @property
+    def steps_done(self) -> int:
+        return self.d - int(self.m[0])
+
+    @property
+    def finished(self) -> bool:
+        return int(self.m[0]) <= 1
+
+    def run(self, nsteps: int) -> int:
+        """Run up to ``nsteps`` more steps; returns the number run."""
+        before = self.steps_done
+        d, n = self.Xc.shape
+        code = _load().lo_causal_order_resume(
+            _ptr(self.Xc), n, d, _ptr(self.U), _ptr(self.m), int(nsteps), int(self.mode[0]),
+            _ptr(self.order), _ptr(self.measures), _ptr(self.gaps))
+        _check(code, "causal_order_resume")
+        return self.steps_done - before
+
+    def save(self, path: str) -> None:
+        np.savez(path, **{k: getattr(self, k) for k in self.FIELDS})
+
+    @classmethod
+    def load(cls, path: str) -> "OrderRun":
+        run = cls()
+        with np.load(path, allow_pickle=False) as z:
+            for k in cls.FIELDS:
+                setattr(run, k, np.ascontiguousarray(z[k]))
+        return run
+
+
 def step_measures_rows(X, prefix, rows) -> np.ndarray:
     """k_list entries for original columns ``rows`` after regressing out ``prefix``."""
     X = np.ascontiguousarray(X, dtype=np.float32)
@@ -233,14 +295,14 @@ def ols_adjacency(E, order) -> np.ndarray:
 
 
 def varlingam(X, lags: int = 1, forced=None, with_measures: bool = False):
-    """VarLiNGAM (Section 3.3): least-squares VAR(lags) with intercept, the
+    """VarLiNGAM (Section 3.2): least-squares VAR(lags) with intercept, the
     DirectLiNGAM order of its residuals, B0 by least squares on the order.
 
     Returns a dict with ``coef`` ((1 + d*lags) x d), ``M`` (lags x d x d,
     M[tau-1][i, j] = coefficient of x_j(t - tau) in the equation of x_i),
     ``resid``, ``order``, ``B0`` (and ``measures`` / ``gaps``).  The residuals
-    are rounded to FP32 before the ordering, as the GPU receives FP32 data
-    only at the input; see the library's varlingam_fit for its own handling.
+    are ordered as FP64 data (reading R9): no FP32 rounding between the VAR
+    fit and the search.
     """
     X = np.ascontiguousarray(X, dtype=np.float64)
     T, d = X.shape
@@ -260,7 +322,7 @@ def varlingam(X, lags: int = 1, forced=None, with_measures: bool = False):
 def var_lagged_effects(M, B0) -> np.ndarray:
     """Lagged effects theta_tau (tau = 1 .. lags) of VarLiNGAM's structural model.
 
-    Section 3.3 writes the model as x(t) = sum over tau = 0 .. k of
+    Section 3.2 writes the model as x(t) = sum over tau = 0 .. k of
     theta_tau x(t - tau) + eps(t), with theta_0 = B0 the instantaneous effects.
     Moving theta_0 x(t) to the left gives (I - B0) x(t) = sum over tau >= 1 of
     theta_tau x(t - tau) + eps(t), so the VAR (reduced-form) matrices are
@@ -277,7 +339,7 @@ def var_lagged_effects(M, B0) -> np.ndarray:
 
 def total_effects(B) -> np.ndarray:
     """Total causal effects of the linear acyclic model x = B x + e (Section
-    2.1): x = (I - B)^-1 e, so T = (I - B)^-1 and T[i, j] is the effect on
+    2.2): x = (I - B)^-1 e, so T = (I - B)^-1 and T[i, j] is the effect on
     x_i of a unit change of x_j along all directed paths (T[i, i] = 1).
     Section 4.2 ranks the variables that exert and receive the largest total
     effects."""

@@ -246,24 +246,39 @@ static int lo_step_literal(const double* Xc, int64_t n, const int32_t* U, int32_
  * D[p * m + q] = diff(U[p], U[q]) of R1, D[p * m + p] = 0.  Each column is
  * standardized once, each marginal entropy and each ordered residual entropy
  * is computed once, and diff(j, i) is taken as -diff(i, j) (which the formula
- * of R1 gives exactly).  Xc is column-major (column v at Xc + v * n). */
+ * of R1 gives exactly).  Xc is column-major (column v at Xc + v * n).
+ *
+ * Pure memoisation of the pair pieces of Algorithm 1: the mean and variance
+ * of every standardized column are computed once (lo_mean / lo_var are
+ * deterministic, so each is the same number the per-pair calls would give),
+ * and the one covariance of a pair serves the collinearity check and both
+ * residual slopes (the product (a - ma)(b - mb) is commutative in IEEE
+ * arithmetic, so cov(z_i, z_j) and cov(z_j, z_i) are the same number).  The
+ * results equal those of lo_check_pair + lo_residual bit for bit. */
 int lo_pair_matrix(const double* Xc, int64_t n, const int32_t* U, int32_t m, double* D) {
   double* Z = (double*)malloc(sizeof(double) * (size_t)m * (size_t)n);
   double* Hm = (double*)malloc(sizeof(double) * (size_t)m);
-  if (!Z || !Hm) {
+  double* mz = (double*)malloc(sizeof(double) * (size_t)m);
+  double* vz = (double*)malloc(sizeof(double) * (size_t)m);
+  if (!Z || !Hm || !mz || !vz) {
     free(Z);
     free(Hm);
+    free(mz);
+    free(vz);
     return LO_NOMEM;
   }
   int status = LO_OK;
 #pragma omp parallel for schedule(static)
   for (int32_t p = 0; p < m; ++p) {
-    int st = lo_standardize(Xc + (int64_t)U[p] * n, n, Z + (int64_t)p * n);
+    double* zp = Z + (int64_t)p * n;
+    int st = lo_standardize(Xc + (int64_t)U[p] * n, n, zp);
     if (st) {
 #pragma omp atomic write
       status = st;
     } else {
-      Hm[p] = lo_entropy(Z + (int64_t)p * n, n);
+      Hm[p] = lo_entropy(zp, n);
+      mz[p] = lo_mean(zp, n);
+      vz[p] = lo_var(zp, n);
     }
   }
   if (status) goto done;
@@ -282,11 +297,24 @@ int lo_pair_matrix(const double* Xc, int64_t n, const int32_t* U, int32_t m, dou
       D[(int64_t)p * m + p] = 0.0;
       for (int32_t q = p + 1; q < m; ++q) {
         const double* zj = Z + (int64_t)q * n;
+        /* cov(z_i, z_j) exactly as lo_cov computes it */
+        double c = 0.0;
+        for (int64_t k = 0; k < n; ++k) c += (zi[k] - mz[p]) * (zj[k] - mz[q]);
+        c /= (double)n;
+        /* R7 (lo_check_pair) */
+        if (!(fabs(c / sqrt(vz[p] * vz[q])) < 1.0 - 1e-12)) {
+#pragma omp atomic write
+          status = LO_DEGENERATE;
+          continue;
+        }
+        /* R3 both ways (lo_residual): slope cov / var of the regressor */
+        const double bij = c / vz[q], bji = c / vz[p];
+        for (int64_t k = 0; k < n; ++k) {
+          ri_j[k] = zi[k] - bij * zj[k];
+          rj_i[k] = zj[k] - bji * zi[k];
+        }
         double h1 = 0.0, h2 = 0.0;
-        int st = lo_check_pair(zi, zj, n);
-        if (!st) st = lo_residual(zi, zj, n, ri_j);
-        if (!st) st = lo_residual(zj, zi, n, rj_i);
-        if (!st) st = lo_entropy_of_scaled(ri_j, n, tmp, &h1);
+        int st = lo_entropy_of_scaled(ri_j, n, tmp, &h1);
         if (!st) st = lo_entropy_of_scaled(rj_i, n, tmp, &h2);
         if (st) {
 #pragma omp atomic write
@@ -303,6 +331,8 @@ int lo_pair_matrix(const double* Xc, int64_t n, const int32_t* U, int32_t m, dou
 done:
   free(Z);
   free(Hm);
+  free(mz);
+  free(vz);
   return status;
 }
 
@@ -329,11 +359,14 @@ static int lo_step_table(const double* Xc, int64_t n, const int32_t* U, int32_t 
   return status;
 }
 
-/* R6: x_v <- x_v - (cov(x_v, x_e)/var(x_e)) x_e for v in U, v != e. */
+/* R6: x_v <- x_v - (cov(x_v, x_e)/var(x_e)) x_e for v in U, v != e.  Every
+ * column is independent of the others, so OpenMP over columns leaves the
+ * numbers unchanged. */
 static int lo_residualize_cols(double* Xc, int64_t n, const int32_t* U, int32_t m, int32_t e) {
   const double* xe = Xc + (int64_t)e * n;
   const double ve = lo_var(xe, n);
   if (!(ve > 0.0)) return LO_DEGENERATE;
+#pragma omp parallel for schedule(static)
   for (int32_t p = 0; p < m; ++p) {
     if (U[p] == e) continue;
     double* xv = Xc + (int64_t)U[p] * n;
@@ -357,32 +390,31 @@ static double* lo_load_columns(const float* X, int64_t n, int64_t d, int64_t ldx
 /* ------------------------------------------------------------------------ */
 
 /*
- * X         FP32 row-major n x d with leading dimension ldx (read only).
- * forced    optional (forced_len entries): at step t < forced_len the variable
- *           forced[t] is taken instead of the argmax (teacher forcing); the
- *           measures are still computed and reported.
- * order     out, int32[d]: original column ids, most exogenous first.
- * measures  optional out, double[(d-1) * d]: row t holds k_list of step t by
- *           original column id (NaN for columns already ordered).
- * gaps      optional out, double[d-1]: best minus runner-up of k_list at step t.
- * mode      0 = literal (Algorithm 1 as written), 1 = table (memoised).
- * Returns LO_OK, LO_INVALID, LO_DEGENERATE or LO_NOMEM.
+ * Steps t0, t0 + 1, ... of the search on a running state, until `nsteps`
+ * steps are done or one variable is left:
+ *   Xc     FP64 column-major n x d (column v at Xc + v * n): the residual data,
+ *          updated in place (R6),
+ *   U, m   the active variables (original ids, ascending) and their count,
+ *          updated in place; t0 = d - m is the index of the next step.
+ * forced  optional (forced_len entries): at step t < forced_len the variable
+ *         forced[t] is taken instead of the argmax (teacher forcing); the
+ *         measures are still computed and reported.
+ * order    out, int32[d]: entry t for every step run; when one variable is
+ *          left, entry d - 1 too.
+ * measures optional out, double[(d-1) * d]: row t holds k_list of step t by
+ *          original column id (NaN for columns already ordered).
+ * gaps     optional out, double[d-1]: best minus runner-up of k_list at step t.
+ * mode     0 = literal (Algorithm 1 as written), 1 = table (memoised).
  */
-static int lo_causal_order_cols(double* Xc, int64_t n, int64_t d, const int32_t* forced,
-                                int32_t forced_len, int32_t mode, int32_t* order,
-                                double* measures, double* gaps) {
-  int32_t* U = (int32_t*)malloc(sizeof(int32_t) * (size_t)d);
+static int lo_search_steps(double* Xc, int64_t n, int64_t d, int32_t* U, int32_t* m_io,
+                           int32_t nsteps, const int32_t* forced, int32_t forced_len,
+                           int32_t mode, int32_t* order, double* measures, double* gaps) {
   double* k_list = (double*)malloc(sizeof(double) * (size_t)d);
-  if (!Xc || !U || !k_list) {
-    free(Xc);
-    free(U);
-    free(k_list);
-    return LO_NOMEM;
-  }
-  for (int32_t v = 0; v < d; ++v) U[v] = v;
-  int32_t m = (int32_t)d;
+  if (!k_list) return LO_NOMEM;
+  int32_t m = *m_io;
   int status = LO_OK;
-  for (int32_t t = 0; m > 1; ++t) {
+  for (int32_t s = 0; s < nsteps && m > 1; ++s) {
+    const int32_t t = (int32_t)d - m;
     status = mode == 1 ? lo_step_table(Xc, n, U, m, k_list)
                        : lo_step_literal(Xc, n, U, m, NULL, k_list);
     if (status) break;
@@ -418,11 +450,45 @@ static int lo_causal_order_cols(double* Xc, int64_t n, int64_t d, const int32_t*
       if (U[p] != chosen) U[w++] = U[p];
     m = w;
   }
-  if (!status) order[d - 1] = U[0];
-  free(Xc);
-  free(U);
+  if (!status && m == 1) order[d - 1] = U[0];
+  *m_io = m;
   free(k_list);
   return status;
+}
+
+/* The whole ordering (DirectLiNGAM outer loop, Section 2.2) on a column-major
+ * FP64 copy that it owns and frees; arguments as for lo_search_steps. */
+static int lo_causal_order_cols(double* Xc, int64_t n, int64_t d, const int32_t* forced,
+                                int32_t forced_len, int32_t mode, int32_t* order,
+                                double* measures, double* gaps) {
+  int32_t* U = (int32_t*)malloc(sizeof(int32_t) * (size_t)d);
+  if (!Xc || !U) {
+    free(Xc);
+    free(U);
+    return LO_NOMEM;
+  }
+  for (int32_t v = 0; v < d; ++v) U[v] = v;
+  int32_t m = (int32_t)d;
+  const int status = lo_search_steps(Xc, n, d, U, &m, (int32_t)d, forced, forced_len, mode,
+                                     order, measures, gaps);
+  free(Xc);
+  free(U);
+  return status;
+}
+
+/* A search that runs in pieces (long orderings, checkpointed between pieces):
+ * the caller owns the state (Xc column-major FP64 n x d, U ascending active
+ * ids, *m their count) and calls this with the next `nsteps`; see
+ * lo_search_steps.  Free-running (no forcing). */
+int lo_causal_order_resume(double* Xc, int64_t n, int64_t d, int32_t* U, int32_t* m,
+                           int32_t nsteps, int32_t mode, int32_t* order, double* measures,
+                           double* gaps) {
+  if (!Xc || !U || !m || !order || n < 2 || d < 1 || *m < 1 || *m > d || nsteps < 0 ||
+      (mode != 0 && mode != 1))
+    return LO_INVALID;
+  for (int32_t p = 0; p < *m; ++p)
+    if (U[p] < 0 || U[p] >= d || (p > 0 && U[p] <= U[p - 1])) return LO_INVALID;
+  return lo_search_steps(Xc, n, d, U, m, nsteps, NULL, 0, mode, order, measures, gaps);
 }
 
 int lo_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, const int32_t* forced,
@@ -549,7 +615,7 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
-/* VarLiNGAM: least-squares VAR(lags) fit with intercept (Section 3.3)       */
+/* VarLiNGAM: least-squares VAR(lags) fit with intercept (Section 3.2)       */
 /* ------------------------------------------------------------------------ */
 
 /* Cholesky factorisation A = L L^T in place (lower triangle), FP64. */
@@ -645,7 +711,7 @@ done:
  *        on all columns that precede c in `order`; 0 elsewhere.
  * Each regression solves its own normal equations on centred data by
  * Cholesky (plain, one variable at a time).  This is the instantaneous
- * matrix that VarLiNGAM estimates from the VAR residuals (Section 3.3).
+ * matrix that VarLiNGAM estimates from the VAR residuals (Section 3.2).
  */
 int lo_ols_adjacency(const double* E, int64_t n, int64_t d, int64_t lde, const int32_t* order,
                      double* B) {

@@ -13,7 +13,7 @@ Functions mirror the C entry points:
 * :func:`residualize` -- ``lingam_residualize`` (least-squares removal of one
   variable's effect, Section 2.2).
 * :func:`varlingam_fit` -- ``varlingam_fit`` (VAR least squares, ordering of
-  the residuals, instantaneous matrix B0; Section 3.3).
+  the residuals, instantaneous matrix B0; Section 3.2).
 * :func:`adjacency` -- ``lingam_adjacency`` (least squares of every
   variable on its order predecessors: the weighted adjacency matrix).
 * :func:`adjacency_pruned` -- ``lingam_adjacency_pruned`` (the adjacency

@@ -21,7 +21,7 @@ Workload recipes (sizes and distributions of the paper's workloads):
   two levels, edges only from level 0 to level 1, theta ~ N(0, 1),
   e ~ U(0, 1).
 * :func:`var_series` -- VAR(1) with an instantaneous DAG (VarLiNGAM model,
-  Section 3.3), reduced-form spectral radius fixed, Student-t(4) noise.
+  Section 3.2), reduced-form spectral radius fixed, Student-t(4) noise.
 * :func:`bootstrap_indices` -- row resampling with replacement.
 """
 from __future__ import annotations

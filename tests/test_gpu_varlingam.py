@@ -1,4 +1,4 @@
-"""GPU VarLiNGAM (Section 3.3) against the FP64 oracle, through the C ABI.
+"""GPU VarLiNGAM (Section 3.2) against the FP64 oracle, through the C ABI.
 
 The oracle receives the same FP32 series (cast to FP64).  VAR coefficients
 and B0 are compared element by element; the residual ordering is compared

@@ -328,7 +328,7 @@ def test_var_fit_consistency():
 
 
 # ---------------------------------------------------------------------------
-# VarLiNGAM pieces (Section 3.3)
+# VarLiNGAM pieces (Section 3.2)
 # ---------------------------------------------------------------------------
 
 def test_ols_adjacency_matches_lstsq():

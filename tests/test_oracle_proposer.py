@@ -78,6 +78,66 @@ def _lists(rng, sizes):
     return offs, tg
 
 
+def _torch_net(flat, bf16: bool):
+    """The network as torch modules, with the parameters sliced from the flat
+    layout the header states (W1[128][16], b1[128], W2[128][128], b2[128],
+    w3[128], b3[1]); BF16 rounding by torch's own conversion."""
+    import torch
+    f = torch.tensor(np.asarray(flat, dtype=np.float64))
+    sizes = [128 * 16, 128, 128 * 128, 128, 128, 1]
+    W1, b1, W2, b2, w3, b3 = torch.split(f, sizes)
+    rnd = (lambda t: t.to(torch.bfloat16).to(torch.float64)) if bf16 else (lambda t: t)
+    l1 = torch.nn.Linear(16, 128, dtype=torch.float64)
+    l2 = torch.nn.Linear(128, 128, dtype=torch.float64)
+    l3 = torch.nn.Linear(128, 1, dtype=torch.float64)
+    with torch.no_grad():
+        l1.weight.copy_(rnd(W1.view(128, 16)))
+        l1.bias.copy_(b1)
+        l2.weight.copy_(rnd(W2.view(128, 128)))
+        l2.bias.copy_(b2)
+        l3.weight.copy_(rnd(w3.view(1, 128)))
+        l3.bias.copy_(b3)
+
+    def run(x):
+        with torch.no_grad():
+            h1 = torch.relu(l1(rnd(torch.tensor(x, dtype=torch.float64))))
+            h2 = torch.relu(l2(rnd(h1)))
+            return l3(h2)[:, 0].numpy()
+    return run
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_forward_matches_torch_modules(bf16):
+    """forward() against torch.nn.Linear / ReLU built from the same flat
+    parameters (non-zero biases, so a dropped bias or a misplaced ReLU fails)."""
+    rng = np.random.default_rng(7)
+    flat = P.init_params(5) + rng.normal(scale=0.05, size=P.N_PARAMS)
+    Xn = rng.normal(size=(300, P.N_FEAT)) * 2.0
+    s, _ = P.forward(flat, Xn, emulate_bf16=bf16)
+    ref = _torch_net(flat, bf16)(Xn)
+    assert np.max(np.abs(s - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.std(ref) > 0.1  # the scores actually vary
+
+
+def test_forward_hand_cases():
+    """A network whose output is known in closed form: unit 0 of each layer
+    passes x0 - 1 through both ReLUs, the output adds b3."""
+    p = {name: np.zeros(shp) for name, shp in P.SHAPES}
+    p["W1"][0, 0] = 1.0
+    p["b1"][0] = -1.0
+    p["W2"][0, 0] = 2.0
+    p["b2"][0] = 0.5
+    p["w3"][0] = 3.0
+    p["b3"][0] = 0.25
+    x = np.zeros((4, P.N_FEAT))
+    x[:, 0] = [-2.0, 0.5, 1.0, 3.0]
+    s, _ = P.forward(P.pack(p), x)
+    # h1 = relu(x0 - 1), h2 = relu(2 h1 + 0.5), s = 3 h2 + 0.25
+    h1 = np.maximum(x[:, 0] - 1.0, 0.0)
+    assert np.array_equal(s, 3.0 * np.maximum(2.0 * h1 + 0.5, 0.0) + 0.25)
+    assert list(s) == [1.75, 1.75, 1.75, 3.0 * 4.5 + 0.25]
+
+
 def test_gradient_central_differences():
     rng = np.random.default_rng(1)
     flat = P.init_params(3) + rng.normal(scale=0.01, size=P.N_PARAMS)
