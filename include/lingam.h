@@ -346,6 +346,20 @@ int lingam_bootstrap_accumulate(const int32_t* order, const double* B, int64_t d
                                 double* coef_sum, void* stream);
 
 /*
+ * Bootstrap probabilities from the counts of lingam_bootstrap_accumulate
+ * after n_resamples resamples: order_prob[i d + j] = P(x_j precedes x_i),
+ * edge_prob[i d + j] = P(|B[i d + j]| > threshold), coef_mean = coef_sum /
+ * n_resamples (skipped when coef_sum is NULL; coef_mean may then be NULL).
+ *   order_count, edge_count  device int32[d * d];  coef_sum  device double[d * d] or NULL.
+ *   order_prob, edge_prob    device double[d * d] outputs;  coef_mean  device double[d * d].
+ * Enqueued on `stream`; no sync.  n_resamples < 1 returns LINGAM_E_INVALID.
+ */
+int lingam_bootstrap_finalize(const int32_t* order_count, const int32_t* edge_count,
+                              const double* coef_sum, int64_t d, int32_t n_resamples,
+                              double* order_prob, double* edge_prob, double* coef_mean,
+                              void* stream);
+
+/*
  * Workspace bytes for varlingam_fit on a T x d series with `lags` lags
  * (0 if unsupported: d < 1, lags < 1, or T - lags <= 1 + lags * d).
  */

@@ -527,12 +527,17 @@ int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStrea
 // one call of the engine
 // --------------------------------------------------------------------------
 
+// Everything a captured call bakes into its kernels' arguments: the device
+// job records (data, outputs and workspace regions), the workspace, the split
+// policy, the CU count, and the learned-form configuration (the caller's
+// proposer buffer is read by the captured network copy).
 std::string graph_key(const std::vector<lg::JobDev>& dj, const Plan& P, void* ws, lg::Tune tu) {
   std::string k;
   k.append(reinterpret_cast<const char*>(dj.data()), dj.size() * sizeof(lg::JobDev));
-  char buf[96];
-  snprintf(buf, sizeof(buf), "|%p|%zu|%d|%d|%d", ws, P.total, tu.target_per_cu, tu.min_iters,
-           P.cu);
+  char buf[256];
+  snprintf(buf, sizeof(buf), "|%p|%zu|%d|%d|%d|%p|%d|%d|%d|%d|%d|%a", ws, P.total,
+           tu.target_per_cu, tu.min_iters, P.cu, (const void*)P.lc.proposer, P.lc.K,
+           P.lc.min_m, P.lc.audit_every, P.lc.max_suspects, P.lc.extension, (double)P.lc.delta);
   k.append(buf);
   return k;
 }
@@ -1105,6 +1110,25 @@ int lingam_bootstrap_accumulate(const int32_t* order, const double* B, int64_t d
   LG_TRY(lg::launch_boot_accumulate(order, B, (int)d, threshold, order_count, edge_count,
                                     coef_sum, (hipStream_t)stream),
          "bootstrap accumulate");
+  return LINGAM_OK;
+}
+
+int lingam_bootstrap_finalize(const int32_t* order_count, const int32_t* edge_count,
+                              const double* coef_sum, int64_t d, int32_t n_resamples,
+                              double* order_prob, double* edge_prob, double* coef_mean,
+                              void* stream) {
+  g_err[0] = 0;
+  if (!order_count || !edge_count || !order_prob || !edge_prob || (coef_sum && !coef_mean))
+    return fail(LINGAM_E_INVALID,
+                "order_count, edge_count, order_prob and edge_prob must be non-NULL, and "
+                "coef_mean when coef_sum is given");
+  if (d < 1) return fail(LINGAM_E_INVALID, "need d >= 1 (got %lld)", (long long)d);
+  if (d > kMaxD) return fail(LINGAM_E_UNSUPPORTED, "d <= %lld supported", (long long)kMaxD);
+  if (n_resamples < 1)
+    return fail(LINGAM_E_INVALID, "need n_resamples >= 1 (got %d)", n_resamples);
+  LG_TRY(lg::launch_boot_finalize(order_count, edge_count, coef_sum, (int)d, n_resamples,
+                                  order_prob, edge_prob, coef_mean, (hipStream_t)stream),
+         "bootstrap finalize");
   return LINGAM_OK;
 }
 

@@ -541,6 +541,11 @@ hipError_t launch_adjacency(const AdjLayout& A, char* ws, const float* X, int64_
 hipError_t launch_boot_accumulate(const int32_t* order, const double* B, int d, double thr,
                                   int32_t* order_count, int32_t* edge_count, double* coef_sum,
                                   hipStream_t st);
+// The counts divided by the number of resamples (see lingam_bootstrap_finalize).
+hipError_t launch_boot_finalize(const int32_t* order_count, const int32_t* edge_count,
+                                const double* coef_sum, int d, int32_t n_resamples,
+                                double* order_prob, double* edge_prob, double* coef_mean,
+                                hipStream_t st);
 
 // Dense FP64 pieces shared by the adjacency and VarLiNGAM.
 // In-place Cholesky of the leading p x p block of A (lower triangle holds L;

@@ -918,6 +918,21 @@ __global__ void k_boot_accumulate(const int32_t* __restrict__ order,
   }
 }
 
+// Bootstrap probabilities: the counts (and the coefficient sum) divided by the
+// number of resamples.
+__global__ void k_boot_finalize(const int32_t* __restrict__ order_count,
+                                const int32_t* __restrict__ edge_count,
+                                const double* __restrict__ coef_sum, int64_t total, double inv,
+                                double* __restrict__ order_prob, double* __restrict__ edge_prob,
+                                double* __restrict__ coef_mean) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    order_prob[e] = (double)order_count[e] * inv;
+    edge_prob[e] = (double)edge_count[e] * inv;
+    if (coef_sum) coef_mean[e] = coef_sum[e] * inv;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1317,6 +1332,17 @@ hipError_t launch_boot_accumulate(const int32_t* order, const double* B, int d, 
   const int64_t g = ((int64_t)d * d + 255) / 256;
   hipLaunchKernelGGL(k_boot_accumulate, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st,
                      order, B, d, thr, order_count, edge_count, coef_sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_boot_finalize(const int32_t* order_count, const int32_t* edge_count,
+                                const double* coef_sum, int d, int32_t n_resamples,
+                                double* order_prob, double* edge_prob, double* coef_mean,
+                                hipStream_t st) {
+  const int64_t total = (int64_t)d * d, g = (total + 255) / 256;
+  hipLaunchKernelGGL(k_boot_finalize, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, st,
+                     order_count, edge_count, coef_sum, total, 1.0 / (double)n_resamples,
+                     order_prob, edge_prob, coef_mean);
   return hipGetLastError();
 }
 

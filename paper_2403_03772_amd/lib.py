@@ -209,6 +209,8 @@ def load():
         lib.lingam_adjacency_pruned.restype = ctypes.c_int
         lib.lingam_bootstrap_accumulate.argtypes = [P, P, i64, ctypes.c_double, P, P, P, P]
         lib.lingam_bootstrap_accumulate.restype = ctypes.c_int
+        lib.lingam_bootstrap_finalize.argtypes = [P, P, P, i64, i32, P, P, P, P]
+        lib.lingam_bootstrap_finalize.restype = ctypes.c_int
         lib.lingam_adjacency.restype = ctypes.c_int
         lib.lingam_total_effects_workspace_size.argtypes = [i64]
         lib.lingam_total_effects_workspace_size.restype = sz
@@ -311,7 +313,7 @@ def residualize_workspace_size(n: int, d: int) -> int:
 def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool = False,
                  workspace=None, sync: bool = True, graph: bool = False,
                  autotune: bool = False, learned: Learned | None = None,
-                 record_features: bool = False, step_log: bool = False):
+                 record_features: bool = False, step_log: bool = False, out=None):
     """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
 
     Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
@@ -321,7 +323,9 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     asked for.  ``forced`` (sequence or tensor of column ids) fixes the first
     ``len(forced)`` choices (teacher forcing).  ``learned`` switches on the
     learned-proposal form; ``step_log`` returns its per-step decisions (see
-    ``lingam_opts.step_log``).
+    ``lingam_opts.step_log``).  ``out``: an int32 CUDA tensor of d entries to
+    receive the order (a graph-mode call replays its graph only for the same
+    buffers).
     """
     import torch
 
@@ -330,7 +334,13 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     n, d = X.shape
     ldx = X.stride(0) if n > 1 else d
     dev = X.device
-    order = torch.empty(d, dtype=torch.int32, device=dev)
+    if out is not None:
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.int32
+                and out.numel() == d and out.is_contiguous()):
+            raise TypeError("out must be a contiguous CUDA int32 tensor of d entries")
+        order = out
+    else:
+        order = torch.empty(d, dtype=torch.int32, device=dev)
     keep = []
     opts, prof, stats = _new_opts(lib, sync=sync, graph=graph, autotune=autotune,
                                   learned=learned, profile=profile, keep=keep)
@@ -525,10 +535,26 @@ def bootstrap(X, resamples, *, threshold: float = 0.0, graph: bool = False,
     for r, o in zip(rows, out["orders"]):
         B = fit(X, o, rows=r, workspace=ws)
         bootstrap_accumulate(o, B, threshold, order_count, edge_count, coef_sum)
-    R = float(len(rows))
-    return {"orders": out["orders"], "order_prob": order_count.double() / R,
-            "edge_prob": edge_count.double() / R, "coef_mean": coef_sum / R, "n": len(rows),
+    probs = bootstrap_finalize(order_count, edge_count, coef_sum, len(rows))
+    return {"orders": out["orders"], **probs, "n": len(rows),
             "order_count": order_count, "edge_count": edge_count}
+
+
+def bootstrap_finalize(order_count, edge_count, coef_sum, n_resamples: int) -> dict:
+    """Order / edge probabilities and mean coefficients from the running
+    counts of :func:`bootstrap_accumulate` (the library divides)."""
+    import torch
+
+    lib = load()
+    d = order_count.shape[0]
+    dev = order_count.device
+    order_prob = torch.empty((d, d), dtype=torch.float64, device=dev)
+    edge_prob = torch.empty_like(order_prob)
+    coef_mean = torch.empty_like(order_prob) if coef_sum is not None else None
+    _check(lib.lingam_bootstrap_finalize(_ptr(order_count), _ptr(edge_count), _ptr(coef_sum), d,
+                                         int(n_resamples), _ptr(order_prob), _ptr(edge_prob),
+                                         _ptr(coef_mean), _stream_ptr(torch, dev)))
+    return {"order_prob": order_prob, "edge_prob": edge_prob, "coef_mean": coef_mean}
 
 
 def varlingam_lagged_effects(M, B0):

@@ -159,6 +159,19 @@ def test_adjacency_argument_errors():
     assert a(thr=-1.0) == L.E_INVALID
     assert a(thr=float("nan")) == L.E_INVALID
     assert a(d=1 << 20) == L.E_UNSUPPORTED
+    f = lambda **k: lib.lingam_bootstrap_finalize(
+        v if k.get("oc", 1) else None, v if k.get("ec", 1) else None,
+        v if k.get("cs", 0) else None, k.get("d", 3), k.get("R", 4),
+        v if k.get("op", 1) else None, v if k.get("ep", 1) else None,
+        v if k.get("cm", 0) else None, None)
+    assert f(oc=0) == L.E_INVALID
+    assert f(ec=0) == L.E_INVALID
+    assert f(op=0) == L.E_INVALID
+    assert f(ep=0) == L.E_INVALID
+    assert f(cs=1) == L.E_INVALID       # a coefficient sum needs its output
+    assert f(d=0) == L.E_INVALID
+    assert f(R=0) == L.E_INVALID
+    assert f(d=1 << 20) == L.E_UNSUPPORTED
     assert lib.lingam_adjacency_workspace_size(1, 3) == 0
     assert lib.lingam_adjacency_workspace_size(10, 0) == 0
     # n = 100, d = 8: covariance, factor and inverse columns dominate

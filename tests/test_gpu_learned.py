@@ -428,3 +428,28 @@ def test_extension_columns_only_shrink_the_rows(lib):
     assert a.expanded > 0 and b.rows_sum < a.rows_sum
     print(f"rows measured: none {a.rows_sum}, 8 columns {c.rows_sum}, 128 columns "
           f"{b.rows_sum} (cleared {b.cleared} of {b.expanded})", flush=True)
+
+
+def test_graph_cache_follows_the_proposer(lib):
+    """Two graph-mode calls that differ only in the proposer buffer (same
+    input, output and workspace buffers) must not share a captured graph: the
+    second call's decisions follow its own network, as the eager calls show."""
+    import torch
+    from paper_2403_03772_amd import train_proposer as TP
+    s = _sem(300, 3000, 43)
+    X = _t(s.X)
+    trained = TP.default_proposer()
+    raw = _t(_proposer(9))
+    cfg = {p: lib.Learned(q, topk=32) for p, q in (("trained", trained), ("raw", raw))}
+    eager = {k: lib.causal_order(X, learned=c)["learned_stats"] for k, c in cfg.items()}
+    assert eager["trained"].certified != eager["raw"].certified  # the networks differ
+    ws = torch.empty(lib.workspace_size(3000, 300, cfg["trained"]), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty(300, dtype=torch.int32, device="cuda")
+    for k in ("trained", "raw", "trained", "raw"):
+        print(f"graph call with the {k} network", flush=True)
+        got = lib.causal_order(X, learned=cfg[k], graph=True, workspace=ws,
+                               out=out)["learned_stats"]
+        ref = eager[k]
+        assert (got.certified, got.expanded, got.suspects_sum, got.fallbacks) == \
+            (ref.certified, ref.expanded, ref.suspects_sum, ref.fallbacks), k
