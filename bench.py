@@ -12,16 +12,19 @@ Metric: sample-pair evaluations per second, where one evaluation is one
 residual-entropy term (log cosh and Gaussian-weighted moment) of one ordered
 pair at one sample; an ordering does n (d^3 - d) / 3 of them.  Also reported:
 the full-ordering time (ms_per_step), the roofline of the pair-moment kernel
-(timed with HIP events on the launch stream over the timed region) and the
-FP64 oracle timed on a bounded sample on the host cores.
+(timed with HIP events on the launch stream over the timed region; 12 flops
+per evaluation against the published FP32 vector peak, and the kernel's own
+issue model from live-measured instruction rates) and the FP64 oracle (table
+mode) timed on step 0 of the same workload on the host cores.
 
 Also reported (when the trained network is present): the learned-proposal
 form on the same input -- time per ordering, speed-up over the plain form,
 Kendall tau to the plain order, its decisions, and the same form with an
-untrained network (ablation) -- and a batched bootstrap workload.
+untrained network (ablation) --, the learned form against the plain one at
+d = 4096, n = 16384 (learned_large), and a batched bootstrap workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gene|large]
-                       [--no-cpu-baseline] [--no-batch] [--no-learned]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gene|large|batch]
+                       [--no-cpu-baseline] [--no-batch] [--no-learned] [--no-large]
 """
 from __future__ import annotations
 
@@ -37,14 +40,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Pair-kernel roofline (VALU-issue bound; see the design notes):
-# one evaluation = 8 FP32 VALU ops + 2 v_exp_f32 (the log of a product is
-# taken once per 16 samples and is not counted).  gfx950 issues 128 FP32
-# lane-ops/clk/CU and 32 transcendental lane-ops/clk/CU from the same issue
-# slots, so an evaluation costs 8/128 + 2/32 CU-clocks.
+# Pair-kernel roofline.  The kernel is bound by vector-ALU issue (not by HBM
+# and not by the matrix cores).  Its algorithmic cost per evaluation (one
+# residual direction of one pair at one sample) is 3 transcendentals (exp,
+# log, exp) + 9 FP32 VALU operations = 12 flops; priced against the published
+# FP32 vector peak of the MI355X (157.3 TFLOP/s: 256 CUs x 2.4 GHz x 256
+# flops/clk/CU, which counts packed FP32 FMAs).
 N_CU, CLOCK_HZ = 256, 2.4e9
+FLOPS_PER_EVAL = 12
+PEAK_FP32_TFLOPS = 157.3
+# Secondary figure, the issue model of the kernel's own instruction stream:
+# an evaluation issues 8 unpacked FP32 VALU instructions and 2 v_exp_f32 (the
+# log of a product is taken once per 16 samples), so it costs
+# 8 / R_fma + 2 / R_exp seconds per lane, with R_fma and R_exp the FP32 FMA
+# and v_exp_f32 lane-operation rates that the probe library measures live.
 VALU_PER_EVAL, TRANS_PER_EVAL = 8, 2
-PEAK_EVALS = N_CU * CLOCK_HZ / (VALU_PER_EVAL / 128.0 + TRANS_PER_EVAL / 32.0)
+
+
+def issue_rates():
+    """FP32 FMA lane-ops/s, v_exp_f32 lane-ops/s and evaluation-shaped units/s
+    (8 FMA + 2 exp2) measured by liblingam_probe.so on the current device."""
+    import ctypes
+
+    from paper_2403_03772_amd import build as b
+
+    if not os.path.exists(b.PROBE_LIB):
+        return None
+    lib = ctypes.CDLL(b.PROBE_LIB)
+    lib.lingam_probe_rates.argtypes = [ctypes.c_void_p]
+    lib.lingam_probe_rates.restype = ctypes.c_int
+    out = (ctypes.c_double * 3)()
+    if lib.lingam_probe_rates(out) != 0:
+        return None
+    return {"fma_lane_ops_per_s": out[0], "exp_lane_ops_per_s": out[1],
+            "eval_mix_per_s": out[2]}
+
+
+def pair_roofline(evals_per_s: float, rates) -> dict:
+    """roofline record of the pair kernel from its measured evaluation rate."""
+    tflops = evals_per_s * FLOPS_PER_EVAL / 1e12
+    rec = {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": tflops / PEAK_FP32_TFLOPS, "evals_per_s": evals_per_s,
+           "flops_per_eval": FLOPS_PER_EVAL}
+    if rates:
+        model = 1.0 / (VALU_PER_EVAL / rates["fma_lane_ops_per_s"]
+                       + TRANS_PER_EVAL / rates["exp_lane_ops_per_s"])
+        rec["issue_model"] = {
+            "evals_per_s": model, "valu_per_eval": VALU_PER_EVAL,
+            "trans_per_eval": TRANS_PER_EVAL, "probe": rates,
+            "fma_lane_ops_per_clk_per_cu": rates["fma_lane_ops_per_s"] / (N_CU * CLOCK_HZ),
+            "exp_lane_ops_per_clk_per_cu": rates["exp_lane_ops_per_s"] / (N_CU * CLOCK_HZ)}
+        rec["issue_model_frac"] = evals_per_s / model
+        rec["eval_mix_frac"] = evals_per_s / rates["eval_mix_per_s"]
+    return rec
 
 
 def evals_per_ordering(n: int, d: int) -> float:
@@ -74,26 +122,39 @@ def measured_traffic(d: int, n: int):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(X32, n: int, d: int, target_s: float = 15.0) -> dict:
-    """Time the FP64 oracle (literal Algorithm 1) on k_list rows of step 0."""
+def host_cpu() -> dict:
+    """The host's logical CPU count, the CPUs this process may use and the CPU
+    model name (from /proc/cpuinfo, the field lscpu prints as "Model name")."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "model": model}
+
+
+def cpu_baseline(X32, n: int, d: int) -> dict:
+    """Time the FP64 oracle in table mode (each ordered residual entropy once
+    per step, OpenMP over candidates) on step 0 of the workload: m (m - 1) n
+    sample-pair evaluations with m = d."""
     import oracle
 
     threads = oracle.num_threads()
-    # calibrate with one row per thread, then scale to ~target_s
-    rows = np.arange(threads, dtype=np.int32)
+    run = oracle.OrderRun(X32, mode="table")
     t0 = time.perf_counter()
-    oracle.step_measures_rows(X32, np.empty(0, np.int32), rows)
-    t1 = time.perf_counter() - t0
-    reps = max(1, min(64, int(target_s / max(t1, 1e-3))))
-    rows = np.arange(min(d, threads * reps), dtype=np.int32)
-    t0 = time.perf_counter()
-    oracle.step_measures_rows(X32, np.empty(0, np.int32), rows)
+    run.run(1)
     dt = time.perf_counter() - t0
-    evals = rows.size * (d - 1) * float(n)  # the algorithmic share of those rows
+    evals = float(d) * (d - 1) * n
+    cpu = host_cpu()
     return {"value": evals / dt, "unit": "sample-pair evals/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"k_list of {rows.size} variables at step 0 of the d={d}, n={n} "
-                      f"workload (literal Algorithm 1, FP64, {dt:.1f} s)"}
+            "sample": f"step 0 (all {d * (d - 1)} ordered pairs) of the d={d}, n={n} workload, "
+                      f"oracle table mode, FP64, {threads} OpenMP threads, {dt:.1f} s",
+            "host": cpu}
 
 
 def bench_batch(steps: int, warmup: int, seed: int) -> dict:
@@ -174,7 +235,8 @@ def reversed_edges(order, B) -> int:
     return int(np.sum(pos[parent] > pos[child]))
 
 
-def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None):
+def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None, rates=None,
+                profile=True):
     """The learned-proposal form on the same input: time per ordering, speed-up
     over the plain form, Kendall tau to the plain order, decisions, the work
     actually performed and the candidate-row kernels against the roofline."""
@@ -194,11 +256,20 @@ def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None):
     dt = (time.perf_counter() - t0) / steps
     order = out["order"].cpu().numpy()
     st = out["learned_stats"]
-    p = lg.causal_order(X, learned=cfg, workspace=ws, profile=True)["profile"]
-    cand_ms, cand_evals, pair_ms, pair_evals = p.cand_ms, p.cand_evals, p.pair_ms, p.pair_evals
-    steps = 1  # the kernel figures below are per profiled ordering
-    small = sum(m * (m - 1) * float(n) for m in range(2, min(64, d) + 1))
-    done = (cand_evals + pair_evals) / steps + small
+    rec = {}
+    if profile:
+        p = lg.causal_order(X, learned=cfg, workspace=ws, profile=True)["profile"]
+        cand_ms, cand_evals, pair_ms, pair_evals = p.cand_ms, p.cand_evals, p.pair_ms, p.pair_evals
+        small = sum(m * (m - 1) * float(n) for m in range(2, min(64, d) + 1))
+        done = cand_evals + pair_evals + small
+        rec = {
+            "evals_done": done,
+            "evals_done_per_s": done / dt,
+            "cand_kernel": dict(pair_roofline(cand_evals / (cand_ms * 1e-3), rates),
+                                kernel="k_pair_cand + k_pair_ext + k_pair_susp",
+                                ms_per_ordering=cand_ms) if cand_ms else None,
+            "full_pair_ms_per_ordering": pair_ms,
+        }
     return {
         "ms_per_ordering": dt * 1e3,
         "speedup_vs_plain": plain_ms / (dt * 1e3),
@@ -215,15 +286,46 @@ def run_learned(lg, X, n, d, steps, warmup, cfg, plain_order, plain_ms, B=None):
                   "suspects_mean": st.suspects_sum / max(st.learned_steps, 1),
                   "cleared": st.cleared,
                   "rows_mean": st.rows_sum / max(st.learned_steps, 1)},
-        "evals_done": done,
-        "evals_done_per_s": done / dt,
-        "cand_kernel": {"bound": "alu", "kernel": "k_pair_cand + k_pair_ext + k_pair_susp",
-                        "achieved": cand_evals / (cand_ms * 1e-3) / 1e9 if cand_ms else None,
-                        "peak": PEAK_EVALS / 1e9, "unit": "Geval/s",
-                        "frac": cand_evals / (cand_ms * 1e-3) / PEAK_EVALS if cand_ms else None,
-                        "ms_per_ordering": cand_ms / steps},
-        "full_pair_ms_per_ordering": pair_ms / steps,
+        **rec,
     }
+
+
+def run_large(lg, tp, seed: int, rates) -> dict:
+    """The learned form's target workload, d = 4096, n = 16384 (the gene family):
+    one plain ordering, then the exact learned ordering, and the exact form
+    with a full-step audit every 32 steps (top-K = 64): time, speed-up over the
+    plain ordering and Kendall tau to the plain order."""
+    import torch
+    from paper_2403_03772_amd import synth
+
+    d, n = 4096, 16384
+    progress(f"large workload: generating d={d}, n={n}")
+    sem = synth.workload_gene_scale(seed=seed, d=d, n=n)
+    X = torch.as_tensor(np.ascontiguousarray(sem.X, dtype=np.float32), device="cuda:0")
+    B = sem.B
+    del sem
+    ws = torch.empty(lg.workspace_size(n, d), dtype=torch.uint8, device="cuda:0")
+    progress("large workload: plain ordering (about two minutes)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    order = lg.causal_order(X, workspace=ws)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    plain_order = order.cpu().numpy()
+    del ws
+    progress(f"large workload: plain {plain_ms / 1e3:.1f} s")
+    prop = tp.default_proposer()
+    rec = {"workload": "gene-expression-scale SEM", "d": d, "n": n, "seed": seed,
+           "plain_ms": plain_ms, "plain_evals_per_s": evals_per_ordering(n, d) / (plain_ms * 1e-3),
+           "plain_reversed_edges": reversed_edges(plain_order, B)}
+    for name, cfg in (("exact", lg.Learned(prop, topk=64)),
+                      ("audited_every_32", lg.Learned(prop, topk=64, audit_every=32))):
+        progress(f"large workload: learned ({name})")
+        rec[name] = run_learned(lg, X, n, d, 1, 0, cfg, plain_order, plain_ms, B, rates,
+                                profile=False)
+        progress(f"large workload: learned ({name}) {rec[name]['ms_per_ordering'] / 1e3:.1f} s, "
+                 f"{rec[name]['speedup_vs_plain']:.2f}x, tau {rec[name]['kendall_tau']:.4f}")
+    return rec
 
 
 def progress(msg: str) -> None:
@@ -356,6 +458,12 @@ def main() -> int:
                     help="skip the batched bootstrap workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal form")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the learned-vs-plain record at d=4096, n=16384 (about "
+                         "three minutes)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="with --workload large: only the exact learned ordering (one, "
+                         "untimed warm-up none; for kernel profiles of the learned form)")
     ap.add_argument("--exact-only", action="store_true",
                     help="of the learned forms, run only the exact one (for its profile)")
     ap.add_argument("--no-aux", action="store_true",
@@ -386,6 +494,25 @@ def main() -> int:
         print(json.dumps(rec), flush=True)
         return 0
 
+    if args.workload == "large" and args.learned_only:
+        d, n = 4096, 16384
+        sem = synth.workload_gene_scale(seed=args.seed, d=d, n=n)
+        X = torch.as_tensor(np.ascontiguousarray(sem.X, dtype=np.float32), device="cuda:0")
+        cfg = lg.Learned(tp.default_proposer(), topk=64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = lg.causal_order(X, learned=cfg)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = out["learned_stats"]
+        print(json.dumps({"workload": "learned exact ordering only", "d": d, "n": n,
+                          "ms": dt * 1e3, "learned_steps": st.learned_steps,
+                          "certified": st.certified, "expanded": st.expanded,
+                          "suspects_mean": st.suspects_sum / max(st.learned_steps, 1),
+                          "rows_mean": st.rows_sum / max(st.learned_steps, 1),
+                          "reversed_edges": reversed_edges(out["order"].cpu().numpy(), sem.B)}),
+              flush=True)
+        return 0
     d, n = (1024, 8192) if args.workload == "gene" else (4096, 16384)
     if args.workload == "large" and args.steps == 3 and args.warmup == 1:
         args.steps, args.warmup = 1, 0  # one plain ordering takes about two minutes
@@ -399,6 +526,14 @@ def main() -> int:
     evals = evals_per_ordering(n, d)
     value = evals * args.steps / dt
     achieved = pl["pair_evals"] / (pl["pair_ms"] * 1e-3)
+    progress("issue-rate probe")
+    rates = issue_rates()
+    launches = max(pl["pair_launches"], 1)
+    # algorithmic bytes of one k_pair launch: one pass over the active FP32
+    # rows (4 n bytes per variable), mean over the launches of an ordering
+    # (steps with m > 64 active variables; smaller steps run the FP64 path)
+    alg_bytes = 4.0 * n * np.mean(np.arange(65, d + 1)) if d > 64 else 0.0
+    traffic = measured_traffic(d, n)
     rec = {
         "metric": f"sample-pair evals/s (plain DirectLiNGAM ordering, d={d}, n={n})",
         "reversed_edges": reversed_edges(pl["order"], sem.B),
@@ -416,27 +551,30 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "gene-expression-scale linear non-Gaussian SEM, plain ordering",
                    "d": d, "n": n, "seed": args.seed, "indeg": 4, "form": "plain"},
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_pair",
-            "achieved": achieved / 1e9,
-            "peak": PEAK_EVALS / 1e9,
-            "unit": "Geval/s",
-            "frac": achieved / PEAK_EVALS,
-            "traffic": measured_traffic(d, n),
-            "traffic_unit": "HBM bytes per launch",
-            "avg_launch_ms": pl["pair_ms"] / max(pl["pair_launches"], 1),
-            "launches": pl["pair_launches"],
-            "share_of_step": pl["pair_ms"] / (dt * 1e3),
-        },
+        "roofline": dict(
+            pair_roofline(achieved, rates),
+            kernel="k_pair",
+            traffic=traffic,
+            traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            algorithmic_bytes=alg_bytes,
+            traffic_over_algorithmic=traffic / alg_bytes if traffic and alg_bytes else None,
+            avg_launch_ms=pl["pair_ms"] / launches,
+            launches=pl["pair_launches"],
+            share_of_step=pl["pair_ms"] / (dt * 1e3),
+        ),
         "gram": {"bound": "mfma", "ms": pl["gram_ms"] / args.steps,
                  "achieved": pl["gram_flops"] / (pl["gram_ms"] * 1e-3) / 1e12
                  if pl["gram_ms"] else None,
                  "peak": 78.6, "unit": "TFLOP/s (fp64)"},
+        # residual update: algorithmic 8 B per sample and remaining variable
+        # (read and write the FP32 residual); the kernel moves 28 B (FP64
+        # master copy read and written, FP32 copy written)
         "resid": {"bound": "hbm", "ms": pl["resid_ms"] / args.steps,
-                  "achieved": pl["resid_bytes"] / (pl["resid_ms"] * 1e-3) / 1e9
+                  "achieved": pl["resid_bytes"] * 8.0 / 28.0 / (pl["resid_ms"] * 1e-3) / 1e9
                   if pl["resid_ms"] else None,
-                  "peak": 8000.0, "unit": "GB/s"},
+                  "peak": 8000.0, "unit": "GB/s",
+                  "moved_gb_per_s": pl["resid_bytes"] / (pl["resid_ms"] * 1e-3) / 1e9
+                  if pl["resid_ms"] else None},
         "learned": None,
     }
     if not args.no_learned and not os.path.exists(tp.WEIGHTS):
@@ -451,7 +589,7 @@ def main() -> int:
         exact = lg.Learned(prop, topk=K)
         progress("learned (exact)")
         rec["learned"] = run_learned(lg, X, n, d, args.steps, lw, exact, pl["order"],
-                                     ms_per_step, B)
+                                     ms_per_step, B, rates)
         rec["learned"]["proposer"] = {k: meta.get(k) for k in
                                       ("sems", "d", "n", "big_sems", "big_d", "target",
                                        "lists", "holdout", "holdout_big")}
@@ -460,14 +598,14 @@ def main() -> int:
         if not args.exact_only:
             progress("learned (fast)")
             rec["learned"]["fast"] = run_learned(lg, X, n, d, args.steps, lw, fast,
-                                                 pl["order"], ms_per_step, B)
+                                                 pl["order"], ms_per_step, B, rates)
         if args.workload == "large" and not args.exact_only:
             # the exact form with a full-step audit every 32 steps (the audits
             # only repeat exact decisions; this records what they cost)
             progress("learned (exact, audited)")
             rec["learned"]["audited"] = run_learned(
                 lg, X, n, d, args.steps, lw, lg.Learned(prop, topk=K, audit_every=32),
-                pl["order"], ms_per_step, B)
+                pl["order"], ms_per_step, B, rates)
         if args.workload == "gene" and not args.exact_only:
             # ablation: the exact form with an untrained (random) network (not on
             # the large workload, where it runs about as long as the plain form)
@@ -476,7 +614,7 @@ def main() -> int:
             progress("learned (untrained)")
             rec["learned"]["untrained"] = run_learned(lg, X, n, d, 1, 0,
                                                       lg.Learned(raw, topk=K), pl["order"],
-                                                      ms_per_step, B)
+                                                      ms_per_step, B, rates)
     if args.workload == "gene" and not args.no_aux:
         progress("adjacency along the plain order")
         rec["adjacency"] = run_adjacency(lg, X, n, d, torch.as_tensor(pl["order"]).cuda())
@@ -492,6 +630,9 @@ def main() -> int:
         if not args.no_aux:
             progress("bootstrap statistics")
             rec["bootstrap"] = bench_bootstrap(args.seed)
+    if (args.workload == "gene" and not args.no_learned and not args.no_large
+            and os.path.exists(tp.WEIGHTS)):
+        rec["learned_large"] = run_large(lg, tp, args.seed, rates)
     if args.copy_calibration:
         src = torch.ones(256 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)

@@ -20,6 +20,8 @@ ctypes and numpy.  Each wrapper names the part of the paper it follows:
   forcing.
 * :class:`OrderRun` -- the same search advanced in resumable pieces.
 * :func:`step_measures_rows` -- k_list entries of chosen rows at one step.
+* :func:`step_measures_all` -- every k_list entry of one teacher-forced step
+  (table mode).
 * :func:`pair_matrix` -- the whole measure matrix between active columns.
 * :func:`residualize` -- least-squares removal of one variable's effect.
 * :func:`var_fit` -- least-squares VAR fit with intercept (Section 3.2, the
@@ -99,6 +101,10 @@ def _load():
         lib.lo_causal_order_f64.restype = ctypes.c_int
         lib.lo_step_measures_rows.argtypes = [P, i64, i64, i64, P, i32, P, i32, P]
         lib.lo_step_measures_rows.restype = ctypes.c_int
+        lib.lo_step_measures_all.argtypes = [P, i64, i64, i64, P, i32, P]
+        lib.lo_step_measures_all.restype = ctypes.c_int
+        lib.lo_step_measures_all_f64.argtypes = [P, i64, i64, i64, P, i32, P]
+        lib.lo_step_measures_all_f64.restype = ctypes.c_int
         lib.lo_residualize.argtypes = [P, i64, i64, i64, P, i32, i32]
         lib.lo_residualize.restype = ctypes.c_int
         lib.lo_var_fit.argtypes = [P, i64, i64, i64, i32, P, P]
@@ -261,6 +267,25 @@ def step_measures_rows(X, prefix, rows) -> np.ndarray:
     code = _load().lo_step_measures_rows(_ptr(X), n, d, d, _ptr(p) if p.size else None,
                                          p.size, _ptr(r) if r.size else None, r.size, _ptr(out))
     _check(code, "step_measures_rows")
+    return out
+
+
+def step_measures_all(X, prefix, fp64: bool = False) -> np.ndarray:
+    """Every k_list entry of step t = len(prefix) after regressing out
+    ``prefix`` in order (table mode), by original column id; NaN for the
+    prefix.  X is cast to FP32 first (what the GPU receives) unless ``fp64``
+    (VAR residuals are FP64 data)."""
+    p = np.ascontiguousarray(prefix, dtype=np.int32)
+    if fp64:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        fn = _load().lo_step_measures_all_f64
+    else:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        fn = _load().lo_step_measures_all
+    n, d = X.shape
+    out = np.empty(d, dtype=np.float64)
+    _check(fn(_ptr(X), n, d, d, _ptr(p) if p.size else None, p.size, _ptr(out)),
+           "step_measures_all")
     return out
 
 

@@ -577,6 +577,78 @@ done:
   return status;
 }
 
+/*
+ * Every k_list entry of step t = prefix_len in table mode, after regressing
+ * out the variables of `prefix` in that order (teacher forcing along a given
+ * order): the residualisation of the outer loop (R6) step by step, then one
+ * table-mode step (the memoised Algorithm 1) on the active columns.
+ *   Xc   FP64 column-major n x d (column v at Xc + v * n), consumed (modified).
+ *   out  double[d]: out[v] = k_list entry of v for active v, NaN for the prefix.
+ */
+static int lo_step_measures_all_cols(double* Xc, int64_t n, int64_t d, const int32_t* prefix,
+                                     int32_t prefix_len, double* out) {
+  int32_t* U = (int32_t*)malloc(sizeof(int32_t) * (size_t)d);
+  double* k_list = (double*)malloc(sizeof(double) * (size_t)d);
+  int status = LO_OK;
+  if (!U || !k_list) {
+    status = LO_NOMEM;
+    goto done;
+  }
+  for (int32_t v = 0; v < d; ++v) U[v] = v;
+  int32_t m = (int32_t)d;
+  for (int32_t t = 0; t < prefix_len; ++t) {
+    const int32_t e = prefix[t];
+    int found = 0;
+    for (int32_t p = 0; p < m; ++p) found |= (U[p] == e);
+    if (!found) {
+      status = LO_INVALID;
+      goto done;
+    }
+    status = lo_residualize_cols(Xc, n, U, m, e);
+    if (status) goto done;
+    int32_t w = 0;
+    for (int32_t p = 0; p < m; ++p)
+      if (U[p] != e) U[w++] = U[p];
+    m = w;
+  }
+  status = lo_step_table(Xc, n, U, m, k_list);
+  if (status) goto done;
+  for (int64_t v = 0; v < d; ++v) out[v] = NAN;
+  for (int32_t p = 0; p < m; ++p) out[U[p]] = k_list[p];
+done:
+  free(U);
+  free(k_list);
+  return status;
+}
+
+/* lo_step_measures_all_cols on FP32 row-major input (what the GPU receives). */
+int lo_step_measures_all(const float* X, int64_t n, int64_t d, int64_t ldx,
+                         const int32_t* prefix, int32_t prefix_len, double* out) {
+  if (!X || !out || n < 2 || d < 2 || ldx < d || prefix_len < 0 || prefix_len > d - 2 ||
+      (prefix_len > 0 && !prefix))
+    return LO_INVALID;
+  double* Xc = lo_load_columns(X, n, d, ldx);
+  if (!Xc) return LO_NOMEM;
+  const int status = lo_step_measures_all_cols(Xc, n, d, prefix, prefix_len, out);
+  free(Xc);
+  return status;
+}
+
+/* The same on FP64 row-major input (VAR residuals are FP64). */
+int lo_step_measures_all_f64(const double* X, int64_t n, int64_t d, int64_t ldx,
+                             const int32_t* prefix, int32_t prefix_len, double* out) {
+  if (!X || !out || n < 2 || d < 2 || ldx < d || prefix_len < 0 || prefix_len > d - 2 ||
+      (prefix_len > 0 && !prefix))
+    return LO_INVALID;
+  double* Xc = (double*)malloc(sizeof(double) * (size_t)n * (size_t)d);
+  if (!Xc) return LO_NOMEM;
+  for (int64_t v = 0; v < d; ++v)
+    for (int64_t k = 0; k < n; ++k) Xc[v * n + k] = X[k * ldx + v];
+  const int status = lo_step_measures_all_cols(Xc, n, d, prefix, prefix_len, out);
+  free(Xc);
+  return status;
+}
+
 /* One residualisation on a row-major FP64 matrix (the primitive the library's
  * lingam_residualize entry point implements): for every active column v != exo,
  * x_v <- x_v - (cov(x_v, x_exo)/var(x_exo)) x_exo.  In place. */

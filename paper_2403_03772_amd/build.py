@@ -15,6 +15,10 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblingam_mi355x.so")
 SOURCES = ["lingam_kernels.hip", "lingam_learned.hip", "lingam_linalg.hip", "lingam_abi.cpp"]
+# the issue-rate probe that bench.py uses for the pair kernel's roofline; a
+# library of its own, not part of the ordering library
+PROBE_LIB = os.path.join(HERE, "liblingam_probe.so")
+PROBE_SOURCE = "lingam_probe.hip"
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -25,8 +29,29 @@ COMMON = [
 ]
 
 
+def _hipcc(cmd, what):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    # hipcc's host pass warns that it does not know the packed-fp32 feature
+    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {what}:\n{err}")
+    return err
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the issue-rate probe library. Returns its path."""
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *COMMON, "-shared", "-o", tmp, os.path.join(CSRC, PROBE_SOURCE)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    _hipcc(cmd, PROBE_SOURCE)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library. Returns its path."""
+    """Compile every source and link the shared library (and the probe
+    library). Returns the library's path."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
@@ -35,11 +60,7 @@ def build(verbose: bool = False) -> str:
         cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        # hipcc's host pass warns that it does not know the packed-fp32 feature
-        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed on {src}:\n{err}")
+        err = _hipcc(cmd, src)
         if verbose and err.strip():
             print(err, file=sys.stderr)
         objs.append(obj)
@@ -49,6 +70,7 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 

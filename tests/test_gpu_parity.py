@@ -39,13 +39,20 @@ def _compare_full(lib, X, label):
     return order
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("seed", list(range(50)))
 def test_small_workload_matches_oracle(lib, seed):
-    """d = 10, n = 1000, ER in-degree 1.5, uniform noise."""
+    """d = 10, n = 1000, ER in-degree 1.5, uniform noise, seeds 0-49: every
+    measure of every step (teacher-forced), and the free-running orders are
+    identical up to the first step where the oracle itself has a near-tie."""
     s = synth.workload_small(seed)
     print(f"case small seed={seed}", flush=True)
     order = _compare_full(lib, s.X, f"small seed {seed}")
-    assert list(order) == list(oracle.causal_order(s.X, mode="table"))
+    free = oracle.causal_order(s.X, mode="table")
+    if list(order) != list(free):
+        t = int(np.flatnonzero(order != free)[0])
+        _, mr, _ = oracle.causal_order(s.X, forced=order[:t], mode="table", with_measures=True)
+        assert near_tie(mr[t], order[t], free[t]), f"seed {seed}: orders differ at step {t}"
+        print(f"seed {seed}: orders part at step {t}, an oracle near-tie")
 
 
 @pytest.mark.parametrize("d,n", [(2, 3), (3, 63), (5, 64), (9, 65), (17, 1000), (37, 777),

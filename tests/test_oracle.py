@@ -258,6 +258,41 @@ def test_teacher_forcing_and_row_measures_agree():
     assert np.max(np.abs(got - meas[3, rows])) <= 1e-12
 
 
+def test_step_measures_all_equals_literal_rows():
+    """Table-mode step after a forced prefix equals literal Algorithm 1 on every
+    active row (1e-12), with NaN exactly on the prefix."""
+    s = synth.er_sem(13, 900, indeg=2.0, noise_family=("uniform", "laplace", "exp"), seed=6)
+    prefix = np.array([5, 0, 11, 2], dtype=np.int32)
+    got = oracle.step_measures_all(s.X, prefix)
+    assert np.array_equal(np.isnan(got), np.isin(np.arange(13), prefix))
+    rows = np.array([v for v in range(13) if v not in prefix], dtype=np.int32)
+    lit = oracle.step_measures_rows(s.X, prefix, rows)
+    assert np.max(np.abs(got[rows] - lit)) <= 1e-12 * max(1.0, np.max(np.abs(lit)))
+    # FP64 input that is exactly the FP32 data gives the same numbers bit for bit
+    got64 = oracle.step_measures_all(s.X.astype(np.float32).astype(np.float64), prefix,
+                                     fp64=True)
+    assert np.array_equal(got64[rows], got[rows])
+
+
+def test_step_measures_all_prefix_is_a_projection():
+    """The outer loop's sequential regressions (R6) leave, up to centring, each
+    remaining column minus its least-squares projection on the prefix columns,
+    and the measures depend on the centred residuals only.  So the forced step
+    equals a plain step 0 on numpy's projection residuals (lstsq on the
+    centred prefix columns) of the remaining columns."""
+    s = synth.er_sem(12, 3000, indeg=2.0, noise_family=("uniform", "laplace"), seed=8)
+    X = s.X.astype(np.float32).astype(np.float64)
+    prefix = np.array([7, 3, 10], dtype=np.int32)
+    rest = np.array([v for v in range(12) if v not in prefix])
+    Xc = X - X.mean(axis=0)
+    A = Xc[:, prefix]
+    coef, *_ = np.linalg.lstsq(A, Xc[:, rest], rcond=None)
+    R = Xc[:, rest] - A @ coef
+    ref = oracle.step_measures_all(R, [], fp64=True)
+    got = oracle.step_measures_all(s.X, prefix)[rest]
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
 def test_degenerate_inputs_are_reported():
     rng = np.random.default_rng(1)
     X = rng.uniform(size=(100, 4))
