@@ -196,6 +196,28 @@ int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32
                         const lingam_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): lingam_causal_order
+ * without a workspace argument.  The workspace is a device array of
+ * LINGAM_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU the
+ * library runs on, held until the process ends; the call itself allocates
+ * nothing.
+ *   Arguments and results as for lingam_causal_order.
+ *   A size whose workspace (lingam_workspace_size(n, d, opts)) exceeds
+ *   LINGAM_NOALLOC_SCRATCH_BYTES returns LINGAM_E_UNSUPPORTED (64 MiB holds,
+ *   for example, d = 512 at n = 8192 or d = 256 at n = 16384); so do
+ *   LINGAM_FLAG_GRAPH, LINGAM_FLAG_AUTOTUNE and a non-NULL opts->profile.
+ * Every call on one GPU uses that GPU's array and leaves its contents behind
+ * (the call initialises what it needs).  Calls that overlap in time on the
+ * same GPU (several streams, several host threads, or a LINGAM_FLAG_NO_SYNC
+ * call still running on another stream) race on the array; calls one after
+ * another on one stream are safe.
+ */
+#define LINGAM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lingam_causal_order_noalloc(const float* X, int64_t n, int64_t d, int64_t ldx,
+                                int32_t* order, const lingam_opts* opts, void* stream);
+
+/*
  * One job of a batched call: the causal order of d columns of a sample
  * matrix, optionally over a resampled set of its rows.
  *   X        device FP32 [n_rows x ldx] row-major, read only (jobs may share it).

@@ -10,6 +10,9 @@ Functions mirror the C entry points:
 
 * :func:`causal_order` -- ``lingam_causal_order`` (DirectLiNGAM ordering,
   Section 2.2 / Algorithm 1 of AcceleratedLiNGAM).
+* :func:`causal_order_noalloc` -- ``lingam_causal_order_noalloc`` (the same
+  ordering with the workspace in the library's per-GPU scratch array: the
+  call allocates nothing).
 * :func:`residualize` -- ``lingam_residualize`` (least-squares removal of one
   variable's effect, Section 2.2).
 * :func:`varlingam_fit` -- ``varlingam_fit`` (VAR least squares, ordering of
@@ -47,6 +50,7 @@ from .lib import (  # noqa: F401
     bootstrap,
     bootstrap_accumulate,
     causal_order,
+    causal_order_noalloc,
     last_error,
     load,
     proposer_adam,

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblingam_mi355x.so")
-SOURCES = ["lingam_kernels.hip", "lingam_learned.hip", "lingam_linalg.hip", "lingam_abi.cpp"]
+SOURCES = ["lingam_kernels.hip", "lingam_learned.hip", "lingam_linalg.hip", "lingam_noalloc.hip",
+           "lingam_abi.cpp"]
 # the issue-rate probe that bench.py uses for the pair kernel's roofline; a
 # library of its own, not part of the ordering library
 PROBE_LIB = os.path.join(HERE, "liblingam_probe.so")

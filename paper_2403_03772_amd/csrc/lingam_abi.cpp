@@ -811,8 +811,15 @@ size_t lingam_workspace_size(int64_t n, int64_t d, const lingam_opts* opts) {
   return make_plan({j}, cu, learn_of(opts)).total;
 }
 
-int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
-                        const lingam_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// lingam_causal_order with the workspace given (ws) or, when noalloc, the
+// current device's scratch array.
+int causal_order_impl(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
+                      const lingam_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                      bool noalloc) {
   g_err[0] = 0;
   lingam_opts dflt;
   lingam_opts_init(&dflt);
@@ -830,6 +837,12 @@ int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32
                 (long long)kMaxD);
   int rc = check_opts(opts, d);
   if (rc != LINGAM_OK) return rc;
+  if (noalloc && (opts->flags & (LINGAM_FLAG_GRAPH | LINGAM_FLAG_AUTOTUNE)))
+    return fail(LINGAM_E_UNSUPPORTED,
+                "lingam_causal_order_noalloc: LINGAM_FLAG_GRAPH and LINGAM_FLAG_AUTOTUNE are "
+                "not available (graph instantiation and tuning allocate)");
+  if (noalloc && opts->profile)
+    return fail(LINGAM_E_UNSUPPORTED, "lingam_causal_order_noalloc: no profile");
   int cu = 0;
   rc = num_cu_of_current(&cu);
   if (rc != LINGAM_OK) return rc;
@@ -837,11 +850,37 @@ int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32
                   opts->forced_order, opts->forced_len, opts->record_features, opts->step_log};
   const std::vector<HostJob> jobs{j};
   const Plan P = make_plan(jobs, cu, learn_of(opts));
+  if (noalloc) {
+    if (P.total > (size_t)LINGAM_NOALLOC_SCRATCH_BYTES)
+      return fail(LINGAM_E_UNSUPPORTED,
+                  "lingam_causal_order_noalloc: n=%lld d=%lld needs %zu bytes of workspace, "
+                  "the scratch array holds %zu",
+                  (long long)n, (long long)d, P.total, (size_t)LINGAM_NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    rc = current_device(&dev);
+    if (rc != LINGAM_OK) return rc;
+    LG_TRY(lg::noalloc_scratch(dev, &ws), "hipGetSymbolAddress(scratch)");
+    ws_bytes = (size_t)LINGAM_NOALLOC_SCRATCH_BYTES;
+  }
   if (!ws || ws_bytes < P.total)
     return fail(LINGAM_E_WORKSPACE, "workspace of %zu bytes needed (got %zu)", P.total,
                 ws ? ws_bytes : (size_t)0);
   return run_engine(P, jobs, opts, nullptr, (char*)ws, (hipStream_t)stream, ok_fill, ok_hip,
                     ok_fill);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,
+                        const lingam_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  return causal_order_impl(X, n, d, ldx, order, opts, ws, ws_bytes, stream, false);
+}
+
+int lingam_causal_order_noalloc(const float* X, int64_t n, int64_t d, int64_t ldx,
+                                int32_t* order, const lingam_opts* opts, void* stream) {
+  return causal_order_impl(X, n, d, ldx, order, opts, nullptr, 0, stream, true);
 }
 
 static int batch_jobs(const lingam_job* jobs, int32_t n_jobs, std::vector<HostJob>* out) {

@@ -18,6 +18,10 @@
 
 namespace lg {
 
+// Device address of this device's scratch array (lingam_noalloc.hip), looked
+// up on the first call per device with that device current, then cached.
+hipError_t noalloc_scratch(int dev, void** ptr);
+
 // Variables per side of a pair tile handled by one workgroup (2 x 2 waves of
 // 4 x 4 variables each).
 constexpr int kTileVars = 8;

@@ -176,6 +176,8 @@ def load():
         lib.lingam_workspace_size.restype = sz
         lib.lingam_causal_order.argtypes = [P, i64, i64, i64, P, O, P, sz, P]
         lib.lingam_causal_order.restype = ctypes.c_int
+        lib.lingam_causal_order_noalloc.argtypes = [P, i64, i64, i64, P, O, P]
+        lib.lingam_causal_order_noalloc.restype = ctypes.c_int
         lib.lingam_residualize_workspace_size.argtypes = [i64, i64]
         lib.lingam_residualize_workspace_size.restype = sz
         lib.lingam_residualize.argtypes = [P, i64, i64, i64, P, i32, i32, P, sz, P]
@@ -313,7 +315,8 @@ def residualize_workspace_size(n: int, d: int) -> int:
 def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool = False,
                  workspace=None, sync: bool = True, graph: bool = False,
                  autotune: bool = False, learned: Learned | None = None,
-                 record_features: bool = False, step_log: bool = False, out=None):
+                 record_features: bool = False, step_log: bool = False, out=None,
+                 _noalloc: bool = False):
     """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
 
     Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
@@ -362,13 +365,18 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     if step_log:
         slog = torch.zeros(d, dtype=torch.int32, device=dev)
         opts.step_log = slog.data_ptr()
-    need = int(lib.lingam_workspace_size(n, d, ctypes.byref(opts)))
-    if need == 0:
-        raise LingamError(E_UNSUPPORTED, last_error() or f"unsupported size n={n} d={d}")
-    if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
-    code = lib.lingam_causal_order(_ptr(X), n, d, ldx, _ptr(order), ctypes.byref(opts),
-                                   _ptr(workspace), workspace.numel(), _stream_ptr(torch, dev))
+    if _noalloc:
+        code = lib.lingam_causal_order_noalloc(_ptr(X), n, d, ldx, _ptr(order),
+                                               ctypes.byref(opts), _stream_ptr(torch, dev))
+    else:
+        need = int(lib.lingam_workspace_size(n, d, ctypes.byref(opts)))
+        if need == 0:
+            raise LingamError(E_UNSUPPORTED, last_error() or f"unsupported size n={n} d={d}")
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        code = lib.lingam_causal_order(_ptr(X), n, d, ldx, _ptr(order), ctypes.byref(opts),
+                                       _ptr(workspace), workspace.numel(),
+                                       _stream_ptr(torch, dev))
     _check(code)
     if not (with_measures or profile or record_features or step_log or learned is not None):
         return order
@@ -382,6 +390,18 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     if stats is not None and sync:
         out["learned_stats"] = _stats_of(stats)
     return out
+
+
+def causal_order_noalloc(X, *, forced=None, with_measures: bool = False, sync: bool = True,
+                         learned: Learned | None = None, step_log: bool = False, out=None):
+    """:func:`causal_order` through ``lingam_causal_order_noalloc``: the library
+    keeps the workspace in its per-GPU scratch array (sizes up to
+    ``LINGAM_NOALLOC_SCRATCH_BYTES`` of workspace), so the call itself
+    allocates no device memory (outputs still come from the caller; here the
+    binding makes the order and measure tensors unless ``out`` is given).
+    Graph capture, autotuning and profiles are not available through it."""
+    return causal_order(X, forced=forced, with_measures=with_measures, sync=sync,
+                        learned=learned, step_log=step_log, out=out, _noalloc=True)
 
 
 def residualize(X, active, exo: int):
