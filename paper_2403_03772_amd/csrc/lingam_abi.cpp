@@ -285,15 +285,14 @@ StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, l
   StepTotals T;
   std::vector<lg::JobStep> js(P.njobs);
   const int K = P.lc.proposer ? P.lc.K : 0;
-  int64_t items = 0, items_c = 0;
+  int64_t items = 0;
   for (int k = 0; k < P.njobs; ++k) {
     js[k] = lg::job_step_base((int32_t)jobs[k].d, t, K, P.lc.min_m, jobs[k].record != nullptr);
     if (js[k].m >= 2 && !js[k].fp64) items += 2LL * js[k].ntiles;
-    if (js[k].learned) items_c += 2LL * js[k].nct;
   }
   for (int k = 0; k < P.njobs; ++k) {
     lg::job_split(js[k], (int32_t)P.L[k].n_pad, items, P.cu, tu);
-    lg::job_split_cand(js[k], (int32_t)P.L[k].n_pad, items_c, P.cu, tu);
+    lg::job_split_cand(js[k]);
     for (int kind = 0; kind < lg::kNumKinds; ++kind)
       T.g[kind] += lg::kind_count(js[k], kind);
     const int m = js[k].m;
@@ -385,7 +384,9 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (T.g[lg::kKPairE] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_ext(table, P.njobs, sc,
-                                   std::min<int32_t>(T.g[lg::kKPairE], P.cu * 8), st),
+                                   std::min<int32_t>(T.g[lg::kKPairE],
+                                                     P.cu * lg::kPairSlotsPerCu),
+                                   st),
                "pair ext");
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_ext_back(table, P.njobs, t, sc,
@@ -397,7 +398,9 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (T.g[lg::kKPairS] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_susp(table, P.njobs, sc,
-                                    std::min<int32_t>(T.g[lg::kKPairS], P.cu * 8), st),
+                                    std::min<int32_t>(T.g[lg::kKPairS],
+                                                      P.cu * lg::kPairSlotsPerCu),
+                                    st),
                "pair susp");
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
       }
@@ -410,7 +413,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     }
     if (T.g[lg::kKPair] > 0) {
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
-      LG_TRY(lg::launch_pair(table, P.njobs, sc, capped(T.g[lg::kKPair], 8), st, gated),
+      LG_TRY(lg::launch_pair(table, P.njobs, sc, capped(T.g[lg::kKPair], lg::kPairSlotsPerCu),
+                             st, gated),
              "pair");
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
       if (pf) pf->pair_evals += T.pair_evals;

@@ -28,6 +28,10 @@ constexpr int kTileVars = 8;
 constexpr int kWaveVars = 4;
 // Samples are padded to a multiple of this (one wavefront of samples).
 constexpr int kSampleQuantum = 64;
+// Resident workgroups per CU of the pair kernels (4 waves each; their
+// register budget allows 5 waves per SIMD): the bounded grids of the
+// suspect and extension passes launch this many per CU.
+constexpr int kPairSlotsPerCu = 5;
 // Steps with at most this many active variables run the FP64 pair kernel.
 constexpr int kFp64MaxM = 64;
 // Most aggressive split policy the workspace is sized for (see Tune).
@@ -200,7 +204,7 @@ struct JobStep {
   int32_t learned;    // 1: learned pass this step (m > min_m)
   int32_t gate;       // 1: the full step is skipped (set after the learned decision)
   int32_t nct;        // candidate tiles (K / 8) * nblk
-  int32_t nsplit_c;   // sample splits of the candidate pair kernel
+  int32_t nsplit_c;   // sample splits of the learned pair kernels (= nsplit)
   int32_t split_len_c;
   int32_t nsus;       // suspects of the second pass (set after the learned decision)
   int32_t nct2;       // suspect tiles ceil(nsus / 8) * nblk
@@ -353,15 +357,16 @@ __host__ __device__ inline int32_t suspect_cap(int32_t m, int32_t K, int32_t cap
   return c > 0 ? c / 8 * 8 : 0;
 }
 
-// Split of the candidate pair kernel given the batch's candidate (tile, direction) items.
-__host__ __device__ inline void job_split_cand(JobStep& s, int32_t n_pad, int64_t items_total,
-                                               int32_t num_cu, Tune tu) {
+// Split of the learned form's pair kernels (candidate, extension and suspect
+// rows): the full step's own split (job_split first).  Every pair then sums
+// its samples over the same ranges in the same order as the full step, so a
+// learned pass measures a pair bit for bit as the full step does and the
+// exact mode makes the plain search's decisions even where measures differ
+// only by rounding.
+__host__ __device__ inline void job_split_cand(JobStep& s) {
   if (!s.learned) return;
-  JobStep c{};
-  c.m = s.m;
-  job_split(c, n_pad, items_total, num_cu, tu);
-  s.nsplit_c = c.nsplit;
-  s.split_len_c = c.split_len;
+  s.nsplit_c = s.nsplit;
+  s.split_len_c = s.split_len;
 }
 
 __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {

@@ -80,22 +80,18 @@ __device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, i
                                    int32_t* __restrict__ pre) {
   const int lane = threadIdx.x & 63;
   JobStep s{};
-  long long mine = 0, mine_c = 0;
+  long long mine = 0;
   if (lane < njobs) {
     const JobDev& J = jobs[lane];
     s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
     if (s.m >= 2 && !s.fp64) mine = 2LL * s.ntiles;
-    if (s.learned) mine_c = 2LL * s.nct;
   }
-  long long items = mine, items_c = mine_c;
+  long long items = mine;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    items += __shfl_xor(items, off);
-    items_c += __shfl_xor(items_c, off);
-  }
+  for (int off = 32; off >= 1; off >>= 1) items += __shfl_xor(items, off);
   if (lane < njobs) {
     job_split(s, jobs[lane].n_pad, items, num_cu, tu);
-    job_split_cand(s, jobs[lane].n_pad, items_c, num_cu, tu);
+    job_split_cand(s);
     js[lane] = s;
   }
   for (int kind = 0; kind < kNumKinds; ++kind) {
@@ -121,25 +117,19 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
   const int tid = threadIdx.x;
   if (tid == 0) items = 0;
   __syncthreads();
-  __shared__ long long items_c;
-  if (tid == 0) items_c = 0;
-  __syncthreads();
-  long long mine = 0, mine_c = 0;
+  long long mine = 0;
   for (int j = tid; j < njobs; j += 1024) {
     const JobDev& J = jobs[j];
     const JobStep s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
     js[j] = s;
     if (s.m >= 2 && !s.fp64) mine += 2LL * s.ntiles;
-    if (s.learned) mine_c += 2LL * s.nct;
   }
   if (mine) atomicAdd(reinterpret_cast<unsigned long long*>(&items), (unsigned long long)mine);
-  if (mine_c)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&items_c), (unsigned long long)mine_c);
   __syncthreads();
   for (int j = tid; j < njobs; j += 1024) {
     JobStep s = js[j];
     job_split(s, jobs[j].n_pad, items, num_cu, tu);
-    job_split_cand(s, jobs[j].n_pad, items_c, num_cu, tu);
+    job_split_cand(s);
     js[j] = s;
   }
   __syncthreads();
@@ -393,8 +383,9 @@ __global__ __launch_bounds__(256) void k_pair(const JobDev* __restrict__ jobs, i
 }
 
 // The same kernel for gated launches (learned form): a bounded grid walks the
-// step's items.
-__global__ __launch_bounds__(256) void k_pair_loop(const JobDev* __restrict__ jobs, int njobs,
+// step's items (held at 5 waves per SIMD like the all-pairs kernel; the loop's
+// few extra values spill outside the sample loop).
+__global__ __launch_bounds__(256, 5) void k_pair_loop(const JobDev* __restrict__ jobs, int njobs,
                                                    const JobStep* __restrict__ js,
                                                    const int32_t* __restrict__ pre, int G) {
   pair_tiles<kModeAll, true>(jobs, njobs, js, pre, G);
@@ -992,7 +983,8 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
     for (int64_t t = 0; t + kFp64MaxM < d; ++t) {
       JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
       if (!s.learned) continue;
-      job_split_cand(s, (int32_t)L.n_pad, 2LL * s.nct, num_cu, worst);
+      job_split(s, (int32_t)L.n_pad, 2LL * s.ntiles, num_cu, worst);
+      job_split_cand(s);
       const size_t need = (size_t)s.nct * (size_t)s.nsplit_c * 256;
       if (need > pc) pc = need;
     }
@@ -1011,7 +1003,8 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
     for (int64_t t = 0; t + kFp64MaxM < d && L.cap_s > 0; ++t) {
       JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
       if (!s.learned) continue;
-      job_split_cand(s, (int32_t)L.n_pad, 2LL * s.nct, num_cu, worst);
+      job_split(s, (int32_t)L.n_pad, 2LL * s.ntiles, num_cu, worst);
+      job_split_cand(s);
       const int32_t cs = suspect_cap(s.m, s.k, L.cap_s);
       const size_t need = (size_t)cdiv(cs, kTileVars) * s.nblk * (size_t)s.nsplit_c * 256;
       if (need > ps) ps = need;

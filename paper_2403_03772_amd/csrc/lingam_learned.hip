@@ -1040,13 +1040,16 @@ __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict
         pre + (int64_t)kind * (njobs + 1), sh);
 }
 
-__global__ __launch_bounds__(256) void k_pair_susp(const JobDev* __restrict__ jobs, int njobs,
+// The bounded-grid pair kernels walk their items in a loop; the launch bound
+// keeps them at the all-pairs kernel's 5 waves per SIMD (the few values the
+// loop adds spill outside the sample loop).
+__global__ __launch_bounds__(256, 5) void k_pair_susp(const JobDev* __restrict__ jobs, int njobs,
                                                    const JobStep* __restrict__ js,
                                                    const int32_t* __restrict__ pre, int G) {
   pair_tiles<kModeSusp, true>(jobs, njobs, js, pre, G);
 }
 
-__global__ __launch_bounds__(256) void k_pair_ext(const JobDev* __restrict__ jobs, int njobs,
+__global__ __launch_bounds__(256, 5) void k_pair_ext(const JobDev* __restrict__ jobs, int njobs,
                                                   const JobStep* __restrict__ js,
                                                   const int32_t* __restrict__ pre, int G) {
   pair_tiles<kModeExt, true>(jobs, njobs, js, pre, G);
