@@ -169,6 +169,11 @@ typedef struct lingam_opts {
                                    pass; bits 4..15 hold the step's suspect count and the
                                    bits from 16 up the suspects whose rows the second
                                    pass measured */
+  int32_t waves_all;            /* launch shape: waves per workgroup of the all-pairs
+                                   kernel (1, 2 or 4), 0 = the default or the autotuned
+                                   choice; results do not depend on it */
+  int32_t waves_rows;           /* ... of the learned form's candidate, extension and
+                                   suspect row kernels */
 } lingam_opts;
 
 /* Fill *opts with defaults (no forcing, no extra outputs, plain search, synchronous). */

@@ -359,6 +359,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
                   lg::Tune tu, Prof* pf) {
   lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
   const lg::SchedDev sc = lg::sched_at(ws + P.sched_off, P.njobs);
+  // bounded grids: one workgroup of w waves per resident slot
+  auto resident = [&](int w) { return P.cu * (lg::kPairWavesPerCu / w); };
   for (int t = 0; t + 1 < P.max_d; ++t) {
     const StepTotals T = step_totals(jobs, P, t, tu);
     if (T.g[lg::kKSel] == 0) break;  // every job finished
@@ -367,7 +369,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       LG_TRY(lg::launch_learned_front(table, P.njobs, t, sc, T.g, st), "features / scores");
     if (T.g[lg::kKPairC] > 0) {
       if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
-      LG_TRY(lg::launch_pair_cand(table, P.njobs, sc, T.g[lg::kKPairC], st), "pair cand");
+      LG_TRY(lg::launch_pair_cand(table, P.njobs, sc, T.g[lg::kKPairC], tu.w_rows, st),
+             "pair cand");
       if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
       if (pf) pf->cand_evals += T.cand_evals;
     }
@@ -384,9 +387,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (T.g[lg::kKPairE] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_ext(table, P.njobs, sc,
-                                   std::min<int32_t>(T.g[lg::kKPairE],
-                                                     P.cu * lg::kPairSlotsPerCu),
-                                   st),
+                                   std::min<int32_t>(T.g[lg::kKPairE], resident(tu.w_rows)),
+                                   tu.w_rows, st),
                "pair ext");
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_ext_back(table, P.njobs, t, sc,
@@ -398,9 +400,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
       if (T.g[lg::kKPairS] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_susp(table, P.njobs, sc,
-                                    std::min<int32_t>(T.g[lg::kKPairS],
-                                                      P.cu * lg::kPairSlotsPerCu),
-                                    st),
+                                    std::min<int32_t>(T.g[lg::kKPairS], resident(tu.w_rows)),
+                                    tu.w_rows, st),
                "pair susp");
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
       }
@@ -413,8 +414,10 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     }
     if (T.g[lg::kKPair] > 0) {
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
-      LG_TRY(lg::launch_pair(table, P.njobs, sc, capped(T.g[lg::kKPair], lg::kPairSlotsPerCu),
-                             st, gated),
+      LG_TRY(lg::launch_pair(table, P.njobs, sc,
+                             gated ? std::min<int32_t>(T.g[lg::kKPair], resident(tu.w_all))
+                                   : T.g[lg::kKPair],
+                             tu.w_all, st, gated),
              "pair");
       if (pf && pf->tm.on) pf->pair_ev.push_back(pf->tm.take(st));
       if (pf) pf->pair_evals += T.pair_evals;
@@ -435,11 +438,13 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
 }
 
 // --------------------------------------------------------------------------
-// split-policy autotuner
+// launch-shape autotuner
 // --------------------------------------------------------------------------
 
-const lg::Tune kDefaultTune{16, 8};
-const lg::Tune kCandidates[] = {{8, 8}, {16, 8}, {16, 4}, {32, 4}, {8, 16}, {16, 16}};
+const lg::Tune kDefaultTune{16, 8, 4, 4};
+// split policies (target workgroups per CU, least sample iterations per split)
+const int32_t kSplitCandidates[][2] = {{8, 8}, {16, 8}, {16, 4}, {32, 4}, {8, 16}, {16, 16}};
+const int32_t kWaveChoices[] = {4, 2, 1};
 
 int ilog2_ceil(double x) {
   int k = 0;
@@ -447,7 +452,8 @@ int ilog2_ceil(double x) {
   return k;
 }
 
-// Bucket key: total sample-pair work, largest padded n, number of jobs.
+// Bucket key: total sample-pair work, largest padded n, number of jobs, and
+// the candidate cap of the learned form (0: plain).
 std::string tune_key(const std::vector<HostJob>& jobs, const Plan& P) {
   double work = 0.0;
   int64_t maxn = 0;
@@ -455,14 +461,21 @@ std::string tune_key(const std::vector<HostJob>& jobs, const Plan& P) {
     work += (double)jobs[k].n * ((double)jobs[k].d * jobs[k].d * jobs[k].d) / 3.0;
     maxn = std::max<int64_t>(maxn, P.L[k].n_pad);
   }
-  char buf[96];
-  snprintf(buf, sizeof(buf), "gfx950/cu%d/w%d/n%d/j%d", P.cu, ilog2_ceil(work),
-           ilog2_ceil((double)maxn), ilog2_ceil((double)P.njobs));
+  char buf[112];
+  snprintf(buf, sizeof(buf), "gfx950/cu%d/w%d/n%d/j%d/k%d", P.cu, ilog2_ceil(work),
+           ilog2_ceil((double)maxn), ilog2_ceil((double)P.njobs),
+           P.lc.proposer ? P.lc.K : 0);
   return buf;
 }
 
-// Persistent cache: one "key target min_iters" line per entry in the file named
-// by LINGAM_AUTOTUNE_CACHE (when that variable is set).
+bool valid_tune(const lg::Tune& t) {
+  return t.target_per_cu >= 1 && t.target_per_cu <= lg::kMaxTargetPerCu &&
+         t.min_iters >= lg::kMinMinIters && lg::valid_waves(t.w_all) &&
+         lg::valid_waves(t.w_rows);
+}
+
+// Persistent cache: one "key target min_iters w_all w_rows" line per entry in
+// the file named by LINGAM_AUTOTUNE_CACHE (when that variable is set).
 void load_tune_file(DevState& ds) {
   if (ds.tunes_loaded) return;
   ds.tunes_loaded = true;
@@ -471,10 +484,10 @@ void load_tune_file(DevState& ds) {
   FILE* f = fopen(path, "r");
   if (!f) return;
   char key[128];
-  int a, b;
-  while (fscanf(f, "%127s %d %d", key, &a, &b) == 3)
-    if (a >= 1 && a <= lg::kMaxTargetPerCu && b >= lg::kMinMinIters)
-      ds.tunes[key] = lg::Tune{a, b};
+  lg::Tune t{};
+  while (fscanf(f, "%127s %d %d %d %d", key, &t.target_per_cu, &t.min_iters, &t.w_all,
+                &t.w_rows) == 5)
+    if (valid_tune(t)) ds.tunes[key] = t;
   fclose(f);
 }
 
@@ -484,14 +497,19 @@ void save_tune_file(const DevState& ds) {
   FILE* f = fopen(path, "w");
   if (!f) return;
   for (const auto& kv : ds.tunes)
-    fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.target_per_cu, kv.second.min_iters);
+    fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.target_per_cu,
+            kv.second.min_iters, kv.second.w_all, kv.second.w_rows);
   fclose(f);
 }
 
-// Time the pair kernel of a few sampled steps under every candidate policy on
-// the call's own data (after the set-up; the pair kernel only writes its
-// partial-sum scratch, and every position below m is valid while the active
-// list is still the identity), keep the fastest.
+// Time the pair kernels of a few sampled steps on the call's own data (after
+// the set-up; the pair kernels only write their partial-sum scratch, and
+// every position below m is valid while the active list is still the
+// identity), in three rounds: the split policy (the only choice that moves
+// results, at the rounding level), then the waves per workgroup of the
+// all-pairs kernel, then, for the learned form, of the row kernels (timed on
+// the candidate pass after that step's features, scores and top-K).  Ties
+// keep the earlier candidate.
 int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStream_t st,
              lg::Tune* out) {
   lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
@@ -505,26 +523,55 @@ int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStrea
   *out = kDefaultTune;
   if (steps.empty()) return LINGAM_OK;
   Timer tm;
-  double best = 1e300;
-  for (const lg::Tune& c : kCandidates) {
+  // summed time of the sampled steps' pair kernel (all pairs, or candidate rows)
+  auto time_steps = [&](const lg::Tune& c, bool rows, double* total) -> int {
     std::vector<std::pair<int, int>> ev;
     for (int t : steps) {
       const StepTotals T = step_totals(jobs, P, t, c);
-      if (T.g[lg::kKPair] <= 0) continue;
+      const int kind = rows ? lg::kKPairC : lg::kKPair;
+      if (T.g[kind] <= 0) continue;
       LG_TRY(lg::launch_step_schedule(table, P.njobs, t, P.cu, c, sc, st), "tune schedule");
+      if (rows)
+        LG_TRY(lg::launch_learned_front(table, P.njobs, t, sc, T.g, st), "tune front");
       const int a = tm.take(st);
-      LG_TRY(lg::launch_pair(table, P.njobs, sc, T.g[lg::kKPair], st), "tune pair");
+      if (rows)
+        LG_TRY(lg::launch_pair_cand(table, P.njobs, sc, T.g[kind], c.w_rows, st), "tune cand");
+      else
+        LG_TRY(lg::launch_pair(table, P.njobs, sc, T.g[kind], c.w_all, st), "tune pair");
       ev.emplace_back(a, tm.take(st));
     }
     LG_TRY(hipStreamSynchronize(st), "tune sync");
-    double tot = 0.0;
-    for (auto& e : ev) tot += tm.ms(e.first, e.second);
-    if (!ev.empty() && tot < best) {
-      best = tot;
-      *out = c;
+    *total = 0.0;
+    for (auto& e : ev) *total += tm.ms(e.first, e.second);
+    if (ev.empty()) *total = -1.0;
+    return LINGAM_OK;
+  };
+  auto pick = [&](lg::Tune c, int field, const int32_t* vals, int nv) -> int {
+    double best = 1e300;
+    for (int i = 0; i < nv; ++i) {
+      if (field == 0) {
+        c.target_per_cu = vals[2 * i];
+        c.min_iters = vals[2 * i + 1];
+      } else if (field == 1) {
+        c.w_all = vals[i];
+      } else {
+        c.w_rows = vals[i];
+      }
+      double ms = 0.0;
+      const int rc = time_steps(c, field == 2, &ms);
+      if (rc != LINGAM_OK) return rc;
+      if (ms >= 0.0 && ms < best) {
+        best = ms;
+        *out = c;
+      }
     }
-  }
-  return LINGAM_OK;
+    return LINGAM_OK;
+  };
+  int rc = pick(kDefaultTune, 0, &kSplitCandidates[0][0],
+                (int)(sizeof(kSplitCandidates) / sizeof(kSplitCandidates[0])));
+  if (rc == LINGAM_OK) rc = pick(*out, 1, kWaveChoices, 3);
+  if (rc == LINGAM_OK && P.lc.proposer) rc = pick(*out, 2, kWaveChoices, 3);
+  return rc;
 }
 
 // --------------------------------------------------------------------------
@@ -539,8 +586,9 @@ std::string graph_key(const std::vector<lg::JobDev>& dj, const Plan& P, void* ws
   std::string k;
   k.append(reinterpret_cast<const char*>(dj.data()), dj.size() * sizeof(lg::JobDev));
   char buf[256];
-  snprintf(buf, sizeof(buf), "|%p|%zu|%d|%d|%d|%p|%d|%d|%d|%d|%d|%a", ws, P.total,
-           tu.target_per_cu, tu.min_iters, P.cu, (const void*)P.lc.proposer, P.lc.K,
+  snprintf(buf, sizeof(buf), "|%p|%zu|%d|%d|%d|%d|%d|%p|%d|%d|%d|%d|%d|%a", ws, P.total,
+           tu.target_per_cu, tu.min_iters, tu.w_all, tu.w_rows, P.cu,
+           (const void*)P.lc.proposer, P.lc.K,
            P.lc.min_m, P.lc.audit_every, P.lc.max_suspects, P.lc.extension, (double)P.lc.delta);
   k.append(buf);
   return k;
@@ -674,6 +722,10 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
     save_tune_file(g_dev[dev]);
   }
 
+  // a launch shape the caller fixed (the results do not depend on it)
+  if (opts->waves_all) tu.w_all = opts->waves_all;
+  if (opts->waves_rows) tu.w_rows = opts->waves_rows;
+
   const bool graph = (opts->flags & LINGAM_FLAG_GRAPH) && !pf.tm.on;
   if (pf.tm.on) pf.all0 = pf.tm.take(st);
   if (!graph) {
@@ -729,6 +781,10 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
 }
 
 int check_learn(const lingam_opts* opts) {
+  if ((opts->waves_all && !lg::valid_waves(opts->waves_all)) ||
+      (opts->waves_rows && !lg::valid_waves(opts->waves_rows)))
+    return fail(LINGAM_E_INVALID, "waves_all %d / waves_rows %d must be 0, 1, 2 or 4",
+                opts->waves_all, opts->waves_rows);
   if (!opts->proposer) return LINGAM_OK;
   if (opts->topk < 8 || opts->topk > lg::kMaxTopK || opts->topk % 8 != 0)
     return fail(LINGAM_E_INVALID, "topk %d must be a multiple of 8 in [8, %d]", opts->topk,

@@ -50,6 +50,38 @@ __device__ __forceinline__ void eval_dir(float x, float y, float r, float c1h, f
   S2 = fmaf(t, e2, S2);
 }
 
+// One evaluation with the pair's scale constant c1 held per lane (pair_item
+// dithers it between its two FP32 neighbours so that its mean over the 64
+// lanes is the FP64 value): one multiply instead of the hi + lo product.
+__device__ __forceinline__ void eval_dir_lane(float x, float y, float r, float c1, float& P,
+                                              float& S1, float& S2) {
+  const float kM2 = (float)(-1.0 / (8.0 * kLog2e));  // rounds with relative error 2.7e-9
+  const float t = fmaf(-r, y, x);
+  const float m1 = c1 * fabsf(t);
+  const float e1 = __builtin_amdgcn_exp2f(m1);
+  P = fmaf(P, e1, P);
+  S1 = fmaf(m1, -0.5f, S1);
+  const float m2 = (kM2 * m1) * m1;
+  const float e2 = __builtin_amdgcn_exp2f(m2);
+  S2 = fmaf(t, e2, S2);
+}
+
+// The two FP32 values around c (equal when c is a float) and how many of the
+// 64 lanes take the upper one so that the lanes' mean is c to 1/128 of a
+// float spacing.
+__device__ inline void dither_float(double c, float& lo, float& hi, int& n_hi) {
+  const float f = (float)c;
+  if ((double)f == c) {
+    lo = hi = f;
+    n_hi = 0;
+    return;
+  }
+  const float g = (double)f < c ? nextafterf(f, INFINITY) : nextafterf(f, -INFINITY);
+  lo = fminf(f, g);
+  hi = fmaxf(f, g);
+  n_hi = (int)rint(64.0 * (c - (double)lo) / ((double)hi - (double)lo));
+}
+
 // FP64 log cosh and Gaussian-weighted term (marginals and the FP64 pair path).
 __device__ inline double logcosh64(double u) {
   const double a = fabs(u);
@@ -264,21 +296,30 @@ template <int kMode>
 __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int local,
                                           int wave, int lane);
 
-template <int kMode, bool kLoop>
+// W waves per workgroup (1, 2 or 4): every (tile, direction, split) item is
+// cut into 4 / W consecutive workgroup items, and the wave's quadrant of the
+// tile is (workgroup item mod 4 / W) * W + its wave in the workgroup.
+template <int kMode, bool kLoop, int W>
 __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int njobs,
                                            const JobStep* __restrict__ js,
                                            const int32_t* __restrict__ pre, int G) {
+  static_assert(W == 1 || W == 2 || W == 4, "1, 2 or 4 waves per workgroup");
+  constexpr int kQ = 4 / W;
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lw = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
   // contiguous range of (job, tile, direction, split) work so that the rows a
   // tile reads are shared in that XCD's L2.
   const int b = blockIdx.x;
   const int Q = G >> 3, R = G & 7, x = b & 7, idx = b >> 3;
   const int p = x * Q + (x < R ? x : R) + idx;
+  auto run = [&](int jb, int local) {
+    const int item = local / kQ;
+    pair_item<kMode>(jobs[jb], js[jb], item, (local - item * kQ) * W + lw, lane);
+  };
   int jb, local;
   if (!kLoop) {  // the grid is the schedule: one item per workgroup
-    if (locate(pre, njobs, p, jb, local)) pair_item<kMode>(jobs[jb], js[jb], local, wave, lane);
+    if (locate(pre, njobs, p, jb, local)) run(jb, local);
     return;
   }
   const int total = pre[njobs];
@@ -286,7 +327,7 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
   for (int it = 0; it < chunk; ++it) {
     const int w = p * chunk + it;
     if (w >= total || !locate(pre, njobs, w, jb, local)) break;
-    pair_item<kMode>(jobs[jb], js[jb], local, wave, lane);
+    run(jb, local);
   }
 }
 
@@ -326,7 +367,14 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   // The wave walks its 4 x 4 block as (a, c): dir 0 scores residual i|j with
   // i = pi0 + a, j = pj0 + c; dir 1 scores residual j|i with j = pj0 + a,
   // i = pi0 + c.  Lane q < 16 computes the coefficients of walk index q.
-  float my_r = 0.f, my_c1h = 0.f, my_c1l = 0.f;
+  // The scale c1 = -2 log2(e) / sqrt(1 - r^2) of a pair is not rounded to one
+  // FP32 value (that would scale every sample of the pair by the same
+  // rounding error and bias its log cosh moment): lanes below n_hi take the
+  // FP32 value above c1, the others the one below, so the lanes' mean is c1
+  // to 1/128 of a float spacing and the sample-to-lane assignment carries no
+  // bias (a lane's samples are s = lane, lane + 64, ...).
+  float my_r = 0.f, my_lo = 0.f, my_hi = 0.f;
+  int my_n = 0;
   {
     const int q = lane & 15, a = q >> 2, c = q & 3;
     const int pi = ipos(dir == 0 ? a : c), pj = jpos(dir == 0 ? c : a);
@@ -337,16 +385,16 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
       r = r > lim ? lim : (r < -lim ? -lim : r);
       const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
       my_r = (float)r;
-      my_c1h = (float)c1;
-      my_c1l = (float)(c1 - (double)my_c1h);
+      dither_float(c1, my_lo, my_hi, my_n);
     }
   }
-  float kr[16], kh[16], kl[16];
+  float kr[16], kc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     kr[q] = readlane_f(my_r, q);
-    kh[q] = readlane_f(my_c1h, q);
-    kl[q] = readlane_f(my_c1l, q);
+    const float lo = readlane_f(my_lo, q), hi = readlane_f(my_hi, q);
+    const int n_hi = __builtin_amdgcn_readlane(my_n, q);
+    kc[q] = lane < n_hi ? hi : lo;
   }
   // Row bases (wave-uniform) and a 32-bit per-lane byte offset, so loads use
   // the scalar-base + vector-offset form.  zr = rows of the regressed
@@ -399,7 +447,7 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int q = a * 4 + c;
-        eval_dir(xa[a], xb[c], kr[q], kh[q], kl[q], P[q], S1[q], S2[q]);
+        eval_dir_lane(xa[a], xb[c], kr[q], kc[q], P[q], S1[q], S2[q]);
       }
     }
     if (++kb == kLogBlock || !more) {

@@ -28,10 +28,11 @@ constexpr int kTileVars = 8;
 constexpr int kWaveVars = 4;
 // Samples are padded to a multiple of this (one wavefront of samples).
 constexpr int kSampleQuantum = 64;
-// Resident workgroups per CU of the pair kernels (4 waves each; their
-// register budget allows 5 waves per SIMD): the bounded grids of the
-// suspect and extension passes launch this many per CU.
-constexpr int kPairSlotsPerCu = 5;
+// Resident waves per CU of the pair kernels (their register budget allows 5
+// waves per SIMD): the bounded grids of the gated full step and of the
+// suspect and extension passes launch kPairWavesPerCu / w workgroups of w
+// waves per CU.
+constexpr int kPairWavesPerCu = 16;
 // Steps with at most this many active variables run the FP64 pair kernel.
 constexpr int kFp64MaxM = 64;
 // Most aggressive split policy the workspace is sized for (see Tune).
@@ -185,12 +186,22 @@ struct JobDev {
   double* kc2;
 };
 
-// Split policy of the pair kernel (autotuned): enough workgroups for
-// target_per_cu per CU, at least min_iters sample iterations per split.
+// Launch shape of the pair kernels (autotuned).
+//   Split policy of the sample range: enough (tile, direction) items for
+//   target_per_cu workgroups per CU, at least min_iters sample iterations per
+//   split.  The split decides which samples each lane sums, so it changes
+//   results at the rounding level.
+//   Waves per workgroup of the all-pairs kernel (w_all) and of the learned
+//   form's row kernels (w_rows), 1, 2 or 4: a workgroup takes w of the four
+//   4 x 4 quadrants of an 8 x 8 tile.  Every wave sums exactly what it sums
+//   in any other shape, so the results do not depend on these two.
 struct Tune {
   int32_t target_per_cu;
   int32_t min_iters;
+  int32_t w_all;
+  int32_t w_rows;
 };
+__host__ __device__ inline bool valid_waves(int32_t w) { return w == 1 || w == 2 || w == 4; }
 
 // One job's plan for one step.
 struct JobStep {
@@ -211,6 +222,8 @@ struct JobStep {
   int32_t k;          // candidates of this step's learned pass
   int32_t ne;         // extension columns (set with the suspect plan)
   int32_t nct3;       // extension tiles ceil(nsus / 8) * ceil(ne / 8)
+  int32_t q_all;      // workgroups per tile item of the all-pairs kernel (4 / w_all)
+  int32_t q_rows;     // ... of the learned row kernels (4 / w_rows)
 };
 
 // Candidates of a learned step with m active variables and at most K: about
@@ -224,7 +237,7 @@ __host__ __device__ inline int32_t step_topk(int32_t m, int32_t K) {
 
 // Workgroup-count kinds with a prefix array each.
 enum Kind : int {
-  kKPair = 0,   // k_pair: ntiles * 2 * nsplit
+  kKPair = 0,   // k_pair: ntiles * 2 * nsplit * q_all
   kKComb,       // k_combine: ceil(ntiles / 4)
   kKP64,        // k_pair64: ceil(m (m - 1) / 2 / 4)
   kKRowk,       // k_rowk: ceil(m / 4)
@@ -233,16 +246,16 @@ enum Kind : int {
   kKFeat,       // k_features: ceil(m / 4)
   kKMlp,        // k_mlp: ceil(m / 16)
   kKTopk,       // k_topk: 1
-  kKPairC,      // k_pair_cand: nct * 2 * nsplit_c
+  kKPairC,      // k_pair_cand: nct * 2 * nsplit_c * q_rows
   kKCombC,      // k_combine_cand: ceil(nct / 4)
   kKRowkC,      // k_cand_k rows: K / 4
   kKColC,       // k_cand_k columns: ceil(m / 64)
   kKLsel,       // k_lselect: 1
   kKWit,        // k_pair_wit: m
-  kKPairE,      // k_pair_ext: nct3 * 2 * nsplit_c (after the learned decision)
+  kKPairE,      // k_pair_ext: nct3 * 2 * nsplit_c * q_rows (after the learned decision)
   kKBoundE,     // k_ext_bound: ceil(nsus / 4) when nct3 > 0
   kKCompE,      // k_ext_compact: 1 when nct3 > 0
-  kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c (after the learned decision)
+  kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c * q_rows (after the learned decision)
   kKCombS,      // k_combine_susp: ceil(nct2 / 4)
   kKRowkS,      // k_susp_rowk: ceil(nsus / 4)
   kKLsel2,      // k_lselect2: 1 when nsus > 0
@@ -329,6 +342,8 @@ __host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t, int32_t K
 // Split of one FP32-path job given the batch's number of (tile, direction) items.
 __host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t items_total,
                                           int32_t num_cu, Tune tu) {
+  s.q_all = valid_waves(tu.w_all) ? 4 / tu.w_all : 1;
+  s.q_rows = valid_waves(tu.w_rows) ? 4 / tu.w_rows : 1;
   if (s.m < 2 || s.fp64) return;
   const int64_t iters = n_pad / kSampleQuantum;
   const int64_t target = (int64_t)num_cu * tu.target_per_cu;
@@ -373,7 +388,7 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
   if (s.m < 2) return 0;
   if (s.gate && gated_kind(kind)) return 0;
   switch (kind) {
-    case kKPair: return s.fp64 ? 0 : s.ntiles * 2 * s.nsplit;
+    case kKPair: return s.fp64 ? 0 : s.ntiles * 2 * s.nsplit * s.q_all;
     case kKComb: return s.fp64 ? 0 : cdiv(s.ntiles, 4);
     case kKP64: return s.fp64 ? cdiv((int64_t)s.m * (s.m - 1) / 2, 4) : 0;
     case kKRowk: return cdiv(s.m, 4);
@@ -382,16 +397,16 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
     case kKFeat: return s.feat ? cdiv(s.m, 4) : 0;
     case kKMlp: return s.learned ? cdiv(s.m, 16) : 0;
     case kKTopk: return s.learned ? 1 : 0;
-    case kKPairC: return s.learned ? s.nct * 2 * s.nsplit_c : 0;
+    case kKPairC: return s.learned ? s.nct * 2 * s.nsplit_c * s.q_rows : 0;
     case kKCombC: return s.learned ? cdiv(s.nct, 4) : 0;
     case kKRowkC: return s.learned ? cdiv(s.k, 4) : 0;
     case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
     case kKWit: return s.learned ? s.m : 0;
-    case kKPairE: return s.nct3 * 2 * s.nsplit_c;
+    case kKPairE: return s.nct3 * 2 * s.nsplit_c * s.q_rows;
     case kKBoundE: return s.nct3 > 0 ? cdiv(s.nsus, 4) : 0;
     case kKCompE: return s.nct3 > 0 ? 1 : 0;
-    case kKPairS: return s.nct2 * 2 * s.nsplit_c;
+    case kKPairS: return s.nct2 * 2 * s.nsplit_c * s.q_rows;
     case kKCombS: return cdiv(s.nct2, 4);
     case kKRowkS: return cdiv(s.nsus, 4);
     case kKLsel2: return s.nsus > 0 ? 1 : 0;
@@ -438,8 +453,8 @@ hipError_t launch_step_schedule(const JobDev* jobs, int njobs, int t, int num_cu
                                 SchedDev sc, hipStream_t st);
 hipError_t launch_gate_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipStream_t st);
 // loop: grid smaller than the schedule (gated launches), workgroups walk items
-hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st,
-                       bool loop = false);
+hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
+                       hipStream_t st, bool loop = false);
 hipError_t launch_combine(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_pair64(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_rowk(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
@@ -460,7 +475,7 @@ hipError_t launch_prop_prep(const float* in, PropDev* out, const JobDev* jobs, i
 // the host's totals of every kind.
 hipError_t launch_learned_front(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                 const int32_t* grid, hipStream_t st);
-hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
                             hipStream_t st);
 hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc,
                                const int32_t* grid, hipStream_t st);
@@ -468,10 +483,11 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
 // walks the items), and combine / row k / exact decision (grid-stride).
 hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, int stage,
                                 hipStream_t st);
-hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
+hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
+                           hipStream_t st);
 hipError_t launch_ext_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_bound,
                            int g_comp, hipStream_t st);
-hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
                             hipStream_t st);
 hipError_t launch_susp_back(const JobDev* jobs, int njobs, int t, SchedDev sc, int g_comb,
                             int g_rowk, int g_sel, hipStream_t st);

@@ -376,19 +376,23 @@ __global__ __launch_bounds__(256) void k_standardize(const JobDev* __restrict__ 
 // the step kernels
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_pair(const JobDev* __restrict__ jobs, int njobs,
-                                              const JobStep* __restrict__ js,
-                                              const int32_t* __restrict__ pre, int G) {
-  pair_tiles<kModeAll, false>(jobs, njobs, js, pre, G);
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_pair(const JobDev* __restrict__ jobs, int njobs,
+                                                 const JobStep* __restrict__ js,
+                                                 const int32_t* __restrict__ pre, int G) {
+  pair_tiles<kModeAll, false, W>(jobs, njobs, js, pre, G);
 }
 
 // The same kernel for gated launches (learned form): a bounded grid walks the
 // step's items (held at 5 waves per SIMD like the all-pairs kernel; the loop's
 // few extra values spill outside the sample loop).
-__global__ __launch_bounds__(256, 5) void k_pair_loop(const JobDev* __restrict__ jobs, int njobs,
-                                                   const JobStep* __restrict__ js,
-                                                   const int32_t* __restrict__ pre, int G) {
-  pair_tiles<kModeAll, true>(jobs, njobs, js, pre, G);
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_pair_loop(const JobDev* __restrict__ jobs,
+                                                         int njobs,
+                                                         const JobStep* __restrict__ js,
+                                                         const int32_t* __restrict__ pre,
+                                                         int G) {
+  pair_tiles<kModeAll, true, W>(jobs, njobs, js, pre, G);
 }
 
 // Sum the sample splits (FP64, fixed order), form both residual entropies and
@@ -960,7 +964,7 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
   L.ctrl = take(sizeof(Ctrl));
   // partial sums: the most splits any policy in range can give a job alone
   // (a batch only ever splits less)
-  const Tune worst{kMaxTargetPerCu, kMinMinIters};
+  const Tune worst{kMaxTargetPerCu, kMinMinIters, 4, 4};
   size_t pe = 0;
   for (int64_t t = 0; t + kFp64MaxM < d; ++t) {
     JobStep s = job_step_base((int32_t)d, (int32_t)t);
@@ -1100,15 +1104,23 @@ hipError_t launch_gate_schedule(const JobDev* jobs, int njobs, SchedDev sc, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st,
-                       bool loop) {
-  if (grid <= 0) return hipSuccess;
+template <int W>
+static void launch_pair_w(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st,
+                          bool loop) {
   if (loop)
-    hipLaunchKernelGGL(k_pair_loop, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+    hipLaunchKernelGGL(k_pair_loop<W>, dim3((unsigned)grid), dim3(64 * W), 0, st, jobs, njobs,
                        (const JobStep*)sc.js, pre_of(sc, njobs, kKPair), grid);
   else
-    hipLaunchKernelGGL(k_pair, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
+    hipLaunchKernelGGL(k_pair<W>, dim3((unsigned)grid), dim3(64 * W), 0, st, jobs, njobs,
                        (const JobStep*)sc.js, pre_of(sc, njobs, kKPair), grid);
+}
+
+hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
+                       hipStream_t st, bool loop) {
+  if (grid <= 0) return hipSuccess;
+  if (waves == 1) launch_pair_w<1>(jobs, njobs, sc, grid, st, loop);
+  else if (waves == 2) launch_pair_w<2>(jobs, njobs, sc, grid, st, loop);
+  else launch_pair_w<4>(jobs, njobs, sc, grid, st, loop);
   return hipGetLastError();
 }
 

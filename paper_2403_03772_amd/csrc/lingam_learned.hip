@@ -616,10 +616,11 @@ __global__ __launch_bounds__(1024) void k_topk(const JobDev* __restrict__ jobs, 
 // candidate rows of the measure
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_pair_cand(const JobDev* __restrict__ jobs, int njobs,
-                                                   const JobStep* __restrict__ js,
-                                                   const int32_t* __restrict__ pre, int G) {
-  pair_tiles<kModeCand, false>(jobs, njobs, js, pre, G);
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_pair_cand(const JobDev* __restrict__ jobs, int njobs,
+                                                      const JobStep* __restrict__ js,
+                                                      const int32_t* __restrict__ pre, int G) {
+  pair_tiles<kModeCand, false, W>(jobs, njobs, js, pre, G);
 }
 
 // Witness pairs: one workgroup per non-candidate position l whose candidate
@@ -1043,16 +1044,22 @@ __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict
 // The bounded-grid pair kernels walk their items in a loop; the launch bound
 // keeps them at the all-pairs kernel's 5 waves per SIMD (the few values the
 // loop adds spill outside the sample loop).
-__global__ __launch_bounds__(256, 5) void k_pair_susp(const JobDev* __restrict__ jobs, int njobs,
-                                                   const JobStep* __restrict__ js,
-                                                   const int32_t* __restrict__ pre, int G) {
-  pair_tiles<kModeSusp, true>(jobs, njobs, js, pre, G);
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_pair_susp(const JobDev* __restrict__ jobs,
+                                                         int njobs,
+                                                         const JobStep* __restrict__ js,
+                                                         const int32_t* __restrict__ pre,
+                                                         int G) {
+  pair_tiles<kModeSusp, true, W>(jobs, njobs, js, pre, G);
 }
 
-__global__ __launch_bounds__(256, 5) void k_pair_ext(const JobDev* __restrict__ jobs, int njobs,
-                                                  const JobStep* __restrict__ js,
-                                                  const int32_t* __restrict__ pre, int G) {
-  pair_tiles<kModeExt, true>(jobs, njobs, js, pre, G);
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_pair_ext(const JobDev* __restrict__ jobs,
+                                                        int njobs,
+                                                        const JobStep* __restrict__ js,
+                                                        const int32_t* __restrict__ pre,
+                                                        int G) {
+  pair_tiles<kModeExt, true, W>(jobs, njobs, js, pre, G);
 }
 
 // The extension columns' share of every listed suspect's k: one wave per
@@ -1587,11 +1594,22 @@ hipError_t launch_learned_front(const JobDev* jobs, int njobs, int t, SchedDev s
   return hipGetLastError();
 }
 
-hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+// The row kernels at 1, 2 or 4 waves per workgroup.
+#define LG_LAUNCH_W(kern, waves, grid, st, ...)                                          \
+  do {                                                                                   \
+    if ((waves) == 1)                                                                    \
+      hipLaunchKernelGGL(kern<1>, dim3((unsigned)(grid)), dim3(64), 0, st, __VA_ARGS__);  \
+    else if ((waves) == 2)                                                               \
+      hipLaunchKernelGGL(kern<2>, dim3((unsigned)(grid)), dim3(128), 0, st, __VA_ARGS__); \
+    else                                                                                 \
+      hipLaunchKernelGGL(kern<4>, dim3((unsigned)(grid)), dim3(256), 0, st, __VA_ARGS__); \
+  } while (0)
+
+hipError_t launch_pair_cand(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
                             hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair_cand, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
-                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKPairC), grid);
+  LG_LAUNCH_W(k_pair_cand, waves, grid, st, jobs, njobs, (const JobStep*)sc.js,
+              pre_kind(sc, njobs, kKPairC), grid);
   return hipGetLastError();
 }
 
@@ -1620,10 +1638,11 @@ hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, int 
   return hipGetLastError();
 }
 
-hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st) {
+hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
+                           hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair_ext, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
-                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKPairE), grid);
+  LG_LAUNCH_W(k_pair_ext, waves, grid, st, jobs, njobs, (const JobStep*)sc.js,
+              pre_kind(sc, njobs, kKPairE), grid);
   return hipGetLastError();
 }
 
@@ -1638,11 +1657,11 @@ hipError_t launch_ext_back(const JobDev* jobs, int njobs, int t, SchedDev sc, in
   return hipGetLastError();
 }
 
-hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid,
+hipError_t launch_pair_susp(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
                             hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair_susp, dim3((unsigned)grid), dim3(256), 0, st, jobs, njobs,
-                     (const JobStep*)sc.js, pre_kind(sc, njobs, kKPairS), grid);
+  LG_LAUNCH_W(k_pair_susp, waves, grid, st, jobs, njobs, (const JobStep*)sc.js,
+              pre_kind(sc, njobs, kKPairS), grid);
   return hipGetLastError();
 }
 

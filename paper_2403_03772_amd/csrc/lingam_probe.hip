@@ -5,9 +5,9 @@
 //     library is built with packed FP32 instruction selection switched off,
 //     so this is the unpacked rate the pair kernel's arithmetic runs at),
 //   * v_exp_f32 lane operations per second,
-//   * evaluation-shaped work per second: 8 FP32 FMAs + 2 v_exp_f32 per unit,
-//     all independent, i.e. the instruction mix of one pair evaluation without
-//     its loads.
+//   * evaluation-shaped work per second: 7 FP32 FMAs + 2 v_exp_f32 per unit,
+//     all independent, i.e. the instruction mix of one pair evaluation
+//     without its loads.
 // Every kernel keeps eight independent dependency chains per lane and enough
 // waves per SIMD that issue, not latency, bounds it; results are written out
 // so that nothing is removed as dead code.
@@ -56,8 +56,9 @@ __global__ __launch_bounds__(kThreads) void k_probe_exp(float* out, int iters) {
   out[gid] = s;
 }
 
-// The evaluation mix: each pass of the inner loop does 4 FMAs on each of 8
-// chains and 1 exp2 on each of 8 other chains, i.e. 4 units of 8 FMAs + 2 exp2.
+// The evaluation mix: each pass of the inner loop does 7 FMAs on each of 8
+// chains and 2 exp2 on each of 8 other chains, i.e. 8 units of 7 FMAs + 2
+// exp2 (the pair kernel's 7 VALU + 2 transcendentals per evaluation).
 __global__ __launch_bounds__(kThreads) void k_probe_mix(float* out, int iters, float a, float b) {
   const int gid = blockIdx.x * kThreads + threadIdx.x;
   float f[8], e[8];
@@ -68,19 +69,17 @@ __global__ __launch_bounds__(kThreads) void k_probe_mix(float* out, int iters, f
   }
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int u = 0; u < kUnroll / 4; ++u) {
+    for (int u = 0; u < kUnroll / 8; ++u) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        f[k] = fmaf(f[k], a, b);
-        f[k] = fmaf(f[k], a, b);
+      for (int r = 0; r < 7; ++r) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f[k] = fmaf(f[k], a, b);
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        f[k] = fmaf(f[k], a, b);
-        f[k] = fmaf(f[k], a, b);
-      }
+      for (int r = 0; r < 2; ++r) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) e[k] = __builtin_amdgcn_exp2f(-e[k]);
+        for (int k = 0; k < 8; ++k) e[k] = __builtin_amdgcn_exp2f(-e[k]);
+      }
     }
   }
   float s = 0.f;
@@ -96,7 +95,7 @@ extern "C" {
 /*
  * Measures the three rates above on the current device and writes them to
  * the host array out[3]: FP32 FMA lane-ops/s, v_exp_f32 lane-ops/s, and
- * evaluation-shaped units/s (8 FMA + 2 exp2 each).  Allocates a small device
+ * evaluation-shaped units/s (7 FMA + 2 exp2 each).  Allocates a small device
  * buffer (measurement only).
  * Returns 0 on success, a HIP error code otherwise.
  */
@@ -143,7 +142,7 @@ int lingam_probe_rates(double* out) {
   if (e != hipSuccess) return (int)e;
   out[0] = lanes * kUnroll * 8 / (ms[0] * 1e-3);
   out[1] = lanes * kUnroll * 8 / (ms[1] * 1e-3);
-  out[2] = lanes * (kUnroll / 4) * 4 / (ms[2] * 1e-3);
+  out[2] = lanes * (kUnroll / 8) * 8 / (ms[2] * 1e-3);
   return 0;
 }
 

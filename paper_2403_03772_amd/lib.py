@@ -88,6 +88,8 @@ class _Opts(ctypes.Structure):
         ("max_suspects", ctypes.c_int32),
         ("extension", ctypes.c_int32),
         ("step_log", ctypes.c_void_p),
+        ("waves_all", ctypes.c_int32),
+        ("waves_rows", ctypes.c_int32),
     ]
 
 
@@ -257,10 +259,13 @@ def _cuda_f32_matrix(torch, X, name="X"):
 
 
 def _new_opts(lib, *, sync=True, graph=False, autotune=False, learned=None, profile=False,
-              keep=None):
-    """lingam_opts with flags, the learned configuration and the profile."""
+              keep=None, waves=None):
+    """lingam_opts with flags, the learned configuration, the profile and the
+    launch shape (``waves`` = (all-pairs, row kernels) waves per workgroup)."""
     opts = _Opts()
     lib.lingam_opts_init(ctypes.byref(opts))
+    if waves is not None:
+        opts.waves_all, opts.waves_rows = int(waves[0]), int(waves[1])
     if not sync:
         opts.flags |= FLAG_NO_SYNC
     if graph:
@@ -316,7 +321,7 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
                  workspace=None, sync: bool = True, graph: bool = False,
                  autotune: bool = False, learned: Learned | None = None,
                  record_features: bool = False, step_log: bool = False, out=None,
-                 _noalloc: bool = False):
+                 waves=None, _noalloc: bool = False):
     """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
 
     Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
@@ -328,7 +333,9 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     learned-proposal form; ``step_log`` returns its per-step decisions (see
     ``lingam_opts.step_log``).  ``out``: an int32 CUDA tensor of d entries to
     receive the order (a graph-mode call replays its graph only for the same
-    buffers).
+    buffers).  ``waves``: (all-pairs, row kernels) waves per workgroup, each
+    1, 2 or 4 (``lingam_opts.waves_all`` / ``waves_rows``; None = default or
+    autotuned); the results do not depend on it.
     """
     import torch
 
@@ -346,7 +353,7 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
         order = torch.empty(d, dtype=torch.int32, device=dev)
     keep = []
     opts, prof, stats = _new_opts(lib, sync=sync, graph=graph, autotune=autotune,
-                                  learned=learned, profile=profile, keep=keep)
+                                  learned=learned, profile=profile, keep=keep, waves=waves)
     if forced is not None:
         f = torch.as_tensor(forced, dtype=torch.int32).to(dev).contiguous()
         keep.append(f)
@@ -650,7 +657,7 @@ def varlingam_fit(X, lags: int = 1, *, forced=None, with_measures: bool = False,
 def batch_causal_order(jobs, *, graph: bool = False, autotune: bool = False,
                        profile: bool = False, workspace=None, with_measures: bool = False,
                        raise_on_error: bool = True, learned: Learned | None = None,
-                       record_features: bool = False):
+                       record_features: bool = False, waves=None):
     """Causal orders of many jobs in one batched run.
 
     ``jobs``: sequence of dicts with ``X`` (CUDA float32, rows x d; jobs may
@@ -695,6 +702,7 @@ def batch_causal_order(jobs, *, graph: bool = False, autotune: bool = False,
         meas.append(m)
         feats.append(f)
     opts, prof, stats = _new_opts(lib, graph=graph, autotune=autotune, learned=learned,
+                                  waves=waves,
                                   profile=profile, keep=keep)
     need = int(lib.lingam_batch_workspace_size(arr, njobs, ctypes.byref(opts)))
     if need == 0:

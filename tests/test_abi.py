@@ -260,6 +260,25 @@ def test_learned_options_are_validated():
     assert lib.lingam_batch_workspace_size(J, 1, ctypes.byref(o)) > 0
 
 
+def test_launch_shape_is_validated():
+    """waves_all / waves_rows: 0 (default or autotuned), 1, 2 or 4 waves per
+    workgroup; anything else is refused on the host."""
+    lib = pkg.load()
+    o = _opts()
+    assert o.waves_all == 0 and o.waves_rows == 0
+    for w in (1, 2, 4):
+        o = _opts()
+        o.waves_all, o.waves_rows = w, w
+        assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) == \
+            lib.lingam_workspace_size(1000, 300, None)
+    for field, bad in (("waves_all", 3), ("waves_all", 8), ("waves_rows", -1), ("waves_rows", 5)):
+        o = _opts()
+        setattr(o, field, bad)
+        assert lib.lingam_workspace_size(1000, 300, ctypes.byref(o)) == 0, field
+        assert _call(opts=o) == L.E_INVALID, field
+        assert "waves" in pkg.last_error()
+
+
 def test_proposer_argument_errors():
     lib = pkg.load()
     P = ctypes.c_void_p(1)
