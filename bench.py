@@ -447,7 +447,7 @@ def run_plain(lg, X, n, d, steps, warmup):
         lg.causal_order(X, workspace=ws)
     torch.cuda.synchronize()
     acc = dict(pair_ms=0.0, pair_evals=0.0, pair_launches=0, gram_ms=0.0, gram_flops=0.0,
-               resid_ms=0.0, resid_bytes=0.0)
+               resid_ms=0.0, resid_bytes=0.0, tie_steps=0, tie_rows=0)
     orders = []
     t0 = time.perf_counter()
     for i in range(steps):
@@ -599,6 +599,9 @@ def main() -> int:
                   "peak": 8000.0, "unit": "GB/s",
                   "moved_gb_per_s": pl["resid_bytes"] / (pl["resid_ms"] * 1e-3) / 1e9
                   if pl["resid_ms"] else None},
+        # near-ties decided in FP64 (per ordering)
+        "fp64_ties": {"steps": pl["tie_steps"] // args.steps,
+                      "rows": pl["tie_rows"] // args.steps},
         "learned": None,
     }
     if not args.no_learned and not os.path.exists(tp.WEIGHTS):

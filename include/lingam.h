@@ -70,10 +70,13 @@ typedef enum {
 #define LINGAM_FLAG_GRAPH 2u    /* capture the whole call into one HIP graph, cache the
                                    instantiated graph per (jobs, buffers, workspace) and
                                    replay it on identical later calls */
-#define LINGAM_FLAG_AUTOTUNE 4u /* time the candidate split policies of the pair kernel on
-                                   this call's data the first time its size bucket is seen
-                                   (cached per process, and in the file named by the
-                                   environment variable LINGAM_AUTOTUNE_CACHE if set) */
+#define LINGAM_FLAG_AUTOTUNE 4u /* time the pair kernels' launch shapes (sample split, waves
+                                   per workgroup) on this call's data the first time its
+                                   size bucket is seen (cached per process, and in the file
+                                   named by the environment variable LINGAM_AUTOTUNE_CACHE
+                                   if set) */
+#define LINGAM_FLAG_FP32_TIES 8u /* decide near-ties from the FP32 measures alone (no FP64
+                                    tie resolution; see lingam_causal_order) */
 
 /* Per-call profile, filled when opts->profile is non-NULL (forces a sync). */
 typedef struct lingam_profile {
@@ -92,6 +95,8 @@ typedef struct lingam_profile {
   double cand_evals;      /* ... its sample-pair evaluations (with the extension and
                              suspect-row passes): 2 K (m - 1) n per step, plus
                              2 n (suspects * extension + measured rows * (m - 1)) */
+  int32_t tie_steps;      /* steps whose choice the FP64 tie resolution made */
+  int32_t tie_rows;       /* ... rows it measured in FP64 */
 } lingam_profile;
 
 /* Decisions of the learned form, summed over the jobs of a call (host). */
@@ -194,7 +199,12 @@ size_t lingam_workspace_size(int64_t n, int64_t d, const lingam_opts* opts);
  *   opts   optional (NULL = defaults).
  *   ws     device workspace of ws_bytes >= lingam_workspace_size(n, d, opts);
  *          its contents on entry do not matter, on exit they are undefined.
- * Ties of the measure go to the smallest original column id.
+ * Ties of the measure go to the smallest original column id.  The pair
+ * measures are computed in FP32 (FP64 when 64 or fewer variables remain);
+ * when the best variable's k and others lie within 0.4% of each other at a
+ * step (a near-tie that FP32 rounding could decide), their k are recomputed
+ * in FP64 from the FP64 residuals and the choice follows those
+ * (LINGAM_FLAG_FP32_TIES switches this off).
  * Returns LINGAM_OK or an error status (see the conventions above).
  */
 int lingam_causal_order(const float* X, int64_t n, int64_t d, int64_t ldx, int32_t* order,

@@ -20,7 +20,10 @@ matrix of the C oracle:
   excluded variable l the candidates' rows already give R(l, c) = -R(c, l),
   so k_l >= LB_l = sum_{c in C} max(0, R(c, l))^2, and its witnesses (its
   most correlated excluded variables w) add min(0, R(l, w))^2 each.  The
-  suspects are the excluded variables with LB_l <= k_best.  No suspect: the best candidate is
+  suspects are the excluded variables with LB_l <= k_best (1 + tie_rel) +
+  tie_abs (the library decides near-ties of that width in FP64, so every
+  variable whose k could come within it needs its exact row; tie_rel =
+  tie_abs = 0 is the FP32-ties form).  No suspect: the best candidate is
   the plain choice (certified).  At most cap(m) = min(1024, m/2 - K) (rounded
   down to a multiple of 8) suspects: their exact k is evaluated and the best
   of candidates and suspects is the plain choice.  More: the best candidate
@@ -356,9 +359,13 @@ def extension_bounds(D, lb, S, E, wit=None) -> np.ndarray:
     return out
 
 
+TIE_REL, TIE_ABS = 4e-3, 1e-12
+
+
 def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: int = 32,
                   min_m: int | None = None, emulate_bf16: bool = True,
-                  max_suspects: int = 1024, n_witness: int = 8, n_ext: int = 0):
+                  max_suspects: int = 1024, n_witness: int = 8, n_ext: int = 0,
+                  tie_rel: float = TIE_REL, tie_abs: float = TIE_ABS):
     """Causal order by the learned-proposal form.
 
     X: n x d samples (cast to FP32 first, like the library's input).
@@ -373,7 +380,8 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
     second pass the suspects' bounds also take the ``n_ext`` variables ranked
     right after the candidates (:func:`extension_bounds`); only suspects whose
     bound still does not exceed the best candidate's k have their rows
-    measured.  Returns (order, [StepInfo]).
+    measured.  A suspect is an excluded variable whose bound does not exceed
+    k_best (1 + tie_rel) + tie_abs.  Returns (order, [StepInfo]).
     """
     X = np.asarray(np.asarray(X, dtype=np.float32), dtype=np.float64).copy()
     n, d = X.shape
@@ -410,7 +418,8 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
             wit = witnesses(X, U, n_witness) if n_witness > 0 else None
             lb = lower_bounds(D, C, wit)
             excl = ~inC
-            sus = np.flatnonzero(excl & ~(lb > k[best]))
+            lim = k[best] * (1.0 + tie_rel) + tie_abs
+            sus = np.flatnonzero(excl & ~(lb > lim))
             certified = sus.size == 0
             s_out = np.max(s[excl]) if excl.any() else -np.inf
             margin = s[best] - s_out
@@ -422,7 +431,7 @@ def learned_order(X, proposer, K: int = 64, delta: float = np.inf, audit_every: 
                 # extension columns first; the rest of the suspects' rows
                 # only where the bound still allows them to win
                 lb2 = extension_bounds(D, lb, sus, E, wit)
-                rest = sus[~(lb2[sus] > k[best])]
+                rest = sus[~(lb2[sus] > lim)]
                 rows = int(rest.size)
             if audit:
                 p, kind = pc, "audit"

@@ -213,7 +213,8 @@ Plan make_plan(const std::vector<HostJob>& jobs, int cu, const Learn& lc = Learn
   return P;
 }
 
-std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& jobs, char* ws) {
+std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& jobs, char* ws,
+                                    bool tie_on) {
   std::vector<lg::JobDev> out(P.njobs);
   for (int k = 0; k < P.njobs; ++k) {
     const HostJob& h = jobs[k];
@@ -228,6 +229,9 @@ std::vector<lg::JobDev> device_jobs(const Plan& P, const std::vector<HostJob>& j
     J.d = (int32_t)h.d;
     J.n_pad = (int32_t)L.n_pad;
     J.ldz = (int32_t)L.ldz;
+    J.tie_on = tie_on ? 1 : 0;
+    J.tie = reinterpret_cast<int32_t*>(b + L.tie);
+    J.tie_r = reinterpret_cast<double*>(b + L.tie_r);
     J.order = h.order;
     J.measures = h.measures;
     J.gaps = h.gaps;
@@ -356,7 +360,7 @@ int enqueue_setup(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, hi
 
 // Enqueue every step of every job.
 int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStream_t st,
-                  lg::Tune tu, Prof* pf) {
+                  lg::Tune tu, Prof* pf, bool ties) {
   lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
   const lg::SchedDev sc = lg::sched_at(ws + P.sched_off, P.njobs);
   // bounded grids: one workgroup of w waves per resident slot
@@ -427,6 +431,9 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     LG_TRY(lg::launch_pair64(table, P.njobs, sc, T.g[lg::kKP64], st), "pair64");
     LG_TRY(lg::launch_rowk(table, P.njobs, sc, capped(T.g[lg::kKRowk], 8), st), "rowk");
     LG_TRY(lg::launch_select(table, P.njobs, t, sc, T.g[lg::kKSel], st), "select");
+    // near-ties of FP32-path steps (full or learned) decided in FP64
+    if (ties && (T.g[lg::kKPair] > 0 || gated))
+      LG_TRY(lg::launch_tie(table, P.njobs, sc, t, P.cu, st), "tie");
     if (T.g[lg::kKRes] > 0) {
       if (pf && pf->tm.on) pf->resid_ev.push_back(pf->tm.take(st));
       LG_TRY(lg::launch_resid(table, P.njobs, sc, T.g[lg::kKRes], st), "resid");
@@ -658,6 +665,10 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
       pr->cand_ms += pf.tm.ms(pf.cand_ev[k], pf.cand_ev[k + 1]);
     pr->cand_launches = (int64_t)(pf.cand_ev.size() / 2);
     pr->cand_evals = pf.cand_evals;
+    for (const lg::Ctrl& c : ctrl) {
+      pr->tie_steps += c.n_ties;
+      pr->tie_rows += c.n_tie_rows;
+    }
     // steps a learned decision took did not run the all-pairs kernel; steps
     // decided by the second pass measured their suspects against the
     // extension columns, then the remaining suspects' rows
@@ -693,7 +704,8 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
   int dev = 0;
   int rc = current_device(&dev);
   if (rc != LINGAM_OK) return rc;
-  const std::vector<lg::JobDev> dj = device_jobs(P, jobs, ws);
+  const bool ties = !(opts->flags & LINGAM_FLAG_FP32_TIES);
+  const std::vector<lg::JobDev> dj = device_jobs(P, jobs, ws, ties);
   Prof pf;
   pf.tm.on = opts->profile != nullptr;
 
@@ -733,7 +745,7 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
     if (rc != LINGAM_OK) return rc;
     rc = enqueue_setup(P, dj, ws, st, &pf, after_gram);
     if (rc != LINGAM_OK) return rc;
-    rc = enqueue_steps(P, jobs, ws, st, tu, &pf);
+    rc = enqueue_steps(P, jobs, ws, st, tu, &pf, ties);
     if (rc != LINGAM_OK) return rc;
     rc = after();
     if (rc != LINGAM_OK) return rc;
@@ -758,7 +770,7 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
     LG_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
     int rc2 = fill();
     if (rc2 == LINGAM_OK) rc2 = enqueue_setup(P, dj, ws, cap, nullptr, after_gram);
-    if (rc2 == LINGAM_OK) rc2 = enqueue_steps(P, jobs, ws, cap, tu, nullptr);
+    if (rc2 == LINGAM_OK) rc2 = enqueue_steps(P, jobs, ws, cap, tu, nullptr, ties);
     if (rc2 == LINGAM_OK) rc2 = after();
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &g);

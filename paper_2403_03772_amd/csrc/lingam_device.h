@@ -89,6 +89,56 @@ __device__ inline double logcosh64(double u) {
 }
 __device__ inline double gauss64(double u) { return u * exp(-0.5 * u * u); }
 
+// R(pi, pj) of two active positions entirely in FP64 from the FP64 residuals
+// (the small-m path and the FP64 decision of near-ties): one wave, lanes over
+// samples, both residual directions; the result is valid in every lane.
+// log cosh u = |u| + log(1 + e^{-2|u|}) - ln 2; the logs of a lane's samples
+// are taken as the log of their product (each factor is in (1, 2], so 512 of
+// them stay below 2^512), one FP64 log per 512 samples.
+__device__ inline double pair_measure64(const JobDev& J, int pi, int pj, int lane) {
+  const int si = J.act[pi], sj = J.act[pj];
+  double r = J.rho[(int64_t)si * J.d + sj];
+  const double lim = 1.0 - kCollinear;
+  r = r > lim ? lim : (r < -lim ? -lim : r);
+  const double al = 1.0 / sqrt(1.0 - r * r);
+  const double* zi = J.zd + (int64_t)si * J.ldz;
+  const double* zj = J.zd + (int64_t)sj * J.ldz;
+  double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+  double pa = 1.0, pb = 1.0;
+  int cnt = 0, tot = 0;
+  for (int s = lane; s < J.n; s += 64) {
+    const double xi = zi[s], xj = zj[s];
+    const double u = al * (xi - r * xj), w = al * (xj - r * xi);
+    const double au = fabs(u), aw = fabs(w);
+    a1 += au;
+    b1 += aw;
+    pa *= 1.0 + exp(-2.0 * au);
+    pb *= 1.0 + exp(-2.0 * aw);
+    a2 += u * exp(-0.5 * u * u);
+    b2 += w * exp(-0.5 * w * w);
+    ++tot;
+    if (++cnt == 512) {
+      a1 += log(pa);
+      b1 += log(pb);
+      pa = pb = 1.0;
+      cnt = 0;
+    }
+  }
+  a1 += log(pa) - (double)tot * kLn2;
+  b1 += log(pb) - (double)tot * kLn2;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a1 += __shfl_xor(a1, off);
+    a2 += __shfl_xor(a2, off);
+    b1 += __shfl_xor(b1, off);
+    b2 += __shfl_xor(b2, off);
+  }
+  const double inv_n = 1.0 / (double)J.n;
+  const double h_ij = entropy_from_moments(a1 * inv_n, a2 * inv_n);
+  const double h_ji = entropy_from_moments(b1 * inv_n, b2 * inv_n);
+  return (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
+}
+
 // Pointers read from the job table are generic; the hot loop casts row bases
 // to the global address space so loads use global_load with a scalar base.
 typedef __attribute__((address_space(1))) const char gchar_t;

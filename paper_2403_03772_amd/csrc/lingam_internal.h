@@ -52,6 +52,18 @@ constexpr int kMaxSuspects = 1024;
 // Witnesses per variable: the most correlated other active variables, whose
 // pair measures join the candidates' in a learned step's lower bound on k.
 constexpr int kWit = 8;
+// FP64 tie resolution.  The FP32 pair kernels measure k to about 1e-3 of its
+// own value at the noise level of the largest workloads, so when the best k
+// of a step and others lie within tie_limit of each other (at most kMaxTie
+// of them), the step's choice is made from their rows recomputed in FP64
+// (the FP64 residuals, correlations and marginal entropies the step already
+// holds) instead of from the FP32 values.
+constexpr int kMaxTie = 16;
+constexpr double kTieRel = 4e-3;
+constexpr double kTieAbs = 1e-12;
+__host__ __device__ inline double tie_limit(double kbest) {
+  return kbest * (1.0 + kTieRel) + kTieAbs;
+}
 // Most extension columns: the variables ranked right after the candidates,
 // measured against the suspects before their full rows are.
 constexpr int kMaxExt = 256;
@@ -95,7 +107,13 @@ struct Ctrl {
   int32_t n_expanded;      // learned steps decided exactly by the second pass
   int32_t n_cleared;       // ... of which every suspect was cleared by the extension columns
   long long n_rows_sum;    // suspects whose full rows the second pass measured
-  int32_t pad[44];
+  int32_t ntie;            // this step: near-tied positions listed for the FP64
+                           // decision (0: the step is committed already)
+  int32_t tie_audit;       // 1: the deferred decision is an audit step's full step
+  int32_t n_ties;          // steps decided by the FP64 tie resolution
+  int32_t n_tie_rows;      // ... rows they measured in FP64
+  int32_t tie_done;        // workgroups of the FP64 decision finished (reset by the last)
+  int32_t pad[39];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 
@@ -133,6 +151,9 @@ struct Layout {
   size_t parts;    // double [parts_elems] partial sums
   size_t rc2;      // double [cap_s * d] R(suspect, position)
   size_t kc2;      // double [cap_s] exact k of every suspect
+  // FP64 tie resolution (every job)
+  size_t tie;      // int32  [kMaxTie] near-tied positions of the current step
+  size_t tie_r;    // double [kMaxTie * d] their FP64 measure rows
   size_t total;
   size_t part_elems;
   size_t partc_elems;
@@ -184,6 +205,10 @@ struct JobDev {
   double* parts;
   double* rc2;
   double* kc2;
+  // FP64 tie resolution
+  int32_t tie_on;        // 1: near-ties are decided in FP64
+  int32_t* tie;
+  double* tie_r;
 };
 
 // Launch shape of the pair kernels (autotuned).
@@ -462,6 +487,9 @@ hipError_t launch_select(const JobDev* jobs, int njobs, int t, SchedDev sc, int 
                          hipStream_t st);
 hipError_t launch_resid(const JobDev* jobs, int njobs, SchedDev sc, int grid, hipStream_t st);
 hipError_t launch_gather_status(const JobDev* jobs, int njobs, int32_t* dst, hipStream_t st);
+// FP64 decision of the steps whose choice was deferred as a near-tie (step t).
+hipError_t launch_tie(const JobDev* jobs, int njobs, SchedDev sc, int t, int num_cu,
+                      hipStream_t st);
 // Writes `count` (at most kJobsPerLaunch) job-table entries from kernel arguments.
 constexpr int kJobsPerLaunch = 8;
 hipError_t launch_set_jobs(JobDev* table, int first, const JobDev* host_jobs, int count,

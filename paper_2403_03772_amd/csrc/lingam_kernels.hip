@@ -454,51 +454,8 @@ __global__ __launch_bounds__(256) void k_pair64(const JobDev* __restrict__ jobs,
     ++pi;
   }
   const int pj = pi + 1 + rem;
-  const int si = J.act[pi], sj = J.act[pj];
-  double r = J.rho[(int64_t)si * J.d + sj];
-  const double lim = 1.0 - kCollinear;
-  r = r > lim ? lim : (r < -lim ? -lim : r);
-  const double al = 1.0 / sqrt(1.0 - r * r);
-  const double* zi = J.zd + (int64_t)si * J.ldz;
-  const double* zj = J.zd + (int64_t)sj * J.ldz;
-  // log cosh u = |u| + log(1 + e^{-2|u|}) - ln 2; the logs of a lane's
-  // samples are taken as the log of their product (each factor is in (1, 2],
-  // so 512 of them stay below 2^512), one FP64 log per 512 samples
-  double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
-  double pa = 1.0, pb = 1.0;
-  int cnt = 0, tot = 0;
-  for (int s = lane; s < J.n; s += 64) {
-    const double xi = zi[s], xj = zj[s];
-    const double u = al * (xi - r * xj), w = al * (xj - r * xi);
-    const double au = fabs(u), aw = fabs(w);
-    a1 += au;
-    b1 += aw;
-    pa *= 1.0 + exp(-2.0 * au);
-    pb *= 1.0 + exp(-2.0 * aw);
-    a2 += u * exp(-0.5 * u * u);
-    b2 += w * exp(-0.5 * w * w);
-    ++tot;
-    if (++cnt == 512) {
-      a1 += log(pa);
-      b1 += log(pb);
-      pa = pb = 1.0;
-      cnt = 0;
-    }
-  }
-  a1 += log(pa) - (double)tot * kLn2;
-  b1 += log(pb) - (double)tot * kLn2;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    a1 += __shfl_xor(a1, off);
-    a2 += __shfl_xor(a2, off);
-    b1 += __shfl_xor(b1, off);
-    b2 += __shfl_xor(b2, off);
-  }
+  const double Rv = pair_measure64(J, pi, pj, lane);
   if (lane == 0) {
-    const double inv_n = 1.0 / (double)J.n;
-    const double h_ij = entropy_from_moments(a1 * inv_n, a2 * inv_n);
-    const double h_ji = entropy_from_moments(b1 * inv_n, b2 * inv_n);
-    const double Rv = (J.hm[sj] + h_ij) - (J.hm[si] + h_ji);
     J.rmat[(int64_t)pi * J.d + pj] = Rv;
     J.rmat[(int64_t)pj * J.d + pi] = -Rv;
   }
@@ -535,7 +492,7 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
                                                  const JobStep* __restrict__ js,
                                                  const int32_t* __restrict__ pre, int t) {
   __shared__ Best sh[1024];
-  __shared__ int forced_pos;
+  __shared__ int forced_pos, ntie;
   for_blocks(pre, njobs, [&](int jb, int) {
   const JobDev& J = jobs[jb];
   const int m = js[jb].m, d = J.d;
@@ -578,21 +535,113 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
     __syncthreads();
     for (int p = tid; p < m; p += 1024) row[act[p]] = J.mvec[p];
   }
+  // near-tie: every position whose k is within tie_limit of the best goes to
+  // the FP64 decision (FP32 steps, not forced, at most kMaxTie of them)
+  if (tid == 0) ntie = 0;
   __syncthreads();
+  const bool refine = J.tie_on && !force && !js[jb].fp64 && best.pos >= 0;
+  if (refine) {
+    const double lim = tie_limit(-best.v);
+    for (int p = tid; p < m; p += 1024) {
+      const double k = -J.mvec[p];
+      if (k <= lim) {
+        const int w = atomicAdd(&ntie, 1);
+        if (w < kMaxTie) J.tie[w] = p;
+      }
+    }
+  }
+  __syncthreads();
+  const bool defer = refine && ntie >= 2 && ntie <= kMaxTie;
   if (tid == 0) {
-    const int slot = act[pos];
-    if (js[jb].learned && J.audit_every > 0 && t % J.audit_every == 0 &&
-        slot == J.ctrl->learned_slot)
-      J.ctrl->n_audit_agree += 1;
-    J.order[t] = slot;
-    J.ctrl->exo_slot = slot;
-    J.ctrl->exo_pos = pos;
+    const bool audit = js[jb].learned && J.audit_every > 0 && t % J.audit_every == 0;
     if (J.gaps) J.gaps[t] = best.v - best.v2;
-    act[pos] = act[m - 1];
-    if (m == 2) J.order[t + 1] = act[0];
+    if (defer) {  // k_tie_select commits
+      J.ctrl->ntie = ntie;
+      J.ctrl->tie_audit = audit ? 1 : 0;
+    } else {
+      const int slot = act[pos];
+      if (audit && slot == J.ctrl->learned_slot) J.ctrl->n_audit_agree += 1;
+      J.order[t] = slot;
+      J.ctrl->exo_slot = slot;
+      J.ctrl->exo_pos = pos;
+      act[pos] = act[m - 1];
+      if (m == 2) J.order[t + 1] = act[0];
+    }
   }
   __syncthreads();  // the next job's item reuses the shared arrays
   });
+}
+
+// The FP64 decision of a deferred near-tie.  Pairs (r, j) for every listed
+// position r and every active position j: both residual directions over all
+// samples in FP64 from the FP64 residuals (the arithmetic of k_pair64), one
+// wave per pair, R(r, r) = 0.  A job owns `per_job` consecutive workgroups;
+// the last of them to finish (counted in ctrl->tie_done) sums k of every
+// listed row in FP64 (one wave per row, columns in a fixed order), takes the
+// largest -k with ties to the smaller original id and commits it as the
+// full selection commits.
+__global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, int njobs,
+                                             const JobStep* __restrict__ js, int per_job,
+                                             int t) {
+  __shared__ double sk[kMaxTie];
+  __shared__ int last;
+  const int jb = blockIdx.x / per_job, sub = blockIdx.x - jb * per_job;
+  if (jb >= njobs) return;
+  const JobDev& J = jobs[jb];
+  Ctrl* C = J.ctrl;
+  const int nt = C->ntie;
+  if (nt < 2) return;  // workgroup-uniform
+  const int m = js[jb].m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t npairs = (int64_t)nt * m;
+  for (int64_t w = (int64_t)sub * 4 + wave; w < npairs; w += (int64_t)per_job * 4) {
+    const int r = (int)(w / m), pj = (int)(w - (int64_t)r * m);
+    const int pi = J.tie[r];
+    double* out = J.tie_r + (int64_t)r * J.d + pj;
+    if (pi == pj) {
+      if (lane == 0) *out = 0.0;
+      continue;
+    }
+    const double Rv = pair_measure64(J, pi, pj, lane);
+    if (lane == 0) *out = Rv;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&C->tie_done, 1) == per_job - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int r = wave; r < nt; r += 4) {
+    const double* row = J.tie_r + (int64_t)r * J.d;
+    double k = 0.0;
+    for (int q = lane; q < m; q += 64) {
+      const double x = row[q];
+      const double ng = x < 0.0 ? x : 0.0;
+      k += ng * ng;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
+    if (lane == 0) sk[r] = k;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int32_t* act = J.act;
+  int bi = 0;
+  for (int r = 1; r < nt; ++r) {
+    const double a = sk[r], b = sk[bi];
+    if (a < b || (a == b && act[J.tie[r]] < act[J.tie[bi]])) bi = r;
+  }
+  const int pos = J.tie[bi], slot = act[pos];
+  if (C->tie_audit && slot == C->learned_slot) C->n_audit_agree += 1;
+  J.order[t] = slot;
+  C->exo_slot = slot;
+  C->exo_pos = pos;
+  act[pos] = act[m - 1];
+  C->n_ties += 1;
+  C->n_tie_rows += nt;
+  C->ntie = 0;
+  C->tie_audit = 0;
+  C->tie_done = 0;
 }
 
 // Remove the chosen variable e from every remaining variable p and keep p
@@ -977,6 +1026,8 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
   L.rmat = take(sizeof(double) * (size_t)d * (size_t)d);
   L.mvec = take(sizeof(double) * (size_t)d);
   L.mom = take(sizeof(double) * 8 * (size_t)d);
+  L.tie = take(sizeof(int32_t) * kMaxTie);
+  L.tie_r = take(sizeof(double) * kMaxTie * (size_t)d);
   L.K = K;
   if (K > 0) {
     L.feat = take(sizeof(float) * kFeat * (size_t)d);
@@ -1121,6 +1172,14 @@ hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, int
   if (waves == 1) launch_pair_w<1>(jobs, njobs, sc, grid, st, loop);
   else if (waves == 2) launch_pair_w<2>(jobs, njobs, sc, grid, st, loop);
   else launch_pair_w<4>(jobs, njobs, sc, grid, st, loop);
+  return hipGetLastError();
+}
+
+hipError_t launch_tie(const JobDev* jobs, int njobs, SchedDev sc, int t, int num_cu,
+                      hipStream_t st) {
+  const int per_job = num_cu * 4 / njobs > 1 ? num_cu * 4 / njobs : 1;
+  hipLaunchKernelGGL(k_tie, dim3((unsigned)(per_job * njobs)), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, per_job, t);
   return hipGetLastError();
 }
 

@@ -656,7 +656,9 @@ __global__ __launch_bounds__(64 * kWitWaves) void k_pair_wit(const JobDev* __res
   double kbest = s_kb[0];
 #pragma unroll
   for (int w = 1; w < kWitWaves; ++w) kbest = fmin(kbest, s_kb[w]);
-  if (J.lb[l] > kbest) return;  // bounded by the candidates alone
+  // bounded by the candidates alone (beyond the near-tie limit when near-ties
+  // are decided in FP64, the suspects' threshold)
+  if (J.lb[l] > (J.tie_on ? tie_limit(kbest) : kbest)) return;
   int wq[kWit];
   bool on[kWit];
   bool any = false;
@@ -915,6 +917,34 @@ __device__ inline void commit_choice(const JobDev& J, int t, int m, const Best& 
   J.act[best.pos] = J.act[m - 1];
 }
 
+// Near-tie set of a learned decision (the full selection's rule): every row
+// of the list (exact k values kv[c] of positions pos[c], c < n) whose k is
+// at most lim, appended to J.tie through the shared counter *cnt.  Called by
+// every thread of the workgroup.
+__device__ inline void gather_ties(const JobDev& J, double lim, const double* kv,
+                                   const int32_t* pos, int n, int* cnt) {
+  for (int c = threadIdx.x; c < n; c += blockDim.x)
+    if (kv[c] <= lim) {
+      const int w = atomicAdd(cnt, 1);
+      if (w < kMaxTie) J.tie[w] = pos[c];
+    }
+}
+
+// The learned choice `best`, or (2 .. kMaxTie near-tied rows listed in
+// J.tie) its deferral to the FP64 decision: the full step is gated off
+// either way.  Thread 0 only.
+__device__ inline void commit_or_defer(const JobDev& J, int t, int m, const Best& best,
+                                       int ntie) {
+  if (J.tie_on && ntie >= 2 && ntie <= kMaxTie) {
+    J.ctrl->ntie = ntie;
+    J.ctrl->tie_audit = 0;
+    J.ctrl->full = 0;
+    if (J.gaps) J.gaps[t] = best.v - best.v2;
+  } else {
+    commit_choice(J, t, m, best);
+  }
+}
+
 // The learned decision of one job (one workgroup).  Best candidate by -k with
 // ties to the smaller original id.  Suspects: non-candidates whose lower bound
 // does not exceed its k (only they could still win).  No suspect: certified,
@@ -936,9 +966,12 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
   const Best best =
       best_of_rows(J.kc, J.cand, K, J.act, Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
   const double kbest = -best.v;
+  // with the FP64 tie resolution, a variable whose k might come within the
+  // near-tie limit of the best must have its exact row too
+  const double lim = J.tie_on ? tie_limit(kbest) : kbest;
   auto suspect = [&](int l) {
     const double v = J.lb[l];
-    return !(v == v && v > kbest);  // NaN bounds count as suspects
+    return !(v == v && v > lim);  // NaN bounds count as suspects
   };
   // count, then (if listed) write in ascending position order: thread chunks
   const int per = (m + 255) / 256;
@@ -975,7 +1008,13 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
     __syncthreads();
     for (int c = tid; c < K; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
   }
+  // a certified choice goes to the FP64 decision when candidates tie with it
+  // (a choice the margin accepted is not exact anyway)
+  if (tid == 0) shs[0] = 0;
   __syncthreads();
+  if (take && certified && J.tie_on) gather_ties(J, lim, J.kc, J.cand, K, &shs[0]);
+  __syncthreads();
+  const int ntie = certified ? shs[0] : 0;
   if (tid != 0) return;
   Ctrl* C = J.ctrl;
   C->full = 1;
@@ -989,7 +1028,7 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
   if (nsus > C->n_suspects_max) C->n_suspects_max = nsus;
   if (J.steplog)
     J.steplog[t] = take ? 1 : (expand ? (4 | (nsus << 4)) : (audit ? 3 : 2));
-  if (take) commit_choice(J, t, m, best);
+  if (take) commit_or_defer(J, t, m, best, ntie);
 }
 
 // Plan of the second pass: per job, the suspects listed at this step (0 for
@@ -1137,6 +1176,7 @@ __global__ __launch_bounds__(256) void k_ext_compact(const JobDev* __restrict__ 
     const Best best =
         best_of_rows(J.kc, J.cand, S.k, J.act, Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
     const double kbest = -best.v;
+    const double lim = J.tie_on ? tie_limit(kbest) : kbest;
     const int per = (n1 + 255) / 256;
     const int c0 = min(tid * per, n1), c1 = min(c0 + per, n1);
     int v[4];
@@ -1147,7 +1187,7 @@ __global__ __launch_bounds__(256) void k_ext_compact(const JobDev* __restrict__ 
       const int c = c0 + i;
       v[i] = c < c1 ? J.cand2[c] : 0;
       const double b = c < c1 ? J.lb[v[i]] : INFINITY;
-      keep[i] = c < c1 && !(b == b && b > kbest);  // NaN bounds stay suspects
+      keep[i] = c < c1 && !(b == b && b > lim);  // NaN bounds stay suspects
       mine += keep[i] ? 1 : 0;
     }
     shs[tid] = mine;
@@ -1172,13 +1212,18 @@ __global__ __launch_bounds__(256) void k_ext_compact(const JobDev* __restrict__ 
       for (int c = tid; c < S.k; c += 256) row[J.act[J.cand[c]]] = -J.kc[c];
     }
     __syncthreads();
+    if (tid == 0) shs[0] = 0;
+    __syncthreads();
+    if (n2 == 0 && J.tie_on) gather_ties(J, lim, J.kc, J.cand, S.k, &shs[0]);
+    __syncthreads();
+    const int ntie = shs[0];
     if (tid == 0) {
       Ctrl* C = J.ctrl;
       C->nsus = n2;
       if (n2 == 0) {
         C->n_expanded += 1;
         C->n_cleared += 1;
-        commit_choice(J, t, m, best);
+        commit_or_defer(J, t, m, best, ntie);
       }
     }
     __syncthreads();
@@ -1259,6 +1304,7 @@ __global__ __launch_bounds__(256) void k_lselect2(const JobDev* __restrict__ job
                                                   const JobStep* __restrict__ js,
                                                   const int32_t* __restrict__ pre, int t) {
   __shared__ Best sh[256];
+  __shared__ int s_tie;
   for_blocks(pre, njobs, [&](int jb, int) {
     const JobDev& J = jobs[jb];
     const JobStep S = js[jb];
@@ -1266,6 +1312,15 @@ __global__ __launch_bounds__(256) void k_lselect2(const JobDev* __restrict__ job
     Best b = best_of_rows(J.kc, J.cand, S.k, J.act,
                           Best{-INFINITY, 0x7fffffff, -1, -INFINITY}, sh);
     b = best_of_rows(J.kc2, J.cand2, S.nsus, J.act, b, sh);
+    if (tid == 0) s_tie = 0;
+    __syncthreads();
+    if (J.tie_on) {
+      const double lim = tie_limit(-b.v);
+      gather_ties(J, lim, J.kc, J.cand, S.k, &s_tie);
+      gather_ties(J, lim, J.kc2, J.cand2, S.nsus, &s_tie);
+    }
+    __syncthreads();
+    const int ntie = s_tie;
     if (J.measures) {
       double* row = J.measures + (int64_t)t * J.d;
       for (int v = tid; v < J.d; v += 256) row[v] = NAN;
@@ -1278,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_lselect2(const JobDev* __restrict__ job
       J.ctrl->n_expanded += 1;
       J.ctrl->n_rows_sum += S.nsus;
       if (J.steplog) J.steplog[t] |= S.nsus << 16;
-      commit_choice(J, t, S.m, b);
+      commit_or_defer(J, t, S.m, b, ntie);
     }
     __syncthreads();
   });

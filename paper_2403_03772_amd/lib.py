@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblingam_mi355x.so")
 
 OK, E_INVALID, E_DEGENERATE, E_HIP, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-FLAG_NO_SYNC, FLAG_GRAPH, FLAG_AUTOTUNE = 1, 2, 4
+FLAG_NO_SYNC, FLAG_GRAPH, FLAG_AUTOTUNE, FLAG_FP32_TIES = 1, 2, 4, 8
 
 # proposer network (include/lingam.h)
 N_FEATURES = 16
@@ -49,6 +49,8 @@ class _Profile(ctypes.Structure):
         ("cand_ms", ctypes.c_double),
         ("cand_launches", ctypes.c_int64),
         ("cand_evals", ctypes.c_double),
+        ("tie_steps", ctypes.c_int32),
+        ("tie_rows", ctypes.c_int32),
     ]
 
 
@@ -121,6 +123,8 @@ class Profile:
     cand_ms: float
     cand_launches: int
     cand_evals: float
+    tie_steps: int
+    tie_rows: int
 
 
 @dataclass
@@ -259,7 +263,7 @@ def _cuda_f32_matrix(torch, X, name="X"):
 
 
 def _new_opts(lib, *, sync=True, graph=False, autotune=False, learned=None, profile=False,
-              keep=None, waves=None):
+              keep=None, waves=None, fp32_ties=False):
     """lingam_opts with flags, the learned configuration, the profile and the
     launch shape (``waves`` = (all-pairs, row kernels) waves per workgroup)."""
     opts = _Opts()
@@ -272,6 +276,8 @@ def _new_opts(lib, *, sync=True, graph=False, autotune=False, learned=None, prof
         opts.flags |= FLAG_GRAPH
     if autotune:
         opts.flags |= FLAG_AUTOTUNE
+    if fp32_ties:
+        opts.flags |= FLAG_FP32_TIES
     stats = None
     if learned is not None:
         import torch
@@ -321,7 +327,7 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
                  workspace=None, sync: bool = True, graph: bool = False,
                  autotune: bool = False, learned: Learned | None = None,
                  record_features: bool = False, step_log: bool = False, out=None,
-                 waves=None, _noalloc: bool = False):
+                 waves=None, fp32_ties: bool = False, _noalloc: bool = False):
     """DirectLiNGAM causal order of the columns of ``X`` (a CUDA float32 tensor, n x d).
 
     Returns ``order`` (int32 CUDA tensor, original column ids, exogenous first),
@@ -335,7 +341,8 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
     receive the order (a graph-mode call replays its graph only for the same
     buffers).  ``waves``: (all-pairs, row kernels) waves per workgroup, each
     1, 2 or 4 (``lingam_opts.waves_all`` / ``waves_rows``; None = default or
-    autotuned); the results do not depend on it.
+    autotuned); the results do not depend on it.  ``fp32_ties``: decide
+    near-ties from the FP32 measures (``LINGAM_FLAG_FP32_TIES``).
     """
     import torch
 
@@ -353,7 +360,8 @@ def causal_order(X, *, forced=None, with_measures: bool = False, profile: bool =
         order = torch.empty(d, dtype=torch.int32, device=dev)
     keep = []
     opts, prof, stats = _new_opts(lib, sync=sync, graph=graph, autotune=autotune,
-                                  learned=learned, profile=profile, keep=keep, waves=waves)
+                                  learned=learned, profile=profile, keep=keep, waves=waves,
+                                  fp32_ties=fp32_ties)
     if forced is not None:
         f = torch.as_tensor(forced, dtype=torch.int32).to(dev).contiguous()
         keep.append(f)

@@ -44,3 +44,24 @@ def check_step(meas_gpu_row, meas_ref_row, chosen):
     ref_best = ids[np.argmax(meas_ref_row[ids])]
     choice_ok = chosen == ref_best or near_tie(meas_ref_row, chosen, ref_best)
     return int((~close).sum()), bool(choice_ok)
+
+
+# The library's FP64 tie resolution: at an FP32-path step, when 2..16 active
+# variables have k <= k_best (1 + 4e-3) + 1e-12 (k = -M from the FP32
+# measures), the choice among them is made from their k recomputed in FP64.
+TIE_REL, TIE_ABS, TIE_MAX = 4e-3, 1e-12, 16
+
+
+def choice_ok(row, chosen):
+    """(ok, resolved): the chosen variable is the step's FP32 argmax (ties to
+    the smallest id), or the step is a near-tie the FP64 resolution decided
+    and the choice lies within its band.  row: measures by original id (NaN =
+    inactive)."""
+    ids = np.flatnonzero(np.isfinite(row))
+    best = row[ids].max()
+    first = ids[np.flatnonzero(row[ids] == best)[0]]
+    if chosen == first:
+        return True, False
+    lim = -best * (1.0 + TIE_REL) + TIE_ABS
+    band = ids[-row[ids] <= lim]
+    return (2 <= band.size <= TIE_MAX and chosen in band), True

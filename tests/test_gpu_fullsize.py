@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2403_03772_amd import synth
-from gpu_helpers import FLOOR, REL, check_step
+from gpu_helpers import FLOOR, REL, check_step, choice_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -40,11 +40,9 @@ def test_every_step_is_consistent(run):
         assert fin.sum() == D - t, t
         assert not fin[order[:t]].any(), t
         assert np.all(row[fin] <= 0.0), t
-        ids = np.flatnonzero(fin)
-        best = row[ids].max()
-        assert row[order[t]] == best, t
-        # ties go to the smallest original id
-        assert order[t] == ids[np.flatnonzero(row[ids] == best)[0]], t
+        # the FP32 argmax (ties to the smallest id), or an FP64-resolved near-tie
+        ok, _ = choice_ok(row, order[t])
+        assert ok, t
         assert gaps[t] >= 0.0
 
 
@@ -110,9 +108,8 @@ def test_other_seeds(lib, seed):
         row = meas[t]
         fin = np.isfinite(row)
         assert fin.sum() == D - t and not fin[order[:t]].any(), t
-        ids = np.flatnonzero(fin)
-        best = row[ids].max()
-        assert order[t] == ids[np.flatnonzero(row[ids] == best)[0]], t
+        ok, _ = choice_ok(row, order[t])
+        assert ok, t
     worst = max(_sampled_rows(X32, order, meas[t], t) for t in (0, 400, 900))
     print(f"seed {seed}: worst scaled error on sampled rows {worst:.3e}")
 

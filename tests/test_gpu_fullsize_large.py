@@ -22,7 +22,7 @@ import pytest
 
 import oracle
 from paper_2403_03772_amd import synth
-from gpu_helpers import FLOOR, REL
+from gpu_helpers import FLOOR, REL, choice_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -67,10 +67,9 @@ def test_learned_steps_are_consistent(run):
             assert fin.sum() >= 32, t
         else:                                # audit or plain step: every active variable
             assert fin.sum() == D - t, t
-        ids = np.flatnonzero(fin)
-        best = row[ids].max()
-        assert row[order[t]] == best, t
-        assert order[t] == ids[np.flatnonzero(row[ids] == best)[0]], t
+        # its best recorded measure, or an FP64-resolved near-tie among them
+        ok, _ = choice_ok(row, order[t])
+        assert ok, t
 
 
 @pytest.mark.parametrize("t", [0, AUDIT, 20 * AUDIT])
