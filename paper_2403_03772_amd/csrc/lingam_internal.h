@@ -107,13 +107,13 @@ struct Ctrl {
   int32_t n_expanded;      // learned steps decided exactly by the second pass
   int32_t n_cleared;       // ... of which every suspect was cleared by the extension columns
   long long n_rows_sum;    // suspects whose full rows the second pass measured
-  int32_t ntie;            // this step: near-tied positions listed for the FP64
-                           // decision (0: the step is committed already)
+  int32_t ntie;            // near-tied positions listed for the FP64 decision of
+  int32_t tie_t;           // ... step tie_t (at any other step: none pending)
   int32_t tie_audit;       // 1: the deferred decision is an audit step's full step
   int32_t n_ties;          // steps decided by the FP64 tie resolution
   int32_t n_tie_rows;      // ... rows they measured in FP64
-  int32_t tie_done;        // workgroups of the FP64 decision finished (reset by the last)
-  int32_t pad[39];
+  int32_t tie_done;        // pairs of the FP64 decision finished
+  int32_t pad[38];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 

@@ -555,8 +555,10 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
   if (tid == 0) {
     const bool audit = js[jb].learned && J.audit_every > 0 && t % J.audit_every == 0;
     if (J.gaps) J.gaps[t] = best.v - best.v2;
-    if (defer) {  // k_tie_select commits
+    if (defer) {  // k_tie commits
       J.ctrl->ntie = ntie;
+      J.ctrl->tie_t = t;
+      J.ctrl->tie_done = 0;
       J.ctrl->tie_audit = audit ? 1 : 0;
     } else {
       const int slot = act[pos];
@@ -572,46 +574,25 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
   });
 }
 
-// The FP64 decision of a deferred near-tie.  Pairs (r, j) for every listed
-// position r and every active position j: both residual directions over all
-// samples in FP64 from the FP64 residuals (the arithmetic of k_pair64), one
-// wave per pair, R(r, r) = 0.  A job owns `per_job` consecutive workgroups;
-// the last of them to finish (counted in ctrl->tie_done) sums k of every
-// listed row in FP64 (one wave per row, columns in a fixed order), takes the
-// largest -k with ties to the smaller original id and commits it as the
-// full selection commits.
-__global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, int njobs,
-                                             const JobStep* __restrict__ js, int per_job,
-                                             int t) {
-  __shared__ double sk[kMaxTie];
-  __shared__ int last;
-  const int jb = blockIdx.x / per_job, sub = blockIdx.x - jb * per_job;
-  if (jb >= njobs) return;
-  const JobDev& J = jobs[jb];
+// The FP64 decision of deferred near-ties.  Pairs (r, j) for every listed
+// position r and every active position j of every job that deferred at this
+// step: both residual directions over all samples in FP64 from the FP64
+// residuals (the arithmetic of k_pair64), one wave per pair, R(r, r) = 0.
+// The pairs of all such jobs form one list, jobs in index order, that the
+// waves of the grid take in turn, so a step where a few jobs of a large batch
+// tie still spreads over the whole device.  Every workgroup rebuilds the list
+// boundaries from the jobs' control blocks (256 jobs at a time); those fields
+// are written by the selection before this launch and only read here.  Each
+// job counts its finished pairs (ctrl->tie_done); the wave that finishes the
+// last one sums k of every listed row in FP64 (columns in a fixed order),
+// takes the largest -k with ties to the smaller original id and commits it
+// as the full selection commits.
+__device__ void tie_commit(const JobDev& J, int m, int nt, int t, int lane) {
   Ctrl* C = J.ctrl;
-  const int nt = C->ntie;
-  if (nt < 2) return;  // workgroup-uniform
-  const int m = js[jb].m;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t npairs = (int64_t)nt * m;
-  for (int64_t w = (int64_t)sub * 4 + wave; w < npairs; w += (int64_t)per_job * 4) {
-    const int r = (int)(w / m), pj = (int)(w - (int64_t)r * m);
-    const int pi = J.tie[r];
-    double* out = J.tie_r + (int64_t)r * J.d + pj;
-    if (pi == pj) {
-      if (lane == 0) *out = 0.0;
-      continue;
-    }
-    const double Rv = pair_measure64(J, pi, pj, lane);
-    if (lane == 0) *out = Rv;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&C->tie_done, 1) == per_job - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int r = wave; r < nt; r += 4) {
+  int32_t* act = J.act;
+  double best_k = 0.0;
+  int bi = -1;
+  for (int r = 0; r < nt; ++r) {
     const double* row = J.tie_r + (int64_t)r * J.d;
     double k = 0.0;
     for (int q = lane; q < m; q += 64) {
@@ -621,16 +602,12 @@ __global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, in
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
-    if (lane == 0) sk[r] = k;
+    if (bi < 0 || k < best_k || (k == best_k && act[J.tie[r]] < act[J.tie[bi]])) {
+      best_k = k;
+      bi = r;
+    }
   }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  int32_t* act = J.act;
-  int bi = 0;
-  for (int r = 1; r < nt; ++r) {
-    const double a = sk[r], b = sk[bi];
-    if (a < b || (a == b && act[J.tie[r]] < act[J.tie[bi]])) bi = r;
-  }
+  if (lane != 0) return;
   const int pos = J.tie[bi], slot = act[pos];
   if (C->tie_audit && slot == C->learned_slot) C->n_audit_agree += 1;
   J.order[t] = slot;
@@ -639,9 +616,61 @@ __global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, in
   act[pos] = act[m - 1];
   C->n_ties += 1;
   C->n_tie_rows += nt;
-  C->ntie = 0;
-  C->tie_audit = 0;
-  C->tie_done = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, int njobs,
+                                             const JobStep* __restrict__ js, int t) {
+  __shared__ int64_t spre[256];  // inclusive prefix of pair counts, this chunk of jobs
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (tid >> 6), nw = (int64_t)gridDim.x * 4;
+  int64_t base = 0;  // pairs of the jobs before this chunk
+  for (int j0 = 0; j0 < njobs; j0 += 256) {
+    const int jc = j0 + tid;
+    int64_t c = 0;
+    if (jc < njobs) {
+      const Ctrl* C = jobs[jc].ctrl;
+      const int nt = C->ntie;
+      if (C->tie_t == t && nt >= 2) c = (int64_t)nt * js[jc].m;
+    }
+    spre[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int64_t v = tid >= off ? spre[tid - off] : 0;
+      __syncthreads();
+      spre[tid] += v;
+      __syncthreads();
+    }
+    const int64_t total = spre[255];
+    // this wave's pairs: list indices w = gw (mod nw) inside [base, base + total)
+    int64_t w = base + ((gw - base % nw) % nw + nw) % nw;
+    for (; w < base + total; w += nw) {
+      const int64_t loc = w - base;
+      int lo = 0, hi = 255;  // first job of the chunk whose prefix exceeds loc
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (spre[mid] > loc) hi = mid;
+        else lo = mid + 1;
+      }
+      const JobDev& J = jobs[j0 + lo];
+      const int m = js[j0 + lo].m;
+      const int64_t q = loc - (lo ? spre[lo - 1] : 0);
+      const int r = (int)(q / m), pj = (int)(q - (int64_t)r * m);
+      const int pi = J.tie[r];
+      double* out = J.tie_r + (int64_t)r * J.d + pj;
+      const double Rv = pi == pj ? 0.0 : pair_measure64(J, pi, pj, lane);
+      if (lane == 0) *out = Rv;
+      __threadfence();
+      int done = 0;
+      if (lane == 0) done = atomicAdd(&J.ctrl->tie_done, 1) + 1;
+      done = __shfl(done, 0);
+      if ((int64_t)done == spre[lo] - (lo ? spre[lo - 1] : 0)) {
+        __threadfence();
+        tie_commit(J, m, J.ctrl->ntie, t, lane);
+      }
+    }
+    base += total;
+    __syncthreads();  // spre is rewritten for the next chunk
+  }
 }
 
 // Remove the chosen variable e from every remaining variable p and keep p
@@ -1177,9 +1206,8 @@ hipError_t launch_pair(const JobDev* jobs, int njobs, SchedDev sc, int grid, int
 
 hipError_t launch_tie(const JobDev* jobs, int njobs, SchedDev sc, int t, int num_cu,
                       hipStream_t st) {
-  const int per_job = num_cu * 4 / njobs > 1 ? num_cu * 4 / njobs : 1;
-  hipLaunchKernelGGL(k_tie, dim3((unsigned)(per_job * njobs)), dim3(256), 0, st, jobs, njobs,
-                     (const JobStep*)sc.js, per_job, t);
+  hipLaunchKernelGGL(k_tie, dim3((unsigned)(num_cu * 4)), dim3(256), 0, st, jobs, njobs,
+                     (const JobStep*)sc.js, t);
   return hipGetLastError();
 }
 

@@ -937,6 +937,8 @@ __device__ inline void commit_or_defer(const JobDev& J, int t, int m, const Best
                                        int ntie) {
   if (J.tie_on && ntie >= 2 && ntie <= kMaxTie) {
     J.ctrl->ntie = ntie;
+    J.ctrl->tie_t = t;
+    J.ctrl->tie_done = 0;
     J.ctrl->tie_audit = 0;
     J.ctrl->full = 0;
     if (J.gaps) J.gaps[t] = best.v - best.v2;
