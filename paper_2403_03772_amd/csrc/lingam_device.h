@@ -79,7 +79,9 @@ __device__ inline void dither_float(double c, float& lo, float& hi, int& n_hi) {
   const float g = (double)f < c ? nextafterf(f, INFINITY) : nextafterf(f, -INFINITY);
   lo = fminf(f, g);
   hi = fmaxf(f, g);
-  n_hi = (int)rint(64.0 * (c - (double)lo) / ((double)hi - (double)lo));
+  // hi - lo is a power of two: scale by its exponent instead of dividing
+  const double gap = (double)hi - (double)lo;
+  n_hi = (int)rint(ldexp(c - (double)lo, 6 - ilogb(gap)));
 }
 
 // FP64 log cosh and Gaussian-weighted term (marginals and the FP64 pair path).
@@ -342,7 +344,7 @@ __device__ __forceinline__ void for_blocks(const int32_t* __restrict__ pre, int 
 // (ceil(nsus / 8) x ceil(ne / 8) tiles whose j side lists positions too).
 enum PairMode : int { kModeAll = 0, kModeCand = 1, kModeSusp = 2, kModeExt = 3 };
 
-template <int kMode>
+template <int kMode, int W>
 __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int local,
                                           int wave, int lane);
 
@@ -365,7 +367,7 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
   const int p = x * Q + (x < R ? x : R) + idx;
   auto run = [&](int jb, int local) {
     const int item = local / kQ;
-    pair_item<kMode>(jobs[jb], js[jb], item, (local - item * kQ) * W + lw, lane);
+    pair_item<kMode, W>(jobs[jb], js[jb], item, (local - item * kQ) * W + lw, lane);
   };
   int jb, local;
   if (!kLoop) {  // the grid is the schedule: one item per workgroup
@@ -381,7 +383,7 @@ __device__ __forceinline__ void pair_tiles(const JobDev* __restrict__ jobs, int 
   }
 }
 
-template <int kMode>
+template <int kMode, int W>
 __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int local,
                                           int wave, int lane) {
   constexpr bool kCand = kMode != kModeAll;
@@ -433,7 +435,7 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
       double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
       const double lim = 1.0 - kCollinear;
       r = r > lim ? lim : (r < -lim ? -lim : r);
-      const double c1 = -2.0 * kLog2e / sqrt(1.0 - r * r);
+      const double c1 = -2.0 * kLog2e * rsqrt(1.0 - r * r);
       my_r = (float)r;
       dither_float(c1, my_lo, my_hi, my_n);
     }
@@ -516,33 +518,40 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
     }
   }
 
-  // FP64 reduction over the 64 lanes: fold the upper half onto the lower, then
-  // a reduce-scatter butterfly over 32 lanes; afterwards lane L < 32 holds sum L.
-  double v[32];
+  // FP64 sums over the 64 lanes through the wave's own LDS block: lane l
+  // writes its 32 sums as column l, then lane L adds, in FP64 and in lane
+  // order, sum L & 31 of lanes 32 (L >> 5) .. 32 (L >> 5) + 31, and the two
+  // halves are added with one exchange; afterwards lane L < 32 holds sum L.
+  // No barrier: a wave's LDS operations complete in the order it issues
+  // them, and no other wave touches the block.
+  constexpr int kPitch = 68;  // floats per row: 16-byte aligned rows, spread banks
+  __shared__ __align__(16) float red[W][32][kPitch];
+  float(*T)[kPitch] = red[threadIdx.x >> 6];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    v[2 * q] = (double)S1[q];
-    v[2 * q + 1] = (double)S2[q];
+    T[2 * q][lane] = S1[q];
+    T[2 * q + 1][lane] = S2[q];
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  double v0 = 0.0;
+  {
+    const float4* row = reinterpret_cast<const float4*>(&T[lane & 31][(lane >> 5) * 32]);
 #pragma unroll
-  for (int k2 = 0; k2 < 32; ++k2) v[k2] += __shfl_xor(v[k2], 32);
-#pragma unroll
-  for (int half = 16; half >= 1; half >>= 1) {
-    const bool up = (lane & half) != 0;
-#pragma unroll
-    for (int k2 = 0; k2 < half; ++k2) {
-      const double lo = v[k2], hi = v[k2 + half];
-      const double send = up ? lo : hi;
-      const double keep = up ? hi : lo;
-      v[k2] = keep + __shfl_xor(send, half);
+    for (int j = 0; j < 8; ++j) {
+      const float4 f = row[j];
+      v0 += (double)f.x;
+      v0 += (double)f.y;
+      v0 += (double)f.z;
+      v0 += (double)f.w;
     }
   }
+  v0 += __shfl_xor(v0, 32);
   if (lane < 32) {
     // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
     const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
     const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
     double* part = kMode == kModeAll ? J.part : (kMode == kModeCand ? J.partc : J.parts);
-    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v[0];
+    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v0;
   }
 }
 

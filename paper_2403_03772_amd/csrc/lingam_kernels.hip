@@ -384,8 +384,7 @@ __global__ __launch_bounds__(64 * W) void k_pair(const JobDev* __restrict__ jobs
 }
 
 // The same kernel for gated launches (learned form): a bounded grid walks the
-// step's items (held at 5 waves per SIMD like the all-pairs kernel; the loop's
-// few extra values spill outside the sample loop).
+// step's items.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_pair_loop(const JobDev* __restrict__ jobs,
                                                          int njobs,

@@ -1082,9 +1082,8 @@ __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict
         pre + (int64_t)kind * (njobs + 1), sh);
 }
 
-// The bounded-grid pair kernels walk their items in a loop; the launch bound
-// keeps them at the all-pairs kernel's 5 waves per SIMD (the few values the
-// loop adds spill outside the sample loop).
+// The bounded-grid pair kernels (suspect and extension rows) walk their items
+// in a loop.
 template <int W>
 __global__ __launch_bounds__(64 * W) void k_pair_susp(const JobDev* __restrict__ jobs,
                                                          int njobs,

@@ -30,6 +30,8 @@ import numpy as np
 from . import lib as L
 from . import synth
 
+N_FEAT = L.N_FEATURES
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "proposer_weights.npz")
 
@@ -49,77 +51,166 @@ def soft_weights(k) -> np.ndarray:
     return ((2.0 * kmin) / (k + kmin)) ** 2
 
 
-def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n_lo: int = 2048,
-            n_hi: int = 16384, steps_per_sem: int = 32, m_floor: int = 64, seed: int = 0,
-            batch: int = 16, workers: int = 8, log=print):
-    """Training lists from plain GPU orderings of ``n_sems`` SEMs (d ~ U[d_lo,
-    d_hi], n log-uniform in [n_lo, n_hi] and at least 2 d, gene-expression-scale
-    family; a draw the plain search finds degenerate is skipped).  At up to
-    ``steps_per_sem`` steps with at least ``m_floor`` active variables, a list
-    holds the features of the active variables; its target is the plain
-    choice, and its variables' k values give the soft target weights.  SEMs
-    are drawn by a pool of ``workers`` processes ahead of the GPU.  Returns
-    (features float32 [rows, 16], offsets int64, targets int64, weights
-    float32 [rows])."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-
-    import torch
-
+def sem_specs(n_sems: int, d_lo: int, d_hi: int, n_lo: int, n_hi: int, seed: int):
+    """(d, n, seed) of ``n_sems`` SEMs: d ~ U[d_lo, d_hi], n log-uniform in
+    [n_lo, n_hi] and at least 2 d."""
     rng = np.random.default_rng(seed)
     specs = []
     for _ in range(n_sems):
         d = int(rng.integers(d_lo, d_hi + 1))
         n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
         specs.append((d, max(n, 2 * d), int(rng.integers(1 << 31))))  # n >= 2 d
-    feats, offs, tgs, wts = [], [0], [], []
-    done = 0
-    t0 = time.time()
+    return specs
+
+
+def label_batches(specs, steps_per_sem: int = 32, m_floor: int = 64, batch: int = 16,
+                  workers: int = 8, log=print):
+    """Training lists from plain GPU orderings of the SEMs ``specs`` (a draw
+    the plain search finds degenerate is skipped), one batched ordering of
+    ``batch`` SEMs at a time.  At up to ``steps_per_sem`` steps with at least
+    ``m_floor`` active variables (drawn from the SEM's own seed), a list holds
+    the features of the active variables; its target is the plain choice, and
+    its variables' k values give the soft target weights.  SEMs are drawn by
+    a pool of ``workers`` processes ahead of the GPU.  Yields, per batch,
+    the number of SEMs it took and its lists (features float32 [rows, 16],
+    offsets int64, targets int64, weights float32 [rows]; empty when every
+    SEM of the batch was skipped)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+
+    n_sems = len(specs)
     pool = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
     futs = [pool.submit(_gen, sp) for sp in specs[:2 * batch]]
     nxt = len(futs)
-    while done < n_sems:
-        cnt = min(batch, n_sems - done)
-        Xs = [futs[done + k].result() for k in range(cnt)]
-        for _ in range(cnt):
-            if nxt < n_sems:
-                futs.append(pool.submit(_gen, specs[nxt]))
-                nxt += 1
-        jobs = [{"X": torch.as_tensor(X, device="cuda")} for X in Xs]
-        out = L.batch_causal_order(jobs, record_features=True, with_measures=True,
-                                   raise_on_error=False)
-        status = out["status"].cpu().numpy()
-        for k, X in enumerate(Xs):
-            d = X.shape[1]
-            futs[done + k] = None
-            if status[k] != 0:  # a degenerate draw (collinear residuals): skip it
-                log(f"collect: SEM {done + k} skipped (status {int(status[k])})")
-                continue
-            order = out["orders"][k].cpu().numpy()
-            R = out["features"][k]
-            Mk = out["measures"][k]
-            last = d - m_floor  # steps t <= last have m >= m_floor
-            if last < 0:
-                continue
-            ts = np.sort(rng.choice(last + 1, size=min(steps_per_sem, last + 1), replace=False))
-            Rt = R[torch.as_tensor(ts, device=R.device)].cpu().numpy()
-            Mt = Mk[torch.as_tensor(ts, device=Mk.device)].cpu().numpy()
-            for i, t in enumerate(ts):
-                act = np.flatnonzero(~np.isnan(Rt[i, :, 0]))
-                w = soft_weights(-Mt[i, act])
-                if not np.isfinite(w).all() or not w.sum() > 0.0:
+    done = 0
+    try:
+        while done < n_sems:
+            cnt = min(batch, n_sems - done)
+            Xs = [futs[done + k].result() for k in range(cnt)]
+            for _ in range(cnt):
+                if nxt < n_sems:
+                    futs.append(pool.submit(_gen, specs[nxt]))
+                    nxt += 1
+            jobs = [{"X": torch.as_tensor(X, device="cuda")} for X in Xs]
+            out = L.batch_causal_order(jobs, record_features=True, with_measures=True,
+                                       raise_on_error=False)
+            status = out["status"].cpu().numpy()
+            feats, offs, tgs, wts = [], [0], [], []
+            for k, X in enumerate(Xs):
+                d = X.shape[1]
+                futs[done + k] = None
+                if status[k] != 0:  # a degenerate draw (collinear residuals): skip it
+                    log(f"label: SEM {done + k} skipped (status {int(status[k])})")
                     continue
-                feats.append(Rt[i, act])
-                wts.append(w.astype(np.float32))
-                tgs.append(offs[-1] + int(np.flatnonzero(act == order[t])[0]))
-                offs.append(offs[-1] + act.size)
-        done += cnt
-        del out, jobs
-        log(f"collect: {done}/{n_sems} SEMs, {len(tgs)} lists, {offs[-1]} rows, "
-            f"{time.time() - t0:.0f} s")
-    pool.shutdown()
-    return (np.concatenate(feats).astype(np.float32), np.asarray(offs, np.int64),
-            np.asarray(tgs, np.int64), np.concatenate(wts).astype(np.float32))
+                order = out["orders"][k].cpu().numpy()
+                R = out["features"][k]
+                Mk = out["measures"][k]
+                last = d - m_floor  # steps t <= last have m >= m_floor
+                if last < 0:
+                    continue
+                rng = np.random.default_rng(specs[done + k][2])
+                ts = np.sort(rng.choice(last + 1, size=min(steps_per_sem, last + 1),
+                                        replace=False))
+                Rt = R[torch.as_tensor(ts, device=R.device)].cpu().numpy()
+                Mt = Mk[torch.as_tensor(ts, device=Mk.device)].cpu().numpy()
+                for i, t in enumerate(ts):
+                    act = np.flatnonzero(~np.isnan(Rt[i, :, 0]))
+                    w = soft_weights(-Mt[i, act])
+                    if not np.isfinite(w).all() or not w.sum() > 0.0:
+                        continue
+                    feats.append(Rt[i, act])
+                    wts.append(w.astype(np.float32))
+                    tgs.append(offs[-1] + int(np.flatnonzero(act == order[t])[0]))
+                    offs.append(offs[-1] + act.size)
+            done += cnt
+            del out, jobs
+            F = (np.concatenate(feats) if feats else np.zeros((0, N_FEAT))).astype(np.float32)
+            W = (np.concatenate(wts) if wts else np.zeros(0)).astype(np.float32)
+            yield cnt, (F, np.asarray(offs, np.int64), np.asarray(tgs, np.int64), W)
+    finally:
+        pool.shutdown(cancel_futures=True)
+
+
+def collect(n_sems: int, d_lo: int = 100, d_hi: int = 1000, n_lo: int = 2048,
+            n_hi: int = 16384, steps_per_sem: int = 32, m_floor: int = 64, seed: int = 0,
+            batch: int = 16, workers: int = 8, log=print):
+    """Training lists of ``n_sems`` SEMs (``sem_specs``, ``label_batches``),
+    all held at once.  Returns (features float32 [rows, 16], offsets int64,
+    targets int64, weights float32 [rows])."""
+    t0 = time.time()
+    sets, lists = [], 0
+    specs = sem_specs(n_sems, d_lo, d_hi, n_lo, n_hi, seed)
+    for _, part in label_batches(specs, steps_per_sem, m_floor, batch, workers, log):
+        sets.append(part)
+        lists += len(part[2])
+        log(f"collect: {lists} lists, {time.time() - t0:.0f} s")
+    return _concat(sets)
+
+
+def _lists(F, offs, tgs, W):
+    """A list set as per-list tuples (features, target row, weights)."""
+    return [(F[offs[i]:offs[i + 1]], int(tgs[i] - offs[i]), W[offs[i]:offs[i + 1]])
+            for i in range(len(tgs))]
+
+
+def _stack(items):
+    """Per-list tuples -> one list set."""
+    sizes = np.array([f.shape[0] for f, _, _ in items], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return (np.concatenate([f for f, _, _ in items]), offs,
+            offs[:-1] + np.array([t for _, t, _ in items], dtype=np.int64),
+            np.concatenate([w for _, _, w in items]))
+
+
+def stream_train(prop, specs, state: dict, *, lr: float, lr_end: float, total_updates: int,
+                 updates_per_batch: int = 4, replay_lists: int = 4096,
+                 lists_per_batch: int = 256, batch: int = 16, steps_per_sem: int = 32,
+                 workers: int = 8, time_budget: float = float("inf"), log=print):
+    """Train ``prop`` while its data is labeled: after each batched plain
+    ordering of ``batch`` SEMs, ``updates_per_batch`` Adam steps on the soft
+    listwise cross-entropy, each on ``lists_per_batch`` lists drawn from a
+    buffer of the newest ``replay_lists`` lists (the full set of 10^4 SEMs
+    would not fit in memory).  The learning rate falls from ``lr`` to
+    ``lr_end`` on a cosine over ``total_updates``.  ``state`` (Adam moments,
+    step, next SEM index into ``specs``, losses) is updated in place so that a
+    run can stop after ``time_budget`` seconds and resume."""
+    import torch
+
+    P = torch.as_tensor(prop, device="cuda")
+    m1 = torch.as_tensor(state["m1"], device="cuda")
+    m2 = torch.as_tensor(state["m2"], device="cuda")
+    buf = []
+    t0 = time.time()
+    ws = None
+    todo = specs[int(state["next_sem"]):]
+    for cnt, part in label_batches(todo, steps_per_sem, batch=batch, workers=workers, log=log):
+        state["next_sem"] += cnt
+        buf.extend(_lists(*part))
+        if not buf:
+            continue
+        del buf[:max(0, len(buf) - replay_lists)]
+        rng = np.random.default_rng([int(state["seed"]), int(state["step"])])
+        losses = []
+        for _ in range(updates_per_batch):
+            sel = rng.choice(len(buf), size=min(lists_per_batch, len(buf)), replace=False)
+            Fb, bo, _, Wb = _stack([buf[i] for i in sel])
+            state["step"] += 1
+            frac = min(1.0, state["step"] / max(total_updates, 1))
+            lr_t = lr_end + 0.5 * (lr - lr_end) * (1.0 + np.cos(np.pi * frac))
+            loss, g, _, ws = L.proposer_grad(P, torch.as_tensor(Fb, device="cuda"), bo,
+                                             weights=torch.as_tensor(Wb, device="cuda"),
+                                             workspace=ws)
+            L.proposer_adam(P, g, m1, m2, state["step"], lr=lr_t)
+            losses.append(float(loss.item()))
+        state["loss"].append(float(np.mean(losses)))
+        log(f"stream: SEMs {state['next_sem']}/{len(specs)}, update {state['step']}, "
+            f"loss {state['loss'][-1]:.4f}, buffer {len(buf)} lists, {time.time() - t0:.0f} s")
+        if time.time() - t0 > time_budget:
+            break
+    state["m1"], state["m2"] = m1.cpu().numpy(), m2.cpu().numpy()
+    return P.cpu().numpy()
 
 
 def normalization(F) -> np.ndarray:
@@ -262,6 +353,73 @@ def _concat(sets):
     return (np.concatenate(Fs), np.concatenate(os_), np.concatenate(ts), np.concatenate(Ws))
 
 
+def _save_state(path: str, prop, state: dict) -> None:
+    scal = {k: v for k, v in state.items() if k not in ("m1", "m2")}
+    np.savez(path, proposer=np.asarray(prop, np.float32), m1=np.asarray(state["m1"], np.float32),
+             m2=np.asarray(state["m2"], np.float32), state=np.array(json.dumps(scal)))
+
+
+def _load_state(path: str):
+    with np.load(path, allow_pickle=False) as z:
+        state = json.loads(str(z["state"]))
+        state["m1"], state["m2"] = z["m1"].astype(np.float32), z["m2"].astype(np.float32)
+        return z["proposer"].astype(np.float32), state
+
+
+def stream_main(a, log) -> int:
+    """Stage two: fine-tune a trained network on ``--sems`` SEMs labeled while
+    it trains (``stream_train``), resumable through ``--ckpt``; once every
+    training SEM is done, evaluate on the held-out SEMs and write ``--out``."""
+    t0 = time.time()
+    specs = sem_specs(a.sems, a.d_lo, a.d_hi, a.n_lo, a.n_hi, a.seed)
+    n_train = a.sems - a.holdout_sems
+    if a.ckpt and os.path.exists(a.ckpt):
+        prop, state = _load_state(a.ckpt)
+        log(f"stream: resuming at SEM {state['next_sem']}, update {state['step']}")
+    else:
+        prop, meta0 = load_weights(a.init)
+        state = {"m1": np.zeros(L.N_PARAMS, np.float32), "m2": np.zeros(L.N_PARAMS, np.float32),
+                 "step": 0, "next_sem": 0, "loss": [], "seed": a.seed, "seconds": 0.0,
+                 "init_meta": meta0}
+    total = -(-n_train // a.batch) * a.updates
+    if state["next_sem"] < n_train:
+        prop = stream_train(prop, specs[:n_train], state, lr=a.lr, lr_end=a.lr_end,
+                            total_updates=total, updates_per_batch=a.updates,
+                            replay_lists=a.replay, batch=a.batch,
+                            steps_per_sem=a.steps_per_sem, workers=a.workers,
+                            time_budget=a.time_budget, log=log)
+        state["seconds"] = float(state["seconds"]) + (time.time() - t0)
+        if a.ckpt:
+            _save_state(a.ckpt, prop, state)
+    if state["next_sem"] < n_train:
+        log(f"stream: stopped at SEM {state['next_sem']} of {n_train} (resume with --ckpt)")
+        return 0
+    log("stream: evaluating on the held-out SEMs")
+    hold = _concat([p for _, p in label_batches(specs[n_train:], a.steps_per_sem,
+                                                batch=a.batch, workers=a.workers, log=log)])
+    init_prop, _ = load_weights(a.init)
+    big = None
+    if a.big_holdout > 0:
+        bs = sem_specs(a.big_holdout, a.big_d_lo, a.big_d_hi, a.big_n_lo, a.big_n_hi,
+                       a.seed + 7)
+        big = _concat([p for _, p in label_batches(bs, a.steps_per_sem, batch=2,
+                                                   workers=a.workers, log=log)])
+    meta = dict(state["init_meta"])
+    meta["stage2"] = {
+        "sems": n_train, "holdout_sems": a.holdout_sems, "d": [a.d_lo, a.d_hi],
+        "n": [a.n_lo, a.n_hi], "steps_per_sem": a.steps_per_sem, "batch": a.batch,
+        "updates_per_batch": a.updates, "replay_lists": a.replay, "lr": [a.lr, a.lr_end],
+        "updates": int(state["step"]), "loss": state["loss"][::10],
+        "seconds": round(float(state["seconds"]), 1),
+        "holdout": evaluate(prop, *hold), "holdout_stage1_net": evaluate(init_prop, *hold)}
+    if big is not None:
+        meta["stage2"]["holdout_big"] = evaluate(prop, *big)
+        meta["stage2"]["holdout_big_stage1_net"] = evaluate(init_prop, *big)
+    save(a.out, prop, meta)
+    log(json.dumps({k: v for k, v in meta["stage2"].items() if k != "loss"}))
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--sems", type=int, default=1000)
@@ -283,8 +441,22 @@ def main(argv=None) -> int:
     ap.add_argument("--holdout", type=float, default=0.1)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", default=WEIGHTS)
+    # stage two (streamed fine-tuning)
+    ap.add_argument("--stream", action="store_true",
+                    help="fine-tune --init on --sems SEMs labeled while it trains")
+    ap.add_argument("--init", default=WEIGHTS)
+    ap.add_argument("--ckpt", default=None, help="resumable state of a streamed run")
+    ap.add_argument("--holdout-sems", type=int, default=200)
+    ap.add_argument("--big-holdout", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--updates", type=int, default=4)
+    ap.add_argument("--replay", type=int, default=4096)
+    ap.add_argument("--lr-end", type=float, default=1e-4)
+    ap.add_argument("--time-budget", type=float, default=float("inf"))
     a = ap.parse_args(argv)
     log = lambda msg: print(msg, flush=True)  # noqa: E731
+    if a.stream:
+        return stream_main(a, log)
     t0 = time.time()
     sets = [collect(a.sems, a.d_lo, a.d_hi, a.n_lo, a.n_hi, a.steps_per_sem,
                     seed=a.seed, workers=a.workers, log=log)]
