@@ -306,25 +306,31 @@ __host__ __device__ inline int32_t cdiv(int64_t a, int64_t b) { return (int32_t)
 // blocks to its right -- so the tiles that run at the same time on one XCD
 // read few distinct rows.  Bijective from [0, nb (nb + 1) / 2).
 constexpr int kSuperTile = 8;
+// 32-bit unsigned arithmetic throughout (tile counts are int32, so every
+// intermediate below stays under 2^32), with shifts where the super-row and
+// the block are full (height and width kSuperTile): in a kernel's prologue a
+// 64-bit division is over a hundred scalar instructions.
 __host__ __device__ inline void decode_tile_st(int tile, int nb, int& bi, int& bj) {
-  constexpr int64_t S = kSuperTile;
-  const int ns = (nb + kSuperTile - 1) / kSuperTile;
+  constexpr uint32_t S = kSuperTile;
+  static_assert(S == 8, "the shifts below assume 8 x 8 super-blocks");
+  const uint32_t t = (uint32_t)tile, B = (uint32_t)nb;
+  const uint32_t ns = (B + S - 1) / S;
   // tiles before full super-row q: q S (S + 1) / 2 + S (q nb - S q (q + 1) / 2)
-  auto pre = [nb](int64_t q) -> int64_t {
-    return q * S * (S + 1) / 2 + S * (q * nb - S * q * (q + 1) / 2);
+  auto pre = [B](uint32_t q) -> uint32_t {
+    return q * (S * (S + 1) / 2) + S * (q * B - S * (q * (q + 1) / 2));
   };
-  int lo = 0, hi = ns - 1;
+  uint32_t lo = 0, hi = ns - 1;
   while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (pre(mid) <= tile) lo = mid;
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (pre(mid) <= t) lo = mid;
     else hi = mid - 1;
   }
-  const int64_t r0 = (int64_t)lo * S;
-  const int64_t h = (int64_t)nb - r0 < S ? (int64_t)nb - r0 : S;
-  int64_t r = tile - pre(lo);
-  const int64_t diag = h * (h + 1) / 2;
+  const uint32_t r0 = lo * S;
+  const uint32_t h = B - r0 < S ? B - r0 : S;
+  uint32_t r = t - pre(lo);
+  const uint32_t diag = h * (h + 1) / 2;
   if (r < diag) {
-    int a = 0;
+    uint32_t a = 0;
     while (r >= h - a) {
       r -= h - a;
       ++a;
@@ -334,12 +340,13 @@ __host__ __device__ inline void decode_tile_st(int tile, int nb, int& bi, int& b
     return;
   }
   r -= diag;
-  const int64_t blk = r / (h * S);
-  const int64_t rem = r - blk * h * S;
-  const int64_t c0 = r0 + S * (blk + 1);
-  const int64_t w = (int64_t)nb - c0 < S ? (int64_t)nb - c0 : S;
-  bi = (int)(r0 + rem / w);
-  bj = (int)(c0 + rem % w);
+  const uint32_t hs = h * S;
+  const uint32_t blk = h == S ? r >> 6 : r / hs;
+  const uint32_t rem = r - blk * hs;
+  const uint32_t c0 = r0 + S * (blk + 1);
+  const uint32_t w = B - c0 < S ? B - c0 : S;
+  bi = (int)(r0 + (w == S ? rem >> 3 : rem / w));
+  bj = (int)(c0 + (w == S ? rem & 7u : rem % w));
 }
 
 // The step's plan for a job without the split (needs the batch-wide sum).
