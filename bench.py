@@ -620,6 +620,10 @@ def main() -> int:
         rec["learned"]["proposer"] = {k: meta.get(k) for k in
                                       ("sems", "d", "n", "big_sems", "big_d", "target",
                                        "lists", "holdout", "holdout_big")}
+        if "stage2" in meta:  # streamed fine-tuning on further SEMs
+            rec["learned"]["proposer"]["stage2"] = {
+                k: meta["stage2"].get(k) for k in ("sems", "d", "n", "updates", "holdout",
+                                                   "holdout_big")}
         # fast form: no second pass, the best candidate is always taken
         fast = lg.Learned(prop, topk=K, margin=-np.inf, max_suspects=0, audit_every=32)
         if not args.exact_only:
