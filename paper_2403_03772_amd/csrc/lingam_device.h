@@ -17,7 +17,7 @@ constexpr double kHnu = 1.41893853320467274178;  // (1 + ln(2 pi)) / 2
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kLog2e = 1.44269504088896340736;
 constexpr double kCollinear = 1e-12;  // |rho| >= 1 - kCollinear is degenerate
-constexpr int kLogBlock = 16;         // samples per lane folded into one log2
+constexpr int kLogBlock = 32;         // samples per lane folded into one log2 (product <= 2^32)
 constexpr float kS1Start = 9.0f;      // start value (negated) of each lane's log cosh sum
 
 constexpr int32_t kStInvalid = -1;

@@ -28,9 +28,10 @@
 // Arithmetic of the hot loop (per sample, per direction), with u = alpha t,
 // t = x - rho y, alpha = 1/sqrt(1 - rho^2):
 //   log cosh u = ln2 * ( |u| log2(e) + log2((1 + e^{-2|u|}) / 2) )
-//   m1 = -2 alpha log2(e) |t|    (pair constant split hi + lo, one FMA: the
-//                                 FP32 rounding of the constant would bias
-//                                 every sample the same way)
+//   m1 = -2 alpha log2(e) |t|    (the pair constant dithered over the lanes
+//                                 between its two FP32 neighbours: one FP32
+//                                 rounding of it would bias every sample the
+//                                 same way)
 //   e1 = 2^m1 = e^{-2|u|};  m2 = -m1^2 / (8 log2 e) = -u^2 log2(e) / 2;
 //   e2 = 2^m2 = e^{-u^2/2}
 //   S1 += -m1/2 ;  P *= (1 + e1) ;  S2 += t e2
