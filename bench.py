@@ -332,16 +332,19 @@ def run_large(lg, tp, seed: int, rates) -> dict:
     progress("large workload: plain ordering (about two minutes)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    order = lg.causal_order(X, workspace=ws)
+    out = lg.causal_order(X, workspace=ws, profile=True)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - t0) * 1e3
-    plain_order = order.cpu().numpy()
+    plain_order = out["order"].cpu().numpy()
+    prof = out["profile"]
     del ws
     progress(f"large workload: plain {plain_ms / 1e3:.1f} s")
     prop = tp.default_proposer()
     rec = {"workload": "gene-expression-scale SEM", "d": d, "n": n, "seed": seed,
            "plain_ms": plain_ms, "plain_evals_per_s": evals_per_ordering(n, d) / (plain_ms * 1e-3),
-           "plain_reversed_edges": reversed_edges(plain_order, B)}
+           "plain_reversed_edges": reversed_edges(plain_order, B),
+           "plain_fp64_ties": {"steps": prof.tie_steps, "rows": prof.tie_rows,
+                               "overflow_steps": prof.tie_overflow}}
     for name, cfg in (("exact", lg.Learned(prop, topk=64)),
                       ("audited_every_32", lg.Learned(prop, topk=64, audit_every=32))):
         progress(f"large workload: learned ({name})")
@@ -447,7 +450,7 @@ def run_plain(lg, X, n, d, steps, warmup):
         lg.causal_order(X, workspace=ws)
     torch.cuda.synchronize()
     acc = dict(pair_ms=0.0, pair_evals=0.0, pair_launches=0, gram_ms=0.0, gram_flops=0.0,
-               resid_ms=0.0, resid_bytes=0.0, tie_steps=0, tie_rows=0)
+               resid_ms=0.0, resid_bytes=0.0, tie_steps=0, tie_rows=0, tie_overflow=0)
     orders = []
     t0 = time.perf_counter()
     for i in range(steps):
@@ -601,7 +604,8 @@ def main() -> int:
                   if pl["resid_ms"] else None},
         # near-ties decided in FP64 (per ordering)
         "fp64_ties": {"steps": pl["tie_steps"] // args.steps,
-                      "rows": pl["tie_rows"] // args.steps},
+                      "rows": pl["tie_rows"] // args.steps,
+                      "overflow_steps": pl["tie_overflow"] // args.steps},
         "learned": None,
     }
     if not args.no_learned and not os.path.exists(tp.WEIGHTS):

@@ -97,6 +97,9 @@ typedef struct lingam_profile {
                              2 n (suspects * extension + measured rows * (m - 1)) */
   int32_t tie_steps;      /* steps whose choice the FP64 tie resolution made */
   int32_t tie_rows;       /* ... rows it measured in FP64 */
+  int32_t tie_overflow;   /* steps whose near-tied set held more than the 16 variables
+                             the FP64 resolution takes (the FP32 measures decided) */
+  int32_t reserved;       /* zero */
 } lingam_profile;
 
 /* Decisions of the learned form, summed over the jobs of a call (host). */

@@ -668,6 +668,7 @@ int finish(const Plan& P, const std::vector<lg::JobDev>& dj, char* ws, const lin
     for (const lg::Ctrl& c : ctrl) {
       pr->tie_steps += c.n_ties;
       pr->tie_rows += c.n_tie_rows;
+      pr->tie_overflow += c.n_tie_overflow;
     }
     // steps a learned decision took did not run the all-pairs kernel; steps
     // decided by the second pass measured their suspects against the

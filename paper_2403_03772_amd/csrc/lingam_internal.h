@@ -113,7 +113,9 @@ struct Ctrl {
   int32_t n_ties;          // steps decided by the FP64 tie resolution
   int32_t n_tie_rows;      // ... rows they measured in FP64
   int32_t tie_done;        // pairs of the FP64 decision finished
-  int32_t pad[38];
+  int32_t n_tie_overflow;  // steps with more than kMaxTie near-tied positions (the
+                           // FP32 measures decided them)
+  int32_t pad[37];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 

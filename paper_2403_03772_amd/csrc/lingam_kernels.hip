@@ -113,7 +113,6 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
     if (threadIdx.x < 64) step_schedule_wave(jobs, njobs, t, num_cu, tu, js, pre);
     return;
   }
-  __shared__ int32_t sh[1024];
   __shared__ long long items;
   const int tid = threadIdx.x;
   if (tid == 0) items = 0;
@@ -134,10 +133,23 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
     js[j] = s;
   }
   __syncthreads();
-  for (int kind = 0; kind < kNumKinds; ++kind)
-    block_scan(
-        njobs, [&](int j) { return kind_count(js[j], kind); },
-        pre + (int64_t)kind * (njobs + 1), sh);
+  // the kinds' prefix sums are independent: one wave per kind, 64 jobs at a
+  // time, no block barriers (a block-wide scan per kind took ~50 us for a few
+  // hundred jobs)
+  const int lane = tid & 63;
+  for (int kind = tid >> 6; kind < kNumKinds; kind += 16) {
+    int32_t* out = pre + (int64_t)kind * (njobs + 1);
+    int32_t run = 0;
+    for (int j0 = 0; j0 < njobs; j0 += 64) {
+      const int j = j0 + lane;
+      const int32_t c = j < njobs ? kind_count(js[j], kind) : 0;
+      int32_t total;
+      const int32_t ex = wave_excl_scan(c, total);
+      if (j < njobs) out[j] = run + ex;
+      run += total;
+    }
+    if (lane == 0) out[njobs] = run;
+  }
 }
 
 // After the learned decisions: gate off the full step of every job whose
@@ -552,6 +564,7 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
   }
   __syncthreads();
   const bool defer = refine && ntie >= 2 && ntie <= kMaxTie;
+  if (tid == 0 && refine && ntie > kMaxTie) J.ctrl->n_tie_overflow += 1;
   if (tid == 0) {
     const bool audit = js[jb].learned && J.audit_every > 0 && t % J.audit_every == 0;
     if (J.gaps) J.gaps[t] = best.v - best.v2;

@@ -935,6 +935,7 @@ __device__ inline void gather_ties(const JobDev& J, double lim, const double* kv
 // either way.  Thread 0 only.
 __device__ inline void commit_or_defer(const JobDev& J, int t, int m, const Best& best,
                                        int ntie) {
+  if (J.tie_on && ntie > kMaxTie) J.ctrl->n_tie_overflow += 1;
   if (J.tie_on && ntie >= 2 && ntie <= kMaxTie) {
     J.ctrl->ntie = ntie;
     J.ctrl->tie_t = t;

@@ -51,6 +51,8 @@ class _Profile(ctypes.Structure):
         ("cand_evals", ctypes.c_double),
         ("tie_steps", ctypes.c_int32),
         ("tie_rows", ctypes.c_int32),
+        ("tie_overflow", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -125,6 +127,8 @@ class Profile:
     cand_evals: float
     tie_steps: int
     tie_rows: int
+    tie_overflow: int
+    reserved: int
 
 
 @dataclass

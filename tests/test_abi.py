@@ -311,7 +311,7 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the ABI structs have the sizes the library expects."""
     o = _opts()
     assert o.struct_size == ctypes.sizeof(L._Opts)
-    assert ctypes.sizeof(L._Profile) == 12 * 8
+    assert ctypes.sizeof(L._Profile) == 13 * 8
     assert ctypes.sizeof(L._LearnedStats) == 48
     assert ctypes.sizeof(L._Job) == 10 * 8
 
