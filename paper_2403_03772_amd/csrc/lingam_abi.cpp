@@ -285,18 +285,22 @@ struct StepTotals {
   double pair_evals = 0.0, resid_bytes = 0.0, cand_evals = 0.0;
 };
 
-StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, lg::Tune tu) {
+// `ties`: the FP64 resolution of near-ties is on (the learned passes then
+// take their own sample splits).
+StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, lg::Tune tu,
+                       bool ties) {
   StepTotals T;
   std::vector<lg::JobStep> js(P.njobs);
   const int K = P.lc.proposer ? P.lc.K : 0;
-  int64_t items = 0;
+  int64_t items = 0, items_c = 0;
   for (int k = 0; k < P.njobs; ++k) {
     js[k] = lg::job_step_base((int32_t)jobs[k].d, t, K, P.lc.min_m, jobs[k].record != nullptr);
     if (js[k].m >= 2 && !js[k].fp64) items += 2LL * js[k].ntiles;
+    if (js[k].learned) items_c += 2LL * js[k].nct;
   }
   for (int k = 0; k < P.njobs; ++k) {
     lg::job_split(js[k], (int32_t)P.L[k].n_pad, items, P.cu, tu);
-    lg::job_split_cand(js[k]);
+    lg::job_split_cand(js[k], (int32_t)P.L[k].n_pad, items_c, P.cu, tu, ties);
     for (int kind = 0; kind < lg::kNumKinds; ++kind)
       T.g[kind] += lg::kind_count(js[k], kind);
     const int m = js[k].m;
@@ -309,6 +313,7 @@ StepTotals step_totals(const std::vector<HostJob>& jobs, const Plan& P, int t, l
           m, b.k,
           std::min<int32_t>(P.L[k].cap_s, P.lc.max_suspects / lg::kTileVars * lg::kTileVars));
       b.nct2 = lg::cdiv(b.nsus, lg::kTileVars) * b.nblk;
+      lg::job_split_susp(b, (int32_t)P.L[k].n_pad, 2LL * b.nct2, P.cu, tu, ties);
       b.ne = lg::ext_count(m, b.k, P.lc.extension);
       b.nct3 = b.ne > 0 ? lg::cdiv(b.nsus, lg::kTileVars) * lg::cdiv(b.ne, lg::kTileVars) : 0;
       for (int kind = lg::kKPairE; kind <= lg::kKLsel2; ++kind)
@@ -366,7 +371,7 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
   // bounded grids: one workgroup of w waves per resident slot
   auto resident = [&](int w) { return P.cu * (lg::kPairWavesPerCu / w); };
   for (int t = 0; t + 1 < P.max_d; ++t) {
-    const StepTotals T = step_totals(jobs, P, t, tu);
+    const StepTotals T = step_totals(jobs, P, t, tu, ties);
     if (T.g[lg::kKSel] == 0) break;  // every job finished
     LG_TRY(lg::launch_step_schedule(table, P.njobs, t, P.cu, tu, sc, st), "step schedule");
     if (T.g[lg::kKFeat] > 0 || T.g[lg::kKMlp] > 0)
@@ -387,7 +392,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
     if (gated) {
       LG_TRY(lg::launch_learned_back(table, P.njobs, t, sc, T.g, st), "learned decision");
       if (P.lc.extension > 0)
-        LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 0, st), "extension schedule");
+        LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 0, P.cu, tu, st),
+               "extension schedule");
       if (T.g[lg::kKPairE] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_ext(table, P.njobs, sc,
@@ -400,7 +406,8 @@ int enqueue_steps(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hip
                                    std::min<int32_t>(T.g[lg::kKCompE], P.njobs), st),
                "extension bounds");
       }
-      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 1, st), "suspect schedule");
+      LG_TRY(lg::launch_susp_schedule(table, P.njobs, sc, 1, P.cu, tu, st),
+             "suspect schedule");
       if (T.g[lg::kKPairS] > 0) {
         if (pf && pf->tm.on) pf->cand_ev.push_back(pf->tm.take(st));
         LG_TRY(lg::launch_pair_susp(table, P.njobs, sc,
@@ -518,7 +525,7 @@ void save_tune_file(const DevState& ds) {
 // the candidate pass after that step's features, scores and top-K).  Ties
 // keep the earlier candidate.
 int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStream_t st,
-             lg::Tune* out) {
+             bool ties, lg::Tune* out) {
   lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
   const lg::SchedDev sc = lg::sched_at(ws + P.sched_off, P.njobs);
   std::vector<int> steps;
@@ -534,7 +541,7 @@ int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStrea
   auto time_steps = [&](const lg::Tune& c, bool rows, double* total) -> int {
     std::vector<std::pair<int, int>> ev;
     for (int t : steps) {
-      const StepTotals T = step_totals(jobs, P, t, c);
+      const StepTotals T = step_totals(jobs, P, t, c, ties);
       const int kind = rows ? lg::kKPairC : lg::kKPair;
       if (T.g[kind] <= 0) continue;
       LG_TRY(lg::launch_step_schedule(table, P.njobs, t, P.cu, c, sc, st), "tune schedule");
@@ -728,7 +735,7 @@ int run_engine(const Plan& P, const std::vector<HostJob>& jobs, const lingam_opt
     if (rc != LINGAM_OK) return rc;
     rc = enqueue_setup(P, dj, ws, st, nullptr, [] { return hipSuccess; });
     if (rc != LINGAM_OK) return rc;
-    rc = autotune(P, jobs, ws, st, &tu);
+    rc = autotune(P, jobs, ws, st, ties, &tu);
     if (rc != LINGAM_OK) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     g_dev[dev].tunes[tkey] = tu;

@@ -388,12 +388,17 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
                                           int wave, int lane) {
   constexpr bool kCand = kMode != kModeAll;
   const int m = S.m;
-  const int nsplit = kCand ? S.nsplit_c : S.nsplit;
+  // sample split: the full step's for all pairs and the extension columns
+  const int nsplit = kMode == kModeCand ? S.nsplit_c
+                     : kMode == kModeSusp ? S.nsplit_s
+                                          : S.nsplit;
   const int ntiles = kMode == kModeAll    ? S.ntiles
                      : kMode == kModeCand ? S.nct
                      : kMode == kModeSusp ? S.nct2
                                           : S.nct3;
-  const int split_len = kCand ? S.split_len_c : S.split_len;
+  const int split_len = kMode == kModeCand ? S.split_len_c
+                        : kMode == kModeSusp ? S.split_len_s
+                                             : S.split_len;
   const int per_tile = 2 * nsplit;
   const int tile = local / per_tile, rem = local - tile * per_tile;
   const int dir = rem / nsplit, split = rem - dir * nsplit;

@@ -242,8 +242,10 @@ struct JobStep {
   int32_t learned;    // 1: learned pass this step (m > min_m)
   int32_t gate;       // 1: the full step is skipped (set after the learned decision)
   int32_t nct;        // candidate tiles (K / 8) * nblk
-  int32_t nsplit_c;   // sample splits of the learned pair kernels (= nsplit)
+  int32_t nsplit_c;   // sample splits of the candidate-row kernel
   int32_t split_len_c;
+  int32_t nsplit_s;   // ... of the suspect-row kernel (set with the suspect plan)
+  int32_t split_len_s;
   int32_t nsus;       // suspects of the second pass (set after the learned decision)
   int32_t nct2;       // suspect tiles ceil(nsus / 8) * nblk
   int32_t k;          // candidates of this step's learned pass
@@ -279,10 +281,10 @@ enum Kind : int {
   kKColC,       // k_cand_k columns: ceil(m / 64)
   kKLsel,       // k_lselect: 1
   kKWit,        // k_pair_wit: m
-  kKPairE,      // k_pair_ext: nct3 * 2 * nsplit_c * q_rows (after the learned decision)
+  kKPairE,      // k_pair_ext: nct3 * 2 * nsplit * q_rows (after the learned decision)
   kKBoundE,     // k_ext_bound: ceil(nsus / 4) when nct3 > 0
   kKCompE,      // k_ext_compact: 1 when nct3 > 0
-  kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_c * q_rows (after the learned decision)
+  kKPairS,      // k_pair_susp: nct2 * 2 * nsplit_s * q_rows (after the learned decision)
   kKCombS,      // k_combine_susp: ceil(nct2 / 4)
   kKRowkS,      // k_susp_rowk: ceil(nsus / 4)
   kKLsel2,      // k_lselect2: 1 when nsus > 0
@@ -373,12 +375,11 @@ __host__ __device__ inline JobStep job_step_base(int32_t d, int32_t t, int32_t K
   return s;
 }
 
-// Split of one FP32-path job given the batch's number of (tile, direction) items.
-__host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t items_total,
-                                          int32_t num_cu, Tune tu) {
-  s.q_all = valid_waves(tu.w_all) ? 4 / tu.w_all : 1;
-  s.q_rows = valid_waves(tu.w_rows) ? 4 / tu.w_rows : 1;
-  if (s.m < 2 || s.fp64) return;
+// Sample split of a pair pass with `items_total` (tile, direction) items over
+// the batch: enough splits for about target_per_cu items per CU, each at
+// least min_iters 64-sample blocks long.
+__host__ __device__ inline void split_for(int64_t items_total, int32_t n_pad, int32_t num_cu,
+                                          Tune tu, int32_t& nsplit, int32_t& split_len) {
   const int64_t iters = n_pad / kSampleQuantum;
   const int64_t target = (int64_t)num_cu * tu.target_per_cu;
   int64_t ns = items_total > 0 ? (target + items_total - 1) / items_total : 1;
@@ -386,8 +387,17 @@ __host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t ite
   if (ns > cap) ns = cap;
   if (ns < 1) ns = 1;
   const int64_t per = (iters + ns - 1) / ns;
-  s.split_len = (int32_t)(per * kSampleQuantum);
-  s.nsplit = (int32_t)((iters + per - 1) / per);
+  split_len = (int32_t)(per * kSampleQuantum);
+  nsplit = (int32_t)((iters + per - 1) / per);
+}
+
+// Split of one FP32-path job given the batch's number of (tile, direction) items.
+__host__ __device__ inline void job_split(JobStep& s, int32_t n_pad, int64_t items_total,
+                                          int32_t num_cu, Tune tu) {
+  s.q_all = valid_waves(tu.w_all) ? 4 / tu.w_all : 1;
+  s.q_rows = valid_waves(tu.w_rows) ? 4 / tu.w_rows : 1;
+  if (s.m < 2 || s.fp64) return;
+  split_for(items_total, n_pad, num_cu, tu, s.nsplit, s.split_len);
 }
 
 // Extension columns of a learned step: the next ne_max ranks after the K
@@ -406,16 +416,35 @@ __host__ __device__ inline int32_t suspect_cap(int32_t m, int32_t K, int32_t cap
   return c > 0 ? c / 8 * 8 : 0;
 }
 
-// Split of the learned form's pair kernels (candidate, extension and suspect
-// rows): the full step's own split (job_split first).  Every pair then sums
-// its samples over the same ranges in the same order as the full step, so a
-// learned pass measures a pair bit for bit as the full step does and the
-// exact mode makes the plain search's decisions even where measures differ
-// only by rounding.
-__host__ __device__ inline void job_split_cand(JobStep& s) {
+// Split of the candidate-row pass (job_split first): its own, from the
+// batch's candidate items, so that a pass of a few rows still fills the
+// device.  Its measures then differ from the full step's by FP32 rounding,
+// and the exact mode's decisions rest on the FP64 resolution of every step
+// whose best measures lie within that rounding (tie_limit).  Without that
+// resolution (`own` false) the pass takes the full step's split, so that it
+// measures every pair bit for bit as the full step does.  The extension
+// pass always takes the full step's split.
+__host__ __device__ inline void job_split_cand(JobStep& s, int32_t n_pad, int64_t items_c,
+                                               int32_t num_cu, Tune tu, bool own) {
   if (!s.learned) return;
-  s.nsplit_c = s.nsplit;
-  s.split_len_c = s.split_len;
+  if (own) {
+    split_for(items_c, n_pad, num_cu, tu, s.nsplit_c, s.split_len_c);
+  } else {
+    s.nsplit_c = s.nsplit;
+    s.split_len_c = s.split_len;
+  }
+}
+
+// Split of the suspect-row pass, set with the suspect plan (the same rule
+// on the batch's suspect items).
+__host__ __device__ inline void job_split_susp(JobStep& s, int32_t n_pad, int64_t items_s,
+                                               int32_t num_cu, Tune tu, bool own) {
+  if (own) {
+    split_for(items_s, n_pad, num_cu, tu, s.nsplit_s, s.split_len_s);
+  } else {
+    s.nsplit_s = s.nsplit;
+    s.split_len_s = s.split_len;
+  }
 }
 
 __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
@@ -437,10 +466,10 @@ __host__ __device__ inline int32_t kind_count(const JobStep& s, int kind) {
     case kKColC: return s.learned ? cdiv(s.m, 64) : 0;
     case kKLsel: return s.learned ? 1 : 0;
     case kKWit: return s.learned ? s.m : 0;
-    case kKPairE: return s.nct3 * 2 * s.nsplit_c * s.q_rows;
+    case kKPairE: return s.nct3 * 2 * s.nsplit * s.q_rows;
     case kKBoundE: return s.nct3 > 0 ? cdiv(s.nsus, 4) : 0;
     case kKCompE: return s.nct3 > 0 ? 1 : 0;
-    case kKPairS: return s.nct2 * 2 * s.nsplit_c * s.q_rows;
+    case kKPairS: return s.nct2 * 2 * s.nsplit_s * s.q_rows;
     case kKCombS: return cdiv(s.nct2, 4);
     case kKRowkS: return cdiv(s.nsus, 4);
     case kKLsel2: return s.nsus > 0 ? 1 : 0;
@@ -519,6 +548,7 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
 // The second (suspect) pass: its schedule, its pair kernel (a bounded grid that
 // walks the items), and combine / row k / exact decision (grid-stride).
 hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, int stage,
+                                int num_cu, Tune tu,
                                 hipStream_t st);
 hipError_t launch_pair_ext(const JobDev* jobs, int njobs, SchedDev sc, int grid, int waves,
                            hipStream_t st);

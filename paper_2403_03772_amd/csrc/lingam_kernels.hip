@@ -81,18 +81,23 @@ __device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, i
                                    int32_t* __restrict__ pre) {
   const int lane = threadIdx.x & 63;
   JobStep s{};
-  long long mine = 0;
+  long long mine = 0, mine_c = 0;
   if (lane < njobs) {
     const JobDev& J = jobs[lane];
     s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
     if (s.m >= 2 && !s.fp64) mine = 2LL * s.ntiles;
+    if (s.learned) mine_c = 2LL * s.nct;
   }
-  long long items = mine;
+  long long items = mine, items_c = mine_c;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) items += __shfl_xor(items, off);
+  for (int off = 32; off >= 1; off >>= 1) {
+    items += __shfl_xor(items, off);
+    items_c += __shfl_xor(items_c, off);
+  }
   if (lane < njobs) {
-    job_split(s, jobs[lane].n_pad, items, num_cu, tu);
-    job_split_cand(s);
+    const JobDev& J = jobs[lane];
+    job_split(s, J.n_pad, items, num_cu, tu);
+    job_split_cand(s, J.n_pad, items_c, num_cu, tu, J.tie_on != 0);
     js[lane] = s;
   }
   for (int kind = 0; kind < kNumKinds; ++kind) {
@@ -113,23 +118,27 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
     if (threadIdx.x < 64) step_schedule_wave(jobs, njobs, t, num_cu, tu, js, pre);
     return;
   }
-  __shared__ long long items;
+  __shared__ long long items, items_c;
   const int tid = threadIdx.x;
-  if (tid == 0) items = 0;
+  if (tid == 0) items = items_c = 0;
   __syncthreads();
-  long long mine = 0;
+  long long mine = 0, mine_c = 0;
   for (int j = tid; j < njobs; j += 1024) {
     const JobDev& J = jobs[j];
     const JobStep s = job_step_base(J.d, t, J.prop ? J.K : 0, J.min_m, J.record != nullptr);
     js[j] = s;
     if (s.m >= 2 && !s.fp64) mine += 2LL * s.ntiles;
+    if (s.learned) mine_c += 2LL * s.nct;
   }
   if (mine) atomicAdd(reinterpret_cast<unsigned long long*>(&items), (unsigned long long)mine);
+  if (mine_c)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&items_c), (unsigned long long)mine_c);
   __syncthreads();
   for (int j = tid; j < njobs; j += 1024) {
     JobStep s = js[j];
-    job_split(s, jobs[j].n_pad, items, num_cu, tu);
-    job_split_cand(s);
+    const JobDev& J = jobs[j];
+    job_split(s, J.n_pad, items, num_cu, tu);
+    job_split_cand(s, J.n_pad, items_c, num_cu, tu, J.tie_on != 0);
     js[j] = s;
   }
   __syncthreads();
@@ -1081,9 +1090,12 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
       JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
       if (!s.learned) continue;
       job_split(s, (int32_t)L.n_pad, 2LL * s.ntiles, num_cu, worst);
-      job_split_cand(s);
-      const size_t need = (size_t)s.nct * (size_t)s.nsplit_c * 256;
-      if (need > pc) pc = need;
+      // either split policy (own split, or the full step's)
+      for (const bool own : {true, false}) {
+        job_split_cand(s, (int32_t)L.n_pad, 2LL * s.nct, num_cu, worst, own);
+        const size_t need = (size_t)s.nct * (size_t)s.nsplit_c * 256;
+        if (need > pc) pc = need;
+      }
     }
     L.partc_elems = pc;
     L.partc = take(sizeof(double) * (pc ? pc : 1));
@@ -1101,9 +1113,13 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
       JobStep s = job_step_base((int32_t)d, (int32_t)t, K, 0, false);
       if (!s.learned) continue;
       job_split(s, (int32_t)L.n_pad, 2LL * s.ntiles, num_cu, worst);
-      job_split_cand(s);
       const int32_t cs = suspect_cap(s.m, s.k, L.cap_s);
-      const size_t need = (size_t)cdiv(cs, kTileVars) * s.nblk * (size_t)s.nsplit_c * 256;
+      const size_t tiles = (size_t)cdiv(cs, kTileVars) * s.nblk;
+      // the full step's split (extension columns; suspect rows without the
+      // FP64 tie resolution), and the suspect pass's own: with T tiles it
+      // takes at most ceil(target / 2T) splits, so T * splits <= T + target / 2
+      const size_t own = tiles + (size_t)num_cu * worst.target_per_cu / 2 + 1;
+      const size_t need = (tiles * (size_t)s.nsplit > own ? tiles * (size_t)s.nsplit : own) * 256;
       if (need > ps) ps = need;
     }
     L.parts_elems = ps;

@@ -1038,11 +1038,13 @@ __global__ __launch_bounds__(256) void k_lselect(const JobDev* __restrict__ jobs
 // jobs without a listing) and the prefix sums of its kinds.  Stage 0 plans
 // the extension columns (kinds kKPairE .. kKCompE) for the suspects k_lselect
 // listed; stage 1 the suspects' full rows (kKPairS .. kKLsel2) for those
-// the extension left (or all listed, without extension columns).
+// the extension left (or all listed, without extension columns), with the
+// suspect pass's sample split from the batch's suspect items.
 __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict__ jobs,
                                                         int njobs, JobStep* __restrict__ js,
-                                                        int32_t* __restrict__ pre, int stage) {
-  auto plan = [&](int j) {
+                                                        int32_t* __restrict__ pre, int stage,
+                                                        int num_cu, Tune tu) {
+  auto plan = [&](int j) -> long long {
     JobStep s = js[j];
     s.nsus = s.learned ? jobs[j].ctrl->nsus : 0;
     if (stage == 0) {
@@ -1052,35 +1054,52 @@ __global__ __launch_bounds__(1024) void k_susp_schedule(const JobDev* __restrict
       s.nct2 = cdiv(s.nsus, kTileVars) * s.nblk;
     }
     js[j] = s;
-    return s;
+    return stage == 1 ? 2LL * s.nct2 : 0;
+  };
+  auto split = [&](int j, long long items_s) {
+    if (stage != 1) return;
+    JobStep s = js[j];
+    job_split_susp(s, jobs[j].n_pad, items_s, num_cu, tu, jobs[j].tie_on != 0);
+    js[j] = s;
   };
   const int k0 = stage == 0 ? kKPairE : kKPairS, k1 = stage == 0 ? kKCompE : kKLsel2;
+  const int tid = threadIdx.x, lane = tid & 63;
   if (njobs <= 64) {  // one wave, no barriers
-    if (threadIdx.x >= 64) return;
-    const int lane = threadIdx.x;
-    JobStep s{};
-    if (lane < njobs) s = plan(lane);
-    for (int kind = k0; kind <= k1; ++kind) {
-      const int32_t c = lane < njobs ? kind_count(s, kind) : 0;
+    if (tid >= 64) return;
+    long long items = lane < njobs ? plan(lane) : 0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) items += __shfl_xor(items, off);
+    if (lane < njobs) split(lane, items);
+  } else {
+    __shared__ long long items;
+    if (tid == 0) items = 0;
+    __syncthreads();
+    long long mine = 0;
+    for (int j = tid; j < njobs; j += 1024) mine += plan(j);
+    if (mine) atomicAdd(reinterpret_cast<unsigned long long*>(&items), (unsigned long long)mine);
+    __syncthreads();
+    for (int j = tid; j < njobs; j += 1024) split(j, items);
+    __syncthreads();
+  }
+  // prefix sums of the kinds: one wave per kind, 64 jobs at a time
+  const int nwaves = njobs <= 64 ? 1 : 16;
+  for (int kind = k0 + (tid >> 6); kind <= k1; kind += nwaves) {
+    int32_t* out = pre + (int64_t)kind * (njobs + 1);
+    int32_t run = 0;
+    for (int j0 = 0; j0 < njobs; j0 += 64) {
+      const int j = j0 + lane;
+      const int32_t c = j < njobs ? kind_count(js[j], kind) : 0;
       int32_t incl = c;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const int32_t o = __shfl_up(incl, off);
         if (lane >= off) incl += o;
       }
-      int32_t* out = pre + (int64_t)kind * (njobs + 1);
-      if (lane < njobs) out[lane] = incl - c;
-      if (lane == 63) out[njobs] = incl;
+      if (j < njobs) out[j] = run + incl - c;
+      run += __shfl(incl, 63);
     }
-    return;
+    if (lane == 0) out[njobs] = run;
   }
-  __shared__ int32_t sh[1024];
-  for (int j = threadIdx.x; j < njobs; j += 1024) plan(j);
-  __syncthreads();
-  for (int kind = k0; kind <= k1; ++kind)
-    block_scan(
-        njobs, [&](int j) { return kind_count(js[j], kind); },
-        pre + (int64_t)kind * (njobs + 1), sh);
 }
 
 // The bounded-grid pair kernels (suspect and extension rows) walk their items
@@ -1123,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_ext_bound(const JobDev* __restrict__ jo
 #pragma unroll
     for (int q = 0; q < kWit; ++q) wl[q] = J.wit[(int64_t)l * kWit + q];
     const double s1_bias =
-        (double)S.nsplit_c * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+        (double)S.nsplit * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
     const double inv_n = 1.0 / (double)J.n;
     const double lim = 1.0 - kCollinear;
     double acc = 0.0;
@@ -1138,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_ext_bound(const JobDev* __restrict__ jo
       const int wave = ((ci % kTileVars) / kWaveVars) * 2 + (e % kTileVars) / kWaveVars;
       const int q = (ci % kWaveVars) * 4 + (e % kWaveVars);
       double sm[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int sp = 0; sp < S.nsplit_c; ++sp) {
+      for (int sp = 0; sp < S.nsplit; ++sp) {
         const double* src = J.parts + (((int64_t)sp * S.nct3 + tile) * 4 + wave) * 64 + q * 4;
 #pragma unroll
         for (int c = 0; c < 4; ++c) sm[c] += src[c];
@@ -1255,13 +1274,13 @@ __global__ __launch_bounds__(256) void k_combine_susp(const JobDev* __restrict__
       return;
     }
     double sm[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int sp = 0; sp < S.nsplit_c; ++sp) {
+    for (int sp = 0; sp < S.nsplit_s; ++sp) {
       const double* src = J.parts + (((int64_t)sp * S.nct2 + tile) * 4 + wave) * 64 + q * 4;
 #pragma unroll
       for (int c = 0; c < 4; ++c) sm[c] += src[c];
     }
     const double s1_bias =
-        (double)S.nsplit_c * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
+        (double)S.nsplit_s * 64.0 * (double)kS1Start + 0.5 * (double)J.n_pad;
     const double inv_n = 1.0 / (double)J.n;
     const int si = J.act[pi], sj = J.act[pj];
     double r = J.rho[(int64_t)si * J.d + sj];
@@ -1689,9 +1708,9 @@ hipError_t launch_learned_back(const JobDev* jobs, int njobs, int t, SchedDev sc
 }
 
 hipError_t launch_susp_schedule(const JobDev* jobs, int njobs, SchedDev sc, int stage,
-                                hipStream_t st) {
+                                int num_cu, Tune tu, hipStream_t st) {
   hipLaunchKernelGGL(k_susp_schedule, dim3(1), dim3(1024), 0, st, jobs, njobs, sc.js, sc.pre,
-                     stage);
+                     stage, num_cu, tu);
   return hipGetLastError();
 }
 
