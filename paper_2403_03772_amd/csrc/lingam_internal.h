@@ -112,10 +112,11 @@ struct Ctrl {
   int32_t tie_audit;       // 1: the deferred decision is an audit step's full step
   int32_t n_ties;          // steps decided by the FP64 tie resolution
   int32_t n_tie_rows;      // ... rows they measured in FP64
-  int32_t tie_done;        // pairs of the FP64 decision finished
+  int32_t tie_done;        // rows of the FP64 decision finished
   int32_t n_tie_overflow;  // steps with more than kMaxTie near-tied positions (the
                            // FP32 measures decided them)
-  int32_t pad[37];
+  int32_t tie_row_done[kMaxTie];  // pairs of each row of the FP64 decision finished
+  int32_t pad[21];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is 256 bytes");
 
@@ -155,7 +156,7 @@ struct Layout {
   size_t kc2;      // double [cap_s] exact k of every suspect
   // FP64 tie resolution (every job)
   size_t tie;      // int32  [kMaxTie] near-tied positions of the current step
-  size_t tie_r;    // double [kMaxTie * d] their FP64 measure rows
+  size_t tie_r;    // double [kMaxTie * d] their FP64 measure rows, then their k [kMaxTie]
   size_t total;
   size_t part_elems;
   size_t partc_elems;

@@ -581,6 +581,7 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
       J.ctrl->ntie = ntie;
       J.ctrl->tie_t = t;
       J.ctrl->tie_done = 0;
+      for (int r = 0; r < kMaxTie; ++r) J.ctrl->tie_row_done[r] = 0;
       J.ctrl->tie_audit = audit ? 1 : 0;
     } else {
       const int slot = act[pos];
@@ -605,31 +606,33 @@ __global__ __launch_bounds__(1024) void k_select(const JobDev* __restrict__ jobs
 // tie still spreads over the whole device.  Every workgroup rebuilds the list
 // boundaries from the jobs' control blocks (256 jobs at a time); those fields
 // are written by the selection before this launch and only read here.  Each
-// job counts its finished pairs (ctrl->tie_done); the wave that finishes the
-// last one sums k of every listed row in FP64 (columns in a fixed order),
-// takes the largest -k with ties to the smaller original id and commits it
-// as the full selection commits.
-__device__ void tie_commit(const JobDev& J, int m, int nt, int t, int lane) {
+// listed row counts its finished pairs (ctrl->tie_row_done); the wave that
+// finishes a row's last pair sums that row's k in FP64 (columns in a fixed
+// order) into the slot after the rows, and the wave that finishes the job's
+// last row (ctrl->tie_done) takes the largest -k with ties to the smaller
+// original id and commits it as the full selection commits.
+__device__ void tie_row_k(const JobDev& J, int m, int r, int lane) {
+  const double* row = J.tie_r + (int64_t)r * J.d;
+  double k = 0.0;
+  for (int q = lane; q < m; q += 64) {
+    const double x = row[q];
+    const double ng = x < 0.0 ? x : 0.0;
+    k += ng * ng;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
+  if (lane == 0) J.tie_r[(int64_t)kMaxTie * J.d + r] = k;
+}
+
+__device__ void tie_commit(const JobDev& J, int m, int nt, int t) {
   Ctrl* C = J.ctrl;
   int32_t* act = J.act;
-  double best_k = 0.0;
-  int bi = -1;
-  for (int r = 0; r < nt; ++r) {
-    const double* row = J.tie_r + (int64_t)r * J.d;
-    double k = 0.0;
-    for (int q = lane; q < m; q += 64) {
-      const double x = row[q];
-      const double ng = x < 0.0 ? x : 0.0;
-      k += ng * ng;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off);
-    if (bi < 0 || k < best_k || (k == best_k && act[J.tie[r]] < act[J.tie[bi]])) {
-      best_k = k;
-      bi = r;
-    }
+  const double* sk = J.tie_r + (int64_t)kMaxTie * J.d;
+  int bi = 0;
+  for (int r = 1; r < nt; ++r) {
+    const double a = sk[r], b = sk[bi];
+    if (a < b || (a == b && act[J.tie[r]] < act[J.tie[bi]])) bi = r;
   }
-  if (lane != 0) return;
   const int pos = J.tie[bi], slot = act[pos];
   if (C->tie_audit && slot == C->learned_slot) C->n_audit_agree += 1;
   J.order[t] = slot;
@@ -674,6 +677,7 @@ __global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, in
         else lo = mid + 1;
       }
       const JobDev& J = jobs[j0 + lo];
+      Ctrl* C = J.ctrl;
       const int m = js[j0 + lo].m;
       const int64_t q = loc - (lo ? spre[lo - 1] : 0);
       const int r = (int)(q / m), pj = (int)(q - (int64_t)r * m);
@@ -683,11 +687,18 @@ __global__ __launch_bounds__(256) void k_tie(const JobDev* __restrict__ jobs, in
       if (lane == 0) *out = Rv;
       __threadfence();
       int done = 0;
-      if (lane == 0) done = atomicAdd(&J.ctrl->tie_done, 1) + 1;
+      if (lane == 0) done = atomicAdd(&C->tie_row_done[r], 1) + 1;
       done = __shfl(done, 0);
-      if ((int64_t)done == spre[lo] - (lo ? spre[lo - 1] : 0)) {
+      if (done != m) continue;  // wave-uniform
+      __threadfence();
+      tie_row_k(J, m, r, lane);  // the row's last pair: its k
+      __threadfence();
+      int rows = 0;
+      if (lane == 0) rows = atomicAdd(&C->tie_done, 1) + 1;
+      rows = __shfl(rows, 0);
+      if (rows == C->ntie && lane == 0) {  // the job's last row: the decision
         __threadfence();
-        tie_commit(J, m, J.ctrl->ntie, t, lane);
+        tie_commit(J, m, rows, t);
       }
     }
     base += total;
@@ -1078,7 +1089,7 @@ Layout make_layout(int64_t n, int64_t d, int num_cu, int K) {
   L.mvec = take(sizeof(double) * (size_t)d);
   L.mom = take(sizeof(double) * 8 * (size_t)d);
   L.tie = take(sizeof(int32_t) * kMaxTie);
-  L.tie_r = take(sizeof(double) * kMaxTie * (size_t)d);
+  L.tie_r = take(sizeof(double) * kMaxTie * ((size_t)d + 1));
   L.K = K;
   if (K > 0) {
     L.feat = take(sizeof(float) * kFeat * (size_t)d);

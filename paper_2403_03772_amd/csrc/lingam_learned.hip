@@ -940,6 +940,7 @@ __device__ inline void commit_or_defer(const JobDev& J, int t, int m, const Best
     J.ctrl->ntie = ntie;
     J.ctrl->tie_t = t;
     J.ctrl->tie_done = 0;
+    for (int r = 0; r < kMaxTie; ++r) J.ctrl->tie_row_done[r] = 0;
     J.ctrl->tie_audit = 0;
     J.ctrl->full = 0;
     if (J.gaps) J.gaps[t] = best.v - best.v2;
