@@ -8,10 +8,13 @@
 * the 16 features recorded during a plain search vs the oracle's features of
   the residuals along the same order;
 * orderings: the exact mode (margin = +inf) and all-audit runs give the plain
-  order; the pure learned order (margin = -inf) equals the oracle's learned
-  order up to the first near-tie;
+  order, with the FP64 resolution of near-ties and with FP32 tie decisions;
+  the pure learned order (margin = -inf) equals the oracle's learned order
+  up to the first near-tie;
 * training on recorded plain orderings lowers the loss.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -209,6 +212,29 @@ def test_exact_mode_and_audits_give_plain_order(lib):
             mv = plain["measures"].cpu().numpy()[t]
             a, b = mv[po[t]], mv[lo[t]]
             assert abs(a - b) <= 2e-4 * max(abs(a), 1e-3 * np.nanmax(np.abs(mv))), (t, a, b)
+
+
+@pytest.mark.parametrize("fp32_ties", [False, True])
+def test_exact_form_equals_plain_with_either_tie_rule(lib, fp32_ties):
+    """The exact learned form returns the plain order under both tie rules:
+    with the FP64 resolution of near-ties (its row passes then take their own
+    sample splits, and near-ties are decided from the FP64 residuals in both
+    forms) and with FP32 decisions (the row passes then take the full step's
+    split, so every row they measure equals the full step's bit for bit).
+    Shipped network, d = 600, n = 6000, two seeds."""
+    from paper_2403_03772_amd import train_proposer as TP
+    if not os.path.exists(TP.WEIGHTS):
+        pytest.skip("no trained network shipped")
+    P = TP.default_proposer()
+    for seed in (5, 6):
+        s = _sem(600, 6000, seed)
+        X = _t(s.X)
+        plain = lib.causal_order(X, fp32_ties=fp32_ties).cpu().numpy()
+        out = lib.causal_order(X, learned=lib.Learned(P, topk=64), fp32_ties=fp32_ties)
+        st = out["learned_stats"]
+        print(f"seed {seed} fp32_ties={fp32_ties}: {st}", flush=True)
+        assert st.learned_steps > 0 and st.fallbacks == 0
+        assert np.array_equal(out["order"].cpu().numpy(), plain), seed
 
 
 def _oracle_step(X32, prefix, prop, K):
