@@ -354,9 +354,15 @@ def _concat(sets):
 
 
 def _save_state(path: str, prop, state: dict) -> None:
+    """Write the resumable state of a streamed run to ``path`` (as named: the
+    file handle keeps numpy from appending a suffix), replacing it whole."""
     scal = {k: v for k, v in state.items() if k not in ("m1", "m2")}
-    np.savez(path, proposer=np.asarray(prop, np.float32), m1=np.asarray(state["m1"], np.float32),
-             m2=np.asarray(state["m2"], np.float32), state=np.array(json.dumps(scal)))
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, proposer=np.asarray(prop, np.float32),
+                 m1=np.asarray(state["m1"], np.float32), m2=np.asarray(state["m2"], np.float32),
+                 state=np.array(json.dumps(scal)))
+    os.replace(tmp, path)
 
 
 def _load_state(path: str):

@@ -46,8 +46,9 @@ def test_state_survives_a_restart(tmp_path):
              "m2": rng.random(L.N_PARAMS).astype(np.float32),
              "step": 123, "next_sem": 4672, "loss": [3.4, 3.3], "seed": 0,
              "seconds": 880.5, "init_meta": {"sems": 1000}}
-    path = str(tmp_path / "state.npz")
+    path = str(tmp_path / "state.bin")  # any name: no suffix is added
     tp._save_state(path, prop, state)
+    assert (tmp_path / "state.bin").exists() and not (tmp_path / "state.bin.npz").exists()
     p2, s2 = tp._load_state(path)
     assert np.array_equal(p2, prop)
     assert np.array_equal(s2["m1"], state["m1"]) and np.array_equal(s2["m2"], state["m2"])
