@@ -412,6 +412,14 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   }
   const int wi = wave >> 1, wj = wave & 1;
   if (!kCand && bi == bj && wi > wj) return;  // mirror image of quadrant (wj, wi)
+  // A quadrant on the diagonal has the same variables on both sides, so its
+  // direction-0 walk (a, c) with a != c already holds both residual
+  // directions of each of its 6 pairs (a > c: the larger position regressed
+  // on the smaller, which is direction 1 of pair (c, a)); its direction-1
+  // item has nothing left to do.  Same rows, coefficients and samples per
+  // lane as that item would use, so the sums are the same bits.
+  const bool diagq = !kCand && bi == bj && wi == wj;
+  if (diagq && dir == 1) return;
   // i side: positions bi * 8 + .. (all pairs) or list entries (candidate /
   // suspect rows; list padding holds position m)
   const int i0 = bi * kTileVars + wi * kWaveVars, pj0 = bj * kTileVars + wj * kWaveVars;
@@ -435,7 +443,7 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   {
     const int q = lane & 15, a = q >> 2, c = q & 3;
     const int pi = ipos(dir == 0 ? a : c), pj = jpos(dir == 0 ? c : a);
-    const bool valid = kCand ? (pi < m && pj < m && pi != pj) : (pi < m && pj < m && pi < pj);
+    const bool valid = pi < m && pj < m && pi != pj;
     if (valid) {
       double r = J.rho[(int64_t)act[pi] * ldr + act[pj]];
       const double lim = 1.0 - kCollinear;
@@ -552,11 +560,14 @@ __device__ __forceinline__ void pair_item(const JobDev& J, const JobStep& S, int
   }
   v0 += __shfl_xor(v0, 32);
   if (lane < 32) {
-    // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order
+    // sum L = (a * 4 + c) * 2 + which, (a, c) in this direction's walk order;
+    // on a diagonal quadrant the walk's lower half is direction 1
     const int a = lane >> 3, c = (lane >> 1) & 3, which = lane & 1;
-    const int q = dir == 0 ? a * 4 + c : c * 4 + a;  // pair index (i-major) of the tile
+    const bool flip = dir == 1 || (diagq && a > c);
+    const int q = flip ? c * 4 + a : a * 4 + c;  // pair index (i-major) of the tile
     double* part = kMode == kModeAll ? J.part : (kMode == kModeCand ? J.partc : J.parts);
-    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + dir * 2 + which] = v0;
+    part[(((int64_t)split * ntiles + tile) * 4 + wave) * 64 + q * 4 + (flip ? 2 : 0) + which] =
+        v0;
   }
 }
 
