@@ -48,6 +48,33 @@ def test_batch_equals_single_jobs(lib):
             assert np.all(np.abs(mb[fin] - ms[fin]) <= 1e-9 * np.maximum(np.abs(ms[fin]), 1e-9))
 
 
+def test_batch_near_ties_equal_single_jobs(lib):
+    """Jobs that defer near-ties to FP64 at the same steps share one list of
+    FP64 pairs in k_tie: three copies each of two independent-source data
+    sets (every k at the noise level, many near-ties; d = 100 and 90) and one
+    job of another size, batched, give each job its single-job order, and the
+    single runs resolve ties in FP64 at the same steps."""
+    import torch
+    a = synth.er_sem(100, 2000, indeg=0.0, noise_family=("uniform", "laplace", "exp"),
+                     seed=501).X
+    b = synth.er_sem(90, 1500, indeg=0.0, noise_family=("uniform", "laplace", "exp"),
+                     seed=502).X
+    c = synth.er_sem(140, 2500, indeg=2.0, noise_family=("uniform", "laplace", "exp"),
+                     seed=503).X
+    Xs = [a, b, a, c, b, a, b]
+    print("case batch of near-tie jobs", flush=True)
+    out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], profile=True)
+    assert int(out["status"].abs().sum()) == 0
+    ties = 0
+    for k, X in enumerate(Xs):
+        single = lib.causal_order(_t(X), profile=True)
+        ties += single["profile"].tie_steps
+        assert np.array_equal(out["orders"][k].cpu().numpy(),
+                              single["order"].cpu().numpy()), k
+    print(f"batch tie steps {out['profile'].tie_steps}, single runs {ties}", flush=True)
+    assert ties > 0 and out["profile"].tie_steps == ties
+
+
 def test_batch_jobs_match_oracle(lib):
     Xs = _uneven_jobs(seed=1, count=4)
     out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], with_measures=True)
