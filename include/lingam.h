@@ -34,8 +34,13 @@
  * and so do its pair measures against its eight most correlated non-candidate
  * variables ("witnesses": sum of min(0, R(l, w))^2), each column counted
  * once; the "suspects" are the variables whose bound does not exceed the best
- * candidate's k.  (a) No suspect: the best candidate is the plain search's
- * choice (certified).  (b) At most min(max_suspects, m/2 - topk) suspects:
+ * candidate's k (with the FP64 resolution of near-ties, the default: its
+ * near-tie limit k (1 + 4e-3) + 1e-12, and a near-tie among the measured rows
+ * is decided in FP64 as the full step decides it; the row passes then choose
+ * their own sample splits, while with LINGAM_FLAG_FP32_TIES they take the
+ * full step's, so that every row they measure equals the full step's bit for
+ * bit).  (a) No suspect: the best candidate is the plain search's choice
+ * (certified).  (b) At most min(max_suspects, m/2 - topk) suspects:
  * the second pass first measures them against the `extension` variables
  * ranked right after the candidates (columns not yet counted), which raises
  * their bounds; the rows of those still at or below the best candidate's k
@@ -43,8 +48,9 @@
  * is the plain choice.  (c) More: the best candidate is taken when
  * its score leads every non-candidate's by at least `margin`.  Otherwise, and
  * at every audit step (t % audit_every == 0, a check of the margin rule), the
- * full step of the exact search decides.  With margin = +inf the order is the plain order.  This proposal layer is not part of the paper's method; it
- * is an addition on top of the exact search it accelerates.
+ * full step of the exact search decides.  With margin = +inf the order is
+ * the plain order.  This proposal layer is not part of the paper's method;
+ * it is an addition on top of the exact search it accelerates.
  */
 #ifndef LINGAM_MI355X_H
 #define LINGAM_MI355X_H
