@@ -75,6 +75,25 @@ def test_batch_near_ties_equal_single_jobs(lib):
     assert ties > 0 and out["profile"].tie_steps == ties
 
 
+def test_many_jobs_equal_single_jobs(lib):
+    """More than 64 jobs (the schedule kernels then scan the jobs one wave
+    per kind, 64 at a time, instead of in one wave): 80 small uneven jobs,
+    each with its single-job order."""
+    rng = np.random.default_rng(77)
+    Xs = []
+    for k in range(80):
+        d = int(rng.integers(2, 90))
+        n = int(rng.integers(100, 700))
+        Xs.append(synth.er_sem(d, n, indeg=2.0, noise_family=("uniform", "laplace", "exp"),
+                               seed=2000 + k).X)
+    print("case 80 jobs", flush=True)
+    out = lib.batch_causal_order([{"X": _t(X)} for X in Xs])
+    assert int(out["status"].abs().sum()) == 0
+    for k, X in enumerate(Xs):
+        single = lib.causal_order(_t(X)).cpu().numpy()
+        assert np.array_equal(out["orders"][k].cpu().numpy(), single), k
+
+
 def test_batch_jobs_match_oracle(lib):
     Xs = _uneven_jobs(seed=1, count=4)
     out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], with_measures=True)

@@ -291,6 +291,30 @@ def test_batch_learned_equals_single(lib):
         assert np.array_equal(out["orders"][k].cpu().numpy(), single), k
 
 
+def test_many_job_learned_batch_equals_single(lib):
+    """More than 64 jobs in the exact learned form (the suspect schedule then
+    scans the jobs one wave per kind): 70 jobs with d in [130, 200], every
+    one with its single-job order, which is the plain order."""
+    from paper_2403_03772_amd import train_proposer as TP
+    if not os.path.exists(TP.WEIGHTS):
+        pytest.skip("no trained network shipped")
+    P = TP.default_proposer()
+    cfg = lib.Learned(P, topk=64)
+    rng = np.random.default_rng(71)
+    Xs = [_sem(int(rng.integers(130, 201)), int(rng.integers(800, 1500)), 3000 + k).X
+          for k in range(70)]
+    print("case 70 learned jobs", flush=True)
+    out = lib.batch_causal_order([{"X": _t(X)} for X in Xs], learned=cfg)
+    assert int(out["status"].abs().sum()) == 0
+    st = out["learned_stats"]
+    assert st.learned_steps > 0 and st.fallbacks == 0
+    for k, X in enumerate(Xs):
+        single = lib.causal_order(_t(X), learned=cfg)["order"].cpu().numpy()
+        plain = lib.causal_order(_t(X)).cpu().numpy()
+        assert np.array_equal(out["orders"][k].cpu().numpy(), single), k
+        assert np.array_equal(single, plain), k
+
+
 def test_bad_proposer_and_lists_rejected(lib):
     import torch
     prop = _proposer(9)
