@@ -74,12 +74,14 @@ __device__ inline int32_t wave_excl_scan(int32_t v, int32_t& total) {
   return incl - v;
 }
 
-// Schedule of a batch of at most 64 jobs: one wave, lane j plans job j, no
-// barriers.  Same arithmetic as the block path below.
+// Schedule of a batch of at most 64 jobs: in every wave of the block lane j
+// plans job j (the same plan in each wave, so no barrier is needed), wave 0
+// stores the plans, and the waves share out the kinds' prefix sums.  Same
+// arithmetic as the block path below.
 __device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, int t,
                                    int num_cu, Tune tu, JobStep* __restrict__ js,
                                    int32_t* __restrict__ pre) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   JobStep s{};
   long long mine = 0, mine_c = 0;
   if (lane < njobs) {
@@ -98,9 +100,9 @@ __device__ void step_schedule_wave(const JobDev* __restrict__ jobs, int njobs, i
     const JobDev& J = jobs[lane];
     job_split(s, J.n_pad, items, num_cu, tu);
     job_split_cand(s, J.n_pad, items_c, num_cu, tu, J.tie_on != 0);
-    js[lane] = s;
+    if (wave == 0) js[lane] = s;
   }
-  for (int kind = 0; kind < kNumKinds; ++kind) {
+  for (int kind = wave; kind < kNumKinds; kind += nwaves) {
     const int32_t c = lane < njobs ? kind_count(s, kind) : 0;
     int32_t total;
     const int32_t ex = wave_excl_scan(c, total);
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(1024) void k_step_schedule(const JobDev* __restrict
                                                         JobStep* __restrict__ js,
                                                         int32_t* __restrict__ pre) {
   if (njobs <= 64) {  // uniform over the block
-    if (threadIdx.x < 64) step_schedule_wave(jobs, njobs, t, num_cu, tu, js, pre);
+    step_schedule_wave(jobs, njobs, t, num_cu, tu, js, pre);
     return;
   }
   __shared__ long long items, items_c;
