@@ -84,6 +84,34 @@ __device__ inline void dither_float(double c, float& lo, float& hi, int& n_hi) {
   n_hi = (int)rint(ldexp(c - (double)lo, 6 - ilogb(gap)));
 }
 
+// e^x in FP64 for x <= 0, the exponentials of the FP64 paths (their arguments
+// are -2|u| and -u^2/2).  Cody and Waite's reduction x = k ln2 + r, |r| <=
+// ln2 / 2, with ln2 split into a 32-bit head (so k * head is exact for |k| <
+// 2^21) and the rest; e^r from its Taylor series to degree 12 (the remainder
+// is below 2.5e-16 of e^r); 2^k applied exactly by ldexp, which takes results
+// below the normal range through the subnormals to 0.  No range checks: the
+// arguments are never positive, infinite or NaN.
+__host__ __device__ inline double exp_nonpos(double x) {
+  constexpr double kLn2Head = 0x1.62e42ffp-1;            // ln 2 to 32 bits
+  constexpr double kLn2Rest = -0x1.718432a1b0e26p-35;    // ln 2 - kLn2Head
+  const double k = rint(x * kLog2e);
+  const double r = fma(-k, kLn2Rest, fma(-k, kLn2Head, x));
+  double p = 1.0 / 479001600.0;  // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
 // FP64 log cosh and Gaussian-weighted term (marginals and the FP64 pair path).
 __device__ inline double logcosh64(double u) {
   const double a = fabs(u);
@@ -114,10 +142,10 @@ __device__ inline double pair_measure64(const JobDev& J, int pi, int pj, int lan
     const double au = fabs(u), aw = fabs(w);
     a1 += au;
     b1 += aw;
-    pa *= 1.0 + exp(-2.0 * au);
-    pb *= 1.0 + exp(-2.0 * aw);
-    a2 += u * exp(-0.5 * u * u);
-    b2 += w * exp(-0.5 * w * w);
+    pa *= 1.0 + exp_nonpos(-2.0 * au);
+    pb *= 1.0 + exp_nonpos(-2.0 * aw);
+    a2 += u * exp_nonpos(-0.5 * u * u);
+    b2 += w * exp_nonpos(-0.5 * w * w);
     ++tot;
     if (++cnt == 512) {
       a1 += log(pa);
@@ -174,8 +202,8 @@ struct MomAcc {
   __device__ inline void add(double z) {
     const double a = fabs(z), z2 = z * z;
     abs_sum += a;
-    prod *= 1.0 + exp(-2.0 * a);
-    g += z * exp(-0.5 * z2);
+    prod *= 1.0 + exp_nonpos(-2.0 * a);
+    g += z * exp_nonpos(-0.5 * z2);
     z3 += z2 * z;
     z4 += z2 * z2;
     ++tot;
