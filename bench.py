@@ -15,13 +15,16 @@ the full-ordering time (ms_per_step), the roofline of the pair-moment kernel
 (timed with HIP events on the launch stream over the timed region; 12 flops
 per evaluation against the published FP32 vector peak, and the kernel's own
 issue model from live-measured instruction rates) and the FP64 oracle (table
-mode) timed on step 0 of the same workload on the host cores.
+mode) timed on steps 0-1 of the same workload on the host cores.
 
 Also reported (when the trained network is present): the learned-proposal
 form on the same input -- time per ordering, speed-up over the plain form,
 Kendall tau to the plain order, its decisions, and the same form with an
 untrained network (ablation) --, the learned form against the plain one at
-d = 4096, n = 16384 (learned_large), and a batched bootstrap workload.
+d = 4096, n = 16384 (learned_large), a batched bootstrap workload, the
+adjacency, VarLiNGAM and bootstrap-statistics records, and the cost of one
+phase boundary of a step (a graph-replayed launch against a grid-wide barrier
+in one persistent launch).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gene|large|batch]
                        [--no-cpu-baseline] [--no-batch] [--no-learned] [--no-large]
@@ -51,7 +54,7 @@ FLOPS_PER_EVAL = 12
 PEAK_FP32_TFLOPS = 157.3
 # Secondary figure, the issue model of the kernel's own instruction stream:
 # an evaluation issues 7 unpacked FP32 VALU instructions and 2 v_exp_f32 (the
-# log of a product is taken once per 16 samples), so it costs
+# log of a product is taken once per 32 samples), so it costs
 # 7 / R_fma + 2 / R_exp seconds per lane, with R_fma and R_exp the FP32 FMA
 # and v_exp_f32 lane-operation rates that the probe library measures live.
 VALU_PER_EVAL, TRANS_PER_EVAL = 7, 2
@@ -74,6 +77,30 @@ def issue_rates():
         return None
     return {"fma_lane_ops_per_s": out[0], "exp_lane_ops_per_s": out[1],
             "eval_mix_per_s": out[2]}
+
+
+def sync_probe(rounds: int = 2000):
+    """Cost of one phase boundary of the ordering step, measured by
+    liblingam_probe.so over the step kernels' grid (4 workgroups per CU): a
+    launch boundary in a replayed HIP graph, an eager launch boundary, and a
+    grid-wide barrier in one cooperative (persistent) launch."""
+    import ctypes
+
+    from paper_2403_03772_amd import build as b
+
+    if not os.path.exists(b.PROBE_LIB):
+        return None
+    lib = ctypes.CDLL(b.PROBE_LIB)
+    lib.lingam_probe_sync.argtypes = [ctypes.c_int, ctypes.c_void_p]
+    lib.lingam_probe_sync.restype = ctypes.c_int
+    out = (ctypes.c_double * 7)()
+    code = lib.lingam_probe_sync(rounds, out)
+    if code != 0:
+        return {"error": code}
+    return {"graph_launch_us": out[0], "eager_launch_us": out[1],
+            "grid_barrier_us": out[2], "grid_barrier_8_groups_us": out[3],
+            "grid_barrier_8_groups_1_per_cu_us": out[4], "workgroups": int(out[5]),
+            "barrier_waits_at_poll_limit": int(out[6]), "rounds": rounds}
 
 
 def pair_roofline(evals_per_s: float, rates) -> dict:
@@ -497,8 +524,9 @@ def main() -> int:
     ap.add_argument("--exact-only", action="store_true",
                     help="of the learned forms, run only the exact one (for its profile)")
     ap.add_argument("--no-aux", action="store_true",
-                    help="skip the adjacency, VarLiNGAM and bootstrap records (their "
-                         "orderings would mix into a profile of the plain one)")
+                    help="skip the adjacency, VarLiNGAM, bootstrap and phase-boundary "
+                         "records (their kernels would mix into a profile of the plain "
+                         "ordering)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device-to-device with a plain copy "
                          "kernel (reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -663,6 +691,8 @@ def main() -> int:
                                                        sem.B)
         progress("varlingam (stock shape)")
         rec["varlingam"] = run_varlingam(lg)
+        progress("phase-boundary probe (launch vs grid barrier)")
+        rec["phase_boundary"] = sync_probe()
     if not args.no_batch and args.workload == "gene":
         rec["batch"] = bench_batch(max(1, args.steps), args.warmup, args.seed, rates)
         if not args.no_aux:
