@@ -521,9 +521,11 @@ void save_tune_file(const DevState& ds) {
 // every position below m is valid while the active list is still the
 // identity), in three rounds: the split policy (the only choice that moves
 // results, at the rounding level), then the waves per workgroup of the
-// all-pairs kernel, then, for the learned form, of the row kernels (timed on
-// the candidate pass after that step's features, scores and top-K).  Ties
-// keep the earlier candidate.
+// all-pairs kernel, then, for the learned form, of the row kernels.  Row
+// kernels are timed on the candidate pass after that step's features, scores
+// and top-K; the learned form's split policy is timed there too, since its
+// candidate passes, not the all-pairs kernel, carry its pair work.  Ties keep
+// the earlier candidate.
 int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStream_t st,
              bool ties, lg::Tune* out) {
   lg::JobDev* table = reinterpret_cast<lg::JobDev*>(ws + P.table_off);
@@ -536,6 +538,7 @@ int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStrea
   }
   *out = kDefaultTune;
   if (steps.empty()) return LINGAM_OK;
+  const bool learned = P.lc.proposer != nullptr;
   Timer tm;
   // summed time of the sampled steps' pair kernel (all pairs, or candidate rows)
   auto time_steps = [&](const lg::Tune& c, bool rows, double* total) -> int {
@@ -578,7 +581,7 @@ int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStrea
     for (int round = 0; round < 2; ++round)
       for (int i = 0; i < nv; ++i) {
         double ms = 0.0;
-        const int rc = time_steps(set(i), field == 2, &ms);
+        const int rc = time_steps(set(i), field == 2 || (field == 0 && learned), &ms);
         if (rc != LINGAM_OK) return rc;
         if (ms >= 0.0 && (score[i] < 0.0 || ms < score[i])) score[i] = ms;
       }
@@ -593,7 +596,7 @@ int autotune(const Plan& P, const std::vector<HostJob>& jobs, char* ws, hipStrea
   int rc = pick(kDefaultTune, 0, &kSplitCandidates[0][0],
                 (int)(sizeof(kSplitCandidates) / sizeof(kSplitCandidates[0])));
   if (rc == LINGAM_OK) rc = pick(*out, 1, kWaveChoices, 3);
-  if (rc == LINGAM_OK && P.lc.proposer) rc = pick(*out, 2, kWaveChoices, 3);
+  if (rc == LINGAM_OK && learned) rc = pick(*out, 2, kWaveChoices, 3);
   return rc;
 }
 

@@ -237,6 +237,27 @@ def test_exact_form_equals_plain_with_either_tie_rule(lib, fp32_ties):
         assert np.array_equal(out["order"].cpu().numpy(), plain), seed
 
 
+def test_autotuned_exact_form_equals_plain(lib):
+    """The launch-shape autotuner on a learned call (split policy and row
+    waves timed on the candidate pass, all-pairs waves on the full step)
+    keeps the exact form's order equal to the plain order, on the tuning call
+    and on a later call that reuses the tuned shape.  Shipped network,
+    d = 600, n = 6000."""
+    from paper_2403_03772_amd import train_proposer as TP
+    if not os.path.exists(TP.WEIGHTS):
+        pytest.skip("no trained network shipped")
+    s = _sem(600, 6000, 7)
+    X = _t(s.X)
+    plain = lib.causal_order(X).cpu().numpy()
+    cfg = lib.Learned(TP.default_proposer(), topk=64)
+    for rep in range(2):
+        out = lib.causal_order(X, learned=cfg, autotune=True)
+        st = out["learned_stats"]
+        print(f"autotuned learned call {rep}: {st}", flush=True)
+        assert st.learned_steps > 0 and st.fallbacks == 0
+        assert np.array_equal(out["order"].cpu().numpy(), plain), rep
+
+
 def _oracle_step(X32, prefix, prop, K):
     """Oracle scores and exact k at the state after `prefix`."""
     Xc = X32.astype(np.float64)
