@@ -244,7 +244,8 @@ int lingam_probe_sync(int rounds, double* out) {
   per_cu = per_cu < 4 ? per_cu : 4;
   const int grid = cu * per_cu;
   if (grid < 1) return (int)hipErrorInvalidConfiguration;
-  const int spin_limit = 5000;  // polls (a device-scope load and a short sleep each): ms per wait at most
+  // a poll is a device-scope load and a short sleep: milliseconds per wait at most
+  const int spin_limit = 5000;
   constexpr int kBar = 64 * 9;  // top count, then 8 group counts 256 bytes apart
   unsigned* buf = nullptr;      // [0, kBar) counts, [kBar] late waits, then per-workgroup
   e = hipMalloc(&buf, sizeof(unsigned) * (size_t)(kBar + 1 + grid));
