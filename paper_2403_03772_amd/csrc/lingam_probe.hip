@@ -291,7 +291,8 @@ int lingam_probe_sync(int rounds, double* out) {
     int rr = rounds, sl = spin_limit;
     void* args[] = {&bar, &cnt, &rr, &sl, &late};
     for (int which = 2; which < 5 && e == hipSuccess; ++which) {
-      const void* fn = which == 2 ? (const void*)k_probe_barrier<1> : (const void*)k_probe_barrier<8>;
+      const void* fn =
+          which == 2 ? (const void*)k_probe_barrier<1> : (const void*)k_probe_barrier<8>;
       const int gw = which == 4 ? cu : grid;
       for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
         e = hipMemsetAsync(bar, 0, sizeof(unsigned) * kBar, st);  // counts restart at 0
