@@ -98,6 +98,21 @@ void check_step(int32_t d, int32_t t, int32_t K, int32_t min_m) {
   }
 }
 
+// The learned step's second-pass and extension sizes: at most cap_s suspects,
+// a multiple of 8, and only while the second pass stays cheaper than the
+// full step (2 (K + S) <= m rows); extension columns clamp m - K to ne_max.
+void check_bounds(int32_t m, int32_t K, int32_t cap) {
+  const int32_t c = suspect_cap(m, K, cap);
+  expect(c >= 0 && c % 8 == 0 && c <= cap, "suspect cap a multiple of 8 within the room", m, K,
+         cap, c);
+  if (c > 0) expect(2 * (K + c) <= m, "second pass cheaper than the full step", m, K, cap, c);
+  for (int32_t ne : {0, 8, 128, kMaxExt}) {
+    const int32_t e = ext_count(m, K, ne);
+    const int32_t want = m - K < 0 ? 0 : (m - K < ne ? m - K : ne);
+    expect(e == want, "extension columns", m, K, ne, e);
+  }
+}
+
 }  // namespace
 
 int main() {
@@ -119,6 +134,10 @@ int main() {
     for (int32_t K : {0, 16, 64, 256})
       for (int32_t min_m : {0, 128})
         for (int32_t t = 0; t < d; t += (d > 300 ? 97 : 1)) check_step(d, t, K, min_m);
+
+  for (int32_t m = 2; m <= 5000; ++m)
+    for (int32_t K : {8, 32, 64, 256})
+      for (int32_t cap : {0, 8, 1000, kMaxSuspects}) check_bounds(m, K, cap);
 
   std::printf("%s %ld checks, %ld failed\n", g_fail ? "FAILED" : "ok", g_checks, g_fail);
   return g_fail ? 1 : 0;

@@ -18,7 +18,10 @@ there makes a kernel skip or repeat work, or read out of bounds.
   counts up to the largest tile count, n_pad up to 2^30 and every policy the
   autotuner can pick;
 * ``job_step_base``: the FP64 path for m <= 64, blocks and tiles covering the
-  active variables, candidates between min(32, K) and K.
+  active variables, candidates between min(32, K) and K;
+* ``suspect_cap`` / ``ext_count``: suspects a multiple of 8 within the
+  layout's room and only while the second pass stays cheaper than the full
+  step; extension columns m - K clamped to the cap.
 """
 import os
 import shutil
