@@ -69,6 +69,15 @@ void check_split(int64_t items, int32_t n_pad, int32_t cu, Tune tu) {
   // workgroups of the largest kind stay in int32: items x splits x 4 quadrant items
   expect((double)items * ns * 4 < 2147483647.0, "workgroup count fits int32", (long)items, n_pad,
          ns, len);
+  // more items over the batch never give a job more splits, so a launch bound
+  // computed from one job's items bounds the plan the device makes from the
+  // batch's (the suspect pass's bound on the host)
+  for (int64_t more : {items + 1, 2 * items, 7 * items + 3}) {
+    int32_t ns2 = 0, len2 = 0;
+    split_for(more, n_pad, cu, tu, ns2, len2);
+    expect(ns2 <= ns, "splits do not grow with the batch's items", (long)items, (long)more, ns,
+           ns2);
+  }
 }
 
 // A step's plan: the FP64 path up to kFp64MaxM active variables, the upper
