@@ -69,6 +69,19 @@ void check_split(int64_t items, int32_t n_pad, int32_t cu, Tune tu) {
   // workgroups of the largest kind stay in int32: items x splits x 4 quadrant items
   expect((double)items * ns * 4 < 2147483647.0, "workgroup count fits int32", (long)items, n_pad,
          ns, len);
+  // the splits stop at about target_per_cu workgroups per CU: items x splits
+  // <= items + num_cu x target_per_cu, so a pass of T tiles (2 T items) holds
+  // at most T + num_cu x target_per_cu / 2 tile-splits of partial sums (the
+  // suspect pass's workspace bound)
+  expect(items * ns <= items + (int64_t)cu * tu.target_per_cu, "splits stop near the target",
+         (long)items, n_pad, ns, (long)cu * tu.target_per_cu);
+  // the most aggressive policy splits the most (the workspace is sized for
+  // it): more splits with a larger target, or a smaller min_iters
+  if (tu.target_per_cu < kMaxTargetPerCu || tu.min_iters > kMinMinIters) {
+    int32_t nsw = 0, lenw = 0;
+    split_for(items, n_pad, cu, Tune{kMaxTargetPerCu, kMinMinIters, 4, 4}, nsw, lenw);
+    expect(nsw >= ns, "the most aggressive policy splits the most", (long)items, n_pad, ns, nsw);
+  }
   // more items over the batch never give a job more splits, so a launch bound
   // computed from one job's items bounds the plan the device makes from the
   // batch's (the suspect pass's bound on the host)

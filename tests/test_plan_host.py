@@ -14,9 +14,12 @@ there makes a kernel skip or repeat work, or read out of bounds.
   supported d (32768 variables: nb = 4096);
 * ``split_for`` covers [0, n_pad) with whole 64-sample quanta, the last split
   non-empty, no split shorter than ``min_iters`` quanta, never more splits
-  than ``min_iters`` allows, workgroup counts within int32, and never more
-  splits for more items (so the host's launch bound from one job's items
-  bounds the device's plan from the batch's), over item counts up to the
+  than ``min_iters`` allows, workgroup counts within int32, items x splits
+  at most items + CUs x target (the suspect pass's workspace bound), the
+  most aggressive policy splitting the most (the policy the workspace is
+  sized for), and never more splits for more items (so the host's launch
+  bound from one job's items bounds the device's plan from the batch's),
+  over item counts up to the
   largest tile count, n_pad up to 2^30 and every policy the autotuner can
   pick;
 * ``job_step_base``: the FP64 path for m <= 64, blocks and tiles covering the
